@@ -1,0 +1,115 @@
+/*
+ * ORACLE for the string sorter -- TEST INFRASTRUCTURE ONLY.
+ *
+ * Only the test suite, the smoke check and the benchmark's CPU-baseline leg
+ * may load this file.  The product (the HIP library and its Python binding)
+ * never calls it, and it shares no code with the GPU path.
+ *
+ * What it computes (the definition of the result, section 2.1 "Notation and
+ * Preliminaries"):
+ *   - string i is chars[offsets[i] .. offsets[i+1]); every byte 0..255 is a
+ *     character, compared as an unsigned value;
+ *   - a < b lexicographically: at the first differing position the smaller
+ *     byte wins; if one string is a proper prefix of the other, the shorter
+ *     one is smaller (the empty string is smallest), which is what the
+ *     zero-terminator convention of section 2.1 gives;
+ *   - equal strings are ordered by their original index, so the output
+ *     permutation is unique;
+ *   - lcp[0] = 0 (the undefined first entry of the LCP array H, read as the
+ *     LCP with the empty string), lcp[k] = length of the longest common
+ *     prefix of the strings at sorted positions k-1 and k (section 2.1).
+ *
+ * ss_oracle_sort: the definition written out -- a library comparison sort
+ *   (qsort) of the indices with a memcmp comparator, then a brute-force
+ *   character loop for each adjacent LCP.  Single-threaded, unoptimised.
+ * ss_oracle_check: verifies a claimed (perm, lcp) against the same
+ *   definition without sorting: perm is a permutation, each adjacent pair is
+ *   strictly increasing in (string, index) order, and each lcp entry equals
+ *   the brute-force common prefix.  Because the correct output is unique,
+ *   passing this check is equivalent to equality with ss_oracle_sort.
+ */
+#define _GNU_SOURCE
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+typedef struct {
+    const uint8_t* chars;
+    const uint64_t* offsets;
+} strset_t;
+
+/* three-way comparison of strings a and b by (bytes, length, index) */
+static int cmp_idx(const strset_t* S, uint32_t a, uint32_t b) {
+    const uint8_t* sa = S->chars + S->offsets[a];
+    const uint8_t* sb = S->chars + S->offsets[b];
+    uint64_t la = S->offsets[a + 1] - S->offsets[a];
+    uint64_t lb = S->offsets[b + 1] - S->offsets[b];
+    uint64_t m = la < lb ? la : lb;
+    int c = m ? memcmp(sa, sb, (size_t)m) : 0;   /* memcmp compares unsigned bytes */
+    if (c) return c < 0 ? -1 : 1;
+    if (la != lb) return la < lb ? -1 : 1;      /* proper prefix is smaller */
+    if (a != b) return a < b ? -1 : 1;          /* ties by original index */
+    return 0;
+}
+
+static int qsort_cmp(const void* pa, const void* pb, void* ctx) {
+    return cmp_idx((const strset_t*)ctx, *(const uint32_t*)pa, *(const uint32_t*)pb);
+}
+
+/* longest common prefix of strings a and b by a character loop */
+static uint32_t lcp_brute(const strset_t* S, uint32_t a, uint32_t b) {
+    const uint8_t* sa = S->chars + S->offsets[a];
+    const uint8_t* sb = S->chars + S->offsets[b];
+    uint64_t la = S->offsets[a + 1] - S->offsets[a];
+    uint64_t lb = S->offsets[b + 1] - S->offsets[b];
+    uint64_t m = la < lb ? la : lb, k = 0;
+    while (k < m && sa[k] == sb[k]) ++k;
+    return (uint32_t)k;
+}
+
+/* Sorts indices 0..n-1 and fills perm[0..n) and lcp[0..n).  Returns 0. */
+int ss_oracle_sort(const uint8_t* chars, const uint64_t* offsets, uint32_t n,
+                   uint32_t* perm, uint32_t* lcp) {
+    strset_t S = {chars, offsets};
+    for (uint32_t i = 0; i < n; ++i) perm[i] = i;
+    qsort_r(perm, n, sizeof(uint32_t), qsort_cmp, &S);
+    if (n) lcp[0] = 0;
+    for (uint32_t k = 1; k < n; ++k) lcp[k] = lcp_brute(&S, perm[k - 1], perm[k]);
+    return 0;
+}
+
+/* Returns -1 when (perm, lcp) is the correct output, otherwise a code
+ *   k               first sorted position k whose lcp entry is wrong,
+ *   n + k           first position k >= 1 where (perm[k-1], perm[k]) is not
+ *                   strictly increasing in (string, index) order,
+ *   2n + i          perm is not a permutation (i = first bad entry),
+ *   3n              lcp[0] != 0.                                           */
+long long ss_oracle_check(const uint8_t* chars, const uint64_t* offsets, uint32_t n,
+                          const uint32_t* perm, const uint32_t* lcp) {
+    strset_t S = {chars, offsets};
+    uint8_t* seen = (uint8_t*)calloc((size_t)n + 1, 1);
+    if (!seen) return -2;
+    for (uint32_t i = 0; i < n; ++i) {
+        if (perm[i] >= n || seen[perm[i]]) { free(seen); return 2LL * n + i; }
+        seen[perm[i]] = 1;
+    }
+    free(seen);
+    if (n && lcp[0] != 0) return 3LL * n;
+    for (uint32_t k = 1; k < n; ++k)
+        if (cmp_idx(&S, perm[k - 1], perm[k]) >= 0) return (long long)n + k;
+    for (uint32_t k = 1; k < n; ++k)
+        if (lcp[k] != lcp_brute(&S, perm[k - 1], perm[k])) return k;
+    return -1;
+}
+
+/* Brute-force LCP of two strings (used by sampled checks). */
+uint32_t ss_oracle_lcp(const uint8_t* chars, const uint64_t* offsets, uint32_t a, uint32_t b) {
+    strset_t S = {chars, offsets};
+    return lcp_brute(&S, a, b);
+}
+
+/* Three-way comparison of two strings by (bytes, length, index). */
+int ss_oracle_compare(const uint8_t* chars, const uint64_t* offsets, uint32_t a, uint32_t b) {
+    strset_t S = {chars, offsets};
+    return cmp_idx(&S, a, b);
+}
