@@ -1,0 +1,174 @@
+/*
+ * libss -- string sample sort on one AMD Instinct MI355X (gfx950).
+ *
+ * C ABI.  Sorts a set of n byte strings lexicographically and returns the
+ * sorted permutation and the LCP array, the problem of section 2.1 of
+ * Bingmann, "Scalable String and Suffix Sorting" (arXiv:1808.00963): the
+ * array S = [s_0 .. s_{n-1}] of n strings with N characters in total is
+ * sorted lexicographically, and the LCP array H holds for each sorted
+ * position k >= 1 the length of the longest common prefix of the strings at
+ * positions k-1 and k.
+ *
+ * Conventions shared by every entry point
+ * ----------------------------------------
+ * Input layout.  `chars` holds the characters of all strings back to back;
+ * `offsets` holds n+1 non-decreasing 64-bit byte offsets into `chars`:
+ * string i is chars[offsets[i] .. offsets[i+1]).  Every byte value 0..255 is
+ * a character (compared unsigned); strings carry explicit lengths instead of
+ * the paper's zero terminator, so a proper prefix sorts before the longer
+ * string, as with a terminator smaller than every character (section 2.1).
+ *
+ * Output.  perm_out[k] = index of the string at sorted position k; equal
+ * strings keep their input order (ties by original index), which makes the
+ * result unique.  lcp_out[0] = 0 (the paper's undefined first entry),
+ * lcp_out[k] = LCP(s_{perm[k-1]}, s_{perm[k]}).
+ *
+ * Memory.  Unless stated otherwise every pointer is a DEVICE pointer on the
+ * current HIP device, allocated and owned by the caller; the library never
+ * frees it.  Inputs are read only.  perm_out and lcp_out must not alias each
+ * other or the inputs.  The chars buffer must be readable up to
+ * offsets[n]; the library also reads the aligned 8-byte words that contain
+ * the first and last character of each string (never past a page that
+ * holds a character).
+ *
+ * Streams and errors.  `stream` is a hipStream_t (NULL = default stream).
+ * Calls enqueue work on `stream`; they synchronise with the host between
+ * recursion levels (the host reads a few counters per level), and return
+ * when the last kernel has been enqueued.  Host-detectable errors return
+ * immediately without touching the outputs.  Errors detected on the device
+ * (non-monotone offsets, a string of 2^31 or more bytes, an internal limit)
+ * are returned by the call that detects them and are sticky in the context:
+ * ss_get_last_error reports them until ss_clear_error.
+ *
+ * Limits.  n <= 2^32 - 2 strings; each string shorter than 2^31 bytes.
+ * n = 0 is a no-op.
+ */
+#ifndef SS_H
+#define SS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int ss_status;
+#define SS_OK 0
+#define SS_INVALID_ARG 1      /* null pointer, bad size, bad set boundaries */
+#define SS_OUT_OF_MEMORY 2    /* workspace allocation failed */
+#define SS_HIP_ERROR 3        /* a HIP runtime call failed */
+#define SS_LIMIT 4            /* n or a string length beyond the limits above,
+                                 or non-monotone offsets (detected on device) */
+#define SS_REJECTED 5         /* serving: request does not fit the budget */
+#define SS_TIMEOUT 6          /* serving: wait timed out */
+#define SS_INTERNAL 7         /* an internal capacity check failed */
+
+typedef struct ss_ctx ss_ctx;
+
+/* Tunable parameters (performance only; results never depend on them). */
+typedef struct {
+    uint32_t max_log_splitters; /* d_max: at most v = 2^d_max - 1 splitters
+                                   per distribution step (section 4.2.2),
+                                   1..10, default 10 */
+    uint32_t bucket_target;     /* expected strings per bucket used to pick
+                                   v for a segment, default 512 */
+    uint32_t base_max;          /* segments with at most this many strings go
+                                   to the in-LDS base case, 64..2048,
+                                   default 2048 */
+} ss_config;
+
+/* Returns a short description of a status code (static storage). */
+const char* ss_status_string(ss_status s);
+
+/* Library version string (static storage). */
+const char* ss_version(void);
+
+/* Creates a context bound to HIP device `device`.  The context owns a
+ * grow-only workspace (freed by ss_ctx_destroy); `scratch_limit` bytes caps
+ * it (0 = no cap; a call needing more returns SS_OUT_OF_MEMORY).  One
+ * context must not be used by two host threads at once. */
+ss_status ss_ctx_create(ss_ctx** ctx, int device, size_t scratch_limit);
+void ss_ctx_destroy(ss_ctx* ctx);
+
+/* Reads / replaces the tuning parameters of a context.  Out-of-range fields
+ * are clamped. */
+ss_status ss_get_config(const ss_ctx* ctx, ss_config* cfg);
+ss_status ss_set_config(ss_ctx* ctx, const ss_config* cfg);
+
+/* Bytes of workspace a sort of n strings needs (host function, no device
+ * access). */
+ss_status ss_workspace_query(const ss_ctx* ctx, uint32_t n, size_t* bytes);
+
+/* Sorts one string set (section 2.1 problem, method of section 4.2:
+ * string sample sort with 8-byte keys, equality buckets and an LCP array).
+ * chars: device, offsets[n] bytes; offsets: device, n+1 uint64;
+ * perm_out, lcp_out: device, n uint32 each. */
+ss_status ss_sort_ex(ss_ctx* ctx, const uint8_t* chars, const uint64_t* offsets, uint32_t n,
+                     uint32_t* perm_out, uint32_t* lcp_out, void* stream);
+
+/* Same as ss_sort_ex with an implicit per-device context (created on first
+ * use on the current device, kept until process exit, internally locked). */
+ss_status ss_sort(const uint8_t* chars, const uint64_t* offsets, uint32_t n,
+                  uint32_t* perm_out, uint32_t* lcp_out, void* stream);
+
+/* Batched form: sorts num_sets independent string sets in one pass of the
+ * pipeline (all sets' segments are processed by the same kernel launches).
+ * The strings of all sets are given as one string array (chars, offsets
+ * with offsets[set_begin[num_sets]] characters); set j consists of strings
+ * set_begin[j] .. set_begin[j+1]-1.  set_begin: device, num_sets+1
+ * non-decreasing uint32 with set_begin[0] = 0; n = set_begin[num_sets] is
+ * passed as `n` and checked on the device.  Output position p of set j
+ * (set_begin[j] <= p < set_begin[j+1]) receives a SET-LOCAL index:
+ * perm_out[p] = i - set_begin[j] for the string i sorted there, and
+ * lcp_out[set_begin[j]] = 0. */
+ss_status ss_sort_batch(ss_ctx* ctx, const uint8_t* chars, const uint64_t* offsets, uint32_t n,
+                        const uint32_t* set_begin, uint32_t num_sets,
+                        uint32_t* perm_out, uint32_t* lcp_out, void* stream);
+
+/* Sticky device-side error of a context (SS_OK if none). */
+ss_status ss_get_last_error(const ss_ctx* ctx);
+void ss_clear_error(ss_ctx* ctx);
+
+/* Statistics of the last sort on a context (host values, filled after the
+ * call returns): recursion levels, distribution steps, base-case segments,
+ * pending boundary LCPs. */
+typedef struct {
+    uint32_t levels;
+    uint32_t dist_segments;
+    uint32_t dist_tiles;
+    uint32_t base_segments;
+    uint32_t pending_lcps;
+    uint32_t max_depth;
+} ss_stats;
+ss_status ss_get_stats(const ss_ctx* ctx, ss_stats* st);
+
+/* ---- host-side test entry points (no device access) -------------------
+ * These run the same primitive functions the kernels use, on the host, so
+ * the test suite can check them on a machine without a GPU. */
+
+/* Key of string bytes s[h .. h+8) (host pointers), big-endian, zero padded;
+ * *r_out = min(len - h, 8). */
+uint64_t ss_host_key(const uint8_t* s, uint64_t len, uint64_t h, uint32_t* r_out);
+
+/* Lemma 4.1 mapping: level-order index of in-order position j (d levels),
+ * and its inverse. */
+uint32_t ss_host_level_index(uint32_t j, uint32_t d);
+uint32_t ss_host_inorder_index(uint32_t l, uint32_t d);
+
+/* Builds the level-order tree of v = 2^d - 1 sorted splitters (host arrays
+ * xk[v], xr[v], in-order) and classifies m keys (ck[m], cr[m]) into
+ * buckets[m] (0..2v).  Returns 0. */
+int ss_host_classify(const uint64_t* xk, const uint32_t* xr, uint32_t d,
+                     const uint64_t* ck, const uint32_t* cr, uint32_t m, uint32_t* buckets);
+
+/* Splitter selection of section 4.2.2 ("Sampling"): from a sorted sample
+ * (host arrays sk[a], sr[a]) picks v = 2^d - 1 in-order splitters
+ * (xk[v], xr[v]) by recursive middle selection skipping duplicates. */
+int ss_host_select_splitters(const uint64_t* sk, const uint32_t* sr, uint32_t a, uint32_t d,
+                             uint64_t* xk, uint32_t* xr);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SS_H */

@@ -1,0 +1,243 @@
+"""String sample sort on one AMD Instinct MI355X (gfx950).
+
+Thin ctypes binding of ``libss.so`` (C ABI in ``include/ss.h``).  Tensors
+provide device memory and streams; every step of the sort runs in the HIP
+kernels of the library.  The binding only marshals arguments: it never sorts
+or computes LCPs itself, and it raises if the compiled library is missing.
+
+    import torch, paper_1808_00963_amd as ss
+    perm, lcp = ss.sort(chars_u8_cuda, offsets_i64_cuda)
+
+Outputs are uint32 values stored in int32 tensors.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch  # loaded first so the library binds to torch's HIP runtime
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libss.so")
+
+SS_OK, SS_INVALID_ARG, SS_OUT_OF_MEMORY, SS_HIP_ERROR, SS_LIMIT, SS_REJECTED, SS_TIMEOUT, SS_INTERNAL = range(8)
+
+_lib = None
+
+
+class SSError(RuntimeError):
+    def __init__(self, status: int, what: str = ""):
+        self.status = status
+        super().__init__(f"{what}: {status_string(status)} (status {status})")
+
+
+class Config(ctypes.Structure):
+    _fields_ = [("max_log_splitters", ctypes.c_uint32), ("bucket_target", ctypes.c_uint32),
+                ("base_max", ctypes.c_uint32)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("levels", ctypes.c_uint32), ("dist_segments", ctypes.c_uint32),
+                ("dist_tiles", ctypes.c_uint32), ("base_segments", ctypes.c_uint32),
+                ("pending_lcps", ctypes.c_uint32), ("max_depth", ctypes.c_uint32)]
+
+
+def lib():
+    """Loads libss.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with paper_1808_00963_amd.build.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, u32, u64, i32 = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int
+        sig = {
+            "ss_status_string": (ctypes.c_char_p, [i32]),
+            "ss_version": (ctypes.c_char_p, []),
+            "ss_ctx_create": (i32, [ctypes.POINTER(vp), i32, ctypes.c_size_t]),
+            "ss_ctx_destroy": (None, [vp]),
+            "ss_get_config": (i32, [vp, ctypes.POINTER(Config)]),
+            "ss_set_config": (i32, [vp, ctypes.POINTER(Config)]),
+            "ss_workspace_query": (i32, [vp, u32, ctypes.POINTER(ctypes.c_size_t)]),
+            "ss_sort_ex": (i32, [vp, vp, vp, u32, vp, vp, vp]),
+            "ss_sort": (i32, [vp, vp, u32, vp, vp, vp]),
+            "ss_sort_batch": (i32, [vp, vp, vp, u32, vp, u32, vp, vp, vp]),
+            "ss_get_last_error": (i32, [vp]),
+            "ss_clear_error": (None, [vp]),
+            "ss_get_stats": (i32, [vp, ctypes.POINTER(Stats)]),
+            "ss_host_key": (u64, [vp, u64, u64, ctypes.POINTER(u32)]),
+            "ss_host_level_index": (u32, [u32, u32]),
+            "ss_host_inorder_index": (u32, [u32, u32]),
+            "ss_host_classify": (i32, [vp, vp, u32, vp, vp, u32, vp]),
+            "ss_host_select_splitters": (i32, [vp, vp, u32, u32, vp, vp]),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def status_string(status: int) -> str:
+    return lib().ss_status_string(status).decode()
+
+
+def version() -> str:
+    return lib().ss_version().decode()
+
+
+def _check(status: int, what: str):
+    if status != SS_OK:
+        raise SSError(status, what)
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _check_inputs(chars: torch.Tensor, offsets: torch.Tensor):
+    if not (chars.is_cuda and offsets.is_cuda):
+        raise ValueError("chars and offsets must be device tensors")
+    if chars.dtype != torch.uint8 or offsets.dtype not in (torch.int64, torch.uint64):
+        raise TypeError("chars must be uint8 and offsets int64/uint64")
+    if not (chars.is_contiguous() and offsets.is_contiguous()):
+        raise ValueError("inputs must be contiguous")
+    if offsets.numel() < 1:
+        raise ValueError("offsets needs n+1 entries")
+
+
+class Context:
+    """An ss_ctx: owns the device workspace of one host thread's sorts."""
+
+    def __init__(self, device: int | None = None, scratch_limit: int = 0):
+        self._h = ctypes.c_void_p()
+        dev = torch.cuda.current_device() if device is None else device
+        _check(lib().ss_ctx_create(ctypes.byref(self._h), dev, scratch_limit), "ss_ctx_create")
+        self.device = dev
+
+    def close(self):
+        if self._h:
+            lib().ss_ctx_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def config(self) -> Config:
+        c = Config()
+        _check(lib().ss_get_config(self._h, ctypes.byref(c)), "ss_get_config")
+        return c
+
+    def set_config(self, max_log_splitters=None, bucket_target=None, base_max=None):
+        c = self.config
+        if max_log_splitters is not None:
+            c.max_log_splitters = max_log_splitters
+        if bucket_target is not None:
+            c.bucket_target = bucket_target
+        if base_max is not None:
+            c.base_max = base_max
+        _check(lib().ss_set_config(self._h, ctypes.byref(c)), "ss_set_config")
+
+    def stats(self) -> dict:
+        s = Stats()
+        _check(lib().ss_get_stats(self._h, ctypes.byref(s)), "ss_get_stats")
+        return {f: getattr(s, f) for f, _ in Stats._fields_}
+
+    def workspace_bytes(self, n: int) -> int:
+        b = ctypes.c_size_t()
+        _check(lib().ss_workspace_query(self._h, n, ctypes.byref(b)), "ss_workspace_query")
+        return b.value
+
+    def last_error(self) -> int:
+        return lib().ss_get_last_error(self._h)
+
+    def clear_error(self):
+        lib().ss_clear_error(self._h)
+
+    def sort(self, chars, offsets, perm=None, lcp=None, stream=None):
+        """Sorts one set; returns (perm, lcp) int32 tensors holding uint32."""
+        _check_inputs(chars, offsets)
+        n = offsets.numel() - 1
+        if perm is None:
+            perm = torch.empty(n, dtype=torch.int32, device=chars.device)
+        if lcp is None:
+            lcp = torch.empty(n, dtype=torch.int32, device=chars.device)
+        st = lib().ss_sort_ex(self._h, ctypes.c_void_p(chars.data_ptr()), ctypes.c_void_p(offsets.data_ptr()), n,
+                              ctypes.c_void_p(perm.data_ptr()), ctypes.c_void_p(lcp.data_ptr()),
+                              _stream_ptr(stream))
+        _check(st, "ss_sort_ex")
+        return perm, lcp
+
+    def sort_batch(self, chars, offsets, set_begin, perm=None, lcp=None, stream=None):
+        """Sorts the sets delimited by set_begin (int32/uint32 device tensor,
+        num_sets+1 entries); outputs hold set-local indices."""
+        _check_inputs(chars, offsets)
+        if not set_begin.is_cuda or set_begin.dtype not in (torch.int32, torch.uint32):
+            raise TypeError("set_begin must be an int32/uint32 device tensor")
+        n = offsets.numel() - 1
+        num_sets = set_begin.numel() - 1
+        if perm is None:
+            perm = torch.empty(n, dtype=torch.int32, device=chars.device)
+        if lcp is None:
+            lcp = torch.empty(n, dtype=torch.int32, device=chars.device)
+        st = lib().ss_sort_batch(self._h, ctypes.c_void_p(chars.data_ptr()), ctypes.c_void_p(offsets.data_ptr()), n,
+                                 ctypes.c_void_p(set_begin.data_ptr()), num_sets,
+                                 ctypes.c_void_p(perm.data_ptr()), ctypes.c_void_p(lcp.data_ptr()),
+                                 _stream_ptr(stream))
+        _check(st, "ss_sort_batch")
+        return perm, lcp
+
+
+def sort(chars, offsets, stream=None):
+    """ss_sort with the implicit per-device context."""
+    _check_inputs(chars, offsets)
+    n = offsets.numel() - 1
+    perm = torch.empty(n, dtype=torch.int32, device=chars.device)
+    lcp = torch.empty(n, dtype=torch.int32, device=chars.device)
+    st = lib().ss_sort(ctypes.c_void_p(chars.data_ptr()), ctypes.c_void_p(offsets.data_ptr()), n,
+                       ctypes.c_void_p(perm.data_ptr()), ctypes.c_void_p(lcp.data_ptr()), _stream_ptr(stream))
+    _check(st, "ss_sort")
+    return perm, lcp
+
+
+# ---- host-side test entry points (no GPU needed) ----
+
+def host_key(s: bytes, h: int):
+    buf = ctypes.create_string_buffer(s, len(s) + 16)
+    r = ctypes.c_uint32()
+    k = lib().ss_host_key(ctypes.cast(buf, ctypes.c_void_p), len(s), h, ctypes.byref(r))
+    return int(k), int(r.value)
+
+
+def host_level_index(j: int, d: int) -> int:
+    return int(lib().ss_host_level_index(j, d))
+
+
+def host_inorder_index(l: int, d: int) -> int:
+    return int(lib().ss_host_inorder_index(l, d))
+
+
+def host_classify(xk, xr, d, ck, cr):
+    import numpy as np
+    xk = np.ascontiguousarray(xk, np.uint64); xr = np.ascontiguousarray(xr, np.uint32)
+    ck = np.ascontiguousarray(ck, np.uint64); cr = np.ascontiguousarray(cr, np.uint32)
+    out = np.zeros(len(ck), np.uint32)
+    _check(lib().ss_host_classify(xk.ctypes.data, xr.ctypes.data, d, ck.ctypes.data, cr.ctypes.data, len(ck),
+                                  out.ctypes.data), "ss_host_classify")
+    return out
+
+
+def host_select_splitters(sk, sr, d):
+    import numpy as np
+    sk = np.ascontiguousarray(sk, np.uint64); sr = np.ascontiguousarray(sr, np.uint32)
+    v = (1 << d) - 1
+    xk = np.zeros(v, np.uint64); xr = np.zeros(v, np.uint32)
+    _check(lib().ss_host_select_splitters(sk.ctypes.data, sr.ctypes.data, len(sk), d, xk.ctypes.data, xr.ctypes.data),
+           "ss_host_select_splitters")
+    return xk, xr

@@ -1,0 +1,135 @@
+// Primitive operations of the string sample sort, shared by the gfx950
+// kernels and by host-side test entry points (so their logic can be checked
+// on the CPU).  Nothing here allocates or launches.
+#pragma once
+#include <stdint.h>
+
+#include <hip/hip_runtime.h>
+
+#define SS_HD __host__ __device__ __forceinline__
+
+namespace ss {
+
+// Characters per machine word: keys hold w = 8 bytes of a string at the
+// current depth, most significant byte first ("chars_h", section 4.2.2,
+// paragraph "Character Reordering").
+constexpr uint32_t W = 8;
+
+// Assembles the 8-byte big-endian key of the bytes starting at byte `sh`
+// (0..7) of the little-endian aligned word `w0`, continuing into `w1`, and
+// keeps only the first `rem` bytes (rem = characters left in the string,
+// clamped to 8); bytes past the string end are zero.
+SS_HD uint64_t key_from_words(uint64_t w0, uint64_t w1, uint32_t sh, uint32_t rem) {
+    if (rem == 0) return 0;
+    uint64_t le = sh ? ((w0 >> (8 * sh)) | (w1 << (64 - 8 * sh))) : w0;
+    uint64_t be = __builtin_bswap64(le);
+    if (rem >= 8) return be;
+    return be & ~(~0ull >> (8 * rem));
+}
+
+// Number of leading equal bytes of two big-endian keys (8 when equal).
+SS_HD uint32_t common_bytes(uint64_t a, uint64_t b) {
+    uint64_t x = a ^ b;
+    return x ? (uint32_t)(__builtin_clzll(x) >> 3) : 8u;
+}
+
+// LCP contribution of one word: the strings agree on the first
+// common_bytes(a, b) characters of the word, but not beyond the end of the
+// shorter string (ra, rb = characters of each string inside the word).
+SS_HD uint32_t lcp_word(uint64_t a, uint32_t ra, uint64_t b, uint32_t rb) {
+    uint32_t c = common_bytes(a, b);
+    c = c < ra ? c : ra;
+    return c < rb ? c : rb;
+}
+
+// Total order on (key, r) pairs: the 8 characters first, then the number
+// of characters inside the word, so a string ending inside the word sorts
+// before a longer one with the same (zero-padded) bytes.
+SS_HD bool kr_greater(uint64_t ka, uint32_t ra, uint64_t kb, uint32_t rb) {
+    return ka > kb || (ka == kb && ra > rb);
+}
+
+// Lemma 4.1 (section 4.2.2): one-based level-order index of the splitter at
+// zero-based in-order ("pre-order" in the paper) position j of a perfect
+// binary search tree with d levels (v = 2^d - 1 splitters).  In-order
+// position j+1 = rank * 2^(t+1) + 2^t where t = trailing zeros; the vertex
+// sits on level d-1-t at position `rank` of that level.
+SS_HD uint32_t level_index(uint32_t j, uint32_t d) {
+    uint32_t q = j + 1;
+    uint32_t t = (uint32_t)__builtin_ctz(q);
+    return (1u << (d - 1 - t)) + (q >> (t + 1));
+}
+
+// Inverse mapping: zero-based in-order position of level-order vertex l.
+SS_HD uint32_t inorder_index(uint32_t l, uint32_t d) {
+    uint32_t level = 31u - (uint32_t)__builtin_clz(l);  // floor(log2 l)
+    uint32_t rank = l - (1u << level);
+    uint32_t t = d - 1 - level;
+    return (rank << (t + 1)) + (1u << t) - 1;
+}
+
+// Classification (Algorithm 4.1, lines 7-11, with the comparison of line 9
+// taken as "go right when c is greater than the splitter"): descend the
+// level-order tree tk/tr (one-based, v = 2^d - 1 vertices) using only
+// comparisons, giving j = number of splitters smaller than c, then test c
+// for equality with the in-order splitter x_j found through level_index.
+// Returns the bucket 2j (strictly between x_{j-1} and x_j) or 2j+1 (equal
+// to x_j); 2v+1 buckets in total.
+template <typename KeyArr, typename RArr>
+SS_HD uint32_t classify(uint64_t c, uint32_t cr, const KeyArr& tk, const RArr& tr, uint32_t d) {
+    uint32_t q = 1;
+    for (uint32_t l = 0; l < d; ++l) {
+        uint32_t gt = kr_greater(c, cr, tk[q], tr[q]) ? 1u : 0u;
+        q = 2 * q + gt;
+    }
+    uint32_t v = (1u << d) - 1;
+    uint32_t j = q - (v + 1);
+    uint32_t b = 2 * j;
+    if (j < v) {
+        uint32_t lq = level_index(j, d);
+        if (tk[lq] == c && (uint32_t)tr[lq] == cr) b += 1;
+    }
+    return b;
+}
+
+// One step of the splitter selection heuristic (section 4.2.2, paragraph
+// "Sampling"): for a non-empty range [lo, hi) of the sorted sample (sk, sr)
+// take the middle sample as the splitter and find the boundaries of the run
+// of samples equal to it, so the two sub-ranges exclude it:
+//   *mid      = (lo + hi) / 2
+//   *left_hi  = first index in [lo, mid] whose sample is not smaller
+//   *right_lo = first index in [mid, hi) whose sample is greater (or hi)
+// Binary searches replace the paper's linear scans; the result is the same.
+template <typename KeyArr, typename RArr>
+SS_HD void select_node(const KeyArr& sk, const RArr& sr, uint32_t lo, uint32_t hi, uint32_t* mid,
+                       uint32_t* left_hi, uint32_t* right_lo) {
+    uint32_t m = (lo + hi) >> 1;
+    uint64_t xk = sk[m];
+    uint32_t xr = sr[m];
+    uint32_t a = lo, b = m;  // lower bound in [lo, m]
+    while (a < b) {
+        uint32_t c = (a + b) >> 1;
+        if (kr_greater(xk, xr, sk[c], sr[c])) a = c + 1; else b = c;
+    }
+    *left_hi = a;
+    a = m + 1; b = hi;       // upper bound in [m+1, hi)
+    while (a < b) {
+        uint32_t c = (a + b) >> 1;
+        if (kr_greater(sk[c], sr[c], xk, xr)) b = c; else a = c + 1;
+    }
+    *right_lo = a;
+    *mid = m;
+}
+
+// Number of splitter levels d for a segment of `size` strings: about
+// size / bucket_target splitters, as a power of two minus one, within
+// [1, max_logv].
+SS_HD uint32_t choose_logv(uint32_t size, uint32_t bucket_target, uint32_t max_logv) {
+    uint32_t q = size / (bucket_target ? bucket_target : 1);
+    uint32_t d = q >= 2 ? 31u - (uint32_t)__builtin_clz(q) : 1u;
+    if (d < 1) d = 1;
+    if (d > max_logv) d = max_logv;
+    return d;
+}
+
+}  // namespace ss

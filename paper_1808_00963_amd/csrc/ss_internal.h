@@ -1,0 +1,121 @@
+// Internal data structures and kernel launchers of libss.
+#pragma once
+#include <stdint.h>
+
+#include <hip/hip_runtime.h>
+
+namespace ss {
+
+// One string in flight: its 8-byte key at the segment's depth, its index in
+// the input (global over a batch) and its length.  16 bytes, so loads and
+// stores are single dwordx4 accesses.
+struct alignas(16) Elem {
+    uint64_t key;
+    uint32_t idx;
+    uint32_t len;
+};
+
+// A segment of the ping-pong element array that still needs a distribution
+// step (sample, classify, scatter; Algorithm 4.1).  All its strings share a
+// common prefix of `depth` characters.
+struct Seg {
+    uint32_t begin;     // first position
+    uint32_t size;      // number of strings
+    uint32_t depth;     // common prefix length h
+    uint32_t logv;      // d: v = 2^d - 1 splitters, 2v+1 buckets
+    uint32_t tree_off;  // first splitter in the tree pool
+    uint32_t cnt_off;   // first counter in the counter pool
+    uint32_t tile_off;  // first tile in the tile list
+    uint32_t obase;     // subtracted from indices written to perm (batch set start)
+};
+
+// A segment small enough for the in-LDS base case.
+struct BaseSeg {
+    uint32_t begin, size, depth, obase;
+};
+
+// Work-list sizes of one recursion level.
+struct Counts {
+    uint32_t n_dist;
+    uint32_t n_tiles;
+    uint32_t n_base;
+    uint32_t n_cnt;
+    uint32_t n_tree;
+    uint32_t max_depth;
+    uint32_t pad[2];
+};
+
+// Device-side control block.
+struct Ctl {
+    Counts c[2];
+    uint32_t n_pend;
+    uint32_t err;
+    uint32_t pad[2];
+};
+
+// Error bits raised on the device.
+enum : uint32_t {
+    ERR_OFFSETS = 1u,      // non-monotone offsets or string too long
+    ERR_CAPACITY = 2u,     // an internal pool overflowed
+    ERR_BOUNDS = 4u,       // a computed position fell outside its segment
+    ERR_SETS = 8u,         // batch set boundaries invalid
+};
+
+constexpr uint32_t PENDING = 0x80000000u;   // lcp entry = PENDING | depth until filled
+constexpr uint32_t MAX_LEN = 0x7FFFFF00u;   // longest accepted string
+constexpr uint32_t BLOCK = 256;             // threads per work group
+constexpr uint32_t WAVES = BLOCK / 64;
+constexpr uint32_t IPT = 32;                // tile elements per thread
+constexpr uint32_t TILE = BLOCK * IPT;      // strings per classify/scatter tile
+constexpr uint32_t MAX_LOGV = 10;           // at most 1023 splitters
+constexpr uint32_t MAX_BUCKETS = (2u << MAX_LOGV) - 1;
+constexpr uint32_t BASE_CAP = 2048;         // largest base-case segment
+
+// Pool capacities of one level, derived from n (see ss_api.cpp).
+struct Caps {
+    uint32_t dist, tiles, base, cnt, tree, pend;
+};
+
+// Pointers to the workspace of one sort.
+struct Work {
+    Elem* buf[2];
+    uint16_t* bkt;
+    uint32_t* cnt[2];
+    uint32_t* partial;
+    Seg* dist[2];
+    BaseSeg* base[2];
+    uint32_t* tile_seg[2];
+    uint64_t* tree_key[2];
+    uint8_t* tree_r[2];
+    uint2* pend;
+    Ctl* ctl;
+    Caps caps;
+};
+
+// Parameters of one sort.
+struct Params {
+    const uint8_t* chars;
+    const uint64_t* offsets;
+    uint32_t n;
+    uint32_t* perm;
+    uint32_t* lcp;
+    uint32_t max_logv;
+    uint32_t bucket_target;
+    uint32_t base_max;
+};
+
+// ---- launchers (ss_kernels.hip) ----
+hipError_t launch_reset(const Work& w, hipStream_t s);
+hipError_t launch_init(const Work& w, const Params& p, hipStream_t s);
+hipError_t launch_roots(const Work& w, const Params& p, const uint32_t* set_begin, uint32_t num_sets,
+                        hipStream_t s);
+hipError_t launch_zero_counts(const Work& w, int which, hipStream_t s);
+hipError_t launch_base(const Work& w, const Params& p, int cur, uint32_t n_base, hipStream_t s);
+hipError_t launch_sample(const Work& w, const Params& p, int cur, uint32_t n_dist, hipStream_t s);
+hipError_t launch_classify(const Work& w, const Params& p, int cur, uint32_t n_tiles, uint32_t n_dist, hipStream_t s);
+hipError_t launch_scan(const Work& w, int cur, uint32_t n_cnt, hipStream_t s);
+hipError_t launch_scatter(const Work& w, const Params& p, int cur, uint32_t n_tiles, uint32_t n_dist, hipStream_t s);
+hipError_t launch_children(const Work& w, const Params& p, int cur, uint32_t n_dist, hipStream_t s);
+hipError_t launch_lcp_fill(const Work& w, const Params& p, hipStream_t s);
+
+}  // namespace ss

@@ -1,0 +1,735 @@
+// gfx950 kernels of the string sample sort.
+//
+// One recursion level of the sort processes every live segment at once:
+//   k_base      segments of <= base_max strings: sorted in LDS, LCPs inside
+//   k_sample    per large segment: regular sample, sort, splitter tree
+//   k_classify  per tile: tree descent -> bucket ids, tile histogram
+//   k_scan_*    exclusive scan over all (bucket-major, tile-minor) counters
+//   k_scatter   per tile: stable scatter into the other ping-pong buffer
+//   k_children  per large segment: buckets -> next-level segments
+// and k_lcp_fill resolves the LCPs at bucket boundaries at the end.
+#include "ss_device.h"
+#include "ss_internal.h"
+
+namespace ss {
+
+// ---------------------------------------------------------------------------
+// helpers
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ uint32_t min_u32(uint32_t a, uint32_t b) { return a < b ? a : b; }
+
+// chars_h(s): the 8 characters of a string starting at depth h, big-endian,
+// zero padded past the end (section 4.2.2, "Character Reordering").  Reads
+// the aligned 8-byte word holding the first character and, only when the
+// key straddles a word boundary, the next one (it then holds a character
+// of the string), so no read touches a page without string data.
+__device__ __forceinline__ uint64_t gather_key(const uint8_t* chars, uint64_t off, uint32_t h, uint32_t len) {
+    uint32_t rem = len > h ? len - h : 0u;
+    rem = min_u32(rem, 8u);
+    if (rem == 0) return 0;
+    uintptr_t a = (uintptr_t)(chars + off + h);
+    const uint64_t* p = (const uint64_t*)(a & ~(uintptr_t)7);
+    uint32_t sh = (uint32_t)(a & 7);
+    uint64_t w0 = __builtin_nontemporal_load(p);
+    uint64_t w1 = (sh + rem > 8) ? __builtin_nontemporal_load(p + 1) : 0ull;
+    return key_from_words(w0, w1, sh, rem);
+}
+
+__device__ __forceinline__ uint32_t rem8(uint32_t len, uint32_t h) { return min_u32(len - h, 8u); }
+
+__device__ __forceinline__ void raise_err(const Work& w, uint32_t bits) { atomicOr(&w.ctl->err, bits); }
+
+// Appends a segment of the next level (positions [begin, begin+size) of
+// buffer `buf`, common prefix `depth`) to the work lists of counts slot
+// `nxt`: a single string is final at once, small segments go to the base
+// case, larger ones get a distribution step with its tree, counters and
+// tiles reserved here.
+__device__ void emit_segment(const Work& w, const Params& p, int nxt, const Elem* buf, uint32_t begin,
+                             uint32_t size, uint32_t depth, uint32_t obase) {
+    if (size == 0) return;
+    if (size == 1) {
+        p.perm[begin] = buf[begin].idx - obase;
+        return;
+    }
+    Counts* c = &w.ctl->c[nxt];
+    atomicMax(&c->max_depth, depth);
+    if (size <= p.base_max) {
+        uint32_t slot = atomicAdd(&c->n_base, 1u);
+        if (slot >= w.caps.base) { raise_err(w, ERR_CAPACITY); return; }
+        w.base[nxt][slot] = BaseSeg{begin, size, depth, obase};
+        return;
+    }
+    uint32_t logv = choose_logv(size, p.bucket_target, p.max_logv);
+    uint32_t v = (1u << logv) - 1, k = 2 * v + 1;
+    uint32_t T = (size + TILE - 1) / TILE;
+    uint32_t slot = atomicAdd(&c->n_dist, 1u);
+    uint32_t toff = atomicAdd(&c->n_tree, v + 1);
+    uint32_t coff = atomicAdd(&c->n_cnt, k * T);
+    uint32_t tioff = atomicAdd(&c->n_tiles, T);
+    if (slot >= w.caps.dist || toff + v + 1 > w.caps.tree || coff + k * T > w.caps.cnt ||
+        tioff + T > w.caps.tiles) {
+        raise_err(w, ERR_CAPACITY);
+        return;
+    }
+    uint32_t* ts = w.tile_seg[nxt] + tioff;
+    for (uint32_t t = 0; t < T; ++t) ts[t] = slot;
+    w.dist[nxt][slot] = Seg{begin, size, depth, logv, toff, coff, tioff, obase};
+}
+
+// wave-level inclusive scans over 64 lanes
+__device__ __forceinline__ uint32_t wave_incl_sum(uint32_t x) {
+    const uint32_t lane = threadIdx.x & 63;
+#pragma unroll
+    for (uint32_t o = 1; o < 64; o <<= 1) {
+        uint32_t y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    return x;
+}
+__device__ __forceinline__ uint32_t wave_incl_max(uint32_t x) {
+    const uint32_t lane = threadIdx.x & 63;
+#pragma unroll
+    for (uint32_t o = 1; o < 64; o <<= 1) {
+        uint32_t y = __shfl_up(x, o, 64);
+        if (lane >= o) x = x > y ? x : y;
+    }
+    return x;
+}
+
+// ---------------------------------------------------------------------------
+// reset / init / roots
+// ---------------------------------------------------------------------------
+
+__global__ void k_reset(Work w) {
+    uint32_t* p = (uint32_t*)w.ctl;
+    for (uint32_t i = threadIdx.x; i < sizeof(Ctl) / 4; i += blockDim.x) p[i] = 0;
+}
+
+__global__ void k_zero_counts(Work w, int which) {
+    uint32_t* p = (uint32_t*)&w.ctl->c[which];
+    for (uint32_t i = threadIdx.x; i < sizeof(Counts) / 4; i += blockDim.x) p[i] = 0;
+}
+
+// Key gather at depth 0 for every string (Algorithm 4.1's chars_h with
+// h = 0), plus offset validation.
+__global__ __launch_bounds__(BLOCK) void k_init(Work w, Params p) {
+    uint32_t i = blockIdx.x * BLOCK + threadIdx.x;
+    if (i >= p.n) return;
+    uint64_t o0 = p.offsets[i], o1 = p.offsets[i + 1];
+    uint32_t len = 0;
+    if (o1 < o0 || o1 - o0 > MAX_LEN || (o1 > o0 && p.chars == nullptr)) raise_err(w, ERR_OFFSETS);
+    else len = (uint32_t)(o1 - o0);
+    Elem e;
+    e.key = gather_key(p.chars, o0, 0, len);
+    e.idx = i;
+    e.len = len;
+    w.buf[0][i] = e;
+}
+
+// One root segment per set (one set = the whole input for a plain sort).
+__global__ void k_roots(Work w, Params p, const uint32_t* set_begin, uint32_t num_sets) {
+    uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= num_sets) return;
+    uint32_t b = 0, e = p.n;
+    if (set_begin) {
+        b = set_begin[j];
+        e = set_begin[j + 1];
+        if (e < b || e > p.n || (j == 0 && b != 0) || (j + 1 == num_sets && e != p.n)) {
+            raise_err(w, ERR_SETS);
+            return;
+        }
+    }
+    if (e > b) p.lcp[b] = 0;
+    emit_segment(w, p, 0, w.buf[0], b, e - b, 0, b);
+}
+
+// ---------------------------------------------------------------------------
+// base case: LDS-resident sort of a small segment with depth refinement
+// ---------------------------------------------------------------------------
+
+// Sort record in LDS: K = key, A = group(16) | r(8) | unused(8) | idx(32).
+// Order: group, then key, then (r, idx).
+__device__ __forceinline__ bool rec_greater(uint64_t ka, uint64_t aa, uint64_t kb, uint64_t ab) {
+    uint32_t ga = (uint32_t)(aa >> 48), gb = (uint32_t)(ab >> 48);
+    if (ga != gb) return ga > gb;
+    if (ka != kb) return ka > kb;
+    return (aa & 0xFFFFFFFFFFFFull) > (ab & 0xFFFFFFFFFFFFull);
+}
+__device__ __forceinline__ uint64_t rec_pack(uint32_t grp, uint32_t r, uint32_t idx) {
+    return ((uint64_t)grp << 48) | ((uint64_t)r << 40) | (uint64_t)idx;
+}
+__device__ __forceinline__ uint32_t rec_grp(uint64_t a) { return (uint32_t)(a >> 48); }
+__device__ __forceinline__ uint32_t rec_r(uint64_t a) { return (uint32_t)(a >> 40) & 0xFFu; }
+
+// In-place bitonic sorting network over P (power of two) LDS records.
+__device__ void bitonic_rec(uint64_t* K, uint64_t* A, uint32_t P) {
+    const uint32_t tid = threadIdx.x;
+    for (uint32_t k = 2; k <= P; k <<= 1) {
+        for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+            for (uint32_t t = tid; t < (P >> 1); t += BLOCK) {
+                uint32_t i = ((t & ~(j - 1)) << 1) | (t & (j - 1));
+                uint32_t l = i | j;
+                bool up = (i & k) == 0;
+                uint64_t ki = K[i], kl = K[l], ai = A[i], al = A[l];
+                if (rec_greater(ki, ai, kl, al) == up) {
+                    K[i] = kl; K[l] = ki; A[i] = al; A[l] = ai;
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// Sorts a segment of m <= BASE_CAP strings with common prefix h by
+// (key, r, index).  Runs of equal full words are then refined at depth
+// h+8, h+16, ... inside LDS (keys re-gathered for those strings only).
+// LCPs of neighbours separated at depth d are d plus the common bytes of
+// their words at d (the "last compared word"); the role of LCP-insertion
+// sort (Algorithm 4.6) as the paper's base case.
+__global__ __launch_bounds__(BLOCK) void k_base(Work w, Params p, int cur) {
+    __shared__ uint64_t K[BASE_CAP];
+    __shared__ uint64_t A[BASE_CAP];
+    __shared__ uint32_t dep[BASE_CAP];
+    __shared__ uint32_t lv[BASE_CAP];
+    __shared__ uint32_t rs[BASE_CAP];
+    __shared__ uint8_t tie[BASE_CAP];
+    __shared__ uint32_t wtot[WAVES];
+    __shared__ uint32_t any;
+
+    const BaseSeg sg = w.base[cur][blockIdx.x];
+    const uint32_t tid = threadIdx.x, m = sg.size, h = sg.depth;
+    if (m < 2 || m > BASE_CAP || m > p.base_max || sg.begin > p.n || m > p.n - sg.begin) {  // uniform
+        if (tid == 0) raise_err(w, ERR_BOUNDS);
+        return;
+    }
+    uint32_t P = 2;
+    while (P < m) P <<= 1;
+    const Elem* in = w.buf[cur] + sg.begin;
+    for (uint32_t i = tid; i < P; i += BLOCK) {
+        if (i < m) {
+            Elem e = in[i];
+            K[i] = e.key;
+            A[i] = rec_pack(0, rem8(e.len, h), e.idx);
+        } else {
+            K[i] = ~0ull;
+            A[i] = ~0ull;
+        }
+        dep[i] = h;
+        lv[i] = 0;
+    }
+    __syncthreads();
+
+    for (;;) {
+        if (tid == 0) any = 0;
+        bitonic_rec(K, A, P);
+        // neighbours inside a group: tie (equal full word, refine) or split
+        for (uint32_t i = tid; i < m; i += BLOCK) {
+            uint32_t t = 0;
+            if (i > 0) {
+                uint64_t a1 = A[i], a0 = A[i - 1];
+                if (rec_grp(a1) == rec_grp(a0)) {
+                    uint32_t r1 = rec_r(a1), r0 = rec_r(a0);
+                    uint64_t k1 = K[i], k0 = K[i - 1];
+                    if (k1 == k0 && r1 == r0 && r1 == 8) t = 1;
+                    else lv[i] = dep[i] + lcp_word(k0, r0, k1, r1);
+                }
+            }
+            tie[i] = (uint8_t)t;
+            if (t) any = 1;
+        }
+        __syncthreads();
+        if (!any) break;
+        // run starts: inclusive max-scan of (tie ? 0 : position)
+        {
+            const uint32_t base = tid * (BASE_CAP / BLOCK);
+            uint32_t loc[BASE_CAP / BLOCK];
+            uint32_t run = 0;
+#pragma unroll
+            for (uint32_t e = 0; e < BASE_CAP / BLOCK; ++e) {
+                uint32_t i = base + e;
+                uint32_t x = (i < m && !tie[i]) ? i : 0u;
+                run = run > x ? run : x;
+                loc[e] = run;
+            }
+            uint32_t incl = wave_incl_max(run);
+            uint32_t excl = __shfl_up(incl, 1, 64);
+            if ((tid & 63) == 0) excl = 0;
+            if ((tid & 63) == 63) wtot[tid >> 6] = incl;
+            __syncthreads();
+            for (uint32_t q = 0; q < (tid >> 6); ++q) excl = excl > wtot[q] ? excl : wtot[q];
+#pragma unroll
+            for (uint32_t e = 0; e < BASE_CAP / BLOCK; ++e) {
+                uint32_t i = base + e;
+                if (i < m) rs[i] = excl > loc[e] ? excl : loc[e];
+            }
+        }
+        __syncthreads();
+        // strings in a run of equal words move on to the next word
+        for (uint32_t i = tid; i < m; i += BLOCK) {
+            uint64_t a = A[i];
+            uint32_t idx = (uint32_t)a;
+            bool act = tie[i] || (i + 1 < m && tie[i + 1]);
+            if (act) {
+                uint32_t d2 = dep[i] + W;
+                dep[i] = d2;
+                uint64_t o0 = p.offsets[idx], o1 = p.offsets[idx + 1];
+                uint32_t len = (uint32_t)(o1 - o0);
+                K[i] = gather_key(p.chars, o0, d2, len);
+                A[i] = rec_pack(rs[i], rem8(len, d2), idx);
+            } else {
+                A[i] = rec_pack(i, rec_r(a), idx);
+            }
+        }
+        __syncthreads();
+    }
+    for (uint32_t i = tid; i < m; i += BLOCK) {
+        p.perm[sg.begin + i] = (uint32_t)A[i] - sg.obase;
+        if (i > 0) p.lcp[sg.begin + i] = lv[i];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// distribution step: sample + splitter tree
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ bool kr_gt(uint64_t ka, uint32_t ra, uint64_t kb, uint32_t rb) {
+    return ka > kb || (ka == kb && ra > rb);
+}
+
+// Algorithm 4.1 lines 1-5: a regular sample of alpha(v+1)-1 keys (alpha =
+// 2) is sorted in LDS; splitters are chosen by recursive middle selection
+// skipping duplicates (section 4.2.2, "Sampling"), level by level, directly
+// into the level-order tree; an empty sub-range repeats its parent's
+// splitter so the in-order splitter sequence stays sorted.
+__global__ __launch_bounds__(BLOCK) void k_sample(Work w, Params p, int cur) {
+    __shared__ uint64_t SK[2 << MAX_LOGV];
+    __shared__ uint32_t SR[2 << MAX_LOGV];
+    __shared__ uint64_t TK[1 << MAX_LOGV];
+    __shared__ uint32_t TR[1 << MAX_LOGV];
+    __shared__ uint16_t NL[1 << MAX_LOGV];
+    __shared__ uint16_t NH[1 << MAX_LOGV];
+    const Seg sg = w.dist[cur][blockIdx.x];
+    const uint32_t tid = threadIdx.x, d = sg.logv;
+    if (d < 1 || d > MAX_LOGV || sg.begin > p.n || sg.size > p.n - sg.begin || sg.size < (4u << d)) {
+        if (tid == 0) raise_err(w, ERR_BOUNDS);
+        return;
+    }
+    const uint32_t v = (1u << d) - 1, a = 2 * v + 1, P = 2u << d;
+    const Elem* in = w.buf[cur];
+    for (uint32_t j = tid; j < P; j += BLOCK) {
+        if (j < a) {
+            uint32_t pos = sg.begin + (uint32_t)(((2ull * j + 1) * sg.size) / (2ull * a));
+            Elem e = in[pos];
+            SK[j] = e.key;
+            SR[j] = rem8(e.len, sg.depth);
+        } else {
+            SK[j] = ~0ull;
+            SR[j] = 0xFFFFFFFFu;
+        }
+    }
+    __syncthreads();
+    for (uint32_t k = 2; k <= P; k <<= 1) {
+        for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+            for (uint32_t t = tid; t < (P >> 1); t += BLOCK) {
+                uint32_t i = ((t & ~(j - 1)) << 1) | (t & (j - 1));
+                uint32_t l = i | j;
+                bool up = (i & k) == 0;
+                uint64_t ki = SK[i], kl = SK[l];
+                uint32_t ri = SR[i], rl = SR[l];
+                if (kr_gt(ki, ri, kl, rl) == up) {
+                    SK[i] = kl; SK[l] = ki; SR[i] = rl; SR[l] = ri;
+                }
+            }
+            __syncthreads();
+        }
+    }
+    if (tid == 0) { NL[1] = 0; NH[1] = (uint16_t)a; }
+    __syncthreads();
+    for (uint32_t L = 0; L < d; ++L) {
+        for (uint32_t q = (1u << L) + tid; q < (2u << L); q += BLOCK) {
+            uint32_t lo = NL[q], hi = NH[q];
+            uint32_t llo = 0, lhi = 0, rlo = 0, rhi = 0;
+            if (lo < hi) {
+                uint32_t mid, lh, rl;
+                select_node(SK, SR, lo, hi, &mid, &lh, &rl);
+                TK[q] = SK[mid];
+                TR[q] = SR[mid];
+                llo = lo; lhi = lh; rlo = rl; rhi = hi;
+            } else {
+                TK[q] = TK[q >> 1];
+                TR[q] = TR[q >> 1];
+            }
+            if (L + 1 < d) {
+                NL[2 * q] = (uint16_t)llo; NH[2 * q] = (uint16_t)lhi;
+                NL[2 * q + 1] = (uint16_t)rlo; NH[2 * q + 1] = (uint16_t)rhi;
+            }
+        }
+        __syncthreads();
+    }
+    uint64_t* tk = w.tree_key[cur] + sg.tree_off;
+    uint8_t* tr = w.tree_r[cur] + sg.tree_off;
+    for (uint32_t q = 1 + tid; q <= v; q += BLOCK) {
+        tk[q - 1] = TK[q];
+        tr[q - 1] = (uint8_t)TR[q];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// distribution step: classification and tile histograms
+// ---------------------------------------------------------------------------
+
+struct TreeView {
+    const uint64_t* k;
+    const uint32_t* r;
+};
+
+// Algorithm 4.1 lines 6-14 for one tile (Theorem 4.4: every tile keeps its
+// own bucket counters): each string's bucket is stored in the oracle array
+// `bkt`, the tile's 2v+1 counts go to the counter pool in bucket-major
+// order (bucket b of tile t of segment s at cnt_off + b*T + t).
+__global__ __launch_bounds__(BLOCK) void k_classify(Work w, Params p, int cur, uint32_t n_dist) {
+    __shared__ uint64_t TK[1 << MAX_LOGV];
+    __shared__ uint32_t TR[1 << MAX_LOGV];
+    __shared__ uint32_t H[MAX_BUCKETS + 1];
+    const uint32_t t = blockIdx.x, tid = threadIdx.x;
+    const uint32_t si = w.tile_seg[cur][t];
+    if (si >= n_dist) {
+        if (tid == 0) raise_err(w, ERR_BOUNDS);
+        return;
+    }
+    const Seg sg = w.dist[cur][si];
+    const uint32_t d = sg.logv, v = (1u << d) - 1, k = 2 * v + 1;
+    const uint32_t T = (sg.size + TILE - 1) / TILE;
+    const uint32_t ti = t - sg.tile_off;
+    if (d < 1 || d > MAX_LOGV || ti >= T || sg.begin > p.n || sg.size > p.n - sg.begin) {
+        if (tid == 0) raise_err(w, ERR_BOUNDS);
+        return;
+    }
+    const uint32_t start = sg.begin + ti * TILE;
+    const uint32_t end = min_u32(start + TILE, sg.begin + sg.size);
+    const uint64_t* gk = w.tree_key[cur] + sg.tree_off;
+    const uint8_t* gr = w.tree_r[cur] + sg.tree_off;
+    for (uint32_t q = 1 + tid; q <= v; q += BLOCK) { TK[q] = gk[q - 1]; TR[q] = gr[q - 1]; }
+    for (uint32_t b = tid; b < k; b += BLOCK) H[b] = 0;
+    __syncthreads();
+    const Elem* in = w.buf[cur];
+    for (uint32_t i = start + tid; i < end; i += BLOCK) {
+        Elem e = in[i];
+        uint32_t b = classify(e.key, rem8(e.len, sg.depth), TK, TR, d);
+        w.bkt[i] = (uint16_t)b;
+        atomicAdd(&H[b], 1u);
+    }
+    __syncthreads();
+    uint32_t* c = w.cnt[cur] + sg.cnt_off + ti;
+    for (uint32_t b = tid; b < k; b += BLOCK) c[(size_t)b * T] = H[b];
+}
+
+// ---------------------------------------------------------------------------
+// exclusive scan over the counter pool ("interleaved global prefix sum",
+// Theorem 4.4)
+// ---------------------------------------------------------------------------
+
+constexpr uint32_t SCAN_PER_THREAD = 16;
+constexpr uint32_t SCAN_CHUNK = BLOCK * SCAN_PER_THREAD;
+
+__global__ __launch_bounds__(BLOCK) void k_scan_reduce(const uint32_t* x, uint32_t n, uint32_t* partial) {
+    __shared__ uint32_t wt[WAVES];
+    const uint32_t base = blockIdx.x * SCAN_CHUNK;
+    uint32_t s = 0;
+    for (uint32_t i = base + threadIdx.x; i < n && i < base + SCAN_CHUNK; i += BLOCK) s += x[i];
+    s = wave_incl_sum(s);
+    if ((threadIdx.x & 63) == 63) wt[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t t = 0;
+        for (uint32_t q = 0; q < WAVES; ++q) t += wt[q];
+        partial[blockIdx.x] = t;
+    }
+}
+
+// exclusive scan of the per-chunk sums, one work group
+__global__ __launch_bounds__(1024) void k_scan_partials(uint32_t* partial, uint32_t nb) {
+    __shared__ uint32_t wt[16];
+    __shared__ uint32_t carry;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (uint32_t base = 0; base < nb; base += 1024) {
+        uint32_t i = base + threadIdx.x;
+        uint32_t x = i < nb ? partial[i] : 0u;
+        uint32_t incl = wave_incl_sum(x);
+        if ((threadIdx.x & 63) == 63) wt[threadIdx.x >> 6] = incl;
+        __syncthreads();
+        uint32_t off = carry;
+        for (uint32_t q = 0; q < (threadIdx.x >> 6); ++q) off += wt[q];
+        if (i < nb) partial[i] = off + incl - x;
+        __syncthreads();
+        if (threadIdx.x == 1023) carry = off + incl;
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(BLOCK) void k_scan_down(uint32_t* x, uint32_t n, const uint32_t* partial) {
+    __shared__ uint32_t wt[WAVES];
+    const uint32_t base = blockIdx.x * SCAN_CHUNK + threadIdx.x * SCAN_PER_THREAD;
+    uint32_t v[SCAN_PER_THREAD];
+    uint32_t s = 0;
+#pragma unroll
+    for (uint32_t e = 0; e < SCAN_PER_THREAD; ++e) {
+        uint32_t i = base + e;
+        v[e] = i < n ? x[i] : 0u;
+        s += v[e];
+    }
+    uint32_t incl = wave_incl_sum(s);
+    if ((threadIdx.x & 63) == 63) wt[threadIdx.x >> 6] = incl;
+    __syncthreads();
+    uint32_t off = partial[blockIdx.x] + incl - s;
+    for (uint32_t q = 0; q < (threadIdx.x >> 6); ++q) off += wt[q];
+#pragma unroll
+    for (uint32_t e = 0; e < SCAN_PER_THREAD; ++e) {
+        uint32_t i = base + e;
+        if (i < n) x[i] = off;
+        off += v[e];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// distribution step: stable scatter
+// ---------------------------------------------------------------------------
+
+// Algorithm 4.1 line 16 for one tile, out of place into the other buffer
+// (section 4.2.8, "Out-of-place Redistribution").  Each wave owns a
+// contiguous quarter of the tile; within a wave, strings with the same
+// bucket are ranked by lane order through a ballot-built peer mask, so the
+// scatter keeps input order inside every bucket (stable).  Strings of an
+// equality bucket whose splitter ends inside the word are identical and
+// final: they are written to perm/lcp directly.  Strings of the other
+// equality buckets get their next key (depth + 8) on the way.
+__global__ __launch_bounds__(BLOCK) void k_scatter(Work w, Params p, int cur, uint32_t n_dist) {
+    __shared__ uint32_t WC[WAVES][MAX_BUCKETS + 1];
+    __shared__ uint32_t GB[MAX_BUCKETS + 1];
+    __shared__ uint32_t BS[MAX_BUCKETS + 1];
+    __shared__ uint8_t XR[1 << MAX_LOGV];
+    const uint32_t t = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const uint32_t si = w.tile_seg[cur][t];
+    if (si >= n_dist) {
+        if (tid == 0) raise_err(w, ERR_BOUNDS);
+        return;
+    }
+    const Seg sg = w.dist[cur][si];
+    const uint32_t d = sg.logv, v = (1u << d) - 1, k = 2 * v + 1;
+    const uint32_t T = (sg.size + TILE - 1) / TILE;
+    const uint32_t ti = t - sg.tile_off;
+    if (d < 1 || d > MAX_LOGV || ti >= T || sg.begin > p.n || sg.size > p.n - sg.begin) {
+        if (tid == 0) raise_err(w, ERR_BOUNDS);
+        return;
+    }
+    const uint32_t start = sg.begin + ti * TILE;
+    const uint32_t end = min_u32(start + TILE, sg.begin + sg.size);
+    for (uint32_t b = tid; b < k; b += BLOCK) {
+#pragma unroll
+        for (uint32_t q = 0; q < WAVES; ++q) WC[q][b] = 0;
+    }
+    const uint8_t* gr = w.tree_r[cur] + sg.tree_off;
+    for (uint32_t j = tid; j < v; j += BLOCK) XR[j] = gr[level_index(j, d) - 1];
+    __syncthreads();
+
+    // phase 1: ranks within the wave's chunk
+    constexpr uint32_t CH = TILE / WAVES;
+    const uint32_t cbeg = start + wv * CH;
+    uint32_t packed[IPT];  // bucket << 16 | rank
+#pragma unroll
+    for (uint32_t it = 0; it < IPT; ++it) {
+        uint32_t i = cbeg + it * 64 + lane;
+        bool valid = i < end;
+        uint32_t b = valid ? (uint32_t)w.bkt[i] : 0u;
+        uint64_t peers = __ballot(valid);
+#pragma unroll
+        for (uint32_t bit = 0; bit < MAX_LOGV + 1; ++bit) {
+            uint64_t m = __ballot((b >> bit) & 1u);
+            peers &= ((b >> bit) & 1u) ? m : ~m;
+        }
+        uint32_t below = __builtin_amdgcn_mbcnt_hi((uint32_t)(peers >> 32),
+                                                   __builtin_amdgcn_mbcnt_lo((uint32_t)peers, 0u));
+        uint32_t leader = valid ? (uint32_t)__builtin_ctzll(peers) : 0u;
+        uint32_t old = 0;
+        if (valid && lane == leader) old = atomicAdd(&WC[wv][b], (uint32_t)__builtin_popcountll(peers));
+        old = __shfl(old, (int)leader, 64);
+        packed[it] = (b << 16) | (old + below);
+    }
+    __syncthreads();
+    // phase 2: per-bucket offsets of the tile and of each wave
+    const uint32_t* sc = w.cnt[cur] + sg.cnt_off;
+    const uint32_t s0 = sc[0];
+    for (uint32_t b = tid; b < k; b += BLOCK) {
+        GB[b] = sg.begin + sc[(size_t)b * T + ti] - s0;
+        BS[b] = sg.begin + sc[(size_t)b * T] - s0;
+        uint32_t run = 0;
+#pragma unroll
+        for (uint32_t q = 0; q < WAVES; ++q) {
+            uint32_t c = WC[q][b];
+            WC[q][b] = run;
+            run += c;
+        }
+    }
+    __syncthreads();
+    // phase 3: move
+    const Elem* in = w.buf[cur];
+    Elem* out = w.buf[cur ^ 1];
+    const uint32_t seg_end = sg.begin + sg.size;
+#pragma unroll 4
+    for (uint32_t it = 0; it < IPT; ++it) {
+        uint32_t i = cbeg + it * 64 + lane;
+        if (i >= end) continue;
+        Elem e = in[i];
+        uint32_t b = packed[it] >> 16, rank = packed[it] & 0xFFFFu;
+        uint32_t pos = GB[b] + WC[wv][b] + rank;
+        if (pos < sg.begin || pos >= seg_end) { raise_err(w, ERR_BOUNDS); continue; }
+        if (b & 1u) {
+            uint32_t rx = XR[b >> 1];
+            if (rx < W) {  // identical strings ending inside this word: final
+                p.perm[pos] = e.idx - sg.obase;
+                if (pos != BS[b]) p.lcp[pos] = sg.depth + rx;
+                continue;
+            }
+            uint32_t d2 = sg.depth + W;
+            e.key = gather_key(p.chars, p.offsets[e.idx], d2, e.len);
+        }
+        out[pos] = e;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// distribution step: children
+// ---------------------------------------------------------------------------
+
+// Output description of Algorithm 4.1: bucket i of a segment with common
+// prefix h holds strings with common prefix h (even i; the keys at h stay
+// valid) or h + 8 (odd i, equation 4.1 with the full word).  Every bucket
+// start inside the segment gets a pending LCP (its neighbours differ within
+// the word at depth h); the value is filled in once the final order is
+// known (figure 4.7).
+__global__ __launch_bounds__(BLOCK) void k_children(Work w, Params p, int cur) {
+    const Seg sg = w.dist[cur][blockIdx.x];
+    const uint32_t tid = threadIdx.x, d = sg.logv, v = (1u << d) - 1, k = 2 * v + 1;
+    const uint32_t T = (sg.size + TILE - 1) / TILE;
+    const int nxt = cur ^ 1;
+    if (d < 1 || d > MAX_LOGV || sg.begin > p.n || sg.size > p.n - sg.begin) {
+        if (tid == 0) raise_err(w, ERR_BOUNDS);
+        return;
+    }
+    const uint32_t* sc = w.cnt[cur] + sg.cnt_off;
+    const uint32_t s0 = sc[0];
+    const uint8_t* gr = w.tree_r[cur] + sg.tree_off;
+    for (uint32_t b = tid; b < k; b += BLOCK) {
+        uint32_t st = sc[(size_t)b * T] - s0;
+        uint32_t en = (b + 1 < k) ? sc[(size_t)(b + 1) * T] - s0 : sg.size;
+        if (en <= st) continue;
+        if (en > sg.size) { raise_err(w, ERR_BOUNDS); continue; }
+        uint32_t pos = sg.begin + st;
+        if (st > 0) {
+            p.lcp[pos] = PENDING | sg.depth;
+            uint32_t slot = atomicAdd(&w.ctl->n_pend, 1u);
+            if (slot < w.caps.pend) w.pend[slot] = make_uint2(pos, sg.obase);
+            else raise_err(w, ERR_CAPACITY);
+        }
+        uint32_t depth = sg.depth;
+        if (b & 1u) {
+            uint32_t rx = gr[level_index(b >> 1, d) - 1];
+            if (rx < W) continue;  // written by the scatter
+            depth += W;
+        }
+        emit_segment(w, p, nxt, w.buf[nxt], pos, en - st, depth, sg.obase);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// boundary LCPs
+// ---------------------------------------------------------------------------
+
+// A pending entry at position q separates two buckets of a segment with
+// common prefix h: the strings now at q-1 and q differ within the word at
+// depth h, so their LCP is h plus the common bytes of those two words.
+__global__ __launch_bounds__(BLOCK) void k_lcp_fill(Work w, Params p) {
+    const uint32_t np = min_u32(w.ctl->n_pend, w.caps.pend);
+    for (uint32_t s = blockIdx.x * BLOCK + threadIdx.x; s < np; s += gridDim.x * BLOCK) {
+        uint2 pe = w.pend[s];
+        uint32_t q = pe.x, ob = pe.y;
+        if (q == 0 || q >= p.n) { raise_err(w, ERR_BOUNDS); continue; }
+        uint32_t h = p.lcp[q];
+        if (!(h & PENDING)) { raise_err(w, ERR_BOUNDS); continue; }
+        h &= ~PENDING;
+        uint32_t a = p.perm[q - 1] + ob, b = p.perm[q] + ob;
+        if (a >= p.n || b >= p.n) { raise_err(w, ERR_BOUNDS); continue; }
+        uint64_t oa = p.offsets[a], ob0 = p.offsets[b];
+        uint32_t la = (uint32_t)(p.offsets[a + 1] - oa), lb = (uint32_t)(p.offsets[b + 1] - ob0);
+        if (la < h || lb < h) { raise_err(w, ERR_BOUNDS); continue; }
+        uint64_t ka = gather_key(p.chars, oa, h, la), kb = gather_key(p.chars, ob0, h, lb);
+        p.lcp[q] = h + lcp_word(ka, rem8(la, h), kb, rem8(lb, h));
+    }
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+
+static inline uint32_t blocks_for(uint64_t n, uint32_t per) { return (uint32_t)((n + per - 1) / per); }
+
+hipError_t launch_reset(const Work& w, hipStream_t s) {
+    hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, s, w);
+    return hipGetLastError();
+}
+hipError_t launch_zero_counts(const Work& w, int which, hipStream_t s) {
+    hipLaunchKernelGGL(k_zero_counts, dim3(1), dim3(64), 0, s, w, which);
+    return hipGetLastError();
+}
+hipError_t launch_init(const Work& w, const Params& p, hipStream_t s) {
+    if (p.n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_init, dim3(blocks_for(p.n, BLOCK)), dim3(BLOCK), 0, s, w, p);
+    return hipGetLastError();
+}
+hipError_t launch_roots(const Work& w, const Params& p, const uint32_t* set_begin, uint32_t num_sets,
+                        hipStream_t s) {
+    if (num_sets == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_roots, dim3(blocks_for(num_sets, 64)), dim3(64), 0, s, w, p, set_begin, num_sets);
+    return hipGetLastError();
+}
+hipError_t launch_base(const Work& w, const Params& p, int cur, uint32_t n_base, hipStream_t s) {
+    hipLaunchKernelGGL(k_base, dim3(n_base), dim3(BLOCK), 0, s, w, p, cur);
+    return hipGetLastError();
+}
+hipError_t launch_sample(const Work& w, const Params& p, int cur, uint32_t n_dist, hipStream_t s) {
+    hipLaunchKernelGGL(k_sample, dim3(n_dist), dim3(BLOCK), 0, s, w, p, cur);
+    return hipGetLastError();
+}
+hipError_t launch_classify(const Work& w, const Params& p, int cur, uint32_t n_tiles, uint32_t n_dist,
+                           hipStream_t s) {
+    hipLaunchKernelGGL(k_classify, dim3(n_tiles), dim3(BLOCK), 0, s, w, p, cur, n_dist);
+    return hipGetLastError();
+}
+hipError_t launch_scan(const Work& w, int cur, uint32_t n_cnt, hipStream_t s) {
+    if (n_cnt == 0) return hipSuccess;
+    uint32_t nb = blocks_for(n_cnt, SCAN_CHUNK);
+    hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(BLOCK), 0, s, w.cnt[cur], n_cnt, w.partial);
+    hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(1024), 0, s, w.partial, nb);
+    hipLaunchKernelGGL(k_scan_down, dim3(nb), dim3(BLOCK), 0, s, w.cnt[cur], n_cnt, (const uint32_t*)w.partial);
+    return hipGetLastError();
+}
+hipError_t launch_scatter(const Work& w, const Params& p, int cur, uint32_t n_tiles, uint32_t n_dist,
+                          hipStream_t s) {
+    hipLaunchKernelGGL(k_scatter, dim3(n_tiles), dim3(BLOCK), 0, s, w, p, cur, n_dist);
+    return hipGetLastError();
+}
+hipError_t launch_children(const Work& w, const Params& p, int cur, uint32_t n_dist, hipStream_t s) {
+    hipLaunchKernelGGL(k_children, dim3(n_dist), dim3(BLOCK), 0, s, w, p, cur);
+    return hipGetLastError();
+}
+hipError_t launch_lcp_fill(const Work& w, const Params& p, hipStream_t s) {
+    uint32_t nb = blocks_for(p.n, BLOCK);
+    if (nb > 2048) nb = 2048;
+    if (nb == 0) nb = 1;
+    hipLaunchKernelGGL(k_lcp_fill, dim3(nb), dim3(BLOCK), 0, s, w, p);
+    return hipGetLastError();
+}
+
+}  // namespace ss
