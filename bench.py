@@ -1,0 +1,186 @@
+#!/usr/bin/env python3
+"""Benchmark of the string sample sort on one MI355X.
+
+One step = one complete sort (permutation + LCP array) of the 16M-string
+Markov workload (lognormal lengths, median 40, order-2 Markov chain over 64
+symbols with Zipf(1.1) transitions, ~0.8 GB of characters), inputs resident
+in HBM.  Prints ONE JSON line on stdout; details go to stderr.
+
+    python bench.py [--gpus 1] [--steps 10] [--warmup 2] [--workload NAME]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "sorted chars/s + strings/s incl. LCP, %HBM peak; batched vs per-set launch"
+HBM_PEAK_GBS = 8000.0
+
+# Algorithmic bytes per work unit of each kernel (what the kernel must move
+# by its definition, not what the hardware ends up fetching).
+#   k_init      per string: offset (8) + first word (<= 8, measured) + element write (16)
+#   k_classify  per string: element read (16) + bucket id write (2)
+#   k_scatter   per string: bucket id (2) + element read (16) + element write (16)
+#   k_base      per string: element read (16) + perm and lcp writes (4 + 4)
+#   k_scan      per counter: reduce read (4) + scan read (4) + write (4)
+#   k_lcp_fill  per boundary: entry (8) + lcp (4+4) + perm (8) + offsets (32) + two words (16)
+BYTES_PER_UNIT = {
+    "k_classify": 18.0,
+    "k_scatter": 34.0,
+    "k_base": 24.0,
+    "k_scan": 12.0,
+    "k_lcp_fill": 72.0,
+}
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("ss_kernels.hip", "ss_device.h", "ss_internal.h"):
+        with open(os.path.join(ROOT, "paper_1808_00963_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel: str, units_per_launch: float):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if
+    it was taken on the current kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    k = t.get("kernels", {}).get(kernel)
+    if not k:
+        return None
+    return k.get("bytes_per_launch")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="c1_markov_16m")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=0, help="strings for the oracle timing (0 = all)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on exactly one GPU (asked for {args.gpus}); "
+              "the sort is single-GPU and multi-GPU sharding is not implemented.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import gen
+    import paper_1808_00963_amd as ss
+
+    model, n, seed = gen.WORKLOADS[args.workload]
+    t0 = time.perf_counter()
+    c, o = gen.generate(model, n, seed)
+    N = int(o[-1])
+    print(f"[bench] generated {args.workload}: n={n} N={N} in {time.perf_counter() - t0:.1f}s", file=sys.stderr, flush=True)
+    dev = torch.device("cuda:0")
+    chars = torch.from_numpy(c).to(dev)
+    offs = torch.from_numpy(o.view(np.int64)).to(dev)
+    perm = torch.empty(n, dtype=torch.int32, device=dev)
+    lcp = torch.empty(n, dtype=torch.int32, device=dev)
+    ctx = ss.Context(0)
+    stream = torch.cuda.current_stream()
+
+    for _ in range(args.warmup):
+        ctx.sort(chars, offs, perm, lcp, stream=stream)
+    torch.cuda.synchronize()
+    stats = ctx.stats()
+
+    # timed region: K complete sorts; per-kernel HIP events on the sort's stream
+    ctx.set_profiling(True)
+    ctx.reset_kernel_times()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ctx.sort(chars, offs, perm, lcp, stream=stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ctx.set_profiling(False)
+    kt = ctx.kernel_times()
+
+    sec = (t1 - t0) / args.steps
+    value = N / sec
+    strings_per_s = n / sec
+
+    # roofline of the dominant kernel
+    bpu = dict(BYTES_PER_UNIT)
+    L = np.diff(o)
+    bpu["k_init"] = 8.0 + float(np.minimum(L, 8).mean()) + 16.0
+    dom = max((k for k in kt if k in bpu and kt[k]["launches"]), key=lambda k: kt[k]["total_ms"])
+    d = kt[dom]
+    alg_bytes_per_launch = d["units"] / d["launches"] * bpu[dom]
+    avg_ms = d["total_ms"] / d["launches"]
+    achieved = alg_bytes_per_launch / (avg_ms * 1e-3) / 1e9
+    traffic = measured_traffic(dom, d["units"] / d["launches"])
+    for k, v in sorted(kt.items(), key=lambda kv: -kv[1]["total_ms"]):
+        if v["launches"]:
+            per = v["total_ms"] / args.steps
+            gbs = (v["units"] * bpu[k] / (v["total_ms"] * 1e-3) / 1e9) if k in bpu and v["total_ms"] else float("nan")
+            print(f"[bench] {k:12s} {per:8.3f} ms/step  launches/step {v['launches'] / args.steps:6.1f}  "
+                  f"{v['units'] / args.steps:12.0f} {v['unit']}/step  {gbs:8.1f} GB/s alg", file=sys.stderr)
+    kernel_ms = sum(v["total_ms"] for v in kt.values()) / args.steps
+    print(f"[bench] step {sec * 1e3:.3f} ms, kernels {kernel_ms:.3f} ms, stats {stats}", file=sys.stderr, flush=True)
+
+    # CPU baseline: the oracle as it is, single thread, on the host cores
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        ns = n if args.cpu_sample <= 0 else min(n, args.cpu_sample)
+        oc = c[: int(o[ns])]
+        oo = o[: ns + 1]
+        t0 = time.perf_counter()
+        oracle.sort(oc, oo)
+        dt = time.perf_counter() - t0
+        cpu = {"value": int(oo[-1]) / dt, "unit": "chars/s", "cores": 1, "kind": "oracle",
+               "sample": f"first {ns} strings ({int(oo[-1])} chars) of {args.workload}, qsort+memcmp and brute LCP, "
+                         f"1 thread, {dt:.2f} s"}
+        print(f"[bench] oracle {dt:.2f}s on {ns} strings", file=sys.stderr, flush=True)
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "chars/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": sec * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u8",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "model": model, "seed": seed, "n_strings": n, "n_chars": N,
+                   "parallelism": "single-gpu"},
+        "strings_per_s": strings_per_s,
+        "hbm_frac_alg_whole_sort": None,
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "alg_bytes_per_launch": alg_bytes_per_launch, "avg_launch_ms": avg_ms},
+        "cpu_baseline": cpu,
+        "kernel_ms_per_step": {k: v["total_ms"] / args.steps for k, v in kt.items() if v["launches"]},
+    }
+    # whole-sort algorithmic bytes over the step time
+    alg_total = sum(v["units"] * bpu[k] for k, v in kt.items() if k in bpu) / args.steps
+    out["hbm_frac_alg_whole_sort"] = alg_total / sec / (HBM_PEAK_GBS * 1e9)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

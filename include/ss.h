@@ -34,7 +34,7 @@
  * Streams and errors.  `stream` is a hipStream_t (NULL = default stream).
  * Calls enqueue work on `stream`; they synchronise with the host between
  * recursion levels (the host reads a few counters per level), and return
- * when the last kernel has been enqueued.  Host-detectable errors return
+ * once the sort has completed on the stream.  Host-detectable errors return
  * immediately without touching the outputs.  Errors detected on the device
  * (non-monotone offsets, a string of 2^31 or more bytes, an internal limit)
  * are returned by the call that detects them and are sticky in the context:
@@ -142,6 +142,23 @@ typedef struct {
     uint32_t max_depth;
 } ss_stats;
 ss_status ss_get_stats(const ss_ctx* ctx, ss_stats* st);
+
+/* Per-kernel timing (tracing).  When enabled on a context, every kernel
+ * launch of a sort is bracketed by a pair of HIP events on the sort's
+ * stream; durations are read at the host synchronisations the sort already
+ * performs and accumulated per kernel until ss_reset_kernel_times.  `units`
+ * counts the work items the launches processed (strings, segments,
+ * counters or boundary entries, see `unit`). */
+typedef struct {
+    const char* name;      /* kernel name (static storage) */
+    const char* unit;      /* what `units` counts (static storage) */
+    uint32_t launches;
+    double total_ms;
+    double units;
+} ss_kernel_time;
+ss_status ss_set_profiling(ss_ctx* ctx, int enable);
+ss_status ss_get_kernel_times(const ss_ctx* ctx, ss_kernel_time* out, uint32_t max_entries, uint32_t* n_entries);
+void ss_reset_kernel_times(ss_ctx* ctx);
 
 /* ---- host-side test entry points (no device access) -------------------
  * These run the same primitive functions the kernels use, on the host, so

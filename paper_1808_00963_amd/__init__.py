@@ -42,6 +42,11 @@ class Stats(ctypes.Structure):
                 ("pending_lcps", ctypes.c_uint32), ("max_depth", ctypes.c_uint32)]
 
 
+class KernelTime(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char_p), ("unit", ctypes.c_char_p), ("launches", ctypes.c_uint32),
+                ("total_ms", ctypes.c_double), ("units", ctypes.c_double)]
+
+
 def lib():
     """Loads libss.so; raises if it has not been built."""
     global _lib
@@ -64,6 +69,9 @@ def lib():
             "ss_get_last_error": (i32, [vp]),
             "ss_clear_error": (None, [vp]),
             "ss_get_stats": (i32, [vp, ctypes.POINTER(Stats)]),
+            "ss_set_profiling": (i32, [vp, i32]),
+            "ss_get_kernel_times": (i32, [vp, ctypes.POINTER(KernelTime), u32, ctypes.POINTER(u32)]),
+            "ss_reset_kernel_times": (None, [vp]),
             "ss_host_key": (u64, [vp, u64, u64, ctypes.POINTER(u32)]),
             "ss_host_level_index": (u32, [u32, u32]),
             "ss_host_inorder_index": (u32, [u32, u32]),
@@ -148,6 +156,21 @@ class Context:
         s = Stats()
         _check(lib().ss_get_stats(self._h, ctypes.byref(s)), "ss_get_stats")
         return {f: getattr(s, f) for f, _ in Stats._fields_}
+
+    def set_profiling(self, on: bool = True):
+        _check(lib().ss_set_profiling(self._h, 1 if on else 0), "ss_set_profiling")
+
+    def kernel_times(self) -> dict:
+        """{kernel: {"launches", "total_ms", "units", "unit"}} accumulated while profiling."""
+        arr = (KernelTime * 32)()
+        cnt = ctypes.c_uint32()
+        _check(lib().ss_get_kernel_times(self._h, arr, 32, ctypes.byref(cnt)), "ss_get_kernel_times")
+        return {arr[i].name.decode(): {"launches": arr[i].launches, "total_ms": arr[i].total_ms,
+                                       "units": arr[i].units, "unit": arr[i].unit.decode()}
+                for i in range(min(cnt.value, 32))}
+
+    def reset_kernel_times(self):
+        lib().ss_reset_kernel_times(self._h)
 
     def workspace_bytes(self, n: int) -> int:
         b = ctypes.c_size_t()

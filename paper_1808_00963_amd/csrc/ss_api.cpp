@@ -7,12 +7,33 @@
 #include <map>
 #include <memory>
 #include <mutex>
+#include <vector>
 
 #include "../../include/ss.h"
 #include "ss_device.h"
 #include "ss_internal.h"
 
 using namespace ss;
+
+namespace {
+enum KernelId { K_INIT, K_ROOTS, K_BASE, K_SAMPLE, K_CLASSIFY, K_SCAN, K_SCATTER, K_CHILDREN, K_LCP_FILL, K_COUNT };
+const char* const KNAME[K_COUNT] = {"k_init", "k_roots", "k_base", "k_sample", "k_classify",
+                                    "k_scan", "k_scatter", "k_children", "k_lcp_fill"};
+const char* const KUNIT[K_COUNT] = {"strings", "sets", "strings", "segments", "strings",
+                                    "counters", "strings", "segments", "boundaries"};
+
+// Event pairs around kernel launches, resolved at the next host sync.
+struct Profiler {
+    bool on = false;
+    std::vector<hipEvent_t> ev;  // pairs (start, stop)
+    std::vector<int> kid;
+    std::vector<double> units;
+    size_t used = 0;
+    double ms[K_COUNT] = {};
+    double unit_sum[K_COUNT] = {};
+    uint32_t launches[K_COUNT] = {};
+};
+}  // namespace
 
 struct ss_ctx {
     int device = 0;
@@ -25,6 +46,7 @@ struct ss_ctx {
     ss_config cfg{10, 512, 2048};
     ss_status sticky = SS_OK;
     ss_stats stats{};
+    Profiler prof;
 };
 
 namespace {
@@ -126,10 +148,52 @@ ss_status device_error_status(uint32_t err) {
     return SS_INTERNAL;
 }
 
+// Launches `fn` and, when profiling, brackets it with an event pair.
+template <typename F>
+hipError_t timed(ss_ctx* ctx, hipStream_t s, int id, double units, F&& fn) {
+    Profiler& P = ctx->prof;
+    if (!P.on) return fn();
+    if (P.used * 2 + 2 > P.ev.size()) {
+        for (int i = 0; i < 64; ++i) {
+            hipEvent_t e;
+            hipError_t r = hipEventCreate(&e);
+            if (r != hipSuccess) return r;
+            P.ev.push_back(e);
+        }
+    }
+    hipEvent_t a = P.ev[2 * P.used], b = P.ev[2 * P.used + 1];
+    hipError_t r = hipEventRecord(a, s);
+    if (r != hipSuccess) return r;
+    r = fn();
+    if (r != hipSuccess) return r;
+    r = hipEventRecord(b, s);
+    if (r != hipSuccess) return r;
+    if (P.kid.size() <= P.used) { P.kid.resize(P.used + 1); P.units.resize(P.used + 1); }
+    P.kid[P.used] = id;
+    P.units[P.used] = units;
+    ++P.used;
+    return hipSuccess;
+}
+
+// Accumulates the durations of all recorded pairs (stream already synced).
+void resolve_timings(ss_ctx* ctx) {
+    Profiler& P = ctx->prof;
+    for (size_t i = 0; i < P.used; ++i) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, P.ev[2 * i], P.ev[2 * i + 1]) == hipSuccess) {
+            P.ms[P.kid[i]] += ms;
+            P.unit_sum[P.kid[i]] += P.units[i];
+            P.launches[P.kid[i]] += 1;
+        }
+    }
+    P.used = 0;
+}
+
 // Reads the control block into the pinned host copy (synchronous).
 ss_status read_ctl(ss_ctx* ctx, hipStream_t s) {
     SS_TRY(hipMemcpyAsync(ctx->host_ctl, ctx->work.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
     SS_TRY(hipStreamSynchronize(s));
+    if (ctx->prof.used) resolve_timings(ctx);
     return SS_OK;
 }
 
@@ -148,9 +212,10 @@ ss_status run_sort(ss_ctx* ctx, const uint8_t* chars, const uint64_t* offsets, u
     const Work& w = ctx->work;
     Params p{chars, offsets, n, perm, lcp, ctx->cfg.max_log_splitters, ctx->cfg.bucket_target, ctx->cfg.base_max};
 
+    const uint32_t nroots = set_begin ? num_sets : 1;
     SS_TRY(launch_reset(w, s));
-    SS_TRY(launch_init(w, p, s));
-    SS_TRY(launch_roots(w, p, set_begin, set_begin ? num_sets : 1, s));
+    SS_TRY(timed(ctx, s, K_INIT, n, [&] { return launch_init(w, p, s); }));
+    SS_TRY(timed(ctx, s, K_ROOTS, nroots, [&] { return launch_roots(w, p, set_begin, nroots, s); }));
     int cur = 0;
     uint32_t level = 0;
     for (;;) {
@@ -162,19 +227,24 @@ ss_status run_sort(ss_ctx* ctx, const uint8_t* chars, const uint64_t* offsets, u
         ctx->stats.dist_tiles += c.n_tiles;
         ctx->stats.base_segments += c.n_base;
         ctx->stats.max_depth = std::max(ctx->stats.max_depth, c.max_depth);
-        if (c.n_base) SS_TRY(launch_base(w, p, cur, c.n_base, s));
+        if (c.n_base)
+            SS_TRY(timed(ctx, s, K_BASE, c.base_strings, [&] { return launch_base(w, p, cur, c.n_base, s); }));
         if (c.n_dist == 0) break;
         SS_TRY(launch_zero_counts(w, cur ^ 1, s));
-        SS_TRY(launch_sample(w, p, cur, c.n_dist, s));
-        SS_TRY(launch_classify(w, p, cur, c.n_tiles, c.n_dist, s));
-        SS_TRY(launch_scan(w, cur, c.n_cnt, s));
-        SS_TRY(launch_scatter(w, p, cur, c.n_tiles, c.n_dist, s));
-        SS_TRY(launch_children(w, p, cur, c.n_dist, s));
+        SS_TRY(timed(ctx, s, K_SAMPLE, c.n_dist, [&] { return launch_sample(w, p, cur, c.n_dist, s); }));
+        SS_TRY(timed(ctx, s, K_CLASSIFY, c.dist_strings,
+                     [&] { return launch_classify(w, p, cur, c.n_tiles, c.n_dist, s); }));
+        SS_TRY(timed(ctx, s, K_SCAN, c.n_cnt, [&] { return launch_scan(w, cur, c.n_cnt, s); }));
+        SS_TRY(timed(ctx, s, K_SCATTER, c.dist_strings,
+                     [&] { return launch_scatter(w, p, cur, c.n_tiles, c.n_dist, s); }));
+        SS_TRY(timed(ctx, s, K_CHILDREN, c.n_dist, [&] { return launch_children(w, p, cur, c.n_dist, s); }));
         cur ^= 1;
         if (++level >= MAX_LEVELS) return SS_INTERNAL;
     }
-    SS_TRY(launch_lcp_fill(w, p, s));
+    // the pending count is known on the device only; units are added below
+    SS_TRY(timed(ctx, s, K_LCP_FILL, 0.0, [&] { return launch_lcp_fill(w, p, s); }));
     if ((st = read_ctl(ctx, s)) != SS_OK) return st;
+    if (ctx->prof.on) ctx->prof.unit_sum[K_LCP_FILL] += ctx->host_ctl->n_pend;
     ctx->stats.pending_lcps = ctx->host_ctl->n_pend;
     if (ctx->host_ctl->err) return device_error_status(ctx->host_ctl->err);
     return SS_OK;
@@ -242,6 +312,7 @@ void ss_ctx_destroy(ss_ctx* ctx) {
     int prev = 0;
     (void)hipGetDevice(&prev);
     (void)hipSetDevice(ctx->device);
+    for (hipEvent_t e : ctx->prof.ev) (void)hipEventDestroy(e);
     if (ctx->ws) (void)hipFree(ctx->ws);
     if (ctx->host_ctl) (void)hipHostFree(ctx->host_ctl);
     (void)hipSetDevice(prev);
@@ -315,6 +386,28 @@ ss_status ss_get_stats(const ss_ctx* ctx, ss_stats* st) {
     if (!ctx || !st) return SS_INVALID_ARG;
     *st = ctx->stats;
     return SS_OK;
+}
+
+ss_status ss_set_profiling(ss_ctx* ctx, int enable) {
+    if (!ctx) return SS_INVALID_ARG;
+    ctx->prof.on = enable != 0;
+    return SS_OK;
+}
+
+ss_status ss_get_kernel_times(const ss_ctx* ctx, ss_kernel_time* out, uint32_t max_entries, uint32_t* n_entries) {
+    if (!ctx || !n_entries || (max_entries && !out)) return SS_INVALID_ARG;
+    uint32_t k = 0;
+    for (int i = 0; i < K_COUNT && k < max_entries; ++i, ++k)
+        out[k] = ss_kernel_time{KNAME[i], KUNIT[i], ctx->prof.launches[i], ctx->prof.ms[i], ctx->prof.unit_sum[i]};
+    *n_entries = K_COUNT;
+    return SS_OK;
+}
+
+void ss_reset_kernel_times(ss_ctx* ctx) {
+    if (!ctx) return;
+    Profiler& P = ctx->prof;
+    P.used = 0;
+    for (int i = 0; i < K_COUNT; ++i) P.ms[i] = P.unit_sum[i] = 0, P.launches[i] = 0;
 }
 
 // ---- host-side test entry points ----

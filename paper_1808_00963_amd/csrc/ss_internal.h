@@ -42,7 +42,8 @@ struct Counts {
     uint32_t n_cnt;
     uint32_t n_tree;
     uint32_t max_depth;
-    uint32_t pad[2];
+    uint32_t base_strings;  // strings in the base-case segments of the level
+    uint32_t dist_strings;  // strings in the distribution segments of the level
 };
 
 // Device-side control block.

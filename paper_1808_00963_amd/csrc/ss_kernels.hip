@@ -56,6 +56,7 @@ __device__ void emit_segment(const Work& w, const Params& p, int nxt, const Elem
     atomicMax(&c->max_depth, depth);
     if (size <= p.base_max) {
         uint32_t slot = atomicAdd(&c->n_base, 1u);
+        atomicAdd(&c->base_strings, size);
         if (slot >= w.caps.base) { raise_err(w, ERR_CAPACITY); return; }
         w.base[nxt][slot] = BaseSeg{begin, size, depth, obase};
         return;
@@ -64,6 +65,7 @@ __device__ void emit_segment(const Work& w, const Params& p, int nxt, const Elem
     uint32_t v = (1u << logv) - 1, k = 2 * v + 1;
     uint32_t T = (size + TILE - 1) / TILE;
     uint32_t slot = atomicAdd(&c->n_dist, 1u);
+    atomicAdd(&c->dist_strings, size);
     uint32_t toff = atomicAdd(&c->n_tree, v + 1);
     uint32_t coff = atomicAdd(&c->n_cnt, k * T);
     uint32_t tioff = atomicAdd(&c->n_tiles, T);
