@@ -35,6 +35,8 @@ BYTES_PER_UNIT = {
     "k_classify": 18.0,
     "k_scatter": 34.0,
     "k_base": 24.0,
+    "k_base_wave1": 24.0,
+    "k_base_wave4": 24.0,
     "k_scan": 12.0,
     "k_lcp_fill": 72.0,
 }

@@ -72,10 +72,9 @@ typedef struct {
                                    per distribution step (section 4.2.2),
                                    1..10, default 10 */
     uint32_t bucket_target;     /* expected strings per bucket used to pick
-                                   v for a segment, default 512 */
+                                   v for a segment, 16..2^20, default 64 */
     uint32_t base_max;          /* segments with at most this many strings go
-                                   to the in-LDS base case, 64..2048,
-                                   default 2048 */
+                                   to the base case, 64..1024, default 1024 */
 } ss_config;
 
 /* Returns a short description of a status code (static storage). */
@@ -140,6 +139,7 @@ typedef struct {
     uint32_t base_segments;
     uint32_t pending_lcps;
     uint32_t max_depth;
+    uint32_t base_rounds;   /* refinement rounds (depth + 8) run inside base cases */
 } ss_stats;
 ss_status ss_get_stats(const ss_ctx* ctx, ss_stats* st);
 

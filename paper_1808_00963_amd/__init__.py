@@ -39,7 +39,8 @@ class Config(ctypes.Structure):
 class Stats(ctypes.Structure):
     _fields_ = [("levels", ctypes.c_uint32), ("dist_segments", ctypes.c_uint32),
                 ("dist_tiles", ctypes.c_uint32), ("base_segments", ctypes.c_uint32),
-                ("pending_lcps", ctypes.c_uint32), ("max_depth", ctypes.c_uint32)]
+                ("pending_lcps", ctypes.c_uint32), ("max_depth", ctypes.c_uint32),
+                ("base_rounds", ctypes.c_uint32)]
 
 
 class KernelTime(ctypes.Structure):

@@ -16,10 +16,13 @@
 using namespace ss;
 
 namespace {
-enum KernelId { K_INIT, K_ROOTS, K_BASE, K_SAMPLE, K_CLASSIFY, K_SCAN, K_SCATTER, K_CHILDREN, K_LCP_FILL, K_COUNT };
-const char* const KNAME[K_COUNT] = {"k_init", "k_roots", "k_base", "k_sample", "k_classify",
-                                    "k_scan", "k_scatter", "k_children", "k_lcp_fill"};
-const char* const KUNIT[K_COUNT] = {"strings", "sets", "strings", "segments", "strings",
+enum KernelId {
+    K_INIT, K_ROOTS, K_BASE_W1, K_BASE_W4, K_BASE, K_SAMPLE, K_CLASSIFY, K_SCAN, K_SCATTER, K_CHILDREN,
+    K_LCP_FILL, K_COUNT
+};
+const char* const KNAME[K_COUNT] = {"k_init", "k_roots", "k_base_wave1", "k_base_wave4", "k_base", "k_sample",
+                                    "k_classify", "k_scan", "k_scatter", "k_children", "k_lcp_fill"};
+const char* const KUNIT[K_COUNT] = {"strings", "sets", "strings", "strings", "strings", "segments", "strings",
                                     "counters", "strings", "segments", "boundaries"};
 
 // Event pairs around kernel launches, resolved at the next host sync.
@@ -43,7 +46,7 @@ struct ss_ctx {
     uint32_t ws_n = 0;  // largest n the workspace was laid out for
     Work work{};
     Ctl* host_ctl = nullptr;  // pinned copy of the device control block
-    ss_config cfg{10, 512, 2048};
+    ss_config cfg{10, 64, 1024};
     ss_status sticky = SS_OK;
     ss_stats stats{};
     Profiler prof;
@@ -67,7 +70,9 @@ Caps caps_for(uint32_t n, const ss_config& c) {
     uint64_t dist = N / (c.base_max + 1) + 2;
     k.dist = (uint32_t)dist;
     k.tiles = (uint32_t)(N / TILE + dist + 2);
-    k.base = (uint32_t)(N / 2 + 2);
+    k.base[0] = (uint32_t)(N / 2 + 2);
+    k.base[1] = (uint32_t)(N / (CLS_MAX[0] + 1) + 2);
+    k.base[2] = (uint32_t)(N / (CLS_MAX[1] + 1) + 2);
     // sum of (2v+1) * tiles: at most MAX_BUCKETS per tile of a multi-tile
     // segment, at most max(3, 2 size / bucket_target) for one-tile segments
     k.cnt = (uint32_t)std::min<uint64_t>(
@@ -94,7 +99,8 @@ size_t layout(uint32_t n, const Caps& k, char* base, Work* w) {
     for (int i = 0; i < 2; ++i) t.cnt[i] = (uint32_t*)take(sizeof(uint32_t) * k.cnt);
     t.partial = (uint32_t*)take(sizeof(uint32_t) * (k.cnt / 4096 + 4));
     for (int i = 0; i < 2; ++i) t.dist[i] = (Seg*)take(sizeof(Seg) * k.dist);
-    for (int i = 0; i < 2; ++i) t.base[i] = (BaseSeg*)take(sizeof(BaseSeg) * k.base);
+    for (int c = 0; c < NCLS; ++c)
+        for (int i = 0; i < 2; ++i) t.base[c][i] = (BaseSeg*)take(sizeof(BaseSeg) * k.base[c]);
     for (int i = 0; i < 2; ++i) t.tile_seg[i] = (uint32_t*)take(sizeof(uint32_t) * k.tiles);
     for (int i = 0; i < 2; ++i) t.tree_key[i] = (uint64_t*)take(sizeof(uint64_t) * k.tree);
     for (int i = 0; i < 2; ++i) t.tree_r[i] = (uint8_t*)take(k.tree);
@@ -225,10 +231,14 @@ ss_status run_sort(ss_ctx* ctx, const uint8_t* chars, const uint64_t* offsets, u
         ctx->stats.levels = level + 1;
         ctx->stats.dist_segments += c.n_dist;
         ctx->stats.dist_tiles += c.n_tiles;
-        ctx->stats.base_segments += c.n_base;
+        ctx->stats.base_segments += c.n_base[0] + c.n_base[1] + c.n_base[2];
         ctx->stats.max_depth = std::max(ctx->stats.max_depth, c.max_depth);
-        if (c.n_base)
-            SS_TRY(timed(ctx, s, K_BASE, c.base_strings, [&] { return launch_base(w, p, cur, c.n_base, s); }));
+        for (int cls = 0; cls < NCLS; ++cls) {
+            if (!c.n_base[cls]) continue;
+            const uint32_t nb = c.n_base[cls];
+            SS_TRY(timed(ctx, s, K_BASE_W1 + cls, c.base_strings[cls],
+                         [&] { return launch_base(w, p, cur, cls, nb, s); }));
+        }
         if (c.n_dist == 0) break;
         SS_TRY(launch_zero_counts(w, cur ^ 1, s));
         SS_TRY(timed(ctx, s, K_SAMPLE, c.n_dist, [&] { return launch_sample(w, p, cur, c.n_dist, s); }));
@@ -246,6 +256,7 @@ ss_status run_sort(ss_ctx* ctx, const uint8_t* chars, const uint64_t* offsets, u
     if ((st = read_ctl(ctx, s)) != SS_OK) return st;
     if (ctx->prof.on) ctx->prof.unit_sum[K_LCP_FILL] += ctx->host_ctl->n_pend;
     ctx->stats.pending_lcps = ctx->host_ctl->n_pend;
+    ctx->stats.base_rounds = ctx->host_ctl->base_rounds;
     if (ctx->host_ctl->err) return device_error_status(ctx->host_ctl->err);
     return SS_OK;
 }
@@ -341,7 +352,7 @@ ss_status ss_set_config(ss_ctx* ctx, const ss_config* cfg) {
 
 ss_status ss_workspace_query(const ss_ctx* ctx, uint32_t n, size_t* bytes) {
     if (!bytes) return SS_INVALID_ARG;
-    ss_config c = ctx ? ctx->cfg : ss_config{10, 512, 2048};
+    ss_config c = ctx ? ctx->cfg : ss_config{10, 64, 1024};
     *bytes = layout(n, caps_for(n, c), nullptr, nullptr);
     return SS_OK;
 }

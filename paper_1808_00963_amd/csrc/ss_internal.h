@@ -34,16 +34,22 @@ struct BaseSeg {
     uint32_t begin, size, depth, obase;
 };
 
+// Base-case size classes: one wave per segment with 1 string per lane
+// (<= 64), one wave with 4 strings per lane (<= 256), one work group with
+// the segment in LDS (<= base_max).
+constexpr int NCLS = 3;
+constexpr uint32_t CLS_MAX[NCLS] = {64, 256, 1024};
+
 // Work-list sizes of one recursion level.
 struct Counts {
     uint32_t n_dist;
     uint32_t n_tiles;
-    uint32_t n_base;
     uint32_t n_cnt;
     uint32_t n_tree;
+    uint32_t n_base[NCLS];
     uint32_t max_depth;
-    uint32_t base_strings;  // strings in the base-case segments of the level
-    uint32_t dist_strings;  // strings in the distribution segments of the level
+    uint32_t base_strings[NCLS];  // strings in the base-case segments of each class
+    uint32_t dist_strings;        // strings in the distribution segments of the level
 };
 
 // Device-side control block.
@@ -51,7 +57,8 @@ struct Ctl {
     Counts c[2];
     uint32_t n_pend;
     uint32_t err;
-    uint32_t pad[2];
+    uint32_t base_rounds;  // refinement rounds run by base cases (statistics)
+    uint32_t pad;
 };
 
 // Error bits raised on the device.
@@ -70,11 +77,11 @@ constexpr uint32_t IPT = 32;                // tile elements per thread
 constexpr uint32_t TILE = BLOCK * IPT;      // strings per classify/scatter tile
 constexpr uint32_t MAX_LOGV = 10;           // at most 1023 splitters
 constexpr uint32_t MAX_BUCKETS = (2u << MAX_LOGV) - 1;
-constexpr uint32_t BASE_CAP = 2048;         // largest base-case segment
+constexpr uint32_t BASE_CAP = 1024;         // largest base-case segment
 
 // Pool capacities of one level, derived from n (see ss_api.cpp).
 struct Caps {
-    uint32_t dist, tiles, base, cnt, tree, pend;
+    uint32_t dist, tiles, base[NCLS], cnt, tree, pend;
 };
 
 // Pointers to the workspace of one sort.
@@ -84,7 +91,7 @@ struct Work {
     uint32_t* cnt[2];
     uint32_t* partial;
     Seg* dist[2];
-    BaseSeg* base[2];
+    BaseSeg* base[NCLS][2];
     uint32_t* tile_seg[2];
     uint64_t* tree_key[2];
     uint8_t* tree_r[2];
@@ -111,7 +118,7 @@ hipError_t launch_init(const Work& w, const Params& p, hipStream_t s);
 hipError_t launch_roots(const Work& w, const Params& p, const uint32_t* set_begin, uint32_t num_sets,
                         hipStream_t s);
 hipError_t launch_zero_counts(const Work& w, int which, hipStream_t s);
-hipError_t launch_base(const Work& w, const Params& p, int cur, uint32_t n_base, hipStream_t s);
+hipError_t launch_base(const Work& w, const Params& p, int cur, int cls, uint32_t n_base, hipStream_t s);
 hipError_t launch_sample(const Work& w, const Params& p, int cur, uint32_t n_dist, hipStream_t s);
 hipError_t launch_classify(const Work& w, const Params& p, int cur, uint32_t n_tiles, uint32_t n_dist, hipStream_t s);
 hipError_t launch_scan(const Work& w, int cur, uint32_t n_cnt, hipStream_t s);

@@ -38,6 +38,24 @@ __device__ __forceinline__ uint64_t gather_key(const uint8_t* chars, uint64_t of
 
 __device__ __forceinline__ uint32_t rem8(uint32_t len, uint32_t h) { return min_u32(len - h, 8u); }
 
+// Length of the common prefix of two strings known to agree on their first
+// `from` characters, by comparing 8-byte words (at most `limit` = the
+// shorter length).
+__device__ __forceinline__ uint32_t lcp_from(const uint8_t* chars, uint64_t oa, uint32_t la, uint64_t ob, uint32_t lb,
+                                             uint32_t from) {
+    const uint32_t limit = la < lb ? la : lb;
+    uint32_t d = from;
+    while (d < limit) {
+        const uint64_t ka = gather_key(chars, oa, d, la), kb = gather_key(chars, ob, d, lb);
+        if (ka != kb) {
+            const uint32_t c = d + common_bytes(ka, kb);
+            return c < limit ? c : limit;
+        }
+        d += W;
+    }
+    return limit;
+}
+
 __device__ __forceinline__ void raise_err(const Work& w, uint32_t bits) { atomicOr(&w.ctl->err, bits); }
 
 // Appends a segment of the next level (positions [begin, begin+size) of
@@ -55,10 +73,11 @@ __device__ void emit_segment(const Work& w, const Params& p, int nxt, const Elem
     Counts* c = &w.ctl->c[nxt];
     atomicMax(&c->max_depth, depth);
     if (size <= p.base_max) {
-        uint32_t slot = atomicAdd(&c->n_base, 1u);
-        atomicAdd(&c->base_strings, size);
-        if (slot >= w.caps.base) { raise_err(w, ERR_CAPACITY); return; }
-        w.base[nxt][slot] = BaseSeg{begin, size, depth, obase};
+        const int cls = size <= CLS_MAX[0] ? 0 : (size <= CLS_MAX[1] ? 1 : 2);
+        uint32_t slot = atomicAdd(&c->n_base[cls], 1u);
+        atomicAdd(&c->base_strings[cls], size);
+        if (slot >= w.caps.base[cls]) { raise_err(w, ERR_CAPACITY); return; }
+        w.base[cls][nxt][slot] = BaseSeg{begin, size, depth, obase};
         return;
     }
     uint32_t logv = choose_logv(size, p.bucket_target, p.max_logv);
@@ -74,8 +93,7 @@ __device__ void emit_segment(const Work& w, const Params& p, int nxt, const Elem
         raise_err(w, ERR_CAPACITY);
         return;
     }
-    uint32_t* ts = w.tile_seg[nxt] + tioff;
-    for (uint32_t t = 0; t < T; ++t) ts[t] = slot;
+    // the tile list entries are written by k_sample (one work group per segment)
     w.dist[nxt][slot] = Seg{begin, size, depth, logv, toff, coff, tioff, obase};
 }
 
@@ -194,12 +212,13 @@ __global__ __launch_bounds__(BLOCK) void k_base(Work w, Params p, int cur) {
     __shared__ uint64_t A[BASE_CAP];
     __shared__ uint32_t dep[BASE_CAP];
     __shared__ uint32_t lv[BASE_CAP];
-    __shared__ uint32_t rs[BASE_CAP];
-    __shared__ uint8_t tie[BASE_CAP];
+    __shared__ uint32_t aux[BASE_CAP];   // bit 31: tie with the left neighbour; low bits: run start
+    __shared__ uint32_t rmin[BASE_CAP];  // per run start: common prefix of the run
     __shared__ uint32_t wtot[WAVES];
     __shared__ uint32_t any;
+    constexpr uint32_t PER = BASE_CAP / BLOCK;
 
-    const BaseSeg sg = w.base[cur][blockIdx.x];
+    const BaseSeg sg = w.base[2][cur][blockIdx.x];
     const uint32_t tid = threadIdx.x, m = sg.size, h = sg.depth;
     if (m < 2 || m > BASE_CAP || m > p.base_max || sg.begin > p.n || m > p.n - sg.begin) {  // uniform
         if (tid == 0) raise_err(w, ERR_BOUNDS);
@@ -237,20 +256,21 @@ __global__ __launch_bounds__(BLOCK) void k_base(Work w, Params p, int cur) {
                     else lv[i] = dep[i] + lcp_word(k0, r0, k1, r1);
                 }
             }
-            tie[i] = (uint8_t)t;
+            aux[i] = t << 31;
             if (t) any = 1;
         }
         __syncthreads();
         if (!any) break;
+        if (tid == 0) atomicAdd(&w.ctl->base_rounds, 1u);
         // run starts: inclusive max-scan of (tie ? 0 : position)
         {
-            const uint32_t base = tid * (BASE_CAP / BLOCK);
-            uint32_t loc[BASE_CAP / BLOCK];
+            const uint32_t base = tid * PER;
+            uint32_t loc[PER];
             uint32_t run = 0;
 #pragma unroll
-            for (uint32_t e = 0; e < BASE_CAP / BLOCK; ++e) {
+            for (uint32_t e = 0; e < PER; ++e) {
                 uint32_t i = base + e;
-                uint32_t x = (i < m && !tie[i]) ? i : 0u;
+                uint32_t x = (i < m && !(aux[i] >> 31)) ? i : 0u;
                 run = run > x ? run : x;
                 loc[e] = run;
             }
@@ -261,24 +281,44 @@ __global__ __launch_bounds__(BLOCK) void k_base(Work w, Params p, int cur) {
             __syncthreads();
             for (uint32_t q = 0; q < (tid >> 6); ++q) excl = excl > wtot[q] ? excl : wtot[q];
 #pragma unroll
-            for (uint32_t e = 0; e < BASE_CAP / BLOCK; ++e) {
+            for (uint32_t e = 0; e < PER; ++e) {
                 uint32_t i = base + e;
-                if (i < m) rs[i] = excl > loc[e] ? excl : loc[e];
+                if (i < m) {
+                    aux[i] = (aux[i] & 0x80000000u) | (excl > loc[e] ? excl : loc[e]);
+                    rmin[i] = ~0u;
+                }
             }
         }
         __syncthreads();
-        // strings in a run of equal words move on to the next word
+        // common prefix of each run: every member's LCP with the run's first
+        // string (all members agree on the word at their depth, so the
+        // comparison starts 8 characters further)
         for (uint32_t i = tid; i < m; i += BLOCK) {
-            uint64_t a = A[i];
-            uint32_t idx = (uint32_t)a;
-            bool act = tie[i] || (i + 1 < m && tie[i + 1]);
+            const uint32_t ai = aux[i];
+            const bool act = (ai >> 31) || (i + 1 < m && (aux[i + 1] >> 31));
+            const uint32_t rs = ai & 0x7FFFFFFFu;
+            if (act && rs != i) {
+                const uint32_t a = (uint32_t)A[i], b = (uint32_t)A[rs];
+                const uint64_t oa = p.offsets[a], ob = p.offsets[b];
+                const uint32_t la = (uint32_t)(p.offsets[a + 1] - oa), lb = (uint32_t)(p.offsets[b + 1] - ob);
+                atomicMin(&rmin[rs], lcp_from(p.chars, oa, la, ob, lb, dep[i] + W));
+            }
+        }
+        __syncthreads();
+        // strings of a run move on to the run's common prefix
+        for (uint32_t i = tid; i < m; i += BLOCK) {
+            const uint32_t ai = aux[i];
+            const bool act = (ai >> 31) || (i + 1 < m && (aux[i + 1] >> 31));
+            const uint64_t a = A[i];
+            const uint32_t idx = (uint32_t)a;
             if (act) {
-                uint32_t d2 = dep[i] + W;
+                const uint32_t rs = ai & 0x7FFFFFFFu;
+                const uint32_t d2 = rmin[rs];
                 dep[i] = d2;
-                uint64_t o0 = p.offsets[idx], o1 = p.offsets[idx + 1];
-                uint32_t len = (uint32_t)(o1 - o0);
+                const uint64_t o0 = p.offsets[idx], o1 = p.offsets[idx + 1];
+                const uint32_t len = (uint32_t)(o1 - o0);
                 K[i] = gather_key(p.chars, o0, d2, len);
-                A[i] = rec_pack(rs[i], rem8(len, d2), idx);
+                A[i] = rec_pack(rs, rem8(len, d2), idx);
             } else {
                 A[i] = rec_pack(i, rec_r(a), idx);
             }
@@ -288,6 +328,183 @@ __global__ __launch_bounds__(BLOCK) void k_base(Work w, Params p, int cur) {
     for (uint32_t i = tid; i < m; i += BLOCK) {
         p.perm[sg.begin + i] = (uint32_t)A[i] - sg.obase;
         if (i > 0) p.lcp[sg.begin + i] = lv[i];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// base case for small segments: one wave per segment, data in registers
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ bool rec_gt(uint64_t ka, uint64_t aa, uint64_t kb, uint64_t ab) {
+    return rec_greater(ka, aa, kb, ab);
+}
+
+// Bitonic sorting network over the 64*E records of one wave, blocked layout
+// (lane holds records lane*E .. lane*E+E-1): partners inside a lane are
+// exchanged in registers, partners in other lanes through cross-lane
+// shuffles.  No LDS, no barriers.
+template <int E>
+__device__ __forceinline__ void wave_bitonic(uint64_t (&K)[E], uint64_t (&A)[E], uint32_t lane) {
+#pragma unroll
+    for (uint32_t k = 2; k <= 64u * E; k <<= 1) {
+#pragma unroll
+        for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+            if (j < (uint32_t)E) {
+#pragma unroll
+                for (uint32_t r = 0; r < (uint32_t)E; ++r) {
+                    if ((r & j) == 0) {
+                        const uint32_t r2 = r | j;
+                        const uint32_t e = lane * E + r;
+                        const bool up = (e & k) == 0;
+                        if (rec_gt(K[r], A[r], K[r2], A[r2]) == up) {
+                            uint64_t tk = K[r]; K[r] = K[r2]; K[r2] = tk;
+                            uint64_t ta = A[r]; A[r] = A[r2]; A[r2] = ta;
+                        }
+                    }
+                }
+            } else {
+                const int lj = (int)(j / E);
+#pragma unroll
+                for (uint32_t r = 0; r < (uint32_t)E; ++r) {
+                    const uint32_t e = lane * E + r;
+                    uint64_t pk = __shfl_xor(K[r], lj, 64);
+                    uint64_t pa = __shfl_xor(A[r], lj, 64);
+                    const bool lower = (e & j) == 0;
+                    const bool up = (e & k) == 0;
+                    const bool keep_min = lower == up;
+                    const bool self_gt = rec_gt(K[r], A[r], pk, pa);
+                    if (self_gt == keep_min) { K[r] = pk; A[r] = pa; }
+                }
+            }
+        }
+    }
+}
+
+// Same job as k_base for a segment of at most 64*E strings: sort by
+// (key, r, index), refine runs of equal full words at depth + 8 (keys
+// re-gathered only for those strings), LCP of neighbours from the word at
+// the depth where they separate.  Depth and LCP are kept per position
+// (a run never moves), keys and records move.
+template <int E>
+__global__ __launch_bounds__(BLOCK) void k_base_wave(Work w, Params p, int cur, int cls, uint32_t nseg) {
+    __shared__ uint32_t LIDX[WAVES][64 * E];  // per run start: index of the run's first string
+    __shared__ uint32_t RMIN[WAVES][64 * E];  // per run start: common prefix of the run
+    const uint32_t lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const uint32_t si = blockIdx.x * WAVES + wv;
+    if (si >= nseg) return;  // uniform per wave
+    const BaseSeg sg = w.base[cls][cur][si];
+    const uint32_t m = sg.size, h = sg.depth;
+    if (m < 2 || m > 64u * E || sg.begin > p.n || m > p.n - sg.begin) {
+        if (lane == 0) raise_err(w, ERR_BOUNDS);
+        return;
+    }
+    const Elem* in = w.buf[cur] + sg.begin;
+    uint64_t K[E], A[E];
+    uint32_t D[E], LV[E];
+#pragma unroll
+    for (uint32_t r = 0; r < (uint32_t)E; ++r) {
+        const uint32_t e = lane * E + r;
+        if (e < m) {
+            Elem x = in[e];
+            K[r] = x.key;
+            A[r] = rec_pack(0, rem8(x.len, h), x.idx);
+        } else {
+            K[r] = ~0ull;
+            A[r] = ~0ull;
+        }
+        D[r] = h;
+        LV[r] = 0;
+    }
+    for (;;) {
+        wave_bitonic<E>(K, A, lane);
+        uint64_t pk0 = __shfl_up(K[E - 1], 1, 64);
+        uint64_t pa0 = __shfl_up(A[E - 1], 1, 64);
+        uint32_t tb = 0;
+#pragma unroll
+        for (uint32_t r = 0; r < (uint32_t)E; ++r) {
+            const uint32_t e = lane * E + r;
+            const uint64_t pk = r == 0 ? pk0 : K[r - 1];
+            const uint64_t pa = r == 0 ? pa0 : A[r - 1];
+            if (e > 0 && e < m && rec_grp(pa) == rec_grp(A[r])) {
+                const uint32_t r1 = rec_r(A[r]), r0 = rec_r(pa);
+                if (K[r] == pk && r1 == r0 && r1 == 8) tb |= 1u << r;
+                else LV[r] = D[r] + lcp_word(pk, r0, K[r], r1);
+            }
+        }
+        if (__ballot(tb != 0) == 0) break;
+        if (lane == 0) atomicAdd(&w.ctl->base_rounds, 1u);
+        // run starts (inclusive max-scan of "tie ? 0 : position")
+        uint32_t loc[E];
+        uint32_t run = 0;
+#pragma unroll
+        for (uint32_t r = 0; r < (uint32_t)E; ++r) {
+            const uint32_t e = lane * E + r;
+            const uint32_t x = ((tb >> r) & 1u) ? 0u : e;
+            run = run > x ? run : x;
+            loc[r] = run;
+        }
+        uint32_t incl = wave_incl_max(run);
+        uint32_t excl = __shfl_up(incl, 1, 64);
+        if (lane == 0) excl = 0;
+        const uint32_t tb_next_lane = __shfl_down(tb, 1, 64);
+        const uint32_t next_tie = lane < 63 ? (tb_next_lane & 1u) : 0u;
+        uint32_t RS[E];
+        uint32_t act = 0;
+#pragma unroll
+        for (uint32_t r = 0; r < (uint32_t)E; ++r) {
+            const uint32_t e = lane * E + r;
+            RS[r] = excl > loc[r] ? excl : loc[r];
+            const bool t_here = (tb >> r) & 1u;
+            const bool t_next = r + 1 < (uint32_t)E ? ((tb >> (r + 1)) & 1u) : next_tie;
+            if (e < m && (t_here || t_next)) act |= 1u << r;
+            if (e < m && RS[r] == e && (act >> r) & 1u) {  // run leader publishes its string
+                LIDX[wv][e] = (uint32_t)A[r];
+                RMIN[wv][e] = ~0u;
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        // common prefix of each run: members' LCP with the leader's string,
+        // starting 8 characters past the shared word
+#pragma unroll
+        for (uint32_t r = 0; r < (uint32_t)E; ++r) {
+            const uint32_t e = lane * E + r;
+            if (!((act >> r) & 1u) || RS[r] == e) continue;
+            const uint32_t a = (uint32_t)A[r], b = LIDX[wv][RS[r]];
+            const uint64_t oa = p.offsets[a], ob = p.offsets[b];
+            const uint32_t la = (uint32_t)(p.offsets[a + 1] - oa), lb = (uint32_t)(p.offsets[b + 1] - ob);
+            atomicMin(&RMIN[wv][RS[r]], lcp_from(p.chars, oa, la, ob, lb, D[r] + W));
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+        for (uint32_t r = 0; r < (uint32_t)E; ++r) {
+            const uint32_t e = lane * E + r;
+            if (e >= m) continue;
+            const uint32_t idx = (uint32_t)A[r];
+            if ((act >> r) & 1u) {
+                const uint32_t d2 = RMIN[wv][RS[r]];
+                D[r] = d2;
+                const uint64_t o0 = p.offsets[idx], o1 = p.offsets[idx + 1];
+                const uint32_t len = (uint32_t)(o1 - o0);
+                K[r] = gather_key(p.chars, o0, d2, len);
+                A[r] = rec_pack(RS[r], rem8(len, d2), idx);
+            } else {
+                A[r] = rec_pack(e, rec_r(A[r]), idx);
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+    }
+#pragma unroll
+    for (uint32_t r = 0; r < (uint32_t)E; ++r) {
+        const uint32_t e = lane * E + r;
+        if (e < m) {
+            p.perm[sg.begin + e] = (uint32_t)A[r] - sg.obase;
+            if (e > 0) p.lcp[sg.begin + e] = LV[r];
+        }
     }
 }
 
@@ -318,6 +535,11 @@ __global__ __launch_bounds__(BLOCK) void k_sample(Work w, Params p, int cur) {
         return;
     }
     const uint32_t v = (1u << d) - 1, a = 2 * v + 1, P = 2u << d;
+    {
+        const uint32_t T = (sg.size + TILE - 1) / TILE;
+        uint32_t* ts = w.tile_seg[cur] + sg.tile_off;
+        for (uint32_t t = tid; t < T; t += BLOCK) ts[t] = blockIdx.x;
+    }
     const Elem* in = w.buf[cur];
     for (uint32_t j = tid; j < P; j += BLOCK) {
         if (j < a) {
@@ -610,8 +832,11 @@ __global__ __launch_bounds__(BLOCK) void k_scatter(Work w, Params p, int cur, ui
 // valid) or h + 8 (odd i, equation 4.1 with the full word).  Every bucket
 // start inside the segment gets a pending LCP (its neighbours differ within
 // the word at depth h); the value is filled in once the final order is
-// known (figure 4.7).
+// known (figure 4.7).  List slots for the children of the whole segment are
+// reserved with one global atomic per list (two passes over the buckets).
 __global__ __launch_bounds__(BLOCK) void k_children(Work w, Params p, int cur) {
+    __shared__ uint32_t n_cls[NCLS], s_cls[NCLS], slot_cls[NCLS], cur_cls[NCLS];
+    __shared__ uint32_t n_pend_l, slot_pend, cur_pend, max_d;
     const Seg sg = w.dist[cur][blockIdx.x];
     const uint32_t tid = threadIdx.x, d = sg.logv, v = (1u << d) - 1, k = 2 * v + 1;
     const uint32_t T = (sg.size + TILE - 1) / TILE;
@@ -620,28 +845,73 @@ __global__ __launch_bounds__(BLOCK) void k_children(Work w, Params p, int cur) {
         if (tid == 0) raise_err(w, ERR_BOUNDS);
         return;
     }
+    if (tid < NCLS) { n_cls[tid] = 0; s_cls[tid] = 0; cur_cls[tid] = 0; }
+    if (tid == 0) { n_pend_l = 0; cur_pend = 0; max_d = 0; }
+    __syncthreads();
     const uint32_t* sc = w.cnt[cur] + sg.cnt_off;
     const uint32_t s0 = sc[0];
     const uint8_t* gr = w.tree_r[cur] + sg.tree_off;
-    for (uint32_t b = tid; b < k; b += BLOCK) {
-        uint32_t st = sc[(size_t)b * T] - s0;
+    const Elem* out = w.buf[nxt];
+    // bucket b -> (start, count, child depth); depth == ~0u: no child segment
+    auto bucket = [&](uint32_t b, uint32_t& st, uint32_t& cnt, uint32_t& depth) {
+        st = sc[(size_t)b * T] - s0;
         uint32_t en = (b + 1 < k) ? sc[(size_t)(b + 1) * T] - s0 : sg.size;
-        if (en <= st) continue;
-        if (en > sg.size) { raise_err(w, ERR_BOUNDS); continue; }
-        uint32_t pos = sg.begin + st;
+        cnt = en > st ? en - st : 0u;
+        if (en > sg.size) { raise_err(w, ERR_BOUNDS); cnt = 0; }
+        depth = sg.depth;
+        if (b & 1u) {
+            if (gr[level_index(b >> 1, d) - 1] < W) depth = ~0u;  // identical strings, written by the scatter
+            else depth += W;
+        }
+    };
+    // pass 1: count per list, finish singletons, large children directly
+    for (uint32_t b = tid; b < k; b += BLOCK) {
+        uint32_t st, cnt, depth;
+        bucket(b, st, cnt, depth);
+        if (cnt == 0) continue;
+        const uint32_t pos = sg.begin + st;
         if (st > 0) {
             p.lcp[pos] = PENDING | sg.depth;
-            uint32_t slot = atomicAdd(&w.ctl->n_pend, 1u);
-            if (slot < w.caps.pend) w.pend[slot] = make_uint2(pos, sg.obase);
-            else raise_err(w, ERR_CAPACITY);
+            atomicAdd(&n_pend_l, 1u);
         }
-        uint32_t depth = sg.depth;
-        if (b & 1u) {
-            uint32_t rx = gr[level_index(b >> 1, d) - 1];
-            if (rx < W) continue;  // written by the scatter
-            depth += W;
+        if (depth == ~0u) continue;
+        if (cnt == 1) { p.perm[pos] = out[pos].idx - sg.obase; continue; }
+        if (cnt <= p.base_max) {
+            const int cls = cnt <= CLS_MAX[0] ? 0 : (cnt <= CLS_MAX[1] ? 1 : 2);
+            atomicAdd(&n_cls[cls], 1u);
+            atomicAdd(&s_cls[cls], cnt);
+            atomicMax(&max_d, depth);
+        } else {
+            emit_segment(w, p, nxt, out, pos, cnt, depth, sg.obase);
         }
-        emit_segment(w, p, nxt, w.buf[nxt], pos, en - st, depth, sg.obase);
+    }
+    __syncthreads();
+    if (tid == 0) {
+        Counts* c = &w.ctl->c[nxt];
+        for (int q = 0; q < NCLS; ++q) {
+            slot_cls[q] = n_cls[q] ? atomicAdd(&c->n_base[q], n_cls[q]) : 0u;
+            if (s_cls[q]) atomicAdd(&c->base_strings[q], s_cls[q]);
+            if (slot_cls[q] + n_cls[q] > w.caps.base[q]) raise_err(w, ERR_CAPACITY);
+        }
+        if (max_d) atomicMax(&c->max_depth, max_d);
+        slot_pend = n_pend_l ? atomicAdd(&w.ctl->n_pend, n_pend_l) : 0u;
+        if (slot_pend + n_pend_l > w.caps.pend) raise_err(w, ERR_CAPACITY);
+    }
+    __syncthreads();
+    // pass 2: write the reserved entries
+    for (uint32_t b = tid; b < k; b += BLOCK) {
+        uint32_t st, cnt, depth;
+        bucket(b, st, cnt, depth);
+        if (cnt == 0) continue;
+        const uint32_t pos = sg.begin + st;
+        if (st > 0) {
+            const uint32_t q = slot_pend + atomicAdd(&cur_pend, 1u);
+            if (q < w.caps.pend) w.pend[q] = make_uint2(pos, sg.obase);
+        }
+        if (depth == ~0u || cnt == 1 || cnt > p.base_max) continue;
+        const int cls = cnt <= CLS_MAX[0] ? 0 : (cnt <= CLS_MAX[1] ? 1 : 2);
+        const uint32_t q = slot_cls[cls] + atomicAdd(&cur_cls[cls], 1u);
+        if (q < w.caps.base[cls]) w.base[cls][nxt][q] = BaseSeg{pos, cnt, depth, sg.obase};
     }
 }
 
@@ -696,8 +966,14 @@ hipError_t launch_roots(const Work& w, const Params& p, const uint32_t* set_begi
     hipLaunchKernelGGL(k_roots, dim3(blocks_for(num_sets, 64)), dim3(64), 0, s, w, p, set_begin, num_sets);
     return hipGetLastError();
 }
-hipError_t launch_base(const Work& w, const Params& p, int cur, uint32_t n_base, hipStream_t s) {
-    hipLaunchKernelGGL(k_base, dim3(n_base), dim3(BLOCK), 0, s, w, p, cur);
+hipError_t launch_base(const Work& w, const Params& p, int cur, int cls, uint32_t n_base, hipStream_t s) {
+    if (n_base == 0) return hipSuccess;
+    if (cls == 0)
+        hipLaunchKernelGGL(k_base_wave<1>, dim3(blocks_for(n_base, WAVES)), dim3(BLOCK), 0, s, w, p, cur, 0, n_base);
+    else if (cls == 1)
+        hipLaunchKernelGGL(k_base_wave<4>, dim3(blocks_for(n_base, WAVES)), dim3(BLOCK), 0, s, w, p, cur, 1, n_base);
+    else
+        hipLaunchKernelGGL(k_base, dim3(n_base), dim3(BLOCK), 0, s, w, p, cur);
     return hipGetLastError();
 }
 hipError_t launch_sample(const Work& w, const Params& p, int cur, uint32_t n_dist, hipStream_t s) {

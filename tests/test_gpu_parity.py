@@ -57,7 +57,7 @@ def _adversarial():
     base = bytes(rng.integers(0, 256, 600, dtype=np.uint8))
     cases["long_common_prefix"] = [base[:512] + bytes([x]) for x in rng.integers(0, 3, 9000)]
     cases["prefix_ladder_bytes"] = [base[:k] for k in rng.integers(0, 520, 12000)]
-    # Skyline string (section 6.4): T_i -> T_{i+1} s_i T_{i+1}, all suffixes
+    # Skyline string (section 6.3): T_i -> T_{i+1} s_i T_{i+1}, all suffixes
     p = 12
     t = b""
     for i in range(p, 0, -1):
@@ -119,3 +119,20 @@ def test_full_size_workloads(name, n):
     c, o = gen.workload(name, n)
     p, l = gpu_sort(c, o)
     assert_equal_to_oracle(c, o, p, l, full=False, label=name)
+
+
+@pytest.mark.parametrize("cfg", [dict(max_log_splitters=1, bucket_target=16, base_max=64),
+                                 dict(max_log_splitters=3, bucket_target=16, base_max=256),
+                                 dict(max_log_splitters=10, bucket_target=16, base_max=300),
+                                 dict(max_log_splitters=6, bucket_target=64, base_max=2048),
+                                 dict(max_log_splitters=10, bucket_target=2048, base_max=2048)],
+                         ids=lambda c: "d{max_log_splitters}_t{bucket_target}_b{base_max}".format(**c))
+@pytest.mark.parametrize("model", ["markov", "urls", "bytes", "suffixes"])
+def test_tuning_parameters_do_not_change_results(model, cfg):
+    import paper_1808_00963_amd as ss
+    note(f"case tuning model={model} cfg={cfg}")
+    ctx = ss.Context()
+    ctx.set_config(**cfg)
+    c, o = gen.generate(model, 60000 if model != "suffixes" else 20000, 77)
+    p, l = gpu_sort(c, o, ctx=ctx)
+    assert_equal_to_oracle(c, o, p, l, label=f"{model}/{cfg}")
