@@ -75,6 +75,11 @@ typedef struct {
                                    v for a segment, 16..2^20, default 64 */
     uint32_t base_max;          /* segments with at most this many strings go
                                    to the base case, 64..1024, default 1024 */
+    uint32_t persistent;        /* 0: one launch per step of every recursion
+                                   level, the host reads the level's work
+                                   counts in between (default); 1: the whole
+                                   sort in ONE persistent launch that walks the
+                                   levels on the device (no host round trips) */
 } ss_config;
 
 /* Returns a short description of a status code (static storage). */
@@ -124,6 +129,25 @@ ss_status ss_sort(const uint8_t* chars, const uint64_t* offsets, uint32_t n,
 ss_status ss_sort_batch(ss_ctx* ctx, const uint8_t* chars, const uint64_t* offsets, uint32_t n,
                         const uint32_t* set_begin, uint32_t num_sets,
                         uint32_t* perm_out, uint32_t* lcp_out, void* stream);
+
+/* Graph form of the batched sort: captures the complete batched sort of the
+ * given buffers (workspace sized and bound at capture time) as a hipGraph
+ * whose only work is a reset kernel and ONE persistent kernel, so repeated
+ * launches cost one graph launch each.  The buffers must stay valid and keep
+ * their shapes while the graph exists; the contents may change between
+ * launches.  Launches of graphs of the same context must not overlap (they
+ * share its workspace).  ss_graph_launch enqueues and returns; the result of
+ * a launch (device-side errors) is read by ss_ctx_sync. */
+typedef struct ss_graph ss_graph;
+ss_status ss_graph_create_batch(ss_ctx* ctx, const uint8_t* chars, const uint64_t* offsets, uint32_t n,
+                                const uint32_t* set_begin, uint32_t num_sets, uint32_t* perm_out,
+                                uint32_t* lcp_out, ss_graph** graph_out);
+ss_status ss_graph_launch(ss_graph* graph, void* stream);
+void ss_graph_destroy(ss_graph* graph);
+
+/* Waits for `stream` and returns the device-side status of the context's
+ * last sort (sticky, as for the other entry points). */
+ss_status ss_ctx_sync(ss_ctx* ctx, void* stream);
 
 /* Sticky device-side error of a context (SS_OK if none). */
 ss_status ss_get_last_error(const ss_ctx* ctx);

@@ -33,7 +33,7 @@ class SSError(RuntimeError):
 
 class Config(ctypes.Structure):
     _fields_ = [("max_log_splitters", ctypes.c_uint32), ("bucket_target", ctypes.c_uint32),
-                ("base_max", ctypes.c_uint32)]
+                ("base_max", ctypes.c_uint32), ("persistent", ctypes.c_uint32)]
 
 
 class Stats(ctypes.Structure):
@@ -70,6 +70,10 @@ def lib():
             "ss_get_last_error": (i32, [vp]),
             "ss_clear_error": (None, [vp]),
             "ss_get_stats": (i32, [vp, ctypes.POINTER(Stats)]),
+            "ss_graph_create_batch": (i32, [vp, vp, vp, u32, vp, u32, vp, vp, ctypes.POINTER(vp)]),
+            "ss_graph_launch": (i32, [vp, vp]),
+            "ss_graph_destroy": (None, [vp]),
+            "ss_ctx_sync": (i32, [vp, vp]),
             "ss_set_profiling": (i32, [vp, i32]),
             "ss_get_kernel_times": (i32, [vp, ctypes.POINTER(KernelTime), u32, ctypes.POINTER(u32)]),
             "ss_reset_kernel_times": (None, [vp]),
@@ -143,7 +147,7 @@ class Context:
         _check(lib().ss_get_config(self._h, ctypes.byref(c)), "ss_get_config")
         return c
 
-    def set_config(self, max_log_splitters=None, bucket_target=None, base_max=None):
+    def set_config(self, max_log_splitters=None, bucket_target=None, base_max=None, persistent=None):
         c = self.config
         if max_log_splitters is not None:
             c.max_log_splitters = max_log_splitters
@@ -151,6 +155,8 @@ class Context:
             c.bucket_target = bucket_target
         if base_max is not None:
             c.base_max = base_max
+        if persistent is not None:
+            c.persistent = 1 if persistent else 0
         _check(lib().ss_set_config(self._h, ctypes.byref(c)), "ss_set_config")
 
     def stats(self) -> dict:
@@ -198,6 +204,23 @@ class Context:
         _check(st, "ss_sort_ex")
         return perm, lcp
 
+    def sync(self, stream=None):
+        """Waits for the stream; raises on a device-side error of the last sort."""
+        _check(lib().ss_ctx_sync(self._h, _stream_ptr(stream)), "ss_ctx_sync")
+
+    def graph_batch(self, chars, offsets, set_begin, perm, lcp) -> "Graph":
+        """Captures the batched sort of these buffers as a hipGraph with one
+        persistent kernel (see ss_graph_create_batch)."""
+        _check_inputs(chars, offsets)
+        n = offsets.numel() - 1
+        g = ctypes.c_void_p()
+        st = lib().ss_graph_create_batch(self._h, ctypes.c_void_p(chars.data_ptr()), ctypes.c_void_p(offsets.data_ptr()),
+                                         n, ctypes.c_void_p(set_begin.data_ptr()), set_begin.numel() - 1,
+                                         ctypes.c_void_p(perm.data_ptr()), ctypes.c_void_p(lcp.data_ptr()),
+                                         ctypes.byref(g))
+        _check(st, "ss_graph_create_batch")
+        return Graph(g, self, (chars, offsets, set_begin, perm, lcp))
+
     def sort_batch(self, chars, offsets, set_begin, perm=None, lcp=None, stream=None):
         """Sorts the sets delimited by set_begin (int32/uint32 device tensor,
         num_sets+1 entries); outputs hold set-local indices."""
@@ -216,6 +239,29 @@ class Context:
                                  _stream_ptr(stream))
         _check(st, "ss_sort_batch")
         return perm, lcp
+
+
+class Graph:
+    """A captured batched sort (ss_graph); keeps its buffers alive."""
+
+    def __init__(self, handle, ctx, keep):
+        self._h = handle
+        self.ctx = ctx
+        self._keep = keep
+
+    def launch(self, stream=None):
+        _check(lib().ss_graph_launch(self._h, _stream_ptr(stream)), "ss_graph_launch")
+
+    def close(self):
+        if self._h:
+            lib().ss_graph_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def sort(chars, offsets, stream=None):

@@ -18,12 +18,12 @@ using namespace ss;
 namespace {
 enum KernelId {
     K_INIT, K_ROOTS, K_BASE_W1, K_BASE_W4, K_BASE, K_SAMPLE, K_CLASSIFY, K_SCAN, K_SCATTER, K_CHILDREN,
-    K_LCP_FILL, K_COUNT
+    K_LCP_FILL, K_PERSIST, K_COUNT
 };
 const char* const KNAME[K_COUNT] = {"k_init", "k_roots", "k_base_wave1", "k_base_wave4", "k_base", "k_sample",
-                                    "k_classify", "k_scan", "k_scatter", "k_children", "k_lcp_fill"};
+                                    "k_classify", "k_scan", "k_scatter", "k_children", "k_lcp_fill", "k_persist"};
 const char* const KUNIT[K_COUNT] = {"strings", "sets", "strings", "strings", "strings", "segments", "strings",
-                                    "counters", "strings", "segments", "boundaries"};
+                                    "counters", "strings", "segments", "boundaries", "strings"};
 
 // Event pairs around kernel launches, resolved at the next host sync.
 struct Profiler {
@@ -46,10 +46,17 @@ struct ss_ctx {
     uint32_t ws_n = 0;  // largest n the workspace was laid out for
     Work work{};
     Ctl* host_ctl = nullptr;  // pinned copy of the device control block
-    ss_config cfg{10, 64, 1024};
+    ss_config cfg{10, 64, 1024, 0};
     ss_status sticky = SS_OK;
     ss_stats stats{};
     Profiler prof;
+    uint32_t persist_blocks = 0;  // co-resident work groups of the persistent kernel
+};
+
+struct ss_graph {
+    ss_ctx* ctx = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
 };
 
 namespace {
@@ -60,6 +67,7 @@ void clamp_config(ss_config* c) {
     c->max_log_splitters = std::min<uint32_t>(std::max<uint32_t>(c->max_log_splitters, 1), MAX_LOGV);
     c->bucket_target = std::min<uint32_t>(std::max<uint32_t>(c->bucket_target, 16), 1u << 20);
     c->base_max = std::min<uint32_t>(std::max<uint32_t>(c->base_max, 64), BASE_CAP);
+    c->persistent = c->persistent ? 1u : 0u;
 }
 
 // Worst-case pool sizes of one recursion level for n strings (the segments
@@ -106,6 +114,7 @@ size_t layout(uint32_t n, const Caps& k, char* base, Work* w) {
     for (int i = 0; i < 2; ++i) t.tree_r[i] = (uint8_t*)take(k.tree);
     t.pend = (uint2*)take(sizeof(uint2) * k.pend);
     t.ctl = (Ctl*)take(sizeof(Ctl));
+    t.bar = (GridBar*)take(sizeof(GridBar));
     t.caps = k;
     if (w) *w = t;
     return off;
@@ -203,6 +212,23 @@ ss_status read_ctl(ss_ctx* ctx, hipStream_t s) {
     return SS_OK;
 }
 
+// Reset + the persistent kernel (no host synchronisation; capturable).
+ss_status enqueue_persistent(ss_ctx* ctx, const Params& p, const uint32_t* set_begin, uint32_t nroots,
+                             hipStream_t s) {
+    if (ctx->persist_blocks == 0) {
+        uint32_t b = 0;
+        SS_TRY(persistent_capacity(ctx->device, &b));
+        if (b == 0) return SS_HIP_ERROR;
+        ctx->persist_blocks = b;
+    }
+    const Work& w = ctx->work;
+    SS_TRY(launch_reset(w, s));
+    SS_TRY(timed(ctx, s, K_PERSIST, p.n, [&] {
+        return launch_persistent(w, p, set_begin, nroots, ctx->persist_blocks, s);
+    }));
+    return SS_OK;
+}
+
 // The sort: initial key gather, roots, then one iteration per recursion
 // level over all live segments, then the boundary LCPs.
 ss_status run_sort(ss_ctx* ctx, const uint8_t* chars, const uint64_t* offsets, uint32_t n,
@@ -219,6 +245,14 @@ ss_status run_sort(ss_ctx* ctx, const uint8_t* chars, const uint64_t* offsets, u
     Params p{chars, offsets, n, perm, lcp, ctx->cfg.max_log_splitters, ctx->cfg.bucket_target, ctx->cfg.base_max};
 
     const uint32_t nroots = set_begin ? num_sets : 1;
+    if (ctx->cfg.persistent) {
+        if ((st = enqueue_persistent(ctx, p, set_begin, nroots, s)) != SS_OK) return st;
+        if ((st = read_ctl(ctx, s)) != SS_OK) return st;
+        ctx->stats.pending_lcps = ctx->host_ctl->n_pend;
+        ctx->stats.base_rounds = ctx->host_ctl->base_rounds;
+        if (ctx->host_ctl->err) return device_error_status(ctx->host_ctl->err);
+        return SS_OK;
+    }
     SS_TRY(launch_reset(w, s));
     SS_TRY(timed(ctx, s, K_INIT, n, [&] { return launch_init(w, p, s); }));
     SS_TRY(timed(ctx, s, K_ROOTS, nroots, [&] { return launch_roots(w, p, set_begin, nroots, s); }));
@@ -352,7 +386,7 @@ ss_status ss_set_config(ss_ctx* ctx, const ss_config* cfg) {
 
 ss_status ss_workspace_query(const ss_ctx* ctx, uint32_t n, size_t* bytes) {
     if (!bytes) return SS_INVALID_ARG;
-    ss_config c = ctx ? ctx->cfg : ss_config{10, 64, 1024};
+    ss_config c = ctx ? ctx->cfg : ss_config{10, 64, 1024, 0};
     *bytes = layout(n, caps_for(n, c), nullptr, nullptr);
     return SS_OK;
 }
@@ -385,6 +419,76 @@ ss_status ss_sort_batch(ss_ctx* ctx, const uint8_t* chars, const uint64_t* offse
     if (num_sets == 0) return n == 0 ? SS_OK : SS_INVALID_ARG;
     if (!set_begin) return SS_INVALID_ARG;
     return sort_checked(ctx, chars, offsets, n, set_begin, num_sets, perm_out, lcp_out, stream);
+}
+
+ss_status ss_graph_create_batch(ss_ctx* ctx, const uint8_t* chars, const uint64_t* offsets, uint32_t n,
+                                const uint32_t* set_begin, uint32_t num_sets, uint32_t* perm_out,
+                                uint32_t* lcp_out, ss_graph** graph_out) {
+    if (!ctx || !graph_out || !offsets || !perm_out || !lcp_out || !set_begin || num_sets == 0 || n == 0)
+        return SS_INVALID_ARG;
+    if (n > 0xFFFFFFFEu) return SS_LIMIT;
+    *graph_out = nullptr;
+    int cur_dev = -1;
+    SS_TRY(hipGetDevice(&cur_dev));
+    if (cur_dev != ctx->device) SS_TRY(hipSetDevice(ctx->device));
+    ss_status st = ensure_workspace(ctx, n);  // no allocation may happen during capture
+    if (st != SS_OK) return st;
+    hipStream_t cs = nullptr;
+    SS_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    const bool prof = ctx->prof.on;
+    ctx->prof.on = false;  // no event records inside the graph
+    Params p{chars, offsets, n, perm_out, lcp_out, ctx->cfg.max_log_splitters, ctx->cfg.bucket_target,
+             ctx->cfg.base_max};
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        st = enqueue_persistent(ctx, p, set_begin, num_sets, cs);
+        hipError_t e2 = hipStreamEndCapture(cs, &g);
+        if (st == SS_OK && e2 != hipSuccess) st = SS_HIP_ERROR;
+    } else {
+        st = SS_HIP_ERROR;
+    }
+    ctx->prof.on = prof;
+    (void)hipStreamDestroy(cs);
+    if (st != SS_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return st;
+    }
+    hipGraphExec_t ex = nullptr;
+    if (hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        return SS_HIP_ERROR;
+    }
+    auto* gr = new ss_graph();
+    gr->ctx = ctx;
+    gr->graph = g;
+    gr->exec = ex;
+    *graph_out = gr;
+    return SS_OK;
+}
+
+ss_status ss_graph_launch(ss_graph* graph, void* stream) {
+    if (!graph || !graph->exec) return SS_INVALID_ARG;
+    return hipGraphLaunch(graph->exec, (hipStream_t)stream) == hipSuccess ? SS_OK : SS_HIP_ERROR;
+}
+
+void ss_graph_destroy(ss_graph* graph) {
+    if (!graph) return;
+    if (graph->exec) (void)hipGraphExecDestroy(graph->exec);
+    if (graph->graph) (void)hipGraphDestroy(graph->graph);
+    delete graph;
+}
+
+ss_status ss_ctx_sync(ss_ctx* ctx, void* stream) {
+    if (!ctx) return SS_INVALID_ARG;
+    ss_status st = read_ctl(ctx, (hipStream_t)stream);
+    if (st != SS_OK) return st;
+    if (ctx->host_ctl->err) {
+        st = device_error_status(ctx->host_ctl->err);
+        ctx->sticky = st;
+        return st;
+    }
+    return SS_OK;
 }
 
 ss_status ss_get_last_error(const ss_ctx* ctx) { return ctx ? ctx->sticky : SS_INVALID_ARG; }

@@ -67,6 +67,17 @@ enum : uint32_t {
     ERR_CAPACITY = 2u,     // an internal pool overflowed
     ERR_BOUNDS = 4u,       // a computed position fell outside its segment
     ERR_SETS = 8u,         // batch set boundaries invalid
+    ERR_BARRIER = 16u,     // a grid barrier of the persistent kernel timed out
+    ERR_LEVELS = 32u,      // the level limit of the persistent kernel was reached
+};
+
+// Grid barrier of the persistent kernel: arrival counter and generation on
+// separate 128-byte lines.
+struct GridBar {
+    uint32_t count;
+    uint32_t pad0[31];
+    uint32_t gen;
+    uint32_t pad1[31];
 };
 
 constexpr uint32_t PENDING = 0x80000000u;   // lcp entry = PENDING | depth until filled
@@ -97,6 +108,7 @@ struct Work {
     uint8_t* tree_r[2];
     uint2* pend;
     Ctl* ctl;
+    GridBar* bar;
     Caps caps;
 };
 
@@ -125,5 +137,12 @@ hipError_t launch_scan(const Work& w, int cur, uint32_t n_cnt, hipStream_t s);
 hipError_t launch_scatter(const Work& w, const Params& p, int cur, uint32_t n_tiles, uint32_t n_dist, hipStream_t s);
 hipError_t launch_children(const Work& w, const Params& p, int cur, uint32_t n_dist, hipStream_t s);
 hipError_t launch_lcp_fill(const Work& w, const Params& p, hipStream_t s);
+// The whole sort (init, roots, every level, boundary LCPs) in one launch of
+// `blocks` work groups that must all be resident; levels are separated by
+// grid barriers.  launch_reset must precede it on the stream.
+hipError_t launch_persistent(const Work& w, const Params& p, const uint32_t* set_begin, uint32_t num_sets,
+                             uint32_t blocks, hipStream_t s);
+// Largest number of co-resident work groups of the persistent kernel.
+hipError_t persistent_capacity(int device, uint32_t* blocks);
 
 }  // namespace ss

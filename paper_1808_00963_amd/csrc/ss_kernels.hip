@@ -117,6 +117,61 @@ __device__ __forceinline__ uint32_t wave_incl_max(uint32_t x) {
     return x;
 }
 
+
+// Shared-memory layouts of the per-item device functions.  Standalone
+// kernels declare the one they need; the persistent kernel declares their
+// union, so its LDS footprint is the largest of them.
+struct SmBase {
+    uint64_t K[BASE_CAP];
+    uint64_t A[BASE_CAP];
+    uint32_t dep[BASE_CAP];
+    uint32_t lv[BASE_CAP];
+    uint32_t aux[BASE_CAP];   // bit 31: tie with the left neighbour; low bits: run start
+    uint32_t rmin[BASE_CAP];  // per run start: common prefix of the run
+    uint32_t wtot[WAVES];
+    uint32_t any;
+};
+struct SmWave {
+    uint32_t LIDX[WAVES][256];  // per run start: index of the run's first string
+    uint32_t RMIN[WAVES][256];  // per run start: common prefix of the run
+};
+struct SmSample {
+    uint64_t SK[2 << MAX_LOGV];
+    uint32_t SR[2 << MAX_LOGV];
+    uint64_t TK[1 << MAX_LOGV];
+    uint32_t TR[1 << MAX_LOGV];
+    uint16_t NL[1 << MAX_LOGV];
+    uint16_t NH[1 << MAX_LOGV];
+};
+struct SmClassify {
+    uint64_t TK[1 << MAX_LOGV];
+    uint32_t TR[1 << MAX_LOGV];
+    uint32_t H[MAX_BUCKETS + 1];
+};
+struct SmScatter {
+    uint32_t WC[WAVES][MAX_BUCKETS + 1];
+    uint32_t GB[MAX_BUCKETS + 1];
+    uint32_t BS[MAX_BUCKETS + 1];
+    uint8_t XR[1 << MAX_LOGV];
+};
+struct SmChildren {
+    uint32_t n_cls[NCLS], s_cls[NCLS], slot_cls[NCLS], cur_cls[NCLS];
+    uint32_t n_pend_l, slot_pend, cur_pend, max_d;
+};
+struct SmScan {
+    uint32_t wt[16];
+    uint32_t carry;
+};
+union SmAll {
+    SmBase base;
+    SmWave wave;
+    SmSample sample;
+    SmClassify classify;
+    SmScatter scatter;
+    SmChildren children;
+    SmScan scan;
+};
+
 // ---------------------------------------------------------------------------
 // reset / init / roots
 // ---------------------------------------------------------------------------
@@ -124,6 +179,8 @@ __device__ __forceinline__ uint32_t wave_incl_max(uint32_t x) {
 __global__ void k_reset(Work w) {
     uint32_t* p = (uint32_t*)w.ctl;
     for (uint32_t i = threadIdx.x; i < sizeof(Ctl) / 4; i += blockDim.x) p[i] = 0;
+    uint32_t* b = (uint32_t*)w.bar;
+    for (uint32_t i = threadIdx.x; i < sizeof(GridBar) / 4; i += blockDim.x) b[i] = 0;
 }
 
 __global__ void k_zero_counts(Work w, int which) {
@@ -133,9 +190,7 @@ __global__ void k_zero_counts(Work w, int which) {
 
 // Key gather at depth 0 for every string (Algorithm 4.1's chars_h with
 // h = 0), plus offset validation.
-__global__ __launch_bounds__(BLOCK) void k_init(Work w, Params p) {
-    uint32_t i = blockIdx.x * BLOCK + threadIdx.x;
-    if (i >= p.n) return;
+__device__ __forceinline__ void dev_init_one(const Work& w, const Params& p, uint32_t i) {
     uint64_t o0 = p.offsets[i], o1 = p.offsets[i + 1];
     uint32_t len = 0;
     if (o1 < o0 || o1 - o0 > MAX_LEN || (o1 > o0 && p.chars == nullptr)) raise_err(w, ERR_OFFSETS);
@@ -147,10 +202,14 @@ __global__ __launch_bounds__(BLOCK) void k_init(Work w, Params p) {
     w.buf[0][i] = e;
 }
 
+__global__ __launch_bounds__(BLOCK) void k_init(Work w, Params p) {
+    uint32_t i = blockIdx.x * BLOCK + threadIdx.x;
+    if (i < p.n) dev_init_one(w, p, i);
+}
+
 // One root segment per set (one set = the whole input for a plain sort).
-__global__ void k_roots(Work w, Params p, const uint32_t* set_begin, uint32_t num_sets) {
-    uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= num_sets) return;
+__device__ __forceinline__ void dev_root_one(const Work& w, const Params& p, const uint32_t* set_begin,
+                                             uint32_t num_sets, uint32_t j) {
     uint32_t b = 0, e = p.n;
     if (set_begin) {
         b = set_begin[j];
@@ -162,6 +221,11 @@ __global__ void k_roots(Work w, Params p, const uint32_t* set_begin, uint32_t nu
     }
     if (e > b) p.lcp[b] = 0;
     emit_segment(w, p, 0, w.buf[0], b, e - b, 0, b);
+}
+
+__global__ void k_roots(Work w, Params p, const uint32_t* set_begin, uint32_t num_sets) {
+    uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < num_sets) dev_root_one(w, p, set_begin, num_sets, j);
 }
 
 // ---------------------------------------------------------------------------
@@ -207,18 +271,18 @@ __device__ void bitonic_rec(uint64_t* K, uint64_t* A, uint32_t P) {
 // LCPs of neighbours separated at depth d are d plus the common bytes of
 // their words at d (the "last compared word"); the role of LCP-insertion
 // sort (Algorithm 4.6) as the paper's base case.
-__global__ __launch_bounds__(BLOCK) void k_base(Work w, Params p, int cur) {
-    __shared__ uint64_t K[BASE_CAP];
-    __shared__ uint64_t A[BASE_CAP];
-    __shared__ uint32_t dep[BASE_CAP];
-    __shared__ uint32_t lv[BASE_CAP];
-    __shared__ uint32_t aux[BASE_CAP];   // bit 31: tie with the left neighbour; low bits: run start
-    __shared__ uint32_t rmin[BASE_CAP];  // per run start: common prefix of the run
-    __shared__ uint32_t wtot[WAVES];
-    __shared__ uint32_t any;
+__device__ void dev_base_wg(const Work& w, const Params& p, int cur, uint32_t item, SmBase& sm) {
+    uint64_t* K = sm.K;
+    uint64_t* A = sm.A;
+    uint32_t* dep = sm.dep;
+    uint32_t* lv = sm.lv;
+    uint32_t* aux = sm.aux;
+    uint32_t* rmin = sm.rmin;
+    uint32_t* wtot = sm.wtot;
+    uint32_t& any = sm.any;
     constexpr uint32_t PER = BASE_CAP / BLOCK;
 
-    const BaseSeg sg = w.base[2][cur][blockIdx.x];
+    const BaseSeg sg = w.base[2][cur][item];
     const uint32_t tid = threadIdx.x, m = sg.size, h = sg.depth;
     if (m < 2 || m > BASE_CAP || m > p.base_max || sg.begin > p.n || m > p.n - sg.begin) {  // uniform
         if (tid == 0) raise_err(w, ERR_BOUNDS);
@@ -331,6 +395,11 @@ __global__ __launch_bounds__(BLOCK) void k_base(Work w, Params p, int cur) {
     }
 }
 
+__global__ __launch_bounds__(BLOCK) void k_base(Work w, Params p, int cur) {
+    __shared__ SmBase sm;
+    dev_base_wg(w, p, cur, blockIdx.x, sm);
+}
+
 // ---------------------------------------------------------------------------
 // base case for small segments: one wave per segment, data in registers
 // ---------------------------------------------------------------------------
@@ -386,11 +455,12 @@ __device__ __forceinline__ void wave_bitonic(uint64_t (&K)[E], uint64_t (&A)[E],
 // the depth where they separate.  Depth and LCP are kept per position
 // (a run never moves), keys and records move.
 template <int E>
-__global__ __launch_bounds__(BLOCK) void k_base_wave(Work w, Params p, int cur, int cls, uint32_t nseg) {
-    __shared__ uint32_t LIDX[WAVES][64 * E];  // per run start: index of the run's first string
-    __shared__ uint32_t RMIN[WAVES][64 * E];  // per run start: common prefix of the run
+__device__ void dev_base_wave(const Work& w, const Params& p, int cur, int cls, uint32_t group, uint32_t nseg,
+                              SmWave& sm) {
+    auto& LIDX = sm.LIDX;
+    auto& RMIN = sm.RMIN;
     const uint32_t lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const uint32_t si = blockIdx.x * WAVES + wv;
+    const uint32_t si = group * WAVES + wv;
     if (si >= nseg) return;  // uniform per wave
     const BaseSeg sg = w.base[cls][cur][si];
     const uint32_t m = sg.size, h = sg.depth;
@@ -508,6 +578,12 @@ __global__ __launch_bounds__(BLOCK) void k_base_wave(Work w, Params p, int cur, 
     }
 }
 
+template <int E>
+__global__ __launch_bounds__(BLOCK) void k_base_wave(Work w, Params p, int cur, int cls, uint32_t nseg) {
+    __shared__ SmWave sm;
+    dev_base_wave<E>(w, p, cur, cls, blockIdx.x, nseg, sm);
+}
+
 // ---------------------------------------------------------------------------
 // distribution step: sample + splitter tree
 // ---------------------------------------------------------------------------
@@ -521,14 +597,14 @@ __device__ __forceinline__ bool kr_gt(uint64_t ka, uint32_t ra, uint64_t kb, uin
 // skipping duplicates (section 4.2.2, "Sampling"), level by level, directly
 // into the level-order tree; an empty sub-range repeats its parent's
 // splitter so the in-order splitter sequence stays sorted.
-__global__ __launch_bounds__(BLOCK) void k_sample(Work w, Params p, int cur) {
-    __shared__ uint64_t SK[2 << MAX_LOGV];
-    __shared__ uint32_t SR[2 << MAX_LOGV];
-    __shared__ uint64_t TK[1 << MAX_LOGV];
-    __shared__ uint32_t TR[1 << MAX_LOGV];
-    __shared__ uint16_t NL[1 << MAX_LOGV];
-    __shared__ uint16_t NH[1 << MAX_LOGV];
-    const Seg sg = w.dist[cur][blockIdx.x];
+__device__ void dev_sample(const Work& w, const Params& p, int cur, uint32_t item, SmSample& sm) {
+    uint64_t* SK = sm.SK;
+    uint32_t* SR = sm.SR;
+    uint64_t* TK = sm.TK;
+    uint32_t* TR = sm.TR;
+    uint16_t* NL = sm.NL;
+    uint16_t* NH = sm.NH;
+    const Seg sg = w.dist[cur][item];
     const uint32_t tid = threadIdx.x, d = sg.logv;
     if (d < 1 || d > MAX_LOGV || sg.begin > p.n || sg.size > p.n - sg.begin || sg.size < (4u << d)) {
         if (tid == 0) raise_err(w, ERR_BOUNDS);
@@ -538,7 +614,7 @@ __global__ __launch_bounds__(BLOCK) void k_sample(Work w, Params p, int cur) {
     {
         const uint32_t T = (sg.size + TILE - 1) / TILE;
         uint32_t* ts = w.tile_seg[cur] + sg.tile_off;
-        for (uint32_t t = tid; t < T; t += BLOCK) ts[t] = blockIdx.x;
+        for (uint32_t t = tid; t < T; t += BLOCK) ts[t] = item;
     }
     const Elem* in = w.buf[cur];
     for (uint32_t j = tid; j < P; j += BLOCK) {
@@ -599,6 +675,11 @@ __global__ __launch_bounds__(BLOCK) void k_sample(Work w, Params p, int cur) {
     }
 }
 
+__global__ __launch_bounds__(BLOCK) void k_sample(Work w, Params p, int cur) {
+    __shared__ SmSample sm;
+    dev_sample(w, p, cur, blockIdx.x, sm);
+}
+
 // ---------------------------------------------------------------------------
 // distribution step: classification and tile histograms
 // ---------------------------------------------------------------------------
@@ -612,11 +693,12 @@ struct TreeView {
 // own bucket counters): each string's bucket is stored in the oracle array
 // `bkt`, the tile's 2v+1 counts go to the counter pool in bucket-major
 // order (bucket b of tile t of segment s at cnt_off + b*T + t).
-__global__ __launch_bounds__(BLOCK) void k_classify(Work w, Params p, int cur, uint32_t n_dist) {
-    __shared__ uint64_t TK[1 << MAX_LOGV];
-    __shared__ uint32_t TR[1 << MAX_LOGV];
-    __shared__ uint32_t H[MAX_BUCKETS + 1];
-    const uint32_t t = blockIdx.x, tid = threadIdx.x;
+__device__ void dev_classify(const Work& w, const Params& p, int cur, uint32_t t, uint32_t n_dist,
+                             SmClassify& sm) {
+    uint64_t* TK = sm.TK;
+    uint32_t* TR = sm.TR;
+    uint32_t* H = sm.H;
+    const uint32_t tid = threadIdx.x;
     const uint32_t si = w.tile_seg[cur][t];
     if (si >= n_dist) {
         if (tid == 0) raise_err(w, ERR_BOUNDS);
@@ -649,6 +731,11 @@ __global__ __launch_bounds__(BLOCK) void k_classify(Work w, Params p, int cur, u
     for (uint32_t b = tid; b < k; b += BLOCK) c[(size_t)b * T] = H[b];
 }
 
+__global__ __launch_bounds__(BLOCK) void k_classify(Work w, Params p, int cur, uint32_t n_dist) {
+    __shared__ SmClassify sm;
+    dev_classify(w, p, cur, blockIdx.x, n_dist, sm);
+}
+
 // ---------------------------------------------------------------------------
 // exclusive scan over the counter pool ("interleaved global prefix sum",
 // Theorem 4.4)
@@ -657,45 +744,43 @@ __global__ __launch_bounds__(BLOCK) void k_classify(Work w, Params p, int cur, u
 constexpr uint32_t SCAN_PER_THREAD = 16;
 constexpr uint32_t SCAN_CHUNK = BLOCK * SCAN_PER_THREAD;
 
-__global__ __launch_bounds__(BLOCK) void k_scan_reduce(const uint32_t* x, uint32_t n, uint32_t* partial) {
-    __shared__ uint32_t wt[WAVES];
-    const uint32_t base = blockIdx.x * SCAN_CHUNK;
+__device__ void dev_scan_reduce(const uint32_t* x, uint32_t n, uint32_t* partial, uint32_t blk, SmScan& sm) {
+    const uint32_t base = blk * SCAN_CHUNK;
     uint32_t s = 0;
     for (uint32_t i = base + threadIdx.x; i < n && i < base + SCAN_CHUNK; i += BLOCK) s += x[i];
     s = wave_incl_sum(s);
-    if ((threadIdx.x & 63) == 63) wt[threadIdx.x >> 6] = s;
+    if ((threadIdx.x & 63) == 63) sm.wt[threadIdx.x >> 6] = s;
     __syncthreads();
     if (threadIdx.x == 0) {
         uint32_t t = 0;
-        for (uint32_t q = 0; q < WAVES; ++q) t += wt[q];
-        partial[blockIdx.x] = t;
+        for (uint32_t q = 0; q < WAVES; ++q) t += sm.wt[q];
+        partial[blk] = t;
     }
 }
 
-// exclusive scan of the per-chunk sums, one work group
-__global__ __launch_bounds__(1024) void k_scan_partials(uint32_t* partial, uint32_t nb) {
-    __shared__ uint32_t wt[16];
-    __shared__ uint32_t carry;
-    if (threadIdx.x == 0) carry = 0;
+// exclusive scan of the per-chunk sums by one work group of any size
+__device__ void dev_scan_partials(uint32_t* partial, uint32_t nb, SmScan& sm) {
+    const uint32_t nt = blockDim.x, nw = nt >> 6;
+    if (threadIdx.x == 0) sm.carry = 0;
     __syncthreads();
-    for (uint32_t base = 0; base < nb; base += 1024) {
+    for (uint32_t base = 0; base < nb; base += nt) {
         uint32_t i = base + threadIdx.x;
         uint32_t x = i < nb ? partial[i] : 0u;
         uint32_t incl = wave_incl_sum(x);
-        if ((threadIdx.x & 63) == 63) wt[threadIdx.x >> 6] = incl;
+        if ((threadIdx.x & 63) == 63) sm.wt[threadIdx.x >> 6] = incl;
         __syncthreads();
-        uint32_t off = carry;
-        for (uint32_t q = 0; q < (threadIdx.x >> 6); ++q) off += wt[q];
+        uint32_t off = sm.carry;
+        for (uint32_t q = 0; q < (threadIdx.x >> 6); ++q) off += sm.wt[q];
         if (i < nb) partial[i] = off + incl - x;
         __syncthreads();
-        if (threadIdx.x == 1023) carry = off + incl;
+        if (threadIdx.x == nt - 1) sm.carry = off + incl;
         __syncthreads();
     }
+    (void)nw;
 }
 
-__global__ __launch_bounds__(BLOCK) void k_scan_down(uint32_t* x, uint32_t n, const uint32_t* partial) {
-    __shared__ uint32_t wt[WAVES];
-    const uint32_t base = blockIdx.x * SCAN_CHUNK + threadIdx.x * SCAN_PER_THREAD;
+__device__ void dev_scan_down(uint32_t* x, uint32_t n, const uint32_t* partial, uint32_t blk, SmScan& sm) {
+    const uint32_t base = blk * SCAN_CHUNK + threadIdx.x * SCAN_PER_THREAD;
     uint32_t v[SCAN_PER_THREAD];
     uint32_t s = 0;
 #pragma unroll
@@ -705,16 +790,29 @@ __global__ __launch_bounds__(BLOCK) void k_scan_down(uint32_t* x, uint32_t n, co
         s += v[e];
     }
     uint32_t incl = wave_incl_sum(s);
-    if ((threadIdx.x & 63) == 63) wt[threadIdx.x >> 6] = incl;
+    if ((threadIdx.x & 63) == 63) sm.wt[threadIdx.x >> 6] = incl;
     __syncthreads();
-    uint32_t off = partial[blockIdx.x] + incl - s;
-    for (uint32_t q = 0; q < (threadIdx.x >> 6); ++q) off += wt[q];
+    uint32_t off = partial[blk] + incl - s;
+    for (uint32_t q = 0; q < (threadIdx.x >> 6); ++q) off += sm.wt[q];
 #pragma unroll
     for (uint32_t e = 0; e < SCAN_PER_THREAD; ++e) {
         uint32_t i = base + e;
         if (i < n) x[i] = off;
         off += v[e];
     }
+}
+
+__global__ __launch_bounds__(BLOCK) void k_scan_reduce(const uint32_t* x, uint32_t n, uint32_t* partial) {
+    __shared__ SmScan sm;
+    dev_scan_reduce(x, n, partial, blockIdx.x, sm);
+}
+__global__ __launch_bounds__(1024) void k_scan_partials(uint32_t* partial, uint32_t nb) {
+    __shared__ SmScan sm;
+    dev_scan_partials(partial, nb, sm);
+}
+__global__ __launch_bounds__(BLOCK) void k_scan_down(uint32_t* x, uint32_t n, const uint32_t* partial) {
+    __shared__ SmScan sm;
+    dev_scan_down(x, n, partial, blockIdx.x, sm);
 }
 
 // ---------------------------------------------------------------------------
@@ -729,12 +827,13 @@ __global__ __launch_bounds__(BLOCK) void k_scan_down(uint32_t* x, uint32_t n, co
 // equality bucket whose splitter ends inside the word are identical and
 // final: they are written to perm/lcp directly.  Strings of the other
 // equality buckets get their next key (depth + 8) on the way.
-__global__ __launch_bounds__(BLOCK) void k_scatter(Work w, Params p, int cur, uint32_t n_dist) {
-    __shared__ uint32_t WC[WAVES][MAX_BUCKETS + 1];
-    __shared__ uint32_t GB[MAX_BUCKETS + 1];
-    __shared__ uint32_t BS[MAX_BUCKETS + 1];
-    __shared__ uint8_t XR[1 << MAX_LOGV];
-    const uint32_t t = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+__device__ void dev_scatter(const Work& w, const Params& p, int cur, uint32_t t, uint32_t n_dist,
+                            SmScatter& sm) {
+    auto& WC = sm.WC;
+    uint32_t* GB = sm.GB;
+    uint32_t* BS = sm.BS;
+    uint8_t* XR = sm.XR;
+    const uint32_t tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const uint32_t si = w.tile_seg[cur][t];
     if (si >= n_dist) {
         if (tid == 0) raise_err(w, ERR_BOUNDS);
@@ -823,6 +922,11 @@ __global__ __launch_bounds__(BLOCK) void k_scatter(Work w, Params p, int cur, ui
     }
 }
 
+__global__ __launch_bounds__(BLOCK) void k_scatter(Work w, Params p, int cur, uint32_t n_dist) {
+    __shared__ SmScatter sm;
+    dev_scatter(w, p, cur, blockIdx.x, n_dist, sm);
+}
+
 // ---------------------------------------------------------------------------
 // distribution step: children
 // ---------------------------------------------------------------------------
@@ -834,10 +938,16 @@ __global__ __launch_bounds__(BLOCK) void k_scatter(Work w, Params p, int cur, ui
 // the word at depth h); the value is filled in once the final order is
 // known (figure 4.7).  List slots for the children of the whole segment are
 // reserved with one global atomic per list (two passes over the buckets).
-__global__ __launch_bounds__(BLOCK) void k_children(Work w, Params p, int cur) {
-    __shared__ uint32_t n_cls[NCLS], s_cls[NCLS], slot_cls[NCLS], cur_cls[NCLS];
-    __shared__ uint32_t n_pend_l, slot_pend, cur_pend, max_d;
-    const Seg sg = w.dist[cur][blockIdx.x];
+__device__ void dev_children(const Work& w, const Params& p, int cur, uint32_t item, SmChildren& sm) {
+    uint32_t* n_cls = sm.n_cls;
+    uint32_t* s_cls = sm.s_cls;
+    uint32_t* slot_cls = sm.slot_cls;
+    uint32_t* cur_cls = sm.cur_cls;
+    uint32_t& n_pend_l = sm.n_pend_l;
+    uint32_t& slot_pend = sm.slot_pend;
+    uint32_t& cur_pend = sm.cur_pend;
+    uint32_t& max_d = sm.max_d;
+    const Seg sg = w.dist[cur][item];
     const uint32_t tid = threadIdx.x, d = sg.logv, v = (1u << d) - 1, k = 2 * v + 1;
     const uint32_t T = (sg.size + TILE - 1) / TILE;
     const int nxt = cur ^ 1;
@@ -915,6 +1025,11 @@ __global__ __launch_bounds__(BLOCK) void k_children(Work w, Params p, int cur) {
     }
 }
 
+__global__ __launch_bounds__(BLOCK) void k_children(Work w, Params p, int cur) {
+    __shared__ SmChildren sm;
+    dev_children(w, p, cur, blockIdx.x, sm);
+}
+
 // ---------------------------------------------------------------------------
 // boundary LCPs
 // ---------------------------------------------------------------------------
@@ -922,9 +1037,10 @@ __global__ __launch_bounds__(BLOCK) void k_children(Work w, Params p, int cur) {
 // A pending entry at position q separates two buckets of a segment with
 // common prefix h: the strings now at q-1 and q differ within the word at
 // depth h, so their LCP is h plus the common bytes of those two words.
-__global__ __launch_bounds__(BLOCK) void k_lcp_fill(Work w, Params p) {
-    const uint32_t np = min_u32(w.ctl->n_pend, w.caps.pend);
-    for (uint32_t s = blockIdx.x * BLOCK + threadIdx.x; s < np; s += gridDim.x * BLOCK) {
+__device__ void dev_lcp_fill(const Work& w, const Params& p, uint32_t first, uint32_t stride) {
+    const uint32_t np = min_u32(__hip_atomic_load(&w.ctl->n_pend, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT),
+                                w.caps.pend);
+    for (uint32_t s = first; s < np; s += stride) {
         uint2 pe = w.pend[s];
         uint32_t q = pe.x, ob = pe.y;
         if (q == 0 || q >= p.n) { raise_err(w, ERR_BOUNDS); continue; }
@@ -939,6 +1055,133 @@ __global__ __launch_bounds__(BLOCK) void k_lcp_fill(Work w, Params p) {
         uint64_t ka = gather_key(p.chars, oa, h, la), kb = gather_key(p.chars, ob0, h, lb);
         p.lcp[q] = h + lcp_word(ka, rem8(la, h), kb, rem8(lb, h));
     }
+}
+
+__global__ __launch_bounds__(BLOCK) void k_lcp_fill(Work w, Params p) {
+    dev_lcp_fill(w, p, blockIdx.x * BLOCK + threadIdx.x, gridDim.x * BLOCK);
+}
+
+
+// ---------------------------------------------------------------------------
+// persistent form: the whole level loop in one launch
+// ---------------------------------------------------------------------------
+
+constexpr uint32_t MAX_LEVELS_DEV = 1u << 16;
+constexpr uint64_t BARRIER_TIMEOUT_TICKS = 300000000ull;  // 3 s of the 100 MHz wall clock
+
+// Grid-wide barrier among `nblocks` resident work groups.  The last block to
+// arrive resets the counter and publishes the next generation; the others
+// wait for it with a wall-clock bound: on timeout the block records
+// ERR_BARRIER and returns false, and the caller leaves the kernel (every
+// other block then times out too, so the grid always drains).  Agent-scope
+// release/acquire fences make each phase's global writes visible to all
+// blocks of the next phase.
+__device__ bool grid_sync(const Work& w, uint32_t nblocks, uint32_t& gen, uint32_t* s_ok) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const uint32_t target = gen + 1;
+        uint32_t good = 1;
+        __threadfence();
+        const uint32_t prev = atomicAdd(&w.bar->count, 1u);
+        if (prev + 1 == nblocks) {
+            atomicExch(&w.bar->count, 0u);
+            __threadfence();
+            __hip_atomic_store(&w.bar->gen, target, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            const uint64_t t0 = wall_clock64();
+            while (__hip_atomic_load(&w.bar->gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) != target) {
+                __builtin_amdgcn_s_sleep(2);
+                if (wall_clock64() - t0 > BARRIER_TIMEOUT_TICKS) {
+                    good = 0;
+                    atomicOr(&w.ctl->err, (uint32_t)ERR_BARRIER);
+                    break;
+                }
+            }
+        }
+        __threadfence();
+        gen = target;
+        *s_ok = good;
+    }
+    __syncthreads();
+    return *s_ok != 0;
+}
+
+__global__ __launch_bounds__(BLOCK) void k_persist(Work w, Params p, const uint32_t* set_begin, uint32_t num_sets) {
+    __shared__ SmAll sm;
+    __shared__ uint32_t s_ok, s_err;
+    __shared__ Counts sc;
+    const uint32_t G = gridDim.x, bid = blockIdx.x, tid = threadIdx.x;
+    uint32_t gen = 0;
+
+    for (uint32_t i = bid * BLOCK + tid; i < p.n; i += G * BLOCK) dev_init_one(w, p, i);
+    if (!grid_sync(w, G, gen, &s_ok)) return;
+    const uint32_t nroots = set_begin ? num_sets : 1u;
+    for (uint32_t j = bid * BLOCK + tid; j < nroots; j += G * BLOCK) dev_root_one(w, p, set_begin, nroots, j);
+    if (!grid_sync(w, G, gen, &s_ok)) return;
+
+    int cur = 0;
+    uint32_t level = 0;
+    for (;; ++level) {
+        // every block reads the level's counts before any block changes them
+        if (tid < sizeof(Counts) / 4)
+            ((uint32_t*)&sc)[tid] = __hip_atomic_load((uint32_t*)&w.ctl->c[cur] + tid, __ATOMIC_RELAXED,
+                                                      __HIP_MEMORY_SCOPE_AGENT);
+        if (tid == 0) s_err = __hip_atomic_load(&w.ctl->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (!grid_sync(w, G, gen, &s_ok)) return;
+        const Counts c = sc;
+        if (s_err) break;
+        if (level >= MAX_LEVELS_DEV) {
+            if (bid == 0 && tid == 0) atomicOr(&w.ctl->err, (uint32_t)ERR_LEVELS);
+            break;
+        }
+        const uint32_t nb0 = (c.n_base[0] + WAVES - 1) / WAVES, nb1 = (c.n_base[1] + WAVES - 1) / WAVES;
+        const uint32_t nb2 = c.n_base[2];
+        const uint32_t nitems = nb0 + nb1 + nb2 + c.n_dist;
+        if (nitems == 0) break;
+        if (bid == 0 && tid < sizeof(Counts) / 4)
+            __hip_atomic_store((uint32_t*)&w.ctl->c[cur ^ 1] + tid, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        // base cases of every class and the splitter trees of the level
+        for (uint32_t it = bid; it < nitems; it += G) {
+            __syncthreads();
+            if (it < nb0) dev_base_wave<1>(w, p, cur, 0, it, c.n_base[0], sm.wave);
+            else if (it < nb0 + nb1) dev_base_wave<4>(w, p, cur, 1, it - nb0, c.n_base[1], sm.wave);
+            else if (it < nb0 + nb1 + nb2) dev_base_wg(w, p, cur, it - nb0 - nb1, sm.base);
+            else dev_sample(w, p, cur, it - nb0 - nb1 - nb2, sm.sample);
+        }
+        if (c.n_dist == 0) break;
+        if (!grid_sync(w, G, gen, &s_ok)) return;
+        for (uint32_t t = bid; t < c.n_tiles; t += G) {
+            __syncthreads();
+            dev_classify(w, p, cur, t, c.n_dist, sm.classify);
+        }
+        if (!grid_sync(w, G, gen, &s_ok)) return;
+        const uint32_t nsb = (c.n_cnt + SCAN_CHUNK - 1) / SCAN_CHUNK;
+        for (uint32_t b = bid; b < nsb; b += G) {
+            __syncthreads();
+            dev_scan_reduce(w.cnt[cur], c.n_cnt, w.partial, b, sm.scan);
+        }
+        if (!grid_sync(w, G, gen, &s_ok)) return;
+        if (bid == 0) dev_scan_partials(w.partial, nsb, sm.scan);
+        if (!grid_sync(w, G, gen, &s_ok)) return;
+        for (uint32_t b = bid; b < nsb; b += G) {
+            __syncthreads();
+            dev_scan_down(w.cnt[cur], c.n_cnt, w.partial, b, sm.scan);
+        }
+        if (!grid_sync(w, G, gen, &s_ok)) return;
+        for (uint32_t t = bid; t < c.n_tiles; t += G) {
+            __syncthreads();
+            dev_scatter(w, p, cur, t, c.n_dist, sm.scatter);
+        }
+        if (!grid_sync(w, G, gen, &s_ok)) return;
+        for (uint32_t q = bid; q < c.n_dist; q += G) {
+            __syncthreads();
+            dev_children(w, p, cur, q, sm.children);
+        }
+        if (!grid_sync(w, G, gen, &s_ok)) return;
+        cur ^= 1;
+    }
+    if (!grid_sync(w, G, gen, &s_ok)) return;
+    dev_lcp_fill(w, p, bid * BLOCK + tid, G * BLOCK);
 }
 
 // ---------------------------------------------------------------------------
@@ -1008,6 +1251,22 @@ hipError_t launch_lcp_fill(const Work& w, const Params& p, hipStream_t s) {
     if (nb == 0) nb = 1;
     hipLaunchKernelGGL(k_lcp_fill, dim3(nb), dim3(BLOCK), 0, s, w, p);
     return hipGetLastError();
+}
+
+hipError_t launch_persistent(const Work& w, const Params& p, const uint32_t* set_begin, uint32_t num_sets,
+                             uint32_t blocks, hipStream_t s) {
+    hipLaunchKernelGGL(k_persist, dim3(blocks), dim3(BLOCK), 0, s, w, p, set_begin, num_sets);
+    return hipGetLastError();
+}
+
+hipError_t persistent_capacity(int device, uint32_t* blocks) {
+    int per_cu = 0, cus = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_persist, BLOCK, 0);
+    if (e != hipSuccess) return e;
+    e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
+    if (e != hipSuccess) return e;
+    *blocks = (uint32_t)(per_cu * cus);
+    return hipSuccess;
 }
 
 }  // namespace ss

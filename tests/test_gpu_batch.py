@@ -1,0 +1,167 @@
+"""Batched form and persistent (single-launch, graph-capturable) form on the
+GPU: every set's result equals the oracle's result for that set alone."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import gen
+import oracle
+from gpu_util import assert_equal_to_oracle, gpu_sort, needs_gpu, to_device, to_host
+
+pytestmark = [pytest.mark.gpu, needs_gpu]
+
+
+def note(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def check_sets(c, o, sb, p, l, full=True):
+    """Each set's slice of (perm, lcp) against the oracle on that set."""
+    for j in range(len(sb) - 1):
+        b, e = int(sb[j]), int(sb[j + 1])
+        if e == b:
+            continue
+        cj = c[int(o[b]):int(o[e])]
+        oj = o[b:e + 1] - o[b]
+        assert_equal_to_oracle(cj, oj, p[b:e], l[b:e], full=full, label=f"set {j}")
+
+
+def run_batch(c, o, sb, ctx=None):
+    import paper_1808_00963_amd as ss
+    ctx = ctx or ss.Context()
+    cd, od = to_device(c, o)
+    sbd = torch.from_numpy(sb.astype(np.int32)).cuda()
+    p, l = ctx.sort_batch(cd, od, sbd)
+    torch.cuda.synchronize()
+    return to_host(p), to_host(l)
+
+
+def small_batch(num_sets=64, seed=11, scale=0.02):
+    return gen.batch_sets(num_sets=num_sets, seed=seed, scale=scale)
+
+
+@pytest.mark.parametrize("persistent", [False, True])
+def test_batch_vs_oracle(persistent):
+    import paper_1808_00963_amd as ss
+    note(f"case batch persistent={persistent}")
+    c, o, sb = small_batch()
+    ctx = ss.Context()
+    ctx.set_config(persistent=persistent)
+    p, l = run_batch(c, o, sb, ctx)
+    check_sets(c, o, sb, p, l)
+
+
+@pytest.mark.parametrize("persistent", [False, True])
+def test_batch_edge_sets(persistent):
+    import paper_1808_00963_amd as ss
+    note(f"case batch edges persistent={persistent}")
+    sets = [[], [b"x"], [b"b", b"a"], [b""] * 5, [b"ab", b"ab", b"a"], [bytes([255, 0])] * 3 + [b""],
+            [b"q" * k for k in range(300)]]
+    strings, sb = [], [0]
+    for s in sets:
+        strings += s
+        sb.append(len(strings))
+    c, o = gen.from_list(strings)
+    sb = np.array(sb, dtype=np.uint32)
+    ctx = ss.Context()
+    ctx.set_config(persistent=persistent)
+    p, l = run_batch(c, o, sb, ctx)
+    check_sets(c, o, sb, p, l)
+
+
+@pytest.mark.parametrize("model", ["random", "markov", "urls", "suffixes", "bytes", "binary"])
+@pytest.mark.parametrize("n", [1, 2, 1000, 50000])
+def test_persistent_single_vs_oracle(model, n):
+    import paper_1808_00963_amd as ss
+    note(f"case persistent model={model} n={n}")
+    ctx = ss.Context()
+    ctx.set_config(persistent=True)
+    c, o = gen.generate(model, n, 500 + n)
+    p, l = gpu_sort(c, o, ctx=ctx)
+    assert_equal_to_oracle(c, o, p, l, label=f"persistent {model}/{n}")
+
+
+def test_persistent_full_size_markov():
+    import paper_1808_00963_amd as ss
+    note("case persistent full c1")
+    ctx = ss.Context()
+    ctx.set_config(persistent=True)
+    c, o = gen.workload("c1_markov_16m")
+    p, l = gpu_sort(c, o, ctx=ctx)
+    assert_equal_to_oracle(c, o, p, l, full=False, label="persistent c1")
+
+
+def test_graph_replays_match_eager():
+    import paper_1808_00963_amd as ss
+    note("case graph replays")
+    c, o, sb = small_batch(num_sets=48, seed=21)
+    ctx = ss.Context()
+    eager = run_batch(c, o, sb, ctx)
+    check_sets(c, o, sb, *eager)
+    cd, od = to_device(c, o)
+    sbd = torch.from_numpy(sb.astype(np.int32)).cuda()
+    n = len(o) - 1
+    perm = torch.full((n,), -1, dtype=torch.int32, device="cuda")
+    lcp = torch.full((n,), -1, dtype=torch.int32, device="cuda")
+    g = ctx.graph_batch(cd, od, sbd, perm, lcp)
+    stream = torch.cuda.current_stream()
+    for rep in range(3):
+        perm.fill_(-1)
+        lcp.fill_(-1)
+        g.launch(stream)
+        ctx.sync(stream)
+        assert np.array_equal(to_host(perm), eager[0]), f"replay {rep} perm"
+        assert np.array_equal(to_host(lcp), eager[1]), f"replay {rep} lcp"
+        # eager work of the program between replays
+        gpu_sort(c[: int(o[100])], o[:101], ctx=ctx)
+    g.close()
+
+
+def test_graph_sees_new_contents():
+    """Same buffers, new string contents: the replay sorts the new data."""
+    import paper_1808_00963_amd as ss
+    note("case graph new contents")
+    c1, o1 = gen.generate("random", 30000, 1)
+    rng = np.random.default_rng(3)
+    c2 = rng.integers(ord("a"), ord("e"), len(c1), dtype=np.uint8)
+    sb = np.array([0, 10000, 30000], dtype=np.uint32)
+    ctx = ss.Context()
+    cd, od = to_device(c1, o1)
+    sbd = torch.from_numpy(sb.astype(np.int32)).cuda()
+    perm = torch.empty(30000, dtype=torch.int32, device="cuda")
+    lcp = torch.empty_like(perm)
+    g = ctx.graph_batch(cd, od, sbd, perm, lcp)
+    g.launch()
+    ctx.sync()
+    check_sets(c1, o1, sb, to_host(perm), to_host(lcp))
+    cd.copy_(torch.from_numpy(c2).cuda())
+    g.launch()
+    ctx.sync()
+    check_sets(c2, o1, sb, to_host(perm), to_host(lcp))
+    g.close()
+
+
+def test_bad_set_boundaries():
+    import paper_1808_00963_amd as ss
+    c, o = gen.generate("random", 1000, 1)
+    cd, od = to_device(c, o)
+    ctx = ss.Context()
+    bad = torch.tensor([0, 600, 500, 1000], dtype=torch.int32, device="cuda")
+    with pytest.raises(ss.SSError) as e:
+        ctx.sort_batch(cd, od, bad)
+    assert e.value.status == ss.SS_INVALID_ARG
+
+
+@pytest.mark.parametrize("persistent", [False, True])
+def test_full_batched_workload(persistent):
+    """4096 sets, character budgets log-uniform in [1e3, 1e6]."""
+    import paper_1808_00963_amd as ss
+    note(f"case full batched persistent={persistent}")
+    c, o, sb = gen.batch_sets()
+    ctx = ss.Context()
+    ctx.set_config(persistent=persistent)
+    p, l = run_batch(c, o, sb, ctx)
+    check_sets(c, o, sb, p, l, full=False)
