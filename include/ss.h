@@ -149,6 +149,63 @@ void ss_graph_destroy(ss_graph* graph);
  * last sort (sticky, as for the other entry points). */
 ss_status ss_ctx_sync(ss_ctx* ctx, void* stream);
 
+/* ---- serving: continuous batching under an HBM budget ------------------
+ * A server owns one device (its own stream and worker thread) and a fixed
+ * device arena sized by `hbm_budget` bytes: character storage plus index
+ * slots (keys, ping-pong elements, offsets, outputs).  Requests are host
+ * buffers; the worker copies a request to the device when its footprint
+ * (ss_server_footprint) fits into the free arena, and adds it as a new root
+ * segment to the recursion level that is running, so requests that arrive
+ * while others are on the GPU share every later kernel launch with them.
+ * A request completes when all its strings are final; its pending boundary
+ * LCPs are resolved and its outputs copied back.  Results are identical to
+ * ss_sort of the request alone (perm set-local, lcp[0] = 0).
+ *
+ * ss_request: chars, offsets (n+1, non-decreasing, string i =
+ * chars[offsets[i] .. offsets[i+1])), perm_out and lcp_out (n entries) are
+ * HOST pointers owned by the caller and must stay valid until
+ * ss_server_wait reports completion (or ss_server_cancel succeeds).
+ * Malformed offsets or a request larger than the whole arena are rejected at
+ * submission (SS_LIMIT / SS_REJECTED). */
+typedef struct ss_server ss_server;
+typedef struct {
+    const uint8_t* chars;
+    const uint64_t* offsets;
+    uint32_t n;
+    uint32_t* perm_out;
+    uint32_t* lcp_out;
+} ss_request;
+typedef struct {
+    uint64_t submitted, completed, rejected, cancelled;
+    uint64_t levels;              /* recursion levels run by the worker */
+    uint64_t strings_completed, chars_completed;
+    uint32_t inflight_max;        /* most requests on the device at once */
+    uint32_t pad;
+    uint64_t footprint_max;       /* largest sum of admitted footprints (bytes) */
+    uint64_t arena_bytes;         /* size of the device arena (<= hbm_budget) */
+    double p50_us, p99_us, mean_us, max_us;  /* latency submit -> outputs on host */
+    double busy_s;                /* wall time with requests in flight */
+} ss_server_stats;
+/* max_inflight: request slots on the device (1..65536); mean_len_hint:
+ * expected characters per string used to split the budget between
+ * characters and index slots (0 = 48); cfg may be NULL (defaults). */
+ss_status ss_server_create(ss_server** out, int device, size_t hbm_budget, uint32_t max_inflight,
+                           uint32_t mean_len_hint, const ss_config* cfg);
+ss_status ss_server_submit(ss_server* srv, const ss_request* req, uint64_t* ticket);
+/* Waits up to timeout_ms (< 0: forever).  Returns SS_OK when the outputs
+ * are on the host (latency_us may be NULL), SS_TIMEOUT, or the request's
+ * failure status.  A completed ticket can be waited for once. */
+ss_status ss_server_wait(ss_server* srv, uint64_t ticket, int timeout_ms, double* latency_us);
+/* Cancels a request that has not been admitted yet (SS_INVALID_ARG if it
+ * already runs or is unknown). */
+ss_status ss_server_cancel(ss_server* srv, uint64_t ticket);
+/* Bytes of the arena a request of n strings and n_chars characters takes. */
+size_t ss_server_footprint(const ss_server* srv, uint32_t n, uint64_t n_chars);
+ss_status ss_server_get_stats(ss_server* srv, ss_server_stats* st);
+void ss_server_reset_stats(ss_server* srv);
+/* Stops the worker after the in-flight and queued requests finish. */
+void ss_server_destroy(ss_server* srv);
+
 /* Sticky device-side error of a context (SS_OK if none). */
 ss_status ss_get_last_error(const ss_ctx* ctx);
 void ss_clear_error(ss_ctx* ctx);

@@ -48,6 +48,21 @@ class KernelTime(ctypes.Structure):
                 ("total_ms", ctypes.c_double), ("units", ctypes.c_double)]
 
 
+class Request(ctypes.Structure):
+    _fields_ = [("chars", ctypes.c_void_p), ("offsets", ctypes.c_void_p), ("n", ctypes.c_uint32),
+                ("perm_out", ctypes.c_void_p), ("lcp_out", ctypes.c_void_p)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64), ("rejected", ctypes.c_uint64),
+                ("cancelled", ctypes.c_uint64), ("levels", ctypes.c_uint64),
+                ("strings_completed", ctypes.c_uint64), ("chars_completed", ctypes.c_uint64),
+                ("inflight_max", ctypes.c_uint32), ("pad", ctypes.c_uint32),
+                ("footprint_max", ctypes.c_uint64), ("arena_bytes", ctypes.c_uint64),
+                ("p50_us", ctypes.c_double), ("p99_us", ctypes.c_double), ("mean_us", ctypes.c_double),
+                ("max_us", ctypes.c_double), ("busy_s", ctypes.c_double)]
+
+
 def lib():
     """Loads libss.so; raises if it has not been built."""
     global _lib
@@ -74,6 +89,14 @@ def lib():
             "ss_graph_launch": (i32, [vp, vp]),
             "ss_graph_destroy": (None, [vp]),
             "ss_ctx_sync": (i32, [vp, vp]),
+            "ss_server_create": (i32, [ctypes.POINTER(vp), i32, ctypes.c_size_t, u32, u32, ctypes.POINTER(Config)]),
+            "ss_server_submit": (i32, [vp, ctypes.POINTER(Request), ctypes.POINTER(u64)]),
+            "ss_server_wait": (i32, [vp, u64, i32, ctypes.POINTER(ctypes.c_double)]),
+            "ss_server_cancel": (i32, [vp, u64]),
+            "ss_server_footprint": (ctypes.c_size_t, [vp, u32, u64]),
+            "ss_server_get_stats": (i32, [vp, ctypes.POINTER(ServerStats)]),
+            "ss_server_reset_stats": (None, [vp]),
+            "ss_server_destroy": (None, [vp]),
             "ss_set_profiling": (i32, [vp, i32]),
             "ss_get_kernel_times": (i32, [vp, ctypes.POINTER(KernelTime), u32, ctypes.POINTER(u32)]),
             "ss_reset_kernel_times": (None, [vp]),
@@ -255,6 +278,72 @@ class Graph:
     def close(self):
         if self._h:
             lib().ss_graph_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Continuous-batching sort server (ss_server): host numpy requests in,
+    host numpy results out.  See include/ss.h."""
+
+    def __init__(self, hbm_budget: int, max_inflight: int = 1024, mean_len_hint: int = 0, device: int | None = None,
+                 config: Config | None = None):
+        self._h = ctypes.c_void_p()
+        dev = torch.cuda.current_device() if device is None else device
+        cfg = ctypes.byref(config) if config is not None else None
+        _check(lib().ss_server_create(ctypes.byref(self._h), dev, hbm_budget, max_inflight, mean_len_hint, cfg),
+               "ss_server_create")
+        self._live = {}
+
+    def footprint(self, n: int, n_chars: int) -> int:
+        return int(lib().ss_server_footprint(self._h, n, n_chars))
+
+    def submit(self, chars, offsets) -> int:
+        """Queues one request (numpy uint8 chars, uint64 offsets); returns a ticket."""
+        import numpy as np
+        chars = np.ascontiguousarray(chars, dtype=np.uint8)
+        offsets = np.ascontiguousarray(offsets, dtype=np.uint64)
+        n = offsets.size - 1
+        perm = np.empty(max(n, 1), dtype=np.uint32)
+        lcp = np.empty(max(n, 1), dtype=np.uint32)
+        req = Request(chars.ctypes.data if chars.size else None, offsets.ctypes.data, n,
+                      perm.ctypes.data, lcp.ctypes.data)
+        t = ctypes.c_uint64()
+        _check(lib().ss_server_submit(self._h, ctypes.byref(req), ctypes.byref(t)), "ss_server_submit")
+        self._live[t.value] = (chars, offsets, perm, lcp, n)
+        return t.value
+
+    def wait(self, ticket: int, timeout_ms: int = -1):
+        """Returns (perm, lcp, latency_us) once the request is done."""
+        lat = ctypes.c_double()
+        st = lib().ss_server_wait(self._h, ticket, timeout_ms, ctypes.byref(lat))
+        if st == SS_TIMEOUT:
+            raise TimeoutError(f"request {ticket} not done after {timeout_ms} ms")
+        keep = self._live.pop(ticket, None)
+        _check(st, "ss_server_wait")
+        _, _, perm, lcp, n = keep
+        return perm[:n], lcp[:n], lat.value
+
+    def cancel(self, ticket: int):
+        _check(lib().ss_server_cancel(self._h, ticket), "ss_server_cancel")
+        self._live.pop(ticket, None)
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        _check(lib().ss_server_get_stats(self._h, ctypes.byref(st)), "ss_server_get_stats")
+        return {f: getattr(st, f) for f, _ in ServerStats._fields_ if f != "pad"}
+
+    def reset_stats(self):
+        lib().ss_server_reset_stats(self._h)
+
+    def close(self):
+        if self._h:
+            lib().ss_server_destroy(self._h)
             self._h = ctypes.c_void_p()
 
     def __del__(self):

@@ -4,9 +4,14 @@
 
 #include <algorithm>
 #include <cstring>
+#include <chrono>
+#include <condition_variable>
+#include <deque>
 #include <map>
 #include <memory>
 #include <mutex>
+#include <thread>
+#include <unordered_map>
 #include <vector>
 
 #include "../../include/ss.h"
@@ -113,8 +118,12 @@ size_t layout(uint32_t n, const Caps& k, char* base, Work* w) {
     for (int i = 0; i < 2; ++i) t.tree_key[i] = (uint64_t*)take(sizeof(uint64_t) * k.tree);
     for (int i = 0; i < 2; ++i) t.tree_r[i] = (uint8_t*)take(k.tree);
     t.pend = (uint2*)take(sizeof(uint2) * k.pend);
+    t.pend2 = nullptr;
     t.ctl = (Ctl*)take(sizeof(Ctl));
     t.bar = (GridBar*)take(sizeof(GridBar));
+    t.set_base = t.ctl ? t.ctl->zero : nullptr;  // a plain sort is one set starting at 0
+    t.remaining = nullptr;
+    t.done = nullptr;
     t.caps = k;
     if (w) *w = t;
     return off;
@@ -213,19 +222,40 @@ ss_status read_ctl(ss_ctx* ctx, hipStream_t s) {
 }
 
 // Reset + the persistent kernel (no host synchronisation; capturable).
-ss_status enqueue_persistent(ss_ctx* ctx, const Params& p, const uint32_t* set_begin, uint32_t nroots,
-                             hipStream_t s) {
+ss_status enqueue_persistent(ss_ctx* ctx, const Work& w, const Params& p, const uint32_t* set_begin,
+                             uint32_t nroots, hipStream_t s) {
     if (ctx->persist_blocks == 0) {
         uint32_t b = 0;
         SS_TRY(persistent_capacity(ctx->device, &b));
         if (b == 0) return SS_HIP_ERROR;
         ctx->persist_blocks = b;
     }
-    const Work& w = ctx->work;
     SS_TRY(launch_reset(w, s));
     SS_TRY(timed(ctx, s, K_PERSIST, p.n, [&] {
         return launch_persistent(w, p, set_begin, nroots, ctx->persist_blocks, s);
     }));
+    return SS_OK;
+}
+
+// Enqueues one recursion level for the counts `c` of list slot `cur`: the
+// base cases of every class and, if there are distribution segments, their
+// sample/classify/scan/scatter/children steps (children go to slot cur^1,
+// which is zeroed first).
+ss_status enqueue_level(ss_ctx* ctx, const Work& w, const Params& p, int cur, const Counts& c, hipStream_t s) {
+    for (int cls = 0; cls < NCLS; ++cls) {
+        if (!c.n_base[cls]) continue;
+        const uint32_t nb = c.n_base[cls];
+        SS_TRY(timed(ctx, s, K_BASE_W1 + cls, c.base_strings[cls], [&] { return launch_base(w, p, cur, cls, nb, s); }));
+    }
+    SS_TRY(launch_zero_counts(w, cur ^ 1, s));
+    if (c.n_dist == 0) return SS_OK;
+    SS_TRY(timed(ctx, s, K_SAMPLE, c.n_dist, [&] { return launch_sample(w, p, cur, c.n_dist, s); }));
+    SS_TRY(timed(ctx, s, K_CLASSIFY, c.dist_strings,
+                 [&] { return launch_classify(w, p, cur, c.n_tiles, c.n_dist, s); }));
+    SS_TRY(timed(ctx, s, K_SCAN, c.n_cnt, [&] { return launch_scan(w, cur, c.n_cnt, s); }));
+    SS_TRY(timed(ctx, s, K_SCATTER, c.dist_strings,
+                 [&] { return launch_scatter(w, p, cur, c.n_tiles, c.n_dist, s); }));
+    SS_TRY(timed(ctx, s, K_CHILDREN, c.n_dist, [&] { return launch_children(w, p, cur, c.n_dist, s); }));
     return SS_OK;
 }
 
@@ -241,12 +271,13 @@ ss_status run_sort(ss_ctx* ctx, const uint8_t* chars, const uint64_t* offsets, u
     if (cur_dev != ctx->device) SS_TRY(hipSetDevice(ctx->device));
     ss_status st = ensure_workspace(ctx, n);
     if (st != SS_OK) return st;
-    const Work& w = ctx->work;
+    Work w = ctx->work;
+    if (set_begin) w.set_base = set_begin;  // perm entries are set-local
     Params p{chars, offsets, n, perm, lcp, ctx->cfg.max_log_splitters, ctx->cfg.bucket_target, ctx->cfg.base_max};
 
     const uint32_t nroots = set_begin ? num_sets : 1;
     if (ctx->cfg.persistent) {
-        if ((st = enqueue_persistent(ctx, p, set_begin, nroots, s)) != SS_OK) return st;
+        if ((st = enqueue_persistent(ctx, w, p, set_begin, nroots, s)) != SS_OK) return st;
         if ((st = read_ctl(ctx, s)) != SS_OK) return st;
         ctx->stats.pending_lcps = ctx->host_ctl->n_pend;
         ctx->stats.base_rounds = ctx->host_ctl->base_rounds;
@@ -267,21 +298,8 @@ ss_status run_sort(ss_ctx* ctx, const uint8_t* chars, const uint64_t* offsets, u
         ctx->stats.dist_tiles += c.n_tiles;
         ctx->stats.base_segments += c.n_base[0] + c.n_base[1] + c.n_base[2];
         ctx->stats.max_depth = std::max(ctx->stats.max_depth, c.max_depth);
-        for (int cls = 0; cls < NCLS; ++cls) {
-            if (!c.n_base[cls]) continue;
-            const uint32_t nb = c.n_base[cls];
-            SS_TRY(timed(ctx, s, K_BASE_W1 + cls, c.base_strings[cls],
-                         [&] { return launch_base(w, p, cur, cls, nb, s); }));
-        }
+        if ((st = enqueue_level(ctx, w, p, cur, c, s)) != SS_OK) return st;
         if (c.n_dist == 0) break;
-        SS_TRY(launch_zero_counts(w, cur ^ 1, s));
-        SS_TRY(timed(ctx, s, K_SAMPLE, c.n_dist, [&] { return launch_sample(w, p, cur, c.n_dist, s); }));
-        SS_TRY(timed(ctx, s, K_CLASSIFY, c.dist_strings,
-                     [&] { return launch_classify(w, p, cur, c.n_tiles, c.n_dist, s); }));
-        SS_TRY(timed(ctx, s, K_SCAN, c.n_cnt, [&] { return launch_scan(w, cur, c.n_cnt, s); }));
-        SS_TRY(timed(ctx, s, K_SCATTER, c.dist_strings,
-                     [&] { return launch_scatter(w, p, cur, c.n_tiles, c.n_dist, s); }));
-        SS_TRY(timed(ctx, s, K_CHILDREN, c.n_dist, [&] { return launch_children(w, p, cur, c.n_dist, s); }));
         cur ^= 1;
         if (++level >= MAX_LEVELS) return SS_INTERNAL;
     }
@@ -439,10 +457,12 @@ ss_status ss_graph_create_batch(ss_ctx* ctx, const uint8_t* chars, const uint64_
     ctx->prof.on = false;  // no event records inside the graph
     Params p{chars, offsets, n, perm_out, lcp_out, ctx->cfg.max_log_splitters, ctx->cfg.bucket_target,
              ctx->cfg.base_max};
+    Work w = ctx->work;
+    w.set_base = set_begin;
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-        st = enqueue_persistent(ctx, p, set_begin, num_sets, cs);
+        st = enqueue_persistent(ctx, w, p, set_begin, num_sets, cs);
         hipError_t e2 = hipStreamEndCapture(cs, &g);
         if (st == SS_OK && e2 != hipSuccess) st = SS_HIP_ERROR;
     } else {
@@ -599,6 +619,495 @@ int ss_host_select_splitters(const uint64_t* sk, const uint32_t* sr, uint32_t a,
         xr[j] = TR[l];
     }
     return 0;
+}
+
+}  // extern "C"
+
+// ===========================================================================
+// serving
+// ===========================================================================
+
+namespace {
+
+// First-fit allocator of ranges of [0, cap).
+class RangeAlloc {
+  public:
+    void init(uint64_t cap) {
+        free_.clear();
+        if (cap) free_[0] = cap;
+    }
+    bool alloc(uint64_t size, uint64_t* out) {
+        if (size == 0) { *out = 0; return true; }
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second >= size) {
+                *out = it->first;
+                const uint64_t b = it->first + size, rest = it->second - size;
+                free_.erase(it);
+                if (rest) free_[b] = rest;
+                return true;
+            }
+        }
+        return false;
+    }
+    void release(uint64_t begin, uint64_t size) {
+        if (size == 0) return;
+        auto next = free_.lower_bound(begin);
+        if (next != free_.begin()) {
+            auto prev = std::prev(next);
+            if (prev->first + prev->second == begin) {
+                begin = prev->first;
+                size += prev->second;
+                free_.erase(prev);
+            }
+        }
+        if (next != free_.end() && begin + size == next->first) {
+            size += next->second;
+            free_.erase(next);
+        }
+        free_[begin] = size;
+    }
+
+  private:
+    std::map<uint64_t, uint64_t> free_;
+};
+
+enum ReqState { RQ_QUEUED, RQ_RUNNING, RQ_DONE };
+
+struct Req {
+    uint64_t ticket = 0;
+    ss_request r{};
+    uint64_t nchars = 0;
+    int state = RQ_QUEUED;
+    ss_status status = SS_OK;
+    uint32_t rid = 0;
+    uint64_t pos = 0, cbase = 0;
+    std::chrono::steady_clock::time_point t_submit, t_done;
+};
+
+using Clock = std::chrono::steady_clock;
+
+}  // namespace
+
+struct ss_server {
+    ss_ctx* ctx = nullptr;
+    int device = 0;
+    uint32_t max_inflight = 0;
+    uint32_t cap_n = 0;        // index slots
+    uint64_t cap_c = 0;        // characters
+    size_t slot_bytes = 0;     // arena bytes per index slot
+    void* mem = nullptr;
+    Work w{};
+    Params p{};
+    uint32_t* d_set_base = nullptr;
+    uint32_t* d_remaining = nullptr;
+    uint8_t* d_done = nullptr;
+    uint32_t* h_remaining = nullptr;  // pinned
+    uint32_t* h_slot = nullptr;       // pinned staging: set_base, remaining per rid
+    uint8_t* h_done = nullptr;        // pinned
+    RangeAlloc idx_alloc, chr_alloc;
+    std::vector<uint32_t> free_rids;
+    std::vector<Req*> running;        // by rid
+    std::deque<Req*> queue;
+    std::unordered_map<uint64_t, Req*> reqs;
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::thread worker;
+    bool stop = false;
+    uint64_t next_ticket = 1;
+    hipStream_t stream = nullptr;
+    int cur = 0;
+    // statistics
+    ss_server_stats st{};
+    std::vector<double> lat_us;
+    double busy_s = 0;
+    uint64_t footprint_now = 0;
+    size_t arena_bytes = 0;
+};
+
+namespace {
+
+size_t server_footprint(const ss_server* s, uint32_t n, uint64_t nchars) {
+    return (size_t)(n + 1) * s->slot_bytes + (size_t)nchars;
+}
+
+void finish_locked(ss_server* S, Req* r, ss_status status) {
+    r->state = RQ_DONE;
+    r->status = status;
+    r->t_done = Clock::now();
+    if (status == SS_OK) {
+        const double us = std::chrono::duration<double, std::micro>(r->t_done - r->t_submit).count();
+        S->lat_us.push_back(us);
+        S->st.completed++;
+        S->st.strings_completed += r->r.n;
+        S->st.chars_completed += r->nchars;
+    }
+}
+
+// Admits queued requests (FIFO) while their footprint fits.
+void admit_locked(ss_server* S, std::vector<Req*>& admitted) {
+    while (!S->queue.empty() && !S->free_rids.empty()) {
+        Req* r = S->queue.front();
+        uint64_t pos = 0, cb = 0;
+        if (!S->idx_alloc.alloc((uint64_t)r->r.n + 1, &pos)) break;
+        if (!S->chr_alloc.alloc(r->nchars, &cb)) {
+            S->idx_alloc.release(pos, (uint64_t)r->r.n + 1);
+            break;
+        }
+        S->queue.pop_front();
+        S->footprint_now += server_footprint(S, r->r.n, r->nchars);
+        S->st.footprint_max = std::max<uint64_t>(S->st.footprint_max, S->footprint_now);
+        r->pos = pos;
+        r->cbase = cb;
+        r->rid = S->free_rids.back();
+        S->free_rids.pop_back();
+        r->state = RQ_RUNNING;
+        S->running[r->rid] = r;
+        admitted.push_back(r);
+    }
+}
+
+void release_locked(ss_server* S, Req* r) {
+    S->footprint_now -= server_footprint(S, r->r.n, r->nchars);
+    S->idx_alloc.release(r->pos, (uint64_t)r->r.n + 1);
+    S->chr_alloc.release(r->cbase, r->nchars);
+    S->running[r->rid] = nullptr;
+    S->free_rids.push_back(r->rid);
+}
+
+// Copies a request to the device and adds it as a root of list slot `cur`.
+ss_status stage_request(ss_server* S, Req* r) {
+    hipStream_t s = S->stream;
+    const uint64_t o0 = r->r.offsets[0];
+    if (r->nchars)
+        SS_TRY(hipMemcpyAsync(const_cast<uint8_t*>(S->p.chars) + r->cbase, r->r.chars + o0, r->nchars,
+                              hipMemcpyHostToDevice, s));
+    uint64_t* off = const_cast<uint64_t*>(S->p.offsets) + r->pos;
+    SS_TRY(hipMemcpyAsync(off, r->r.offsets, sizeof(uint64_t) * ((size_t)r->r.n + 1), hipMemcpyHostToDevice, s));
+    SS_TRY(launch_rebase(off, off, r->r.n, r->cbase - o0, s));
+    S->h_slot[2 * r->rid] = (uint32_t)r->pos;
+    S->h_slot[2 * r->rid + 1] = r->r.n;
+    SS_TRY(hipMemcpyAsync(S->d_set_base + r->rid, &S->h_slot[2 * r->rid], 4, hipMemcpyHostToDevice, s));
+    SS_TRY(hipMemcpyAsync(S->d_remaining + r->rid, &S->h_slot[2 * r->rid + 1], 4, hipMemcpyHostToDevice, s));
+    SS_TRY(launch_admit(S->w, S->p, S->cur, (uint32_t)r->pos, r->r.n, r->rid, s));
+    return SS_OK;
+}
+
+void fail_all_locked(ss_server* S, ss_status st) {
+    for (auto& r : S->running)
+        if (r) {
+            finish_locked(S, r, st);
+            release_locked(S, r);
+        }
+}
+
+// One iteration of the engine: admit, run one level for every live request,
+// complete finished requests.
+void server_loop(ss_server* S) {
+    (void)hipSetDevice(S->device);
+    ss_ctx* ctx = S->ctx;
+    for (;;) {
+        std::vector<Req*> admitted;
+        {
+            std::unique_lock<std::mutex> lk(S->mu);
+            for (;;) {
+                size_t live = 0;
+                for (auto* r : S->running) live += r != nullptr;
+                admit_locked(S, admitted);
+                live += admitted.size();
+                if (live) {
+                    S->st.inflight_max = std::max<uint32_t>(S->st.inflight_max, (uint32_t)live);
+                    break;
+                }
+                if (S->stop && S->queue.empty()) return;
+                S->cv_work.wait(lk);
+            }
+        }
+        const auto t_begin = Clock::now();
+        ss_status st = SS_OK;
+        for (Req* r : admitted)
+            if ((st = stage_request(S, r)) != SS_OK) break;
+        if (st == SS_OK) st = read_ctl(ctx, S->stream);
+        if (st == SS_OK && ctx->host_ctl->err) st = device_error_status(ctx->host_ctl->err);
+        if (st == SS_OK) {
+            const Counts c = ctx->host_ctl->c[S->cur];
+            st = enqueue_level(ctx, S->w, S->p, S->cur, c, S->stream);
+            S->cur ^= 1;
+        }
+        // which requests are finished?
+        std::vector<Req*> finished;
+        if (st == SS_OK) {
+            hipError_t e = hipMemcpyAsync(S->h_remaining, S->d_remaining, sizeof(uint32_t) * S->max_inflight,
+                                          hipMemcpyDeviceToHost, S->stream);
+            if (e == hipSuccess) e = hipStreamSynchronize(S->stream);
+            if (e != hipSuccess) st = SS_HIP_ERROR;
+        }
+        if (st == SS_OK) {
+            std::lock_guard<std::mutex> lk(S->mu);
+            S->st.levels++;
+            for (auto* r : S->running)
+                if (r && S->h_remaining[r->rid] == 0) finished.push_back(r);
+        }
+        if (st == SS_OK && !finished.empty()) {
+            for (Req* r : finished) S->h_done[r->rid] = 1;
+            hipError_t e = hipMemcpyAsync(S->d_done, S->h_done, S->max_inflight, hipMemcpyHostToDevice, S->stream);
+            if (e == hipSuccess) e = launch_pend_filter(S->w, S->p, S->stream);
+            if (e == hipSuccess) e = launch_pend_swap(S->w, S->stream);
+            std::swap(S->w.pend, S->w.pend2);
+            for (Req* r : finished) {
+                if (e != hipSuccess) break;
+                if (r->r.n) {
+                    e = hipMemcpyAsync(r->r.perm_out, S->p.perm + r->pos, sizeof(uint32_t) * r->r.n,
+                                       hipMemcpyDeviceToHost, S->stream);
+                    if (e == hipSuccess)
+                        e = hipMemcpyAsync(r->r.lcp_out, S->p.lcp + r->pos, sizeof(uint32_t) * r->r.n,
+                                           hipMemcpyDeviceToHost, S->stream);
+                }
+            }
+            if (e == hipSuccess) e = hipStreamSynchronize(S->stream);
+            for (Req* r : finished) S->h_done[r->rid] = 0;
+            if (e == hipSuccess) e = hipMemcpyAsync(S->d_done, S->h_done, S->max_inflight, hipMemcpyHostToDevice, S->stream);
+            if (e != hipSuccess) st = SS_HIP_ERROR;
+            if (st == SS_OK && ctx->host_ctl->err == 0) {
+                if (read_ctl(ctx, S->stream) != SS_OK) st = SS_HIP_ERROR;
+                else if (ctx->host_ctl->err) st = device_error_status(ctx->host_ctl->err);
+            }
+        }
+        {
+            std::lock_guard<std::mutex> lk(S->mu);
+            S->busy_s += std::chrono::duration<double>(Clock::now() - t_begin).count();
+            if (st != SS_OK) {
+                fail_all_locked(S, st);
+                // start over with an empty device state
+                (void)launch_reset(S->w, S->stream);
+                (void)hipStreamSynchronize(S->stream);
+                S->cur = 0;
+            } else {
+                for (Req* r : finished) {
+                    finish_locked(S, r, SS_OK);
+                    release_locked(S, r);
+                }
+            }
+        }
+        S->cv_done.notify_all();
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t ss_server_footprint(const ss_server* srv, uint32_t n, uint64_t n_chars) {
+    return srv ? server_footprint(srv, n, n_chars) : 0;
+}
+
+ss_status ss_server_create(ss_server** out, int device, size_t hbm_budget, uint32_t max_inflight,
+                           uint32_t mean_len_hint, const ss_config* cfg) {
+    if (!out || max_inflight == 0 || max_inflight > 65536) return SS_INVALID_ARG;
+    *out = nullptr;
+    auto* S = new ss_server();
+    ss_status st = ss_ctx_create(&S->ctx, device, 0);
+    if (st != SS_OK) {
+        delete S;
+        return st;
+    }
+    if (cfg) {
+        ss_config c = *cfg;
+        c.persistent = 0;
+        clamp_config(&c);
+        S->ctx->cfg = c;
+    }
+    S->device = device;
+    S->max_inflight = max_inflight;
+    const uint64_t L = mean_len_hint ? mean_len_hint : 48;
+    // arena bytes per index slot: workspace + offsets + perm + lcp + second pending list
+    const uint32_t probe = 1u << 20;
+    const size_t ws = layout(probe, caps_for(probe, S->ctx->cfg), nullptr, nullptr);
+    S->slot_bytes = ws / probe + 1 + sizeof(uint64_t) + 2 * sizeof(uint32_t) + sizeof(uint2);
+    // 1% of the budget is left for the fixed tables and alignment
+    const uint64_t cap_n = std::min<uint64_t>((hbm_budget - hbm_budget / 100) / (S->slot_bytes + L), 0xFFFFFFF0ull);
+    if (cap_n < 1024) {
+        ss_ctx_destroy(S->ctx);
+        delete S;
+        return SS_INVALID_ARG;
+    }
+    S->cap_n = (uint32_t)cap_n;
+    S->cap_c = cap_n * L;
+    (void)hipSetDevice(device);
+    // one allocation: workspace | offsets | perm | lcp | pend2 | chars | slot tables
+    const Caps k = caps_for(S->cap_n, S->ctx->cfg);
+    const size_t ws_bytes = layout(S->cap_n, k, nullptr, nullptr);
+    size_t off = ws_bytes;
+    auto take = [&](size_t b) { size_t o = off; off += align_up(b); return o; };
+    const size_t o_off = take(sizeof(uint64_t) * ((size_t)S->cap_n + 1));
+    const size_t o_perm = take(sizeof(uint32_t) * (size_t)S->cap_n);
+    const size_t o_lcp = take(sizeof(uint32_t) * (size_t)S->cap_n);
+    const size_t o_pend2 = take(sizeof(uint2) * k.pend);
+    const size_t o_chars = take(S->cap_c + 16);
+    const size_t o_base = take(sizeof(uint32_t) * max_inflight);
+    const size_t o_rem = take(sizeof(uint32_t) * max_inflight);
+    const size_t o_done = take(max_inflight);
+    if (off > hbm_budget) {  // the fixed part does not fit the budget
+        ss_ctx_destroy(S->ctx);
+        delete S;
+        return SS_INVALID_ARG;
+    }
+    S->arena_bytes = off;
+    if (hipMalloc(&S->mem, off) != hipSuccess) {
+        (void)hipGetLastError();
+        ss_ctx_destroy(S->ctx);
+        delete S;
+        return SS_OUT_OF_MEMORY;
+    }
+    char* base = (char*)S->mem;
+    layout(S->cap_n, k, base, &S->w);
+    S->w.pend2 = (uint2*)(base + o_pend2);
+    S->d_set_base = (uint32_t*)(base + o_base);
+    S->d_remaining = (uint32_t*)(base + o_rem);
+    S->d_done = (uint8_t*)(base + o_done);
+    S->w.set_base = S->d_set_base;
+    S->w.remaining = S->d_remaining;
+    S->w.done = S->d_done;
+    S->ctx->work = S->w;
+    const ss_config& c = S->ctx->cfg;
+    S->p = Params{(const uint8_t*)(base + o_chars), (const uint64_t*)(base + o_off), S->cap_n,
+                  (uint32_t*)(base + o_perm), (uint32_t*)(base + o_lcp), c.max_log_splitters, c.bucket_target,
+                  c.base_max};
+    bool ok = hipHostMalloc((void**)&S->h_remaining, sizeof(uint32_t) * max_inflight, hipHostMallocDefault) == hipSuccess &&
+              hipHostMalloc((void**)&S->h_slot, 2 * sizeof(uint32_t) * max_inflight, hipHostMallocDefault) == hipSuccess &&
+              hipHostMalloc((void**)&S->h_done, max_inflight, hipHostMallocDefault) == hipSuccess &&
+              hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking) == hipSuccess;
+    if (ok) {
+        std::memset(S->h_done, 0, max_inflight);
+        std::memset(S->h_remaining, 0, sizeof(uint32_t) * max_inflight);
+        ok = hipMemcpyAsync(S->d_done, S->h_done, max_inflight, hipMemcpyHostToDevice, S->stream) == hipSuccess &&
+             hipMemcpyAsync(S->d_remaining, S->h_remaining, sizeof(uint32_t) * max_inflight, hipMemcpyHostToDevice,
+                            S->stream) == hipSuccess &&
+             launch_reset(S->w, S->stream) == hipSuccess && hipStreamSynchronize(S->stream) == hipSuccess;
+    }
+    if (!ok) {
+        ss_server_destroy(S);
+        return SS_HIP_ERROR;
+    }
+    S->idx_alloc.init(S->cap_n);
+    S->chr_alloc.init(S->cap_c);
+    S->running.assign(max_inflight, nullptr);
+    for (uint32_t r = max_inflight; r-- > 0;) S->free_rids.push_back(r);
+    S->worker = std::thread(server_loop, S);
+    *out = S;
+    return SS_OK;
+}
+
+ss_status ss_server_submit(ss_server* S, const ss_request* req, uint64_t* ticket) {
+    if (!S || !req || !ticket || !req->offsets) return SS_INVALID_ARG;
+    if (req->n && (!req->perm_out || !req->lcp_out)) return SS_INVALID_ARG;
+    const uint64_t* o = req->offsets;
+    for (uint32_t i = 0; i < req->n; ++i)
+        if (o[i + 1] < o[i] || o[i + 1] - o[i] > MAX_LEN) return SS_LIMIT;
+    const uint64_t nchars = o[req->n] - o[0];
+    if (nchars && !req->chars) return SS_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(S->mu);
+    S->st.submitted++;
+    if ((uint64_t)req->n + 1 > S->cap_n || nchars > S->cap_c) {
+        S->st.rejected++;
+        return SS_REJECTED;
+    }
+    auto* r = new Req();
+    r->ticket = S->next_ticket++;
+    r->r = *req;
+    r->nchars = nchars;
+    r->t_submit = Clock::now();
+    S->reqs[r->ticket] = r;
+    S->queue.push_back(r);
+    *ticket = r->ticket;
+    S->cv_work.notify_one();
+    return SS_OK;
+}
+
+ss_status ss_server_wait(ss_server* S, uint64_t ticket, int timeout_ms, double* latency_us) {
+    if (!S) return SS_INVALID_ARG;
+    std::unique_lock<std::mutex> lk(S->mu);
+    auto it = S->reqs.find(ticket);
+    if (it == S->reqs.end()) return SS_INVALID_ARG;
+    Req* r = it->second;
+    auto pred = [&] { return r->state == RQ_DONE; };
+    if (timeout_ms < 0) S->cv_done.wait(lk, pred);
+    else if (!S->cv_done.wait_for(lk, std::chrono::milliseconds(timeout_ms), pred)) return SS_TIMEOUT;
+    const ss_status st = r->status;
+    if (latency_us) *latency_us = std::chrono::duration<double, std::micro>(r->t_done - r->t_submit).count();
+    S->reqs.erase(it);
+    delete r;
+    return st;
+}
+
+ss_status ss_server_cancel(ss_server* S, uint64_t ticket) {
+    if (!S) return SS_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(S->mu);
+    auto it = S->reqs.find(ticket);
+    if (it == S->reqs.end() || it->second->state != RQ_QUEUED) return SS_INVALID_ARG;
+    Req* r = it->second;
+    for (auto q = S->queue.begin(); q != S->queue.end(); ++q)
+        if (*q == r) {
+            S->queue.erase(q);
+            break;
+        }
+    S->st.cancelled++;
+    S->reqs.erase(it);
+    delete r;
+    return SS_OK;
+}
+
+ss_status ss_server_get_stats(ss_server* S, ss_server_stats* out) {
+    if (!S || !out) return SS_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(S->mu);
+    ss_server_stats st = S->st;
+    std::vector<double> v = S->lat_us;
+    if (!v.empty()) {
+        std::sort(v.begin(), v.end());
+        auto pct = [&](double q) { return v[std::min(v.size() - 1, (size_t)(q * (double)(v.size() - 1) + 0.5))]; };
+        st.p50_us = pct(0.50);
+        st.p99_us = pct(0.99);
+        double sum = 0;
+        for (double x : v) sum += x;
+        st.mean_us = sum / (double)v.size();
+        st.max_us = v.back();
+    }
+    st.busy_s = S->busy_s;
+    st.arena_bytes = S->arena_bytes;
+    *out = st;
+    return SS_OK;
+}
+
+void ss_server_reset_stats(ss_server* S) {
+    if (!S) return;
+    std::lock_guard<std::mutex> lk(S->mu);
+    S->st = ss_server_stats{};
+    S->st.footprint_max = S->footprint_now;
+    S->lat_us.clear();
+    S->busy_s = 0;
+}
+
+void ss_server_destroy(ss_server* S) {
+    if (!S) return;
+    if (S->worker.joinable()) {
+        {
+            std::lock_guard<std::mutex> lk(S->mu);
+            S->stop = true;
+        }
+        S->cv_work.notify_all();
+        S->worker.join();
+    }
+    (void)hipSetDevice(S->device);
+    if (S->stream) (void)hipStreamDestroy(S->stream);
+    if (S->mem) (void)hipFree(S->mem);
+    if (S->h_remaining) (void)hipHostFree(S->h_remaining);
+    if (S->h_slot) (void)hipHostFree(S->h_slot);
+    if (S->h_done) (void)hipHostFree(S->h_done);
+    for (auto& kv : S->reqs) delete kv.second;
+    if (S->ctx) {
+        S->ctx->ws = nullptr;  // the server's arena is freed above
+        ss_ctx_destroy(S->ctx);
+    }
+    delete S;
 }
 
 }  // extern "C"

@@ -26,12 +26,12 @@ struct Seg {
     uint32_t tree_off;  // first splitter in the tree pool
     uint32_t cnt_off;   // first counter in the counter pool
     uint32_t tile_off;  // first tile in the tile list
-    uint32_t obase;     // subtracted from indices written to perm (batch set start)
+    uint32_t rid;       // set (batch) or request (serving) the segment belongs to
 };
 
 // A segment small enough for the in-LDS base case.
 struct BaseSeg {
-    uint32_t begin, size, depth, obase;
+    uint32_t begin, size, depth, rid;
 };
 
 // Base-case size classes: one wave per segment with 1 string per lane
@@ -58,7 +58,8 @@ struct Ctl {
     uint32_t n_pend;
     uint32_t err;
     uint32_t base_rounds;  // refinement rounds run by base cases (statistics)
-    uint32_t pad;
+    uint32_t n_pend2;      // survivors of a pending-list filter (serving)
+    uint32_t zero[4];      // set base of a plain sort (one set starting at 0)
 };
 
 // Error bits raised on the device.
@@ -106,9 +107,13 @@ struct Work {
     uint32_t* tile_seg[2];
     uint64_t* tree_key[2];
     uint8_t* tree_r[2];
-    uint2* pend;
+    uint2* pend;              // pending boundary LCPs: (position, set/request id)
+    uint2* pend2;             // filter target (serving)
     Ctl* ctl;
     GridBar* bar;
+    const uint32_t* set_base; // per set/request id: its first position (subtracted from perm entries)
+    uint32_t* remaining;      // per request id: strings not yet final (serving; else null)
+    const uint8_t* done;      // per request id: 1 once finished (serving; else null)
     Caps caps;
 };
 
@@ -142,6 +147,18 @@ hipError_t launch_lcp_fill(const Work& w, const Params& p, hipStream_t s);
 // grid barriers.  launch_reset must precede it on the stream.
 hipError_t launch_persistent(const Work& w, const Params& p, const uint32_t* set_begin, uint32_t num_sets,
                              uint32_t blocks, hipStream_t s);
+// Serving: gathers keys at depth 0 for positions [pos, pos+m) into buffer
+// `cur` and makes them one root segment of request `rid` in the lists of
+// `cur`.
+hipError_t launch_admit(const Work& w, const Params& p, int cur, uint32_t pos, uint32_t m, uint32_t rid,
+                        hipStream_t s);
+// Serving: offsets_out[i] = offsets_in[i] + add for i <= m.
+hipError_t launch_rebase(uint64_t* out, const uint64_t* in, uint32_t m, uint64_t add, hipStream_t s);
+// Serving: resolves the pending LCPs of finished requests and keeps the
+// others (moved to pend2; the caller swaps the lists).
+hipError_t launch_pend_filter(const Work& w, const Params& p, hipStream_t s);
+hipError_t launch_pend_swap(const Work& w, hipStream_t s);
+// Zeroes counts slot `which` (no memset: stays capturable).
 // Largest number of co-resident work groups of the persistent kernel.
 hipError_t persistent_capacity(int device, uint32_t* blocks);
 

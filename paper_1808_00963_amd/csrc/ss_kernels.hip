@@ -64,10 +64,11 @@ __device__ __forceinline__ void raise_err(const Work& w, uint32_t bits) { atomic
 // case, larger ones get a distribution step with its tree, counters and
 // tiles reserved here.
 __device__ void emit_segment(const Work& w, const Params& p, int nxt, const Elem* buf, uint32_t begin,
-                             uint32_t size, uint32_t depth, uint32_t obase) {
+                             uint32_t size, uint32_t depth, uint32_t rid) {
     if (size == 0) return;
     if (size == 1) {
-        p.perm[begin] = buf[begin].idx - obase;
+        p.perm[begin] = buf[begin].idx - w.set_base[rid];
+        if (w.remaining) atomicSub(&w.remaining[rid], 1u);
         return;
     }
     Counts* c = &w.ctl->c[nxt];
@@ -77,7 +78,7 @@ __device__ void emit_segment(const Work& w, const Params& p, int nxt, const Elem
         uint32_t slot = atomicAdd(&c->n_base[cls], 1u);
         atomicAdd(&c->base_strings[cls], size);
         if (slot >= w.caps.base[cls]) { raise_err(w, ERR_CAPACITY); return; }
-        w.base[cls][nxt][slot] = BaseSeg{begin, size, depth, obase};
+        w.base[cls][nxt][slot] = BaseSeg{begin, size, depth, rid};
         return;
     }
     uint32_t logv = choose_logv(size, p.bucket_target, p.max_logv);
@@ -94,7 +95,7 @@ __device__ void emit_segment(const Work& w, const Params& p, int nxt, const Elem
         return;
     }
     // the tile list entries are written by k_sample (one work group per segment)
-    w.dist[nxt][slot] = Seg{begin, size, depth, logv, toff, coff, tioff, obase};
+    w.dist[nxt][slot] = Seg{begin, size, depth, logv, toff, coff, tioff, rid};
 }
 
 // wave-level inclusive scans over 64 lanes
@@ -220,7 +221,7 @@ __device__ __forceinline__ void dev_root_one(const Work& w, const Params& p, con
         }
     }
     if (e > b) p.lcp[b] = 0;
-    emit_segment(w, p, 0, w.buf[0], b, e - b, 0, b);
+    emit_segment(w, p, 0, w.buf[0], b, e - b, 0, set_begin ? j : 0u);
 }
 
 __global__ void k_roots(Work w, Params p, const uint32_t* set_begin, uint32_t num_sets) {
@@ -389,10 +390,12 @@ __device__ void dev_base_wg(const Work& w, const Params& p, int cur, uint32_t it
         }
         __syncthreads();
     }
+    const uint32_t obase = w.set_base[sg.rid];
     for (uint32_t i = tid; i < m; i += BLOCK) {
-        p.perm[sg.begin + i] = (uint32_t)A[i] - sg.obase;
+        p.perm[sg.begin + i] = (uint32_t)A[i] - obase;
         if (i > 0) p.lcp[sg.begin + i] = lv[i];
     }
+    if (tid == 0 && w.remaining) atomicSub(&w.remaining[sg.rid], m);
 }
 
 __global__ __launch_bounds__(BLOCK) void k_base(Work w, Params p, int cur) {
@@ -568,14 +571,16 @@ __device__ void dev_base_wave(const Work& w, const Params& p, int cur, int cls, 
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
     }
+    const uint32_t obase = w.set_base[sg.rid];
 #pragma unroll
     for (uint32_t r = 0; r < (uint32_t)E; ++r) {
         const uint32_t e = lane * E + r;
         if (e < m) {
-            p.perm[sg.begin + e] = (uint32_t)A[r] - sg.obase;
+            p.perm[sg.begin + e] = (uint32_t)A[r] - obase;
             if (e > 0) p.lcp[sg.begin + e] = LV[r];
         }
     }
+    if (lane == 0 && w.remaining) atomicSub(&w.remaining[sg.rid], m);
 }
 
 template <int E>
@@ -900,6 +905,7 @@ __device__ void dev_scatter(const Work& w, const Params& p, int cur, uint32_t t,
     const Elem* in = w.buf[cur];
     Elem* out = w.buf[cur ^ 1];
     const uint32_t seg_end = sg.begin + sg.size;
+    const uint32_t obase = w.set_base[sg.rid];
 #pragma unroll 4
     for (uint32_t it = 0; it < IPT; ++it) {
         uint32_t i = cbeg + it * 64 + lane;
@@ -911,7 +917,7 @@ __device__ void dev_scatter(const Work& w, const Params& p, int cur, uint32_t t,
         if (b & 1u) {
             uint32_t rx = XR[b >> 1];
             if (rx < W) {  // identical strings ending inside this word: final
-                p.perm[pos] = e.idx - sg.obase;
+                p.perm[pos] = e.idx - obase;
                 if (pos != BS[b]) p.lcp[pos] = sg.depth + rx;
                 continue;
             }
@@ -962,6 +968,7 @@ __device__ void dev_children(const Work& w, const Params& p, int cur, uint32_t i
     const uint32_t s0 = sc[0];
     const uint8_t* gr = w.tree_r[cur] + sg.tree_off;
     const Elem* out = w.buf[nxt];
+    const uint32_t obase = w.set_base[sg.rid];
     // bucket b -> (start, count, child depth); depth == ~0u: no child segment
     auto bucket = [&](uint32_t b, uint32_t& st, uint32_t& cnt, uint32_t& depth) {
         st = sc[(size_t)b * T] - s0;
@@ -984,15 +991,22 @@ __device__ void dev_children(const Work& w, const Params& p, int cur, uint32_t i
             p.lcp[pos] = PENDING | sg.depth;
             atomicAdd(&n_pend_l, 1u);
         }
-        if (depth == ~0u) continue;
-        if (cnt == 1) { p.perm[pos] = out[pos].idx - sg.obase; continue; }
+        if (depth == ~0u) {  // identical strings: final (written by the scatter)
+            if (w.remaining) atomicSub(&w.remaining[sg.rid], cnt);
+            continue;
+        }
+        if (cnt == 1) {
+            p.perm[pos] = out[pos].idx - obase;
+            if (w.remaining) atomicSub(&w.remaining[sg.rid], 1u);
+            continue;
+        }
         if (cnt <= p.base_max) {
             const int cls = cnt <= CLS_MAX[0] ? 0 : (cnt <= CLS_MAX[1] ? 1 : 2);
             atomicAdd(&n_cls[cls], 1u);
             atomicAdd(&s_cls[cls], cnt);
             atomicMax(&max_d, depth);
         } else {
-            emit_segment(w, p, nxt, out, pos, cnt, depth, sg.obase);
+            emit_segment(w, p, nxt, out, pos, cnt, depth, sg.rid);
         }
     }
     __syncthreads();
@@ -1016,12 +1030,12 @@ __device__ void dev_children(const Work& w, const Params& p, int cur, uint32_t i
         const uint32_t pos = sg.begin + st;
         if (st > 0) {
             const uint32_t q = slot_pend + atomicAdd(&cur_pend, 1u);
-            if (q < w.caps.pend) w.pend[q] = make_uint2(pos, sg.obase);
+            if (q < w.caps.pend) w.pend[q] = make_uint2(pos, sg.rid);
         }
         if (depth == ~0u || cnt == 1 || cnt > p.base_max) continue;
         const int cls = cnt <= CLS_MAX[0] ? 0 : (cnt <= CLS_MAX[1] ? 1 : 2);
         const uint32_t q = slot_cls[cls] + atomicAdd(&cur_cls[cls], 1u);
-        if (q < w.caps.base[cls]) w.base[cls][nxt][q] = BaseSeg{pos, cnt, depth, sg.obase};
+        if (q < w.caps.base[cls]) w.base[cls][nxt][q] = BaseSeg{pos, cnt, depth, sg.rid};
     }
 }
 
@@ -1037,23 +1051,28 @@ __global__ __launch_bounds__(BLOCK) void k_children(Work w, Params p, int cur) {
 // A pending entry at position q separates two buckets of a segment with
 // common prefix h: the strings now at q-1 and q differ within the word at
 // depth h, so their LCP is h plus the common bytes of those two words.
+// Resolves one pending entry (position q, set/request id rid).
+__device__ __forceinline__ void resolve_pending(const Work& w, const Params& p, uint32_t q, uint32_t rid) {
+    if (q == 0 || q >= p.n) { raise_err(w, ERR_BOUNDS); return; }
+    uint32_t h = p.lcp[q];
+    if (!(h & PENDING)) { raise_err(w, ERR_BOUNDS); return; }
+    h &= ~PENDING;
+    const uint32_t ob = w.set_base[rid];
+    const uint32_t a = p.perm[q - 1] + ob, b = p.perm[q] + ob;
+    if (a >= p.n || b >= p.n) { raise_err(w, ERR_BOUNDS); return; }
+    const uint64_t oa = p.offsets[a], ob0 = p.offsets[b];
+    const uint32_t la = (uint32_t)(p.offsets[a + 1] - oa), lb = (uint32_t)(p.offsets[b + 1] - ob0);
+    if (la < h || lb < h) { raise_err(w, ERR_BOUNDS); return; }
+    const uint64_t ka = gather_key(p.chars, oa, h, la), kb = gather_key(p.chars, ob0, h, lb);
+    p.lcp[q] = h + lcp_word(ka, rem8(la, h), kb, rem8(lb, h));
+}
+
 __device__ void dev_lcp_fill(const Work& w, const Params& p, uint32_t first, uint32_t stride) {
     const uint32_t np = min_u32(__hip_atomic_load(&w.ctl->n_pend, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT),
                                 w.caps.pend);
     for (uint32_t s = first; s < np; s += stride) {
-        uint2 pe = w.pend[s];
-        uint32_t q = pe.x, ob = pe.y;
-        if (q == 0 || q >= p.n) { raise_err(w, ERR_BOUNDS); continue; }
-        uint32_t h = p.lcp[q];
-        if (!(h & PENDING)) { raise_err(w, ERR_BOUNDS); continue; }
-        h &= ~PENDING;
-        uint32_t a = p.perm[q - 1] + ob, b = p.perm[q] + ob;
-        if (a >= p.n || b >= p.n) { raise_err(w, ERR_BOUNDS); continue; }
-        uint64_t oa = p.offsets[a], ob0 = p.offsets[b];
-        uint32_t la = (uint32_t)(p.offsets[a + 1] - oa), lb = (uint32_t)(p.offsets[b + 1] - ob0);
-        if (la < h || lb < h) { raise_err(w, ERR_BOUNDS); continue; }
-        uint64_t ka = gather_key(p.chars, oa, h, la), kb = gather_key(p.chars, ob0, h, lb);
-        p.lcp[q] = h + lcp_word(ka, rem8(la, h), kb, rem8(lb, h));
+        const uint2 pe = w.pend[s];
+        resolve_pending(w, p, pe.x, pe.y);
     }
 }
 
@@ -1184,6 +1203,58 @@ __global__ __launch_bounds__(BLOCK) void k_persist(Work w, Params p, const uint3
     dev_lcp_fill(w, p, bid * BLOCK + tid, G * BLOCK);
 }
 
+
+// ---------------------------------------------------------------------------
+// serving helpers
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(BLOCK) void k_rebase(uint64_t* out, const uint64_t* in, uint32_t m, uint64_t add) {
+    const uint32_t i = blockIdx.x * BLOCK + threadIdx.x;
+    if (i <= m) out[i] = in[i] + add;
+}
+
+__global__ __launch_bounds__(BLOCK) void k_admit_init(Work w, Params p, int cur, uint32_t pos, uint32_t m) {
+    const uint32_t i = blockIdx.x * BLOCK + threadIdx.x;
+    if (i >= m) return;
+    const uint32_t g = pos + i;
+    const uint64_t o0 = p.offsets[g], o1 = p.offsets[g + 1];
+    uint32_t len = 0;
+    if (o1 < o0 || o1 - o0 > MAX_LEN) raise_err(w, ERR_OFFSETS);
+    else len = (uint32_t)(o1 - o0);
+    Elem e;
+    e.key = gather_key(p.chars, o0, 0, len);
+    e.idx = g;
+    e.len = len;
+    w.buf[cur][g] = e;
+}
+
+__global__ void k_admit_root(Work w, Params p, int cur, uint32_t pos, uint32_t m, uint32_t rid) {
+    if (threadIdx.x != 0) return;
+    if (m) p.lcp[pos] = 0;
+    emit_segment(w, p, cur, w.buf[cur], pos, m, 0, rid);
+}
+
+__global__ __launch_bounds__(BLOCK) void k_pend_filter(Work w, Params p) {
+    const uint32_t np = min_u32(w.ctl->n_pend, w.caps.pend);
+    for (uint32_t s = blockIdx.x * BLOCK + threadIdx.x; s < np; s += gridDim.x * BLOCK) {
+        const uint2 pe = w.pend[s];
+        if (w.done[pe.y]) {
+            resolve_pending(w, p, pe.x, pe.y);
+        } else {
+            const uint32_t q = atomicAdd(&w.ctl->n_pend2, 1u);
+            if (q < w.caps.pend) w.pend2[q] = pe;
+            else raise_err(w, ERR_CAPACITY);
+        }
+    }
+}
+
+__global__ void k_pend_swap(Work w) {
+    if (threadIdx.x == 0) {
+        w.ctl->n_pend = min_u32(w.ctl->n_pend2, w.caps.pend);
+        w.ctl->n_pend2 = 0;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
@@ -1267,6 +1338,25 @@ hipError_t persistent_capacity(int device, uint32_t* blocks) {
     if (e != hipSuccess) return e;
     *blocks = (uint32_t)(per_cu * cus);
     return hipSuccess;
+}
+
+hipError_t launch_admit(const Work& w, const Params& p, int cur, uint32_t pos, uint32_t m, uint32_t rid,
+                        hipStream_t s) {
+    if (m) hipLaunchKernelGGL(k_admit_init, dim3(blocks_for(m, BLOCK)), dim3(BLOCK), 0, s, w, p, cur, pos, m);
+    hipLaunchKernelGGL(k_admit_root, dim3(1), dim3(64), 0, s, w, p, cur, pos, m, rid);
+    return hipGetLastError();
+}
+hipError_t launch_rebase(uint64_t* out, const uint64_t* in, uint32_t m, uint64_t add, hipStream_t s) {
+    hipLaunchKernelGGL(k_rebase, dim3(blocks_for((uint64_t)m + 1, BLOCK)), dim3(BLOCK), 0, s, out, in, m, add);
+    return hipGetLastError();
+}
+hipError_t launch_pend_filter(const Work& w, const Params& p, hipStream_t s) {
+    hipLaunchKernelGGL(k_pend_filter, dim3(512), dim3(BLOCK), 0, s, w, p);
+    return hipGetLastError();
+}
+hipError_t launch_pend_swap(const Work& w, hipStream_t s) {
+    hipLaunchKernelGGL(k_pend_swap, dim3(1), dim3(64), 0, s, w);
+    return hipGetLastError();
 }
 
 }  // namespace ss
