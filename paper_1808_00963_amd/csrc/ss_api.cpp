@@ -121,7 +121,8 @@ size_t layout(uint32_t n, const Caps& k, char* base, Work* w) {
     t.pend2 = nullptr;
     t.ctl = (Ctl*)take(sizeof(Ctl));
     t.bar = (GridBar*)take(sizeof(GridBar));
-    t.set_base = t.ctl ? t.ctl->zero : nullptr;  // a plain sort is one set starting at 0
+    t.zero_base = (uint32_t*)take(256);
+    t.set_base = t.zero_base;  // a plain sort is one set starting at 0
     t.remaining = nullptr;
     t.done = nullptr;
     t.caps = k;
@@ -292,7 +293,7 @@ ss_status run_sort(ss_ctx* ctx, const uint8_t* chars, const uint64_t* offsets, u
     for (;;) {
         if ((st = read_ctl(ctx, s)) != SS_OK) return st;
         if (ctx->host_ctl->err) return device_error_status(ctx->host_ctl->err);
-        const Counts c = ctx->host_ctl->c[cur];
+        const Counts c = ctx->host_ctl->cl[cur].c;
         ctx->stats.levels = level + 1;
         ctx->stats.dist_segments += c.n_dist;
         ctx->stats.dist_tiles += c.n_tiles;
@@ -829,7 +830,7 @@ void server_loop(ss_server* S) {
         if (st == SS_OK) st = read_ctl(ctx, S->stream);
         if (st == SS_OK && ctx->host_ctl->err) st = device_error_status(ctx->host_ctl->err);
         if (st == SS_OK) {
-            const Counts c = ctx->host_ctl->c[S->cur];
+            const Counts c = ctx->host_ctl->cl[S->cur].c;
             st = enqueue_level(ctx, S->w, S->p, S->cur, c, S->stream);
             S->cur ^= 1;
         }

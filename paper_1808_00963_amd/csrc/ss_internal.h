@@ -52,14 +52,22 @@ struct Counts {
     uint32_t dist_strings;        // strings in the distribution segments of the level
 };
 
-// Device-side control block.
+// Device-side control block.  Every group of fields that kernels update
+// with atomics sits on its own 128-byte line, so the atomics never share a
+// line with data other waves read.
+struct alignas(128) Counts128 {
+    Counts c;
+    uint32_t pad[32 - sizeof(Counts) / 4];
+};
 struct Ctl {
-    Counts c[2];
+    Counts128 cl[2];
     uint32_t n_pend;
-    uint32_t err;
-    uint32_t base_rounds;  // refinement rounds run by base cases (statistics)
     uint32_t n_pend2;      // survivors of a pending-list filter (serving)
-    uint32_t zero[4];      // set base of a plain sort (one set starting at 0)
+    uint32_t pad0[30];
+    uint32_t err;
+    uint32_t pad1[31];
+    uint32_t base_rounds;  // refinement rounds run by base cases (statistics)
+    uint32_t pad2[31];
 };
 
 // Error bits raised on the device.
@@ -112,6 +120,7 @@ struct Work {
     Ctl* ctl;
     GridBar* bar;
     const uint32_t* set_base; // per set/request id: its first position (subtracted from perm entries)
+    uint32_t* zero_base;      // one zero word on its own line: set base of a plain sort
     uint32_t* remaining;      // per request id: strings not yet final (serving; else null)
     const uint8_t* done;      // per request id: 1 once finished (serving; else null)
     Caps caps;

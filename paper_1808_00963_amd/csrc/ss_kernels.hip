@@ -58,6 +58,17 @@ __device__ __forceinline__ uint32_t lcp_from(const uint8_t* chars, uint64_t oa, 
 
 __device__ __forceinline__ void raise_err(const Work& w, uint32_t bits) { atomicOr(&w.ctl->err, bits); }
 
+// Block -> tile mapping that keeps consecutive tiles on the same XCD (work
+// groups are dispatched to the 8 XCDs round robin): the tiles of XCD x are a
+// contiguous range, so concurrently running neighbours write adjacent parts
+// of the same buckets through the same L2.
+__device__ __forceinline__ uint32_t xcd_tile(uint32_t b, uint32_t nt) {
+    constexpr uint32_t X = 8;
+    const uint32_t x = b % X, i = b / X, q = nt / X, r = nt % X;
+    return x * q + (x < r ? x : r) + i;
+}
+
+
 // Appends a segment of the next level (positions [begin, begin+size) of
 // buffer `buf`, common prefix `depth`) to the work lists of counts slot
 // `nxt`: a single string is final at once, small segments go to the base
@@ -71,7 +82,7 @@ __device__ void emit_segment(const Work& w, const Params& p, int nxt, const Elem
         if (w.remaining) atomicSub(&w.remaining[rid], 1u);
         return;
     }
-    Counts* c = &w.ctl->c[nxt];
+    Counts* c = &w.ctl->cl[nxt].c;
     atomicMax(&c->max_depth, depth);
     if (size <= p.base_max) {
         const int cls = size <= CLS_MAX[0] ? 0 : (size <= CLS_MAX[1] ? 1 : 2);
@@ -180,12 +191,13 @@ union SmAll {
 __global__ void k_reset(Work w) {
     uint32_t* p = (uint32_t*)w.ctl;
     for (uint32_t i = threadIdx.x; i < sizeof(Ctl) / 4; i += blockDim.x) p[i] = 0;
+    if (threadIdx.x == 0) w.zero_base[0] = 0;
     uint32_t* b = (uint32_t*)w.bar;
     for (uint32_t i = threadIdx.x; i < sizeof(GridBar) / 4; i += blockDim.x) b[i] = 0;
 }
 
 __global__ void k_zero_counts(Work w, int which) {
-    uint32_t* p = (uint32_t*)&w.ctl->c[which];
+    uint32_t* p = (uint32_t*)&w.ctl->cl[which].c;
     for (uint32_t i = threadIdx.x; i < sizeof(Counts) / 4; i += blockDim.x) p[i] = 0;
 }
 
@@ -285,6 +297,7 @@ __device__ void dev_base_wg(const Work& w, const Params& p, int cur, uint32_t it
 
     const BaseSeg sg = w.base[2][cur][item];
     const uint32_t tid = threadIdx.x, m = sg.size, h = sg.depth;
+    uint32_t rounds = 0;
     if (m < 2 || m > BASE_CAP || m > p.base_max || sg.begin > p.n || m > p.n - sg.begin) {  // uniform
         if (tid == 0) raise_err(w, ERR_BOUNDS);
         return;
@@ -326,7 +339,7 @@ __device__ void dev_base_wg(const Work& w, const Params& p, int cur, uint32_t it
         }
         __syncthreads();
         if (!any) break;
-        if (tid == 0) atomicAdd(&w.ctl->base_rounds, 1u);
+        ++rounds;
         // run starts: inclusive max-scan of (tie ? 0 : position)
         {
             const uint32_t base = tid * PER;
@@ -396,6 +409,7 @@ __device__ void dev_base_wg(const Work& w, const Params& p, int cur, uint32_t it
         if (i > 0) p.lcp[sg.begin + i] = lv[i];
     }
     if (tid == 0 && w.remaining) atomicSub(&w.remaining[sg.rid], m);
+    if (tid == 0 && rounds) atomicAdd(&w.ctl->base_rounds, rounds);
 }
 
 __global__ __launch_bounds__(BLOCK) void k_base(Work w, Params p, int cur) {
@@ -467,6 +481,7 @@ __device__ void dev_base_wave(const Work& w, const Params& p, int cur, int cls, 
     if (si >= nseg) return;  // uniform per wave
     const BaseSeg sg = w.base[cls][cur][si];
     const uint32_t m = sg.size, h = sg.depth;
+    uint32_t rounds = 0;
     if (m < 2 || m > 64u * E || sg.begin > p.n || m > p.n - sg.begin) {
         if (lane == 0) raise_err(w, ERR_BOUNDS);
         return;
@@ -505,7 +520,7 @@ __device__ void dev_base_wave(const Work& w, const Params& p, int cur, int cls, 
             }
         }
         if (__ballot(tb != 0) == 0) break;
-        if (lane == 0) atomicAdd(&w.ctl->base_rounds, 1u);
+        ++rounds;
         // run starts (inclusive max-scan of "tie ? 0 : position")
         uint32_t loc[E];
         uint32_t run = 0;
@@ -581,6 +596,7 @@ __device__ void dev_base_wave(const Work& w, const Params& p, int cur, int cls, 
         }
     }
     if (lane == 0 && w.remaining) atomicSub(&w.remaining[sg.rid], m);
+    if (lane == 0 && rounds) atomicAdd(&w.ctl->base_rounds, rounds);
 }
 
 template <int E>
@@ -738,7 +754,7 @@ __device__ void dev_classify(const Work& w, const Params& p, int cur, uint32_t t
 
 __global__ __launch_bounds__(BLOCK) void k_classify(Work w, Params p, int cur, uint32_t n_dist) {
     __shared__ SmClassify sm;
-    dev_classify(w, p, cur, blockIdx.x, n_dist, sm);
+    dev_classify(w, p, cur, xcd_tile(blockIdx.x, gridDim.x), n_dist, sm);
 }
 
 // ---------------------------------------------------------------------------
@@ -908,21 +924,20 @@ __device__ void dev_scatter(const Work& w, const Params& p, int cur, uint32_t t,
     const uint32_t obase = w.set_base[sg.rid];
 #pragma unroll 4
     for (uint32_t it = 0; it < IPT; ++it) {
-        uint32_t i = cbeg + it * 64 + lane;
+        const uint32_t i = cbeg + it * 64 + lane;
         if (i >= end) continue;
         Elem e = in[i];
-        uint32_t b = packed[it] >> 16, rank = packed[it] & 0xFFFFu;
-        uint32_t pos = GB[b] + WC[wv][b] + rank;
+        const uint32_t b = packed[it] >> 16, rank = packed[it] & 0xFFFFu;
+        const uint32_t pos = GB[b] + WC[wv][b] + rank;
         if (pos < sg.begin || pos >= seg_end) { raise_err(w, ERR_BOUNDS); continue; }
         if (b & 1u) {
-            uint32_t rx = XR[b >> 1];
+            const uint32_t rx = XR[b >> 1];
             if (rx < W) {  // identical strings ending inside this word: final
                 p.perm[pos] = e.idx - obase;
                 if (pos != BS[b]) p.lcp[pos] = sg.depth + rx;
                 continue;
             }
-            uint32_t d2 = sg.depth + W;
-            e.key = gather_key(p.chars, p.offsets[e.idx], d2, e.len);
+            e.key = gather_key(p.chars, p.offsets[e.idx], sg.depth + W, e.len);
         }
         out[pos] = e;
     }
@@ -930,7 +945,7 @@ __device__ void dev_scatter(const Work& w, const Params& p, int cur, uint32_t t,
 
 __global__ __launch_bounds__(BLOCK) void k_scatter(Work w, Params p, int cur, uint32_t n_dist) {
     __shared__ SmScatter sm;
-    dev_scatter(w, p, cur, blockIdx.x, n_dist, sm);
+    dev_scatter(w, p, cur, xcd_tile(blockIdx.x, gridDim.x), n_dist, sm);
 }
 
 // ---------------------------------------------------------------------------
@@ -1011,7 +1026,7 @@ __device__ void dev_children(const Work& w, const Params& p, int cur, uint32_t i
     }
     __syncthreads();
     if (tid == 0) {
-        Counts* c = &w.ctl->c[nxt];
+        Counts* c = &w.ctl->cl[nxt].c;
         for (int q = 0; q < NCLS; ++q) {
             slot_cls[q] = n_cls[q] ? atomicAdd(&c->n_base[q], n_cls[q]) : 0u;
             if (s_cls[q]) atomicAdd(&c->base_strings[q], s_cls[q]);
@@ -1143,7 +1158,7 @@ __global__ __launch_bounds__(BLOCK) void k_persist(Work w, Params p, const uint3
     for (;; ++level) {
         // every block reads the level's counts before any block changes them
         if (tid < sizeof(Counts) / 4)
-            ((uint32_t*)&sc)[tid] = __hip_atomic_load((uint32_t*)&w.ctl->c[cur] + tid, __ATOMIC_RELAXED,
+            ((uint32_t*)&sc)[tid] = __hip_atomic_load((uint32_t*)&w.ctl->cl[cur].c + tid, __ATOMIC_RELAXED,
                                                       __HIP_MEMORY_SCOPE_AGENT);
         if (tid == 0) s_err = __hip_atomic_load(&w.ctl->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (!grid_sync(w, G, gen, &s_ok)) return;
@@ -1158,7 +1173,7 @@ __global__ __launch_bounds__(BLOCK) void k_persist(Work w, Params p, const uint3
         const uint32_t nitems = nb0 + nb1 + nb2 + c.n_dist;
         if (nitems == 0) break;
         if (bid == 0 && tid < sizeof(Counts) / 4)
-            __hip_atomic_store((uint32_t*)&w.ctl->c[cur ^ 1] + tid, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store((uint32_t*)&w.ctl->cl[cur ^ 1].c + tid, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         // base cases of every class and the splitter trees of the level
         for (uint32_t it = bid; it < nitems; it += G) {
             __syncthreads();
