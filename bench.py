@@ -278,10 +278,44 @@ def run_serve(args):
     print(json.dumps(out), flush=True)
 
 
+def run_profile(args):
+    """Program for hardware-counter runs: 3 streaming copies of 1 GiB (known
+    traffic, for calibration) followed by warm-up + timed sorts of the plain
+    workload.  Prints the copy bandwidth."""
+    import numpy as np
+    import torch
+
+    import gen
+    import paper_1808_00963_amd as ss
+
+    nbytes = 1 << 30
+    src = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    src.fill_(1)
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(3):
+        a = time.perf_counter()
+        ss.hbm_copy(dst, src)
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - a)
+    print(f"[bench] copy 1 GiB: {2 * nbytes / min(ts) / 1e9:.1f} GB/s (read + write)", file=sys.stderr, flush=True)
+    del src, dst
+    model, n, seed = gen.WORKLOADS[args.workload]
+    c, o = gen.generate(model, n, seed)
+    chars = torch.from_numpy(c).cuda()
+    offs = torch.from_numpy(o.view(np.int64)).cuda()
+    ctx = ss.Context(0)
+    for _ in range(args.warmup + args.steps):
+        ctx.sort(chars, offs)
+    torch.cuda.synchronize()
+    print(json.dumps({"mode": "profile", "workload": args.workload, "copy_gbs": 2 * nbytes / min(ts) / 1e9}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--mode", choices=["plain", "batch", "serve"], default="plain")
+    ap.add_argument("--mode", choices=["plain", "batch", "serve", "profile"], default="plain")
     ap.add_argument("--pool", type=int, default=128)
     ap.add_argument("--requests", type=int, default=2000)
     ap.add_argument("--serve-warmup", type=int, default=200)
@@ -302,6 +336,9 @@ def main():
         return
     if args.mode == "serve":
         run_serve(args)
+        return
+    if args.mode == "profile":
+        run_profile(args)
         return
 
     import numpy as np

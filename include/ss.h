@@ -241,6 +241,12 @@ ss_status ss_set_profiling(ss_ctx* ctx, int enable);
 ss_status ss_get_kernel_times(const ss_ctx* ctx, ss_kernel_time* out, uint32_t max_entries, uint32_t* n_entries);
 void ss_reset_kernel_times(ss_ctx* ctx);
 
+/* Streaming copy of `bytes` bytes (device pointers, 16-byte aligned, bytes a
+ * multiple of 16) on `stream`.  Used to measure the achievable HBM
+ * bandwidth and to calibrate hardware byte counters against a kernel whose
+ * traffic is known (2 * bytes). */
+ss_status ss_hbm_copy(void* dst, const void* src, size_t bytes, void* stream);
+
 /* ---- host-side test entry points (no device access) -------------------
  * These run the same primitive functions the kernels use, on the host, so
  * the test suite can check them on a machine without a GPU. */

@@ -100,6 +100,7 @@ def lib():
             "ss_set_profiling": (i32, [vp, i32]),
             "ss_get_kernel_times": (i32, [vp, ctypes.POINTER(KernelTime), u32, ctypes.POINTER(u32)]),
             "ss_reset_kernel_times": (None, [vp]),
+            "ss_hbm_copy": (i32, [vp, vp, ctypes.c_size_t, vp]),
             "ss_host_key": (u64, [vp, u64, u64, ctypes.POINTER(u32)]),
             "ss_host_level_index": (u32, [u32, u32]),
             "ss_host_inorder_index": (u32, [u32, u32]),
@@ -363,6 +364,15 @@ def sort(chars, offsets, stream=None):
                        ctypes.c_void_p(perm.data_ptr()), ctypes.c_void_p(lcp.data_ptr()), _stream_ptr(stream))
     _check(st, "ss_sort")
     return perm, lcp
+
+
+def hbm_copy(dst, src, stream=None):
+    """Streaming device copy (bandwidth calibration); tensors of equal byte size."""
+    nbytes = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != nbytes:
+        raise ValueError("size mismatch")
+    _check(lib().ss_hbm_copy(ctypes.c_void_p(dst.data_ptr()), ctypes.c_void_p(src.data_ptr()), nbytes,
+                             _stream_ptr(stream)), "ss_hbm_copy")
 
 
 # ---- host-side test entry points (no GPU needed) ----

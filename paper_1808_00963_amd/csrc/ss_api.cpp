@@ -546,6 +546,12 @@ void ss_reset_kernel_times(ss_ctx* ctx) {
     for (int i = 0; i < K_COUNT; ++i) P.ms[i] = P.unit_sum[i] = 0, P.launches[i] = 0;
 }
 
+ss_status ss_hbm_copy(void* dst, const void* src, size_t bytes, void* stream) {
+    if (!dst || !src || (bytes & 15) || (((uintptr_t)dst | (uintptr_t)src) & 15)) return SS_INVALID_ARG;
+    SS_TRY(launch_copy(dst, src, bytes / 16, (hipStream_t)stream));
+    return SS_OK;
+}
+
 // ---- host-side test entry points ----
 
 uint64_t ss_host_key(const uint8_t* s, uint64_t len, uint64_t h, uint32_t* r_out) {

@@ -167,6 +167,8 @@ hipError_t launch_rebase(uint64_t* out, const uint64_t* in, uint32_t m, uint64_t
 // others (moved to pend2; the caller swaps the lists).
 hipError_t launch_pend_filter(const Work& w, const Params& p, hipStream_t s);
 hipError_t launch_pend_swap(const Work& w, hipStream_t s);
+// Streaming copy (bandwidth calibration).
+hipError_t launch_copy(void* dst, const void* src, size_t n16, hipStream_t s);
 // Zeroes counts slot `which` (no memset: stays capturable).
 // Largest number of co-resident work groups of the persistent kernel.
 hipError_t persistent_capacity(int device, uint32_t* blocks);

@@ -8,6 +8,8 @@
 //   k_scatter   per tile: stable scatter into the other ping-pong buffer
 //   k_children  per large segment: buckets -> next-level segments
 // and k_lcp_fill resolves the LCPs at bucket boundaries at the end.
+#include <algorithm>
+
 #include "ss_device.h"
 #include "ss_internal.h"
 
@@ -1371,6 +1373,19 @@ hipError_t launch_pend_filter(const Work& w, const Params& p, hipStream_t s) {
 }
 hipError_t launch_pend_swap(const Work& w, hipStream_t s) {
     hipLaunchKernelGGL(k_pend_swap, dim3(1), dim3(64), 0, s, w);
+    return hipGetLastError();
+}
+
+// Plain streaming copy, 16 bytes per lane per iteration.
+__global__ __launch_bounds__(BLOCK) void k_copy(uint4* __restrict__ dst, const uint4* __restrict__ src, size_t n16) {
+    const size_t stride = (size_t)gridDim.x * BLOCK;
+    for (size_t i = (size_t)blockIdx.x * BLOCK + threadIdx.x; i < n16; i += stride) dst[i] = src[i];
+}
+
+hipError_t launch_copy(void* dst, const void* src, size_t n16, hipStream_t s) {
+    if (n16 == 0) return hipSuccess;
+    const uint32_t nb = (uint32_t)std::min<size_t>((n16 + BLOCK - 1) / BLOCK, 256u * 32u);
+    hipLaunchKernelGGL(k_copy, dim3(nb), dim3(BLOCK), 0, s, (uint4*)dst, (const uint4*)src, n16);
     return hipGetLastError();
 }
 
