@@ -36,6 +36,7 @@ BYTES_PER_UNIT = {
     "k_scatter": 34.0,
     "k_base": 24.0,
     "k_base_wave1": 24.0,
+    "k_base_wave2": 24.0,
     "k_base_wave4": 24.0,
     "k_scan": 12.0,
     "k_lcp_fill": 72.0,

@@ -22,13 +22,14 @@ using namespace ss;
 
 namespace {
 enum KernelId {
-    K_INIT, K_ROOTS, K_BASE_W1, K_BASE_W4, K_BASE, K_SAMPLE, K_CLASSIFY, K_SCAN, K_SCATTER, K_CHILDREN,
+    K_INIT, K_ROOTS, K_BASE_W1, K_BASE_W2, K_BASE_W4, K_BASE, K_SAMPLE, K_CLASSIFY, K_SCAN, K_SCATTER, K_CHILDREN,
     K_LCP_FILL, K_PERSIST, K_COUNT
 };
-const char* const KNAME[K_COUNT] = {"k_init", "k_roots", "k_base_wave1", "k_base_wave4", "k_base", "k_sample",
-                                    "k_classify", "k_scan", "k_scatter", "k_children", "k_lcp_fill", "k_persist"};
-const char* const KUNIT[K_COUNT] = {"strings", "sets", "strings", "strings", "strings", "segments", "strings",
-                                    "counters", "strings", "segments", "boundaries", "strings"};
+const char* const KNAME[K_COUNT] = {"k_init", "k_roots", "k_base_wave1", "k_base_wave2", "k_base_wave4", "k_base",
+                                    "k_sample", "k_classify", "k_scan", "k_scatter", "k_children", "k_lcp_fill",
+                                    "k_persist"};
+const char* const KUNIT[K_COUNT] = {"strings", "sets", "strings", "strings", "strings", "strings", "segments",
+                                    "strings", "counters", "strings", "segments", "boundaries", "strings"};
 
 // Event pairs around kernel launches, resolved at the next host sync.
 struct Profiler {
@@ -84,8 +85,7 @@ Caps caps_for(uint32_t n, const ss_config& c) {
     k.dist = (uint32_t)dist;
     k.tiles = (uint32_t)(N / TILE + dist + 2);
     k.base[0] = (uint32_t)(N / 2 + 2);
-    k.base[1] = (uint32_t)(N / (CLS_MAX[0] + 1) + 2);
-    k.base[2] = (uint32_t)(N / (CLS_MAX[1] + 1) + 2);
+    for (int c = 1; c < NCLS; ++c) k.base[c] = (uint32_t)(N / (CLS_MAX[c - 1] + 1) + 2);
     // sum of (2v+1) * tiles: at most MAX_BUCKETS per tile of a multi-tile
     // segment, at most max(3, 2 size / bucket_target) for one-tile segments
     k.cnt = (uint32_t)std::min<uint64_t>(
@@ -297,7 +297,7 @@ ss_status run_sort(ss_ctx* ctx, const uint8_t* chars, const uint64_t* offsets, u
         ctx->stats.levels = level + 1;
         ctx->stats.dist_segments += c.n_dist;
         ctx->stats.dist_tiles += c.n_tiles;
-        ctx->stats.base_segments += c.n_base[0] + c.n_base[1] + c.n_base[2];
+        for (int q = 0; q < NCLS; ++q) ctx->stats.base_segments += c.n_base[q];
         ctx->stats.max_depth = std::max(ctx->stats.max_depth, c.max_depth);
         if ((st = enqueue_level(ctx, w, p, cur, c, s)) != SS_OK) return st;
         if (c.n_dist == 0) break;

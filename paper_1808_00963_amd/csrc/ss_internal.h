@@ -34,11 +34,15 @@ struct BaseSeg {
     uint32_t begin, size, depth, rid;
 };
 
-// Base-case size classes: one wave per segment with 1 string per lane
-// (<= 64), one wave with 4 strings per lane (<= 256), one work group with
-// the segment in LDS (<= base_max).
-constexpr int NCLS = 3;
-constexpr uint32_t CLS_MAX[NCLS] = {64, 256, 1024};
+// Base-case size classes: one wave per segment with 1, 2 or 4 strings per
+// lane (<= 64, <= 128, <= 256), one work group with the segment in LDS
+// (<= base_max).
+constexpr int NCLS = 4;
+constexpr int CLS_WG = NCLS - 1;
+constexpr uint32_t CLS_MAX[NCLS] = {64, 128, 256, 1024};
+__host__ __device__ constexpr int size_class(uint32_t size) {
+    return size <= CLS_MAX[0] ? 0 : size <= CLS_MAX[1] ? 1 : size <= CLS_MAX[2] ? 2 : 3;
+}
 
 // Work-list sizes of one recursion level.
 struct Counts {

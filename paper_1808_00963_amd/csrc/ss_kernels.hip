@@ -87,7 +87,7 @@ __device__ void emit_segment(const Work& w, const Params& p, int nxt, const Elem
     Counts* c = &w.ctl->cl[nxt].c;
     atomicMax(&c->max_depth, depth);
     if (size <= p.base_max) {
-        const int cls = size <= CLS_MAX[0] ? 0 : (size <= CLS_MAX[1] ? 1 : 2);
+        const int cls = size_class(size);
         uint32_t slot = atomicAdd(&c->n_base[cls], 1u);
         atomicAdd(&c->base_strings[cls], size);
         if (slot >= w.caps.base[cls]) { raise_err(w, ERR_CAPACITY); return; }
@@ -118,6 +118,14 @@ __device__ __forceinline__ uint32_t wave_incl_sum(uint32_t x) {
     for (uint32_t o = 1; o < 64; o <<= 1) {
         uint32_t y = __shfl_up(x, o, 64);
         if (lane >= o) x += y;
+    }
+    return x;
+}
+__device__ __forceinline__ uint32_t wave_max(uint32_t x) {
+#pragma unroll
+    for (uint32_t o = 1; o < 64; o <<= 1) {
+        uint32_t y = __shfl_xor(x, o, 64);
+        x = x > y ? x : y;
     }
     return x;
 }
@@ -163,10 +171,7 @@ struct SmClassify {
     uint32_t H[MAX_BUCKETS + 1];
 };
 struct SmScatter {
-    uint32_t WC[WAVES][MAX_BUCKETS + 1];
-    uint32_t GB[MAX_BUCKETS + 1];
-    uint32_t BS[MAX_BUCKETS + 1];
-    uint8_t XR[1 << MAX_LOGV];
+    uint32_t WC[WAVES][MAX_BUCKETS + 1];  // per-wave counts, then per-wave write bases
 };
 struct SmChildren {
     uint32_t n_cls[NCLS], s_cls[NCLS], slot_cls[NCLS], cur_cls[NCLS];
@@ -297,7 +302,7 @@ __device__ void dev_base_wg(const Work& w, const Params& p, int cur, uint32_t it
     uint32_t& any = sm.any;
     constexpr uint32_t PER = BASE_CAP / BLOCK;
 
-    const BaseSeg sg = w.base[2][cur][item];
+    const BaseSeg sg = w.base[CLS_WG][cur][item];
     const uint32_t tid = threadIdx.x, m = sg.size, h = sg.depth;
     uint32_t rounds = 0;
     if (m < 2 || m > BASE_CAP || m > p.base_max || sg.begin > p.n || m > p.n - sg.begin) {  // uniform
@@ -468,6 +473,58 @@ __device__ __forceinline__ void wave_bitonic(uint64_t (&K)[E], uint64_t (&A)[E],
     }
 }
 
+// One step of odd-even transposition sort over the blocked 64*E records:
+// pairs (2i, 2i+1) on even steps, (2i+1, 2i+2) on odd steps, each put in
+// order.  Records of different groups are already in order (groups are
+// contiguous and numbered by position), so L steps sort every run of at
+// most L records without disturbing anything else.
+template <int E>
+__device__ __forceinline__ void wave_oddeven_step(uint64_t (&K)[E], uint64_t (&A)[E], uint32_t lane, bool odd) {
+    if (E == 1) {
+        const uint64_t xk = __shfl_xor(K[0], 1, 64), xa = __shfl_xor(A[0], 1, 64);
+        const uint64_t dk = __shfl_down(K[0], 1, 64), da = __shfl_down(A[0], 1, 64);
+        const uint64_t uk = __shfl_up(K[0], 1, 64), ua = __shfl_up(A[0], 1, 64);
+        bool lower, has;
+        uint64_t pk, pa;
+        if (!odd) {
+            lower = (lane & 1) == 0; has = true; pk = xk; pa = xa;
+        } else {
+            lower = (lane & 1) == 1;
+            has = lower ? lane < 63 : lane > 0;
+            pk = lower ? dk : uk;
+            pa = lower ? da : ua;
+        }
+        if (has) {
+            const bool take = lower ? rec_gt(K[0], A[0], pk, pa) : rec_gt(pk, pa, K[0], A[0]);
+            if (take) { K[0] = pk; A[0] = pa; }
+        }
+        return;
+    }
+    // neighbours across the lane boundary (old values, before any exchange)
+    const uint64_t nk = __shfl_down(K[0], 1, 64), na = __shfl_down(A[0], 1, 64);
+    const uint64_t pk = __shfl_up(K[E - 1], 1, 64), pa = __shfl_up(A[E - 1], 1, 64);
+    if (!odd) {
+#pragma unroll
+        for (uint32_t r = 0; r + 1 < (uint32_t)E; r += 2) {
+            if (rec_gt(K[r], A[r], K[r + 1], A[r + 1])) {
+                uint64_t t = K[r]; K[r] = K[r + 1]; K[r + 1] = t;
+                t = A[r]; A[r] = A[r + 1]; A[r + 1] = t;
+            }
+        }
+    } else {
+        uint64_t k0 = K[0], a0 = A[0], kl = K[E - 1], al = A[E - 1];
+#pragma unroll
+        for (uint32_t r = 1; r + 1 < (uint32_t)E; r += 2) {
+            if (rec_gt(K[r], A[r], K[r + 1], A[r + 1])) {
+                uint64_t t = K[r]; K[r] = K[r + 1]; K[r + 1] = t;
+                t = A[r]; A[r] = A[r + 1]; A[r + 1] = t;
+            }
+        }
+        if (lane < 63 && rec_gt(kl, al, nk, na)) { K[E - 1] = nk; A[E - 1] = na; }
+        if (lane > 0 && rec_gt(pk, pa, k0, a0)) { K[0] = pk; A[0] = pa; }
+    }
+}
+
 // Same job as k_base for a segment of at most 64*E strings: sort by
 // (key, r, index), refine runs of equal full words at depth + 8 (keys
 // re-gathered only for those strings), LCP of neighbours from the word at
@@ -505,8 +562,13 @@ __device__ void dev_base_wave(const Work& w, const Params& p, int cur, int cls, 
         D[r] = h;
         LV[r] = 0;
     }
+    uint32_t span = ~0u;
     for (;;) {
-        wave_bitonic<E>(K, A, lane);
+        if (span <= (E == 1 ? 12u : 32u)) {
+            for (uint32_t st = 0; st < span; ++st) wave_oddeven_step<E>(K, A, lane, (st & 1u) != 0);
+        } else {
+            wave_bitonic<E>(K, A, lane);
+        }
         uint64_t pk0 = __shfl_up(K[E - 1], 1, 64);
         uint64_t pa0 = __shfl_up(A[E - 1], 1, 64);
         uint32_t tb = 0;
@@ -540,13 +602,17 @@ __device__ void dev_base_wave(const Work& w, const Params& p, int cur, int cls, 
         const uint32_t next_tie = lane < 63 ? (tb_next_lane & 1u) : 0u;
         uint32_t RS[E];
         uint32_t act = 0;
+        span = 0;
 #pragma unroll
         for (uint32_t r = 0; r < (uint32_t)E; ++r) {
             const uint32_t e = lane * E + r;
             RS[r] = excl > loc[r] ? excl : loc[r];
             const bool t_here = (tb >> r) & 1u;
             const bool t_next = r + 1 < (uint32_t)E ? ((tb >> (r + 1)) & 1u) : next_tie;
-            if (e < m && (t_here || t_next)) act |= 1u << r;
+            if (e < m && (t_here || t_next)) {
+                act |= 1u << r;
+                span = span > e - RS[r] + 1 ? span : e - RS[r] + 1;
+            }
             if (e < m && RS[r] == e && (act >> r) & 1u) {  // run leader publishes its string
                 LIDX[wv][e] = (uint32_t)A[r];
                 RMIN[wv][e] = ~0u;
@@ -556,14 +622,25 @@ __device__ void dev_base_wave(const Work& w, const Params& p, int cur, int cls, 
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         // common prefix of each run: members' LCP with the leader's string,
-        // starting 8 characters past the shared word
+        // starting 8 characters past the shared word; every string of a run
+        // keeps its offset and length for the re-gather below
+        uint64_t OA[E];
+        uint32_t LA[E];
 #pragma unroll
         for (uint32_t r = 0; r < (uint32_t)E; ++r) {
             const uint32_t e = lane * E + r;
-            if (!((act >> r) & 1u) || RS[r] == e) continue;
-            const uint32_t a = (uint32_t)A[r], b = LIDX[wv][RS[r]];
-            const uint64_t oa = p.offsets[a], ob = p.offsets[b];
-            const uint32_t la = (uint32_t)(p.offsets[a + 1] - oa), lb = (uint32_t)(p.offsets[b + 1] - ob);
+            OA[r] = 0;
+            LA[r] = 0;
+            if (!((act >> r) & 1u)) continue;
+            const uint32_t a = (uint32_t)A[r];
+            const uint64_t oa = p.offsets[a];
+            const uint32_t la = (uint32_t)(p.offsets[a + 1] - oa);
+            OA[r] = oa;
+            LA[r] = la;
+            if (RS[r] == e) continue;
+            const uint32_t b = LIDX[wv][RS[r]];
+            const uint64_t ob = p.offsets[b];
+            const uint32_t lb = (uint32_t)(p.offsets[b + 1] - ob);
             atomicMin(&RMIN[wv][RS[r]], lcp_from(p.chars, oa, la, ob, lb, D[r] + W));
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -577,16 +654,15 @@ __device__ void dev_base_wave(const Work& w, const Params& p, int cur, int cls, 
             if ((act >> r) & 1u) {
                 const uint32_t d2 = RMIN[wv][RS[r]];
                 D[r] = d2;
-                const uint64_t o0 = p.offsets[idx], o1 = p.offsets[idx + 1];
-                const uint32_t len = (uint32_t)(o1 - o0);
-                K[r] = gather_key(p.chars, o0, d2, len);
-                A[r] = rec_pack(RS[r], rem8(len, d2), idx);
+                K[r] = gather_key(p.chars, OA[r], d2, LA[r]);
+                A[r] = rec_pack(RS[r], rem8(LA[r], d2), idx);
             } else {
                 A[r] = rec_pack(e, rec_r(A[r]), idx);
             }
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
+        span = wave_max(span);
     }
     const uint32_t obase = w.set_base[sg.rid];
 #pragma unroll
@@ -853,9 +929,6 @@ __global__ __launch_bounds__(BLOCK) void k_scan_down(uint32_t* x, uint32_t n, co
 __device__ void dev_scatter(const Work& w, const Params& p, int cur, uint32_t t, uint32_t n_dist,
                             SmScatter& sm) {
     auto& WC = sm.WC;
-    uint32_t* GB = sm.GB;
-    uint32_t* BS = sm.BS;
-    uint8_t* XR = sm.XR;
     const uint32_t tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const uint32_t si = w.tile_seg[cur][t];
     if (si >= n_dist) {
@@ -877,13 +950,12 @@ __device__ void dev_scatter(const Work& w, const Params& p, int cur, uint32_t t,
         for (uint32_t q = 0; q < WAVES; ++q) WC[q][b] = 0;
     }
     const uint8_t* gr = w.tree_r[cur] + sg.tree_off;
-    for (uint32_t j = tid; j < v; j += BLOCK) XR[j] = gr[level_index(j, d) - 1];
     __syncthreads();
 
     // phase 1: ranks within the wave's chunk
     constexpr uint32_t CH = TILE / WAVES;
     const uint32_t cbeg = start + wv * CH;
-    uint32_t packed[IPT];  // bucket << 16 | rank
+    uint32_t rank2[IPT / 2];  // two 16-bit ranks per register (bucket ids are re-read in phase 3)
 #pragma unroll
     for (uint32_t it = 0; it < IPT; ++it) {
         uint32_t i = cbeg + it * 64 + lane;
@@ -901,19 +973,19 @@ __device__ void dev_scatter(const Work& w, const Params& p, int cur, uint32_t t,
         uint32_t old = 0;
         if (valid && lane == leader) old = atomicAdd(&WC[wv][b], (uint32_t)__builtin_popcountll(peers));
         old = __shfl(old, (int)leader, 64);
-        packed[it] = (b << 16) | (old + below);
+        const uint32_t rk = old + below;
+        if (it & 1) rank2[it >> 1] |= rk << 16;
+        else rank2[it >> 1] = rk;
     }
     __syncthreads();
-    // phase 2: per-bucket offsets of the tile and of each wave
+    // phase 2: absolute write base of every (wave, bucket) of the tile
     const uint32_t* sc = w.cnt[cur] + sg.cnt_off;
     const uint32_t s0 = sc[0];
     for (uint32_t b = tid; b < k; b += BLOCK) {
-        GB[b] = sg.begin + sc[(size_t)b * T + ti] - s0;
-        BS[b] = sg.begin + sc[(size_t)b * T] - s0;
-        uint32_t run = 0;
+        uint32_t run = sg.begin + sc[(size_t)b * T + ti] - s0;
 #pragma unroll
         for (uint32_t q = 0; q < WAVES; ++q) {
-            uint32_t c = WC[q][b];
+            const uint32_t c = WC[q][b];
             WC[q][b] = run;
             run += c;
         }
@@ -929,14 +1001,14 @@ __device__ void dev_scatter(const Work& w, const Params& p, int cur, uint32_t t,
         const uint32_t i = cbeg + it * 64 + lane;
         if (i >= end) continue;
         Elem e = in[i];
-        const uint32_t b = packed[it] >> 16, rank = packed[it] & 0xFFFFu;
-        const uint32_t pos = GB[b] + WC[wv][b] + rank;
+        const uint32_t b = w.bkt[i], rank = (rank2[it >> 1] >> (16 * (it & 1))) & 0xFFFFu;
+        const uint32_t pos = WC[wv][b] + rank;
         if (pos < sg.begin || pos >= seg_end) { raise_err(w, ERR_BOUNDS); continue; }
         if (b & 1u) {
-            const uint32_t rx = XR[b >> 1];
+            const uint32_t rx = gr[level_index(b >> 1, d) - 1];
             if (rx < W) {  // identical strings ending inside this word: final
                 p.perm[pos] = e.idx - obase;
-                if (pos != BS[b]) p.lcp[pos] = sg.depth + rx;
+                if (pos != sg.begin + sc[(size_t)b * T] - s0) p.lcp[pos] = sg.depth + rx;
                 continue;
             }
             e.key = gather_key(p.chars, p.offsets[e.idx], sg.depth + W, e.len);
@@ -1018,7 +1090,7 @@ __device__ void dev_children(const Work& w, const Params& p, int cur, uint32_t i
             continue;
         }
         if (cnt <= p.base_max) {
-            const int cls = cnt <= CLS_MAX[0] ? 0 : (cnt <= CLS_MAX[1] ? 1 : 2);
+            const int cls = size_class(cnt);
             atomicAdd(&n_cls[cls], 1u);
             atomicAdd(&s_cls[cls], cnt);
             atomicMax(&max_d, depth);
@@ -1050,7 +1122,7 @@ __device__ void dev_children(const Work& w, const Params& p, int cur, uint32_t i
             if (q < w.caps.pend) w.pend[q] = make_uint2(pos, sg.rid);
         }
         if (depth == ~0u || cnt == 1 || cnt > p.base_max) continue;
-        const int cls = cnt <= CLS_MAX[0] ? 0 : (cnt <= CLS_MAX[1] ? 1 : 2);
+        const int cls = size_class(cnt);
         const uint32_t q = slot_cls[cls] + atomicAdd(&cur_cls[cls], 1u);
         if (q < w.caps.base[cls]) w.base[cls][nxt][q] = BaseSeg{pos, cnt, depth, sg.rid};
     }
@@ -1171,8 +1243,8 @@ __global__ __launch_bounds__(BLOCK) void k_persist(Work w, Params p, const uint3
             break;
         }
         const uint32_t nb0 = (c.n_base[0] + WAVES - 1) / WAVES, nb1 = (c.n_base[1] + WAVES - 1) / WAVES;
-        const uint32_t nb2 = c.n_base[2];
-        const uint32_t nitems = nb0 + nb1 + nb2 + c.n_dist;
+        const uint32_t nb2 = (c.n_base[2] + WAVES - 1) / WAVES, nb3 = c.n_base[3];
+        const uint32_t nitems = nb0 + nb1 + nb2 + nb3 + c.n_dist;
         if (nitems == 0) break;
         if (bid == 0 && tid < sizeof(Counts) / 4)
             __hip_atomic_store((uint32_t*)&w.ctl->cl[cur ^ 1].c + tid, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -1180,9 +1252,10 @@ __global__ __launch_bounds__(BLOCK) void k_persist(Work w, Params p, const uint3
         for (uint32_t it = bid; it < nitems; it += G) {
             __syncthreads();
             if (it < nb0) dev_base_wave<1>(w, p, cur, 0, it, c.n_base[0], sm.wave);
-            else if (it < nb0 + nb1) dev_base_wave<4>(w, p, cur, 1, it - nb0, c.n_base[1], sm.wave);
-            else if (it < nb0 + nb1 + nb2) dev_base_wg(w, p, cur, it - nb0 - nb1, sm.base);
-            else dev_sample(w, p, cur, it - nb0 - nb1 - nb2, sm.sample);
+            else if (it < nb0 + nb1) dev_base_wave<2>(w, p, cur, 1, it - nb0, c.n_base[1], sm.wave);
+            else if (it < nb0 + nb1 + nb2) dev_base_wave<4>(w, p, cur, 2, it - nb0 - nb1, c.n_base[2], sm.wave);
+            else if (it < nb0 + nb1 + nb2 + nb3) dev_base_wg(w, p, cur, it - nb0 - nb1 - nb2, sm.base);
+            else dev_sample(w, p, cur, it - nb0 - nb1 - nb2 - nb3, sm.sample);
         }
         if (c.n_dist == 0) break;
         if (!grid_sync(w, G, gen, &s_ok)) return;
@@ -1302,7 +1375,9 @@ hipError_t launch_base(const Work& w, const Params& p, int cur, int cls, uint32_
     if (cls == 0)
         hipLaunchKernelGGL(k_base_wave<1>, dim3(blocks_for(n_base, WAVES)), dim3(BLOCK), 0, s, w, p, cur, 0, n_base);
     else if (cls == 1)
-        hipLaunchKernelGGL(k_base_wave<4>, dim3(blocks_for(n_base, WAVES)), dim3(BLOCK), 0, s, w, p, cur, 1, n_base);
+        hipLaunchKernelGGL(k_base_wave<2>, dim3(blocks_for(n_base, WAVES)), dim3(BLOCK), 0, s, w, p, cur, 1, n_base);
+    else if (cls == 2)
+        hipLaunchKernelGGL(k_base_wave<4>, dim3(blocks_for(n_base, WAVES)), dim3(BLOCK), 0, s, w, p, cur, 2, n_base);
     else
         hipLaunchKernelGGL(k_base, dim3(n_base), dim3(BLOCK), 0, s, w, p, cur);
     return hipGetLastError();
