@@ -138,11 +138,20 @@ def run_batch(args):
     results["batched_graph"] = timed(graph_run, args.steps)
     outs["batched_graph"] = (perm.clone(), lcp.clone())
     g.close()
+    # autotuned batched form: the tuner times its grid on this batch, then
+    # the chosen configuration is timed like the others
+    tctx = ss.Context(0)
+    t_a = time.perf_counter()
+    tuned_cfg, tuned_ms, _, _ = tctx.autotune(chars, offs, sbd, perm, lcp, reps=2, stream=stream)
+    tune_s = time.perf_counter() - t_a
+    results["batched_autotuned"] = timed(lambda: tctx.sort_batch(chars, offs, sbd, perm, lcp, stream), args.steps)
+    outs["batched_autotuned"] = (perm.clone(), lcp.clone())
     ref = outs["per_set_launches"]
     identical = all(torch.equal(v[0], ref[0]) and torch.equal(v[1], ref[1]) for v in outs.values())
     for k, v in results.items():
         print(f"[bench] {k:22s} {v * 1e3:9.2f} ms  {N / v / 1e9:8.2f} G chars/s", file=sys.stderr, flush=True)
-    best = min(("batched_levels", "batched_persistent", "batched_graph"), key=lambda k: results[k])
+    best = min(("batched_levels", "batched_persistent", "batched_graph", "batched_autotuned"),
+               key=lambda k: results[k])
     out = {
         "metric": METRIC,
         "value": N / results[best],
@@ -160,6 +169,7 @@ def run_batch(args):
         "batched_vs_per_set": results["per_set_launches"] / results[best],
         "ms": {k: v * 1e3 for k, v in results.items()},
         "outputs_identical": identical,
+        "autotune": {"config": tuned_cfg, "tuner_median_ms": tuned_ms, "tuning_s": tune_s},
     }
     print(json.dumps(out), flush=True)
 

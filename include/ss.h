@@ -149,6 +149,28 @@ void ss_graph_destroy(ss_graph* graph);
  * last sort (sticky, as for the other entry points). */
 ss_status ss_ctx_sync(ss_ctx* ctx, void* stream);
 
+/* Autotuner (variant tuning of section 4.4 / the evaluation's tuned
+ * variants; results never depend on the configuration).  Times candidate
+ * configurations on the given input -- a grid over max_log_splitters
+ * {8,9,10} x bucket_target {32,64,128} x base_max {512,1024} in the
+ * level-by-level form, then the persistent form with the winner's
+ * parameters -- as the median of `reps` sorts after one warm-up each, and
+ * keeps the fastest: it becomes the context's configuration and is cached
+ * per process under (device, floor(log2) of n, of the character count and
+ * of the set count).  With use_cache != 0 a cached entry for the signature
+ * is applied without timing.  Afterwards perm_out / lcp_out hold the sort's
+ * result (identical under every configuration).  set_begin == NULL with
+ * num_sets == 1 tunes the single-set sort; otherwise the arguments are those
+ * of ss_sort_batch.  Candidates that fail (e.g. beyond the workspace cap)
+ * are skipped; SS_INTERNAL if all fail (the configuration is then left as
+ * it was).  best / best_ms (may be NULL) receive the chosen configuration
+ * and its median milliseconds.  Synchronizes `stream`. */
+ss_status ss_autotune(ss_ctx* ctx, const uint8_t* chars, const uint64_t* offsets, uint32_t n,
+                      const uint32_t* set_begin, uint32_t num_sets, uint32_t* perm_out, uint32_t* lcp_out,
+                      void* stream, uint32_t reps, int use_cache, ss_config* best, double* best_ms);
+/* Forgets every cached autotuning result of the process. */
+void ss_autotune_clear_cache(void);
+
 /* ---- serving: continuous batching under an HBM budget ------------------
  * A server owns one device (its own stream and worker thread) and a fixed
  * device arena sized by `hbm_budget` bytes: character storage plus index
@@ -221,6 +243,9 @@ typedef struct {
     uint32_t pending_lcps;
     uint32_t max_depth;
     uint32_t base_rounds;   /* refinement rounds (depth + 8) run inside base cases */
+    uint32_t base_segments_by_class[4]; /* base-case segments of <= 64, <= 128,
+                                           <= 256 and <= base_max strings */
+    uint64_t base_strings_by_class[4];  /* strings in those segments */
 } ss_stats;
 ss_status ss_get_stats(const ss_ctx* ctx, ss_stats* st);
 

@@ -40,7 +40,8 @@ class Stats(ctypes.Structure):
     _fields_ = [("levels", ctypes.c_uint32), ("dist_segments", ctypes.c_uint32),
                 ("dist_tiles", ctypes.c_uint32), ("base_segments", ctypes.c_uint32),
                 ("pending_lcps", ctypes.c_uint32), ("max_depth", ctypes.c_uint32),
-                ("base_rounds", ctypes.c_uint32)]
+                ("base_rounds", ctypes.c_uint32), ("base_segments_by_class", ctypes.c_uint32 * 4),
+                ("base_strings_by_class", ctypes.c_uint64 * 4)]
 
 
 class KernelTime(ctypes.Structure):
@@ -101,6 +102,9 @@ def lib():
             "ss_get_kernel_times": (i32, [vp, ctypes.POINTER(KernelTime), u32, ctypes.POINTER(u32)]),
             "ss_reset_kernel_times": (None, [vp]),
             "ss_hbm_copy": (i32, [vp, vp, ctypes.c_size_t, vp]),
+            "ss_autotune": (i32, [vp, vp, vp, u32, vp, u32, vp, vp, vp, u32, i32, ctypes.POINTER(Config),
+                                  ctypes.POINTER(ctypes.c_double)]),
+            "ss_autotune_clear_cache": (None, []),
             "ss_host_key": (u64, [vp, u64, u64, ctypes.POINTER(u32)]),
             "ss_host_level_index": (u32, [u32, u32]),
             "ss_host_inorder_index": (u32, [u32, u32]),
@@ -186,7 +190,11 @@ class Context:
     def stats(self) -> dict:
         s = Stats()
         _check(lib().ss_get_stats(self._h, ctypes.byref(s)), "ss_get_stats")
-        return {f: getattr(s, f) for f, _ in Stats._fields_}
+        out = {}
+        for f, _ in Stats._fields_:
+            v = getattr(s, f)
+            out[f] = list(v) if isinstance(v, ctypes.Array) else v
+        return out
 
     def set_profiling(self, on: bool = True):
         _check(lib().ss_set_profiling(self._h, 1 if on else 0), "ss_set_profiling")
@@ -263,6 +271,38 @@ class Context:
                                  _stream_ptr(stream))
         _check(st, "ss_sort_batch")
         return perm, lcp
+
+
+    def autotune(self, chars, offsets, set_begin=None, perm=None, lcp=None, reps=3, use_cache=True,
+                 stream=None):
+        """Times candidate configurations on this input (ss_autotune), keeps
+        the fastest as this context's configuration and returns
+        (config dict, median ms, perm, lcp); perm/lcp hold the result."""
+        _check_inputs(chars, offsets)
+        n = offsets.numel() - 1
+        if set_begin is None:
+            sb, num_sets = None, 1
+        else:
+            if not set_begin.is_cuda or set_begin.dtype not in (torch.int32, torch.uint32):
+                raise TypeError("set_begin must be an int32/uint32 device tensor")
+            sb, num_sets = ctypes.c_void_p(set_begin.data_ptr()), set_begin.numel() - 1
+        if perm is None:
+            perm = torch.empty(n, dtype=torch.int32, device=chars.device)
+        if lcp is None:
+            lcp = torch.empty(n, dtype=torch.int32, device=chars.device)
+        best = Config()
+        ms = ctypes.c_double(0.0)
+        st = lib().ss_autotune(self._h, ctypes.c_void_p(chars.data_ptr()), ctypes.c_void_p(offsets.data_ptr()), n,
+                               sb, num_sets, ctypes.c_void_p(perm.data_ptr()), ctypes.c_void_p(lcp.data_ptr()),
+                               _stream_ptr(stream), reps, 1 if use_cache else 0, ctypes.byref(best),
+                               ctypes.byref(ms))
+        _check(st, "ss_autotune")
+        cfg = {f: int(getattr(best, f)) for f, _ in Config._fields_}
+        return cfg, ms.value, perm, lcp
+
+
+def autotune_clear_cache():
+    lib().ss_autotune_clear_cache()
 
 
 class Graph:

@@ -11,6 +11,7 @@
 #include <memory>
 #include <mutex>
 #include <thread>
+#include <tuple>
 #include <unordered_map>
 #include <vector>
 
@@ -68,6 +69,7 @@ struct ss_graph {
 namespace {
 
 constexpr uint32_t MAX_LEVELS = 1u << 17;
+static_assert(NCLS == 4, "ss_stats reports four base-case classes");
 
 void clamp_config(ss_config* c) {
     c->max_log_splitters = std::min<uint32_t>(std::max<uint32_t>(c->max_log_splitters, 1), MAX_LOGV);
@@ -293,11 +295,15 @@ ss_status run_sort(ss_ctx* ctx, const uint8_t* chars, const uint64_t* offsets, u
     for (;;) {
         if ((st = read_ctl(ctx, s)) != SS_OK) return st;
         if (ctx->host_ctl->err) return device_error_status(ctx->host_ctl->err);
-        const Counts c = ctx->host_ctl->cl[cur].c;
+        const Counts c = counts_of(ctx->host_ctl->cl[cur]);
         ctx->stats.levels = level + 1;
         ctx->stats.dist_segments += c.n_dist;
         ctx->stats.dist_tiles += c.n_tiles;
-        for (int q = 0; q < NCLS; ++q) ctx->stats.base_segments += c.n_base[q];
+        for (int q = 0; q < NCLS; ++q) {
+            ctx->stats.base_segments += c.n_base[q];
+            ctx->stats.base_segments_by_class[q] += c.n_base[q];
+            ctx->stats.base_strings_by_class[q] += c.base_strings[q];
+        }
         ctx->stats.max_depth = std::max(ctx->stats.max_depth, c.max_depth);
         if ((st = enqueue_level(ctx, w, p, cur, c, s)) != SS_OK) return st;
         if (c.n_dist == 0) break;
@@ -510,6 +516,130 @@ ss_status ss_ctx_sync(ss_ctx* ctx, void* stream) {
         return st;
     }
     return SS_OK;
+}
+
+namespace {
+
+// Autotuner state: the best configuration found per (device, workload
+// signature).  The signature buckets n, the character count and the set
+// count by powers of two, so workloads of about the same shape share an
+// entry.
+struct TuneKey {
+    int device;
+    uint32_t log_n, log_chars, log_sets;
+    bool operator<(const TuneKey& o) const {
+        return std::tie(device, log_n, log_chars, log_sets) < std::tie(o.device, o.log_n, o.log_chars, o.log_sets);
+    }
+};
+struct TuneEntry {
+    ss_config cfg;
+    double ms;
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, TuneEntry> g_tune;
+
+uint32_t ilog2_u64(uint64_t x) { return x ? 63u - (uint32_t)__builtin_clzll(x) : 0u; }
+
+// Median wall time of `reps` sorts under `c` on `s` (after one warm-up);
+// negative on failure.
+double time_config(ss_ctx* ctx, const ss_config& c, const uint8_t* chars, const uint64_t* offsets, uint32_t n,
+                   const uint32_t* set_begin, uint32_t num_sets, uint32_t* perm, uint32_t* lcp, hipStream_t s,
+                   uint32_t reps, hipEvent_t e0, hipEvent_t e1) {
+    if (ss_set_config(ctx, &c) != SS_OK) return -1.0;
+    if (sort_checked(ctx, chars, offsets, n, set_begin, num_sets, perm, lcp, s) != SS_OK) return -1.0;
+    if (ss_ctx_sync(ctx, s) != SS_OK) return -1.0;
+    std::vector<double> t;
+    for (uint32_t r = 0; r < reps; ++r) {
+        if (hipEventRecord(e0, s) != hipSuccess) return -1.0;
+        if (sort_checked(ctx, chars, offsets, n, set_begin, num_sets, perm, lcp, s) != SS_OK) return -1.0;
+        if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) return -1.0;
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) return -1.0;
+        t.push_back(ms);
+    }
+    if (ss_ctx_sync(ctx, s) != SS_OK) return -1.0;
+    std::sort(t.begin(), t.end());
+    return t[t.size() / 2];
+}
+
+}  // namespace
+
+ss_status ss_autotune(ss_ctx* ctx, const uint8_t* chars, const uint64_t* offsets, uint32_t n,
+                      const uint32_t* set_begin, uint32_t num_sets, uint32_t* perm_out, uint32_t* lcp_out,
+                      void* stream, uint32_t reps, int use_cache, ss_config* best, double* best_ms) {
+    if (!ctx || !offsets || !perm_out || !lcp_out || n == 0) return SS_INVALID_ARG;
+    if (set_begin ? num_sets == 0 : num_sets != 1) return SS_INVALID_ARG;
+    if (n > 0xFFFFFFFEu) return SS_LIMIT;
+    reps = std::max<uint32_t>(1, std::min<uint32_t>(reps, 50));
+    hipStream_t s = (hipStream_t)stream;
+    int cur_dev = -1;
+    SS_TRY(hipGetDevice(&cur_dev));
+    if (cur_dev != ctx->device) SS_TRY(hipSetDevice(ctx->device));
+    uint64_t total_chars = 0;
+    SS_TRY(hipMemcpyAsync(&total_chars, offsets + n, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+    SS_TRY(hipStreamSynchronize(s));
+    const TuneKey key{ctx->device, ilog2_u64(n), ilog2_u64(total_chars), ilog2_u64(num_sets)};
+    if (use_cache) {
+        std::lock_guard<std::mutex> lock(g_tune_mu);
+        auto it = g_tune.find(key);
+        if (it != g_tune.end()) {
+            ss_set_config(ctx, &it->second.cfg);
+            if (best) *best = it->second.cfg;
+            if (best_ms) *best_ms = it->second.ms;
+            return sort_checked(ctx, chars, offsets, n, set_begin, num_sets, perm_out, lcp_out, stream);
+        }
+    }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    SS_TRY(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return SS_HIP_ERROR;
+    }
+    const ss_config start = ctx->cfg;
+    ss_config top = start;
+    double top_ms = -1.0;
+    auto consider = [&](const ss_config& c) {
+        double ms = time_config(ctx, c, chars, offsets, n, set_begin, num_sets, perm_out, lcp_out, s, reps, e0, e1);
+        if (ms < 0) {
+            ctx->sticky = SS_OK;  // a failed candidate (e.g. workspace cap) is skipped
+            return;
+        }
+        if (top_ms < 0 || ms < top_ms) {
+            top_ms = ms;
+            top = c;
+        }
+    };
+    // stage 1: the level-by-level form over splitter count, bucket target
+    // and base-case size; stage 2: the persistent form with the winner's
+    // parameters
+    for (uint32_t d : {8u, 9u, 10u})
+        for (uint32_t bt : {32u, 64u, 128u})
+            for (uint32_t bm : {512u, 1024u}) consider(ss_config{d, bt, bm, 0});
+    if (top_ms >= 0) {
+        ss_config pc = top;
+        pc.persistent = 1;
+        consider(pc);
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (top_ms < 0) {
+        ss_set_config(ctx, &start);
+        return SS_INTERNAL;
+    }
+    ss_set_config(ctx, &top);
+    {
+        std::lock_guard<std::mutex> lock(g_tune_mu);
+        g_tune[key] = TuneEntry{top, top_ms};
+    }
+    if (best) *best = top;
+    if (best_ms) *best_ms = top_ms;
+    // the outputs hold the result of the chosen configuration
+    return sort_checked(ctx, chars, offsets, n, set_begin, num_sets, perm_out, lcp_out, stream);
+}
+
+void ss_autotune_clear_cache(void) {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    g_tune.clear();
 }
 
 ss_status ss_get_last_error(const ss_ctx* ctx) { return ctx ? ctx->sticky : SS_INVALID_ARG; }
@@ -836,7 +966,7 @@ void server_loop(ss_server* S) {
         if (st == SS_OK) st = read_ctl(ctx, S->stream);
         if (st == SS_OK && ctx->host_ctl->err) st = device_error_status(ctx->host_ctl->err);
         if (st == SS_OK) {
-            const Counts c = ctx->host_ctl->cl[S->cur].c;
+            const Counts c = counts_of(ctx->host_ctl->cl[S->cur]);
             st = enqueue_level(ctx, S->w, S->p, S->cur, c, S->stream);
             S->cur ^= 1;
         }

@@ -56,15 +56,49 @@ struct Counts {
     uint32_t dist_strings;        // strings in the distribution segments of the level
 };
 
+// Device-side form of a level's counts: every counter word on its own
+// 128-byte line (atomics on different lines proceed in parallel), and
+// counters that are always advanced together share one 64-bit word, so one
+// atomic reserves both.
+struct alignas(128) CLine {
+    unsigned long long v;
+    uint32_t pad[30];
+};
+struct CountLines {
+    CLine dist;        // n_dist | dist_strings << 32
+    CLine tree_tiles;  // n_tree | n_tiles << 32
+    CLine cnt;         // n_cnt
+    CLine depth;       // max_depth
+    CLine base[NCLS];  // n_base[q] | base_strings[q] << 32
+};
+constexpr uint32_t COUNT_LINES = sizeof(CountLines) / sizeof(CLine);
+
+__host__ __device__ inline Counts counts_of(const unsigned long long* v) {
+    Counts c{};
+    c.n_dist = (uint32_t)v[0];
+    c.dist_strings = (uint32_t)(v[0] >> 32);
+    c.n_tree = (uint32_t)v[1];
+    c.n_tiles = (uint32_t)(v[1] >> 32);
+    c.n_cnt = (uint32_t)v[2];
+    c.max_depth = (uint32_t)v[3];
+    for (int q = 0; q < NCLS; ++q) {
+        c.n_base[q] = (uint32_t)v[4 + q];
+        c.base_strings[q] = (uint32_t)(v[4 + q] >> 32);
+    }
+    return c;
+}
+inline Counts counts_of(const CountLines& l) {
+    unsigned long long v[COUNT_LINES];
+    const CLine* L = &l.dist;
+    for (uint32_t i = 0; i < COUNT_LINES; ++i) v[i] = L[i].v;
+    return counts_of(v);
+}
+
 // Device-side control block.  Every group of fields that kernels update
 // with atomics sits on its own 128-byte line, so the atomics never share a
 // line with data other waves read.
-struct alignas(128) Counts128 {
-    Counts c;
-    uint32_t pad[32 - sizeof(Counts) / 4];
-};
 struct Ctl {
-    Counts128 cl[2];
+    CountLines cl[2];
     uint32_t n_pend;
     uint32_t n_pend2;      // survivors of a pending-list filter (serving)
     uint32_t pad0[30];

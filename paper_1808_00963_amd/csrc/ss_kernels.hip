@@ -59,6 +59,11 @@ __device__ __forceinline__ uint32_t lcp_from(const uint8_t* chars, uint64_t oa, 
 }
 
 __device__ __forceinline__ void raise_err(const Work& w, uint32_t bits) { atomicOr(&w.ctl->err, bits); }
+// Two counters in one 64-bit atomic word (low, high); neither half of a
+// level's counters reaches 2^32, so no carry crosses.
+__device__ __forceinline__ unsigned long long pack2(uint32_t lo, uint32_t hi) {
+    return (unsigned long long)lo | ((unsigned long long)hi << 32);
+}
 
 // Block -> tile mapping that keeps consecutive tiles on the same XCD (work
 // groups are dispatched to the 8 XCDs round robin): the tiles of XCD x are a
@@ -84,12 +89,11 @@ __device__ void emit_segment(const Work& w, const Params& p, int nxt, const Elem
         if (w.remaining) atomicSub(&w.remaining[rid], 1u);
         return;
     }
-    Counts* c = &w.ctl->cl[nxt].c;
-    atomicMax(&c->max_depth, depth);
+    CountLines* c = &w.ctl->cl[nxt];
+    atomicMax(&c->depth.v, (unsigned long long)depth);
     if (size <= p.base_max) {
         const int cls = size_class(size);
-        uint32_t slot = atomicAdd(&c->n_base[cls], 1u);
-        atomicAdd(&c->base_strings[cls], size);
+        const uint32_t slot = (uint32_t)atomicAdd(&c->base[cls].v, pack2(1u, size));
         if (slot >= w.caps.base[cls]) { raise_err(w, ERR_CAPACITY); return; }
         w.base[cls][nxt][slot] = BaseSeg{begin, size, depth, rid};
         return;
@@ -97,11 +101,10 @@ __device__ void emit_segment(const Work& w, const Params& p, int nxt, const Elem
     uint32_t logv = choose_logv(size, p.bucket_target, p.max_logv);
     uint32_t v = (1u << logv) - 1, k = 2 * v + 1;
     uint32_t T = (size + TILE - 1) / TILE;
-    uint32_t slot = atomicAdd(&c->n_dist, 1u);
-    atomicAdd(&c->dist_strings, size);
-    uint32_t toff = atomicAdd(&c->n_tree, v + 1);
-    uint32_t coff = atomicAdd(&c->n_cnt, k * T);
-    uint32_t tioff = atomicAdd(&c->n_tiles, T);
+    const uint32_t slot = (uint32_t)atomicAdd(&c->dist.v, pack2(1u, size));
+    const unsigned long long tt = atomicAdd(&c->tree_tiles.v, pack2(v + 1, T));
+    const uint32_t toff = (uint32_t)tt, tioff = (uint32_t)(tt >> 32);
+    const uint32_t coff = (uint32_t)atomicAdd(&c->cnt.v, (unsigned long long)(k * T));
     if (slot >= w.caps.dist || toff + v + 1 > w.caps.tree || coff + k * T > w.caps.cnt ||
         tioff + T > w.caps.tiles) {
         raise_err(w, ERR_CAPACITY);
@@ -160,10 +163,15 @@ struct SmWave {
 struct SmSample {
     uint64_t SK[2 << MAX_LOGV];
     uint32_t SR[2 << MAX_LOGV];
-    uint64_t TK[1 << MAX_LOGV];
-    uint32_t TR[1 << MAX_LOGV];
-    uint16_t NL[1 << MAX_LOGV];
-    uint16_t NH[1 << MAX_LOGV];
+    union {
+        uint64_t SA[2 << MAX_LOGV];  // sort records' second words (while sorting)
+        struct {
+            uint64_t TK[1 << MAX_LOGV];
+            uint32_t TR[1 << MAX_LOGV];
+            uint16_t NL[1 << MAX_LOGV];
+            uint16_t NH[1 << MAX_LOGV];
+        };
+    };
 };
 struct SmClassify {
     uint64_t TK[1 << MAX_LOGV];
@@ -174,8 +182,13 @@ struct SmScatter {
     uint32_t WC[WAVES][MAX_BUCKETS + 1];  // per-wave counts, then per-wave write bases
 };
 struct SmChildren {
+    uint32_t ST[MAX_BUCKETS + 1];  // bucket starts relative to the segment
     uint32_t n_cls[NCLS], s_cls[NCLS], slot_cls[NCLS], cur_cls[NCLS];
     uint32_t n_pend_l, slot_pend, cur_pend, max_d;
+    // distribution children: counts / sums, reserved bases, running offsets
+    uint32_t nd, sd, ntree, ncnt, ntile;
+    uint32_t bd, btree, bcnt, btile;
+    uint32_t cd, ctree, ccnt, ctile;
 };
 struct SmScan {
     uint32_t wt[16];
@@ -204,8 +217,8 @@ __global__ void k_reset(Work w) {
 }
 
 __global__ void k_zero_counts(Work w, int which) {
-    uint32_t* p = (uint32_t*)&w.ctl->cl[which].c;
-    for (uint32_t i = threadIdx.x; i < sizeof(Counts) / 4; i += blockDim.x) p[i] = 0;
+    CLine* L = &w.ctl->cl[which].dist;
+    for (uint32_t i = threadIdx.x; i < COUNT_LINES; i += blockDim.x) L[i].v = 0;
 }
 
 // Key gather at depth 0 for every string (Algorithm 4.1's chars_h with
@@ -428,49 +441,126 @@ __global__ __launch_bounds__(BLOCK) void k_base(Work w, Params p, int cur) {
 // base case for small segments: one wave per segment, data in registers
 // ---------------------------------------------------------------------------
 
-__device__ __forceinline__ bool rec_gt(uint64_t ka, uint64_t aa, uint64_t kb, uint64_t ab) {
-    return rec_greater(ka, aa, kb, ab);
+// Sort record of the register networks (wave base case, sample sort): two
+// words compared as one unsigned 128-bit number, so a single comparison
+// orders by (group, key, r, idx):
+//   hi = group(16) | key bits 63..16,   lo = key bits 15..0 | 0(12) | r(4) | idx(32).
+__device__ __forceinline__ void pr_pack(uint32_t grp, uint64_t key, uint32_t r, uint32_t idx, uint64_t& hi,
+                                        uint64_t& lo) {
+    hi = ((uint64_t)grp << 48) | (key >> 16);
+    lo = (key << 48) | ((uint64_t)r << 32) | (uint64_t)idx;
+}
+__device__ __forceinline__ uint64_t pr_key(uint64_t hi, uint64_t lo) { return (hi << 16) | (lo >> 48); }
+__device__ __forceinline__ uint32_t pr_grp(uint64_t hi) { return (uint32_t)(hi >> 48); }
+__device__ __forceinline__ uint32_t pr_r(uint64_t lo) { return (uint32_t)(lo >> 32) & 0xFu; }
+__device__ __forceinline__ uint32_t pr_idx(uint64_t lo) { return (uint32_t)lo; }
+__device__ __forceinline__ uint64_t pr_regroup(uint64_t hi, uint32_t grp) {
+    return (hi & 0x0000FFFFFFFFFFFFull) | ((uint64_t)grp << 48);
+}
+__device__ __forceinline__ bool pr_gt(uint64_t ah, uint64_t al, uint64_t bh, uint64_t bl) {
+    return ah > bh || (ah == bh && al > bl);
 }
 
-// Bitonic sorting network over the 64*E records of one wave, blocked layout
-// (lane holds records lane*E .. lane*E+E-1): partners inside a lane are
-// exchanged in registers, partners in other lanes through cross-lane
-// shuffles.  No LDS, no barriers.
+// Value of lane (lane ^ J) of a wave, without the LDS crossbar: DPP row
+// permutations for J < 16 (quad_perm for 1 and 2; i^4 = half_mirror then
+// quad reverse; i^8 = row mirror then half mirror) and the gfx950 row-swap
+// permutes for 16 and 32 (after the swap the two results hold the even and
+// the odd rows / halves; each lane picks the one of its partner).
+template <uint32_t J>
+__device__ __forceinline__ uint32_t xlane32(uint32_t x) {
+    static_assert(J == 1 || J == 2 || J == 4 || J == 8 || J == 16 || J == 32, "lane distance");
+    const int v = (int)x;
+    if constexpr (J == 1) {
+        return (uint32_t)__builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, false);  // quad_perm [1,0,3,2]
+    } else if constexpr (J == 2) {
+        return (uint32_t)__builtin_amdgcn_update_dpp(0, v, 0x4E, 0xF, 0xF, false);  // quad_perm [2,3,0,1]
+    } else if constexpr (J == 4) {
+        const int y = __builtin_amdgcn_update_dpp(0, v, 0x141, 0xF, 0xF, false);    // row_half_mirror
+        return (uint32_t)__builtin_amdgcn_update_dpp(0, y, 0x1B, 0xF, 0xF, false);  // quad_perm [3,2,1,0]
+    } else if constexpr (J == 8) {
+        const int y = __builtin_amdgcn_update_dpp(0, v, 0x140, 0xF, 0xF, false);     // row_mirror
+        return (uint32_t)__builtin_amdgcn_update_dpp(0, y, 0x141, 0xF, 0xF, false);  // row_half_mirror
+    } else if constexpr (J == 16) {
+        const auto r = __builtin_amdgcn_permlane16_swap(x, x, false, false);
+        return (__lane_id() & 16) ? r[0] : r[1];
+    } else {
+        const auto r = __builtin_amdgcn_permlane32_swap(x, x, false, false);
+        return (__lane_id() & 32) ? r[0] : r[1];
+    }
+}
+template <uint32_t J>
+__device__ __forceinline__ uint64_t xlane64(uint64_t x) {
+    return (uint64_t)xlane32<J>((uint32_t)x) | ((uint64_t)xlane32<J>((uint32_t)(x >> 32)) << 32);
+}
+__device__ __forceinline__ uint64_t xlane(uint64_t x, uint32_t lj) {
+    switch (lj) {  // lj is a compile-time constant at every call site after unrolling
+    case 1: return xlane64<1>(x);
+    case 2: return xlane64<2>(x);
+    case 4: return xlane64<4>(x);
+    case 8: return xlane64<8>(x);
+    case 16: return xlane64<16>(x);
+    default: return xlane64<32>(x);
+    }
+}
+
+// One compare-exchange stage (k, j) of a bitonic network over records in
+// blocked layout (lane holds records lane*E .. lane*E+E-1 of a block whose
+// first record has global index `base`): partners inside a lane are
+// exchanged in registers, partners in other lanes (j >= E) through
+// cross-lane shuffles.  Directions follow the global index, so blocks of
+// several waves can form one network.
 template <int E>
-__device__ __forceinline__ void wave_bitonic(uint64_t (&K)[E], uint64_t (&A)[E], uint32_t lane) {
+__device__ __forceinline__ void wave_stage(uint64_t (&K)[E], uint64_t (&A)[E], uint32_t lane, uint32_t base,
+                                           uint32_t k, uint32_t j) {
+    if (j < (uint32_t)E) {
 #pragma unroll
-    for (uint32_t k = 2; k <= 64u * E; k <<= 1) {
-#pragma unroll
-        for (uint32_t j = k >> 1; j > 0; j >>= 1) {
-            if (j < (uint32_t)E) {
-#pragma unroll
-                for (uint32_t r = 0; r < (uint32_t)E; ++r) {
-                    if ((r & j) == 0) {
-                        const uint32_t r2 = r | j;
-                        const uint32_t e = lane * E + r;
-                        const bool up = (e & k) == 0;
-                        if (rec_gt(K[r], A[r], K[r2], A[r2]) == up) {
-                            uint64_t tk = K[r]; K[r] = K[r2]; K[r2] = tk;
-                            uint64_t ta = A[r]; A[r] = A[r2]; A[r2] = ta;
-                        }
-                    }
-                }
-            } else {
-                const int lj = (int)(j / E);
-#pragma unroll
-                for (uint32_t r = 0; r < (uint32_t)E; ++r) {
-                    const uint32_t e = lane * E + r;
-                    uint64_t pk = __shfl_xor(K[r], lj, 64);
-                    uint64_t pa = __shfl_xor(A[r], lj, 64);
-                    const bool lower = (e & j) == 0;
-                    const bool up = (e & k) == 0;
-                    const bool keep_min = lower == up;
-                    const bool self_gt = rec_gt(K[r], A[r], pk, pa);
-                    if (self_gt == keep_min) { K[r] = pk; A[r] = pa; }
+        for (uint32_t r = 0; r < (uint32_t)E; ++r) {
+            if ((r & j) == 0) {
+                const uint32_t r2 = r | j;
+                const uint32_t e = base + lane * E + r;
+                const bool up = (e & k) == 0;
+                if (pr_gt(K[r], A[r], K[r2], A[r2]) == up) {
+                    uint64_t tk = K[r]; K[r] = K[r2]; K[r2] = tk;
+                    uint64_t ta = A[r]; A[r] = A[r2]; A[r2] = ta;
                 }
             }
         }
+    } else {
+        const uint32_t lj = j / E;
+#pragma unroll
+        for (uint32_t r = 0; r < (uint32_t)E; ++r) {
+            const uint32_t e = base + lane * E + r;
+            const uint64_t pk = xlane(K[r], lj);
+            const uint64_t pa = xlane(A[r], lj);
+            const bool lower = (e & j) == 0;
+            const bool up = (e & k) == 0;
+            const bool keep_min = lower == up;
+            const bool self_gt = pr_gt(K[r], A[r], pk, pa);
+            if (self_gt == keep_min) { K[r] = pk; A[r] = pa; }
+        }
     }
+}
+
+// Bitonic sorting network over the 64*E records of one wave (merge sizes
+// k = 2 .. 64E).  No LDS, no barriers.  With base = 0 the block ends up
+// ascending; as part of a larger network (base = wave * 64E) blocks
+// alternate in direction.
+template <int E>
+__device__ __forceinline__ void wave_bitonic(uint64_t (&K)[E], uint64_t (&A)[E], uint32_t lane, uint32_t base = 0) {
+#pragma unroll
+    for (uint32_t k = 2; k <= 64u * E; k <<= 1) {
+#pragma unroll
+        for (uint32_t j = k >> 1; j > 0; j >>= 1) wave_stage<E>(K, A, lane, base, k, j);
+    }
+}
+
+// The stages j = 32E .. 1 of merge size k (> 64E) of a larger bitonic
+// network, on one wave's block.
+template <int E>
+__device__ __forceinline__ void wave_merge_tail(uint64_t (&K)[E], uint64_t (&A)[E], uint32_t lane, uint32_t base,
+                                                uint32_t k) {
+#pragma unroll
+    for (uint32_t j = 32u * E; j > 0; j >>= 1) wave_stage<E>(K, A, lane, base, k, j);
 }
 
 // One step of odd-even transposition sort over the blocked 64*E records:
@@ -495,7 +585,7 @@ __device__ __forceinline__ void wave_oddeven_step(uint64_t (&K)[E], uint64_t (&A
             pa = lower ? da : ua;
         }
         if (has) {
-            const bool take = lower ? rec_gt(K[0], A[0], pk, pa) : rec_gt(pk, pa, K[0], A[0]);
+            const bool take = lower ? pr_gt(K[0], A[0], pk, pa) : pr_gt(pk, pa, K[0], A[0]);
             if (take) { K[0] = pk; A[0] = pa; }
         }
         return;
@@ -506,7 +596,7 @@ __device__ __forceinline__ void wave_oddeven_step(uint64_t (&K)[E], uint64_t (&A
     if (!odd) {
 #pragma unroll
         for (uint32_t r = 0; r + 1 < (uint32_t)E; r += 2) {
-            if (rec_gt(K[r], A[r], K[r + 1], A[r + 1])) {
+            if (pr_gt(K[r], A[r], K[r + 1], A[r + 1])) {
                 uint64_t t = K[r]; K[r] = K[r + 1]; K[r + 1] = t;
                 t = A[r]; A[r] = A[r + 1]; A[r + 1] = t;
             }
@@ -515,13 +605,13 @@ __device__ __forceinline__ void wave_oddeven_step(uint64_t (&K)[E], uint64_t (&A
         uint64_t k0 = K[0], a0 = A[0], kl = K[E - 1], al = A[E - 1];
 #pragma unroll
         for (uint32_t r = 1; r + 1 < (uint32_t)E; r += 2) {
-            if (rec_gt(K[r], A[r], K[r + 1], A[r + 1])) {
+            if (pr_gt(K[r], A[r], K[r + 1], A[r + 1])) {
                 uint64_t t = K[r]; K[r] = K[r + 1]; K[r + 1] = t;
                 t = A[r]; A[r] = A[r + 1]; A[r + 1] = t;
             }
         }
-        if (lane < 63 && rec_gt(kl, al, nk, na)) { K[E - 1] = nk; A[E - 1] = na; }
-        if (lane > 0 && rec_gt(pk, pa, k0, a0)) { K[0] = pk; A[0] = pa; }
+        if (lane < 63 && pr_gt(kl, al, nk, na)) { K[E - 1] = nk; A[E - 1] = na; }
+        if (lane > 0 && pr_gt(pk, pa, k0, a0)) { K[0] = pk; A[0] = pa; }
     }
 }
 
@@ -553,8 +643,7 @@ __device__ void dev_base_wave(const Work& w, const Params& p, int cur, int cls, 
         const uint32_t e = lane * E + r;
         if (e < m) {
             Elem x = in[e];
-            K[r] = x.key;
-            A[r] = rec_pack(0, rem8(x.len, h), x.idx);
+            pr_pack(0, x.key, rem8(x.len, h), x.idx, K[r], A[r]);
         } else {
             K[r] = ~0ull;
             A[r] = ~0ull;
@@ -577,10 +666,11 @@ __device__ void dev_base_wave(const Work& w, const Params& p, int cur, int cls, 
             const uint32_t e = lane * E + r;
             const uint64_t pk = r == 0 ? pk0 : K[r - 1];
             const uint64_t pa = r == 0 ? pa0 : A[r - 1];
-            if (e > 0 && e < m && rec_grp(pa) == rec_grp(A[r])) {
-                const uint32_t r1 = rec_r(A[r]), r0 = rec_r(pa);
-                if (K[r] == pk && r1 == r0 && r1 == 8) tb |= 1u << r;
-                else LV[r] = D[r] + lcp_word(pk, r0, K[r], r1);
+            if (e > 0 && e < m && pr_grp(pk) == pr_grp(K[r])) {
+                // same group: equal words with r = 8 tie, else the LCP is final
+                const uint32_t r1 = pr_r(A[r]), r0 = pr_r(pa);
+                if (K[r] == pk && (A[r] >> 32) == (pa >> 32) && r1 == 8) tb |= 1u << r;
+                else LV[r] = D[r] + lcp_word(pr_key(pk, pa), r0, pr_key(K[r], A[r]), r1);
             }
         }
         if (__ballot(tb != 0) == 0) break;
@@ -614,7 +704,7 @@ __device__ void dev_base_wave(const Work& w, const Params& p, int cur, int cls, 
                 span = span > e - RS[r] + 1 ? span : e - RS[r] + 1;
             }
             if (e < m && RS[r] == e && (act >> r) & 1u) {  // run leader publishes its string
-                LIDX[wv][e] = (uint32_t)A[r];
+                LIDX[wv][e] = pr_idx(A[r]);
                 RMIN[wv][e] = ~0u;
             }
         }
@@ -632,7 +722,7 @@ __device__ void dev_base_wave(const Work& w, const Params& p, int cur, int cls, 
             OA[r] = 0;
             LA[r] = 0;
             if (!((act >> r) & 1u)) continue;
-            const uint32_t a = (uint32_t)A[r];
+            const uint32_t a = pr_idx(A[r]);
             const uint64_t oa = p.offsets[a];
             const uint32_t la = (uint32_t)(p.offsets[a + 1] - oa);
             OA[r] = oa;
@@ -650,14 +740,13 @@ __device__ void dev_base_wave(const Work& w, const Params& p, int cur, int cls, 
         for (uint32_t r = 0; r < (uint32_t)E; ++r) {
             const uint32_t e = lane * E + r;
             if (e >= m) continue;
-            const uint32_t idx = (uint32_t)A[r];
+            const uint32_t idx = pr_idx(A[r]);
             if ((act >> r) & 1u) {
                 const uint32_t d2 = RMIN[wv][RS[r]];
                 D[r] = d2;
-                K[r] = gather_key(p.chars, OA[r], d2, LA[r]);
-                A[r] = rec_pack(RS[r], rem8(LA[r], d2), idx);
+                pr_pack(RS[r], gather_key(p.chars, OA[r], d2, LA[r]), rem8(LA[r], d2), idx, K[r], A[r]);
             } else {
-                A[r] = rec_pack(e, rec_r(A[r]), idx);
+                K[r] = pr_regroup(K[r], e);
             }
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -669,7 +758,7 @@ __device__ void dev_base_wave(const Work& w, const Params& p, int cur, int cls, 
     for (uint32_t r = 0; r < (uint32_t)E; ++r) {
         const uint32_t e = lane * E + r;
         if (e < m) {
-            p.perm[sg.begin + e] = (uint32_t)A[r] - obase;
+            p.perm[sg.begin + e] = pr_idx(A[r]) - obase;
             if (e > 0) p.lcp[sg.begin + e] = LV[r];
         }
     }
@@ -691,8 +780,88 @@ __device__ __forceinline__ bool kr_gt(uint64_t ka, uint32_t ra, uint64_t kb, uin
     return ka > kb || (ka == kb && ra > rb);
 }
 
+// The regular sample of a segment (a = 2v+1 keys at evenly spaced
+// positions) sorted by (key, r) into SK / SR, padded with maxima to a power
+// of two.  The NB blocks of 64E records are sorted in registers by the
+// waves (block b by wave b mod WAVES); with several blocks they are merged
+// by a bitonic network whose cross-block stages go through LDS and whose
+// in-block stages run in registers again.
+template <int E>
+__device__ __forceinline__ void sample_sort(const Work& w, const Params& p, int cur, const Seg& sg, uint32_t a,
+                                            uint32_t NB, SmSample& sm) {
+    constexpr uint32_t R = 64u * E;  // records per block
+    const uint32_t tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const Elem* in = w.buf[cur];
+    uint64_t K[E], A[E];
+    for (uint32_t b = wv; b < NB; b += WAVES) {  // uniform per wave
+#pragma unroll
+        for (uint32_t r = 0; r < (uint32_t)E; ++r) {
+            const uint32_t j = b * R + lane * E + r;
+            K[r] = ~0ull;
+            A[r] = ~0ull;
+            if (j < a) {
+                const uint32_t pos = sg.begin + (uint32_t)(((2ull * j + 1) * sg.size) / (2ull * a));
+                const Elem e = in[pos];
+                pr_pack(0, e.key, rem8(e.len, sg.depth), j, K[r], A[r]);
+            }
+        }
+        wave_bitonic<E>(K, A, lane, NB > 1 ? b * R : 0u);
+#pragma unroll
+        for (uint32_t r = 0; r < (uint32_t)E; ++r) {
+            const uint32_t j = b * R + lane * E + r;
+            if (NB == 1) {
+                sm.SK[j] = pr_key(K[r], A[r]);
+                sm.SR[j] = A[r] == ~0ull ? 0xFFFFFFFFu : pr_r(A[r]);
+            } else {
+                sm.SK[j] = K[r];
+                sm.SA[j] = A[r];
+            }
+        }
+    }
+    __syncthreads();
+    if (NB == 1) return;
+    for (uint32_t k = 2 * R; k <= NB * R; k <<= 1) {
+        // cross-block stages (k, j >= R) over all NB*R records in LDS
+        for (uint32_t j = k >> 1; j >= R; j >>= 1) {
+            for (uint32_t t = tid; t < NB * R / 2; t += BLOCK) {
+                const uint32_t i = ((t & ~(j - 1)) << 1) | (t & (j - 1));
+                const uint32_t l = i | j;
+                const bool up = (i & k) == 0;
+                const uint64_t ki = sm.SK[i], kl = sm.SK[l], ai = sm.SA[i], al = sm.SA[l];
+                if (pr_gt(ki, ai, kl, al) == up) {
+                    sm.SK[i] = kl; sm.SK[l] = ki; sm.SA[i] = al; sm.SA[l] = ai;
+                }
+            }
+            __syncthreads();
+        }
+        // in-block stages: each wave on its own blocks
+        const bool last = k == NB * R;
+        for (uint32_t b = wv; b < NB; b += WAVES) {
+#pragma unroll
+            for (uint32_t r = 0; r < (uint32_t)E; ++r) {
+                const uint32_t j = b * R + lane * E + r;
+                K[r] = sm.SK[j];
+                A[r] = sm.SA[j];
+            }
+            wave_merge_tail<E>(K, A, lane, b * R, k);
+#pragma unroll
+            for (uint32_t r = 0; r < (uint32_t)E; ++r) {
+                const uint32_t j = b * R + lane * E + r;
+                if (last) {
+                    sm.SK[j] = pr_key(K[r], A[r]);
+                    sm.SR[j] = A[r] == ~0ull ? 0xFFFFFFFFu : pr_r(A[r]);
+                } else {
+                    sm.SK[j] = K[r];
+                    sm.SA[j] = A[r];
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
 // Algorithm 4.1 lines 1-5: a regular sample of alpha(v+1)-1 keys (alpha =
-// 2) is sorted in LDS; splitters are chosen by recursive middle selection
+// 2) is sorted (sample_sort); splitters are chosen by recursive middle selection
 // skipping duplicates (section 4.2.2, "Sampling"), level by level, directly
 // into the level-order tree; an empty sub-range repeats its parent's
 // splitter so the in-order splitter sequence stays sorted.
@@ -715,34 +884,8 @@ __device__ void dev_sample(const Work& w, const Params& p, int cur, uint32_t ite
         uint32_t* ts = w.tile_seg[cur] + sg.tile_off;
         for (uint32_t t = tid; t < T; t += BLOCK) ts[t] = item;
     }
-    const Elem* in = w.buf[cur];
-    for (uint32_t j = tid; j < P; j += BLOCK) {
-        if (j < a) {
-            uint32_t pos = sg.begin + (uint32_t)(((2ull * j + 1) * sg.size) / (2ull * a));
-            Elem e = in[pos];
-            SK[j] = e.key;
-            SR[j] = rem8(e.len, sg.depth);
-        } else {
-            SK[j] = ~0ull;
-            SR[j] = 0xFFFFFFFFu;
-        }
-    }
-    __syncthreads();
-    for (uint32_t k = 2; k <= P; k <<= 1) {
-        for (uint32_t j = k >> 1; j > 0; j >>= 1) {
-            for (uint32_t t = tid; t < (P >> 1); t += BLOCK) {
-                uint32_t i = ((t & ~(j - 1)) << 1) | (t & (j - 1));
-                uint32_t l = i | j;
-                bool up = (i & k) == 0;
-                uint64_t ki = SK[i], kl = SK[l];
-                uint32_t ri = SR[i], rl = SR[l];
-                if (kr_gt(ki, ri, kl, rl) == up) {
-                    SK[i] = kl; SK[l] = ki; SR[i] = rl; SR[l] = ri;
-                }
-            }
-            __syncthreads();
-        }
-    }
+    // blocks of 256 records (the last padded); P <= 2^(MAX_LOGV+1) = 8 blocks
+    sample_sort<4>(w, p, cur, sg, a, P > 256 ? P / 256 : 1u, sm);
     if (tid == 0) { NL[1] = 0; NH[1] = (uint16_t)a; }
     __syncthreads();
     for (uint32_t L = 0; L < d; ++L) {
@@ -1034,14 +1177,6 @@ __global__ __launch_bounds__(BLOCK) void k_scatter(Work w, Params p, int cur, ui
 // known (figure 4.7).  List slots for the children of the whole segment are
 // reserved with one global atomic per list (two passes over the buckets).
 __device__ void dev_children(const Work& w, const Params& p, int cur, uint32_t item, SmChildren& sm) {
-    uint32_t* n_cls = sm.n_cls;
-    uint32_t* s_cls = sm.s_cls;
-    uint32_t* slot_cls = sm.slot_cls;
-    uint32_t* cur_cls = sm.cur_cls;
-    uint32_t& n_pend_l = sm.n_pend_l;
-    uint32_t& slot_pend = sm.slot_pend;
-    uint32_t& cur_pend = sm.cur_pend;
-    uint32_t& max_d = sm.max_d;
     const Seg sg = w.dist[cur][item];
     const uint32_t tid = threadIdx.x, d = sg.logv, v = (1u << d) - 1, k = 2 * v + 1;
     const uint32_t T = (sg.size + TILE - 1) / TILE;
@@ -1050,18 +1185,25 @@ __device__ void dev_children(const Work& w, const Params& p, int cur, uint32_t i
         if (tid == 0) raise_err(w, ERR_BOUNDS);
         return;
     }
-    if (tid < NCLS) { n_cls[tid] = 0; s_cls[tid] = 0; cur_cls[tid] = 0; }
-    if (tid == 0) { n_pend_l = 0; cur_pend = 0; max_d = 0; }
-    __syncthreads();
+    if (tid < NCLS) { sm.n_cls[tid] = 0; sm.s_cls[tid] = 0; sm.cur_cls[tid] = 0; }
+    if (tid == 0) {
+        sm.n_pend_l = 0; sm.cur_pend = 0; sm.max_d = 0;
+        sm.nd = 0; sm.sd = 0; sm.ntree = 0; sm.ncnt = 0; sm.ntile = 0;
+        sm.cd = 0; sm.ctree = 0; sm.ccnt = 0; sm.ctile = 0;
+    }
+    // bucket starts: the first tile's scanned counter of every bucket
     const uint32_t* sc = w.cnt[cur] + sg.cnt_off;
     const uint32_t s0 = sc[0];
+    for (uint32_t b = tid; b < k; b += BLOCK) sm.ST[b] = sc[(size_t)b * T] - s0;
+    if (tid == 0) sm.ST[k] = sg.size;
+    __syncthreads();
     const uint8_t* gr = w.tree_r[cur] + sg.tree_off;
     const Elem* out = w.buf[nxt];
     const uint32_t obase = w.set_base[sg.rid];
     // bucket b -> (start, count, child depth); depth == ~0u: no child segment
     auto bucket = [&](uint32_t b, uint32_t& st, uint32_t& cnt, uint32_t& depth) {
-        st = sc[(size_t)b * T] - s0;
-        uint32_t en = (b + 1 < k) ? sc[(size_t)(b + 1) * T] - s0 : sg.size;
+        st = sm.ST[b];
+        const uint32_t en = sm.ST[b + 1];
         cnt = en > st ? en - st : 0u;
         if (en > sg.size) { raise_err(w, ERR_BOUNDS); cnt = 0; }
         depth = sg.depth;
@@ -1070,7 +1212,14 @@ __device__ void dev_children(const Work& w, const Params& p, int cur, uint32_t i
             else depth += W;
         }
     };
-    // pass 1: count per list, finish singletons, large children directly
+    // shape of a distribution child of `cnt` strings
+    auto dist_shape = [&](uint32_t cnt, uint32_t& logv, uint32_t& nv, uint32_t& nk, uint32_t& nt) {
+        logv = choose_logv(cnt, p.bucket_target, p.max_logv);
+        nv = 1u << logv;  // v + 1 tree slots
+        nk = 2 * nv - 1;  // 2v + 1 buckets
+        nt = (cnt + TILE - 1) / TILE;
+    };
+    // pass 1: count per list, finish singletons
     for (uint32_t b = tid; b < k; b += BLOCK) {
         uint32_t st, cnt, depth;
         bucket(b, st, cnt, depth);
@@ -1078,7 +1227,7 @@ __device__ void dev_children(const Work& w, const Params& p, int cur, uint32_t i
         const uint32_t pos = sg.begin + st;
         if (st > 0) {
             p.lcp[pos] = PENDING | sg.depth;
-            atomicAdd(&n_pend_l, 1u);
+            atomicAdd(&sm.n_pend_l, 1u);
         }
         if (depth == ~0u) {  // identical strings: final (written by the scatter)
             if (w.remaining) atomicSub(&w.remaining[sg.rid], cnt);
@@ -1089,26 +1238,45 @@ __device__ void dev_children(const Work& w, const Params& p, int cur, uint32_t i
             if (w.remaining) atomicSub(&w.remaining[sg.rid], 1u);
             continue;
         }
+        atomicMax(&sm.max_d, depth);
         if (cnt <= p.base_max) {
             const int cls = size_class(cnt);
-            atomicAdd(&n_cls[cls], 1u);
-            atomicAdd(&s_cls[cls], cnt);
-            atomicMax(&max_d, depth);
+            atomicAdd(&sm.n_cls[cls], 1u);
+            atomicAdd(&sm.s_cls[cls], cnt);
         } else {
-            emit_segment(w, p, nxt, out, pos, cnt, depth, sg.rid);
+            uint32_t logv, nv, nk, nt;
+            dist_shape(cnt, logv, nv, nk, nt);
+            atomicAdd(&sm.nd, 1u);
+            atomicAdd(&sm.sd, cnt);
+            atomicAdd(&sm.ntree, nv);
+            atomicAdd(&sm.ncnt, nk * nt);
+            atomicAdd(&sm.ntile, nt);
         }
     }
     __syncthreads();
+    // one reservation per list for the whole segment
     if (tid == 0) {
-        Counts* c = &w.ctl->cl[nxt].c;
+        CountLines* c = &w.ctl->cl[nxt];
         for (int q = 0; q < NCLS; ++q) {
-            slot_cls[q] = n_cls[q] ? atomicAdd(&c->n_base[q], n_cls[q]) : 0u;
-            if (s_cls[q]) atomicAdd(&c->base_strings[q], s_cls[q]);
-            if (slot_cls[q] + n_cls[q] > w.caps.base[q]) raise_err(w, ERR_CAPACITY);
+            sm.slot_cls[q] = sm.n_cls[q] ? (uint32_t)atomicAdd(&c->base[q].v, pack2(sm.n_cls[q], sm.s_cls[q])) : 0u;
+            if (sm.slot_cls[q] + sm.n_cls[q] > w.caps.base[q]) raise_err(w, ERR_CAPACITY);
         }
-        if (max_d) atomicMax(&c->max_depth, max_d);
-        slot_pend = n_pend_l ? atomicAdd(&w.ctl->n_pend, n_pend_l) : 0u;
-        if (slot_pend + n_pend_l > w.caps.pend) raise_err(w, ERR_CAPACITY);
+        if (sm.max_d) atomicMax(&c->depth.v, (unsigned long long)sm.max_d);
+        sm.slot_pend = sm.n_pend_l ? atomicAdd(&w.ctl->n_pend, sm.n_pend_l) : 0u;
+        if (sm.slot_pend + sm.n_pend_l > w.caps.pend) raise_err(w, ERR_CAPACITY);
+        sm.bd = sm.btree = sm.bcnt = sm.btile = 0;
+        if (sm.nd) {
+            sm.bd = (uint32_t)atomicAdd(&c->dist.v, pack2(sm.nd, sm.sd));
+            const unsigned long long tt = atomicAdd(&c->tree_tiles.v, pack2(sm.ntree, sm.ntile));
+            sm.btree = (uint32_t)tt;
+            sm.btile = (uint32_t)(tt >> 32);
+            sm.bcnt = (uint32_t)atomicAdd(&c->cnt.v, (unsigned long long)sm.ncnt);
+            if (sm.bd + sm.nd > w.caps.dist || sm.btree + sm.ntree > w.caps.tree ||
+                sm.bcnt + sm.ncnt > w.caps.cnt || sm.btile + sm.ntile > w.caps.tiles) {
+                raise_err(w, ERR_CAPACITY);
+                sm.nd = 0;  // write no distribution child
+            }
+        }
     }
     __syncthreads();
     // pass 2: write the reserved entries
@@ -1118,13 +1286,24 @@ __device__ void dev_children(const Work& w, const Params& p, int cur, uint32_t i
         if (cnt == 0) continue;
         const uint32_t pos = sg.begin + st;
         if (st > 0) {
-            const uint32_t q = slot_pend + atomicAdd(&cur_pend, 1u);
+            const uint32_t q = sm.slot_pend + atomicAdd(&sm.cur_pend, 1u);
             if (q < w.caps.pend) w.pend[q] = make_uint2(pos, sg.rid);
         }
-        if (depth == ~0u || cnt == 1 || cnt > p.base_max) continue;
-        const int cls = size_class(cnt);
-        const uint32_t q = slot_cls[cls] + atomicAdd(&cur_cls[cls], 1u);
-        if (q < w.caps.base[cls]) w.base[cls][nxt][q] = BaseSeg{pos, cnt, depth, sg.rid};
+        if (depth == ~0u || cnt == 1) continue;
+        if (cnt <= p.base_max) {
+            const int cls = size_class(cnt);
+            const uint32_t q = sm.slot_cls[cls] + atomicAdd(&sm.cur_cls[cls], 1u);
+            if (q < w.caps.base[cls]) w.base[cls][nxt][q] = BaseSeg{pos, cnt, depth, sg.rid};
+        } else if (sm.nd) {
+            uint32_t logv, nv, nk, nt;
+            dist_shape(cnt, logv, nv, nk, nt);
+            const uint32_t slot = sm.bd + atomicAdd(&sm.cd, 1u);
+            const uint32_t toff = sm.btree + atomicAdd(&sm.ctree, nv);
+            const uint32_t coff = sm.bcnt + atomicAdd(&sm.ccnt, nk * nt);
+            const uint32_t tioff = sm.btile + atomicAdd(&sm.ctile, nt);
+            // the tile list entries are written by k_sample (one work group per segment)
+            w.dist[nxt][slot] = Seg{pos, cnt, depth, logv, toff, coff, tioff, sg.rid};
+        }
     }
 }
 
@@ -1217,7 +1396,7 @@ __device__ bool grid_sync(const Work& w, uint32_t nblocks, uint32_t& gen, uint32
 __global__ __launch_bounds__(BLOCK) void k_persist(Work w, Params p, const uint32_t* set_begin, uint32_t num_sets) {
     __shared__ SmAll sm;
     __shared__ uint32_t s_ok, s_err;
-    __shared__ Counts sc;
+    __shared__ unsigned long long sc[COUNT_LINES];
     const uint32_t G = gridDim.x, bid = blockIdx.x, tid = threadIdx.x;
     uint32_t gen = 0;
 
@@ -1231,12 +1410,11 @@ __global__ __launch_bounds__(BLOCK) void k_persist(Work w, Params p, const uint3
     uint32_t level = 0;
     for (;; ++level) {
         // every block reads the level's counts before any block changes them
-        if (tid < sizeof(Counts) / 4)
-            ((uint32_t*)&sc)[tid] = __hip_atomic_load((uint32_t*)&w.ctl->cl[cur].c + tid, __ATOMIC_RELAXED,
-                                                      __HIP_MEMORY_SCOPE_AGENT);
+        if (tid < COUNT_LINES)
+            sc[tid] = __hip_atomic_load(&(&w.ctl->cl[cur].dist)[tid].v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (tid == 0) s_err = __hip_atomic_load(&w.ctl->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (!grid_sync(w, G, gen, &s_ok)) return;
-        const Counts c = sc;
+        const Counts c = counts_of(sc);
         if (s_err) break;
         if (level >= MAX_LEVELS_DEV) {
             if (bid == 0 && tid == 0) atomicOr(&w.ctl->err, (uint32_t)ERR_LEVELS);
@@ -1246,8 +1424,8 @@ __global__ __launch_bounds__(BLOCK) void k_persist(Work w, Params p, const uint3
         const uint32_t nb2 = (c.n_base[2] + WAVES - 1) / WAVES, nb3 = c.n_base[3];
         const uint32_t nitems = nb0 + nb1 + nb2 + nb3 + c.n_dist;
         if (nitems == 0) break;
-        if (bid == 0 && tid < sizeof(Counts) / 4)
-            __hip_atomic_store((uint32_t*)&w.ctl->cl[cur ^ 1].c + tid, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (bid == 0 && tid < COUNT_LINES)
+            __hip_atomic_store(&(&w.ctl->cl[cur ^ 1].dist)[tid].v, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         // base cases of every class and the splitter trees of the level
         for (uint32_t it = bid; it < nitems; it += G) {
             __syncthreads();

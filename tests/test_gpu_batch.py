@@ -165,3 +165,36 @@ def test_full_batched_workload(persistent):
     ctx.set_config(persistent=persistent)
     p, l = run_batch(c, o, sb, ctx)
     check_sets(c, o, sb, p, l, full=False)
+
+
+def test_autotune_batch_and_cache():
+    """The autotuner leaves the batch's correct result in the outputs, picks
+    a configuration from its grid and answers a repeat from its cache."""
+    import paper_1808_00963_amd as ss
+    note("case autotune batch")
+    ss.autotune_clear_cache()
+    c, o, sb = small_batch(num_sets=40, seed=31)
+    cd, od = to_device(c, o)
+    sbd = torch.from_numpy(sb.astype(np.int32)).cuda()
+    ctx = ss.Context()
+    cfg, ms, p, l = ctx.autotune(cd, od, sbd, reps=1)
+    torch.cuda.synchronize()
+    check_sets(c, o, sb, to_host(p), to_host(l))
+    assert cfg["max_log_splitters"] in (8, 9, 10) and cfg["bucket_target"] in (32, 64, 128)
+    assert cfg["base_max"] in (512, 1024) and ms > 0
+    assert {f: int(getattr(ctx.config, f)) for f in cfg} == cfg
+    cfg2, ms2, p2, l2 = ctx.autotune(cd, od, sbd, reps=1)
+    torch.cuda.synchronize()
+    assert cfg2 == cfg and ms2 == ms
+    assert np.array_equal(to_host(p2), to_host(p)) and np.array_equal(to_host(l2), to_host(l))
+
+
+def test_autotune_single_set():
+    import paper_1808_00963_amd as ss
+    note("case autotune single")
+    c, o = gen.generate("urls", 20000, 12)
+    cd, od = to_device(c, o)
+    ctx = ss.Context()
+    cfg, ms, p, l = ctx.autotune(cd, od, reps=1, use_cache=False)
+    torch.cuda.synchronize()
+    assert_equal_to_oracle(c, o, to_host(p), to_host(l), label="autotune single")
