@@ -75,21 +75,36 @@ SS_HD uint32_t inorder_index(uint32_t l, uint32_t d) {
 // for equality with the in-order splitter x_j found through level_index.
 // Returns the bucket 2j (strictly between x_{j-1} and x_j) or 2j+1 (equal
 // to x_j); 2v+1 buckets in total.
+// classify_n does the same for N strings at once, their descents
+// interleaved so their tree reads overlap.
+template <uint32_t N, typename KeyArr, typename RArr>
+SS_HD void classify_n(const uint64_t (&c)[N], const uint32_t (&cr)[N], const KeyArr& tk, const RArr& tr, uint32_t d,
+                      uint32_t (&b)[N]) {
+    uint32_t q[N];
+    for (uint32_t u = 0; u < N; ++u) q[u] = 1;
+    for (uint32_t l = 0; l < d; ++l) {
+        for (uint32_t u = 0; u < N; ++u) {
+            const uint32_t gt = kr_greater(c[u], cr[u], tk[q[u]], tr[q[u]]) ? 1u : 0u;
+            q[u] = 2 * q[u] + gt;
+        }
+    }
+    const uint32_t v = (1u << d) - 1;
+    for (uint32_t u = 0; u < N; ++u) {
+        const uint32_t j = q[u] - (v + 1);
+        b[u] = 2 * j;
+        if (j < v) {
+            const uint32_t lq = level_index(j, d);
+            if (tk[lq] == c[u] && (uint32_t)tr[lq] == cr[u]) b[u] += 1;
+        }
+    }
+}
 template <typename KeyArr, typename RArr>
 SS_HD uint32_t classify(uint64_t c, uint32_t cr, const KeyArr& tk, const RArr& tr, uint32_t d) {
-    uint32_t q = 1;
-    for (uint32_t l = 0; l < d; ++l) {
-        uint32_t gt = kr_greater(c, cr, tk[q], tr[q]) ? 1u : 0u;
-        q = 2 * q + gt;
-    }
-    uint32_t v = (1u << d) - 1;
-    uint32_t j = q - (v + 1);
-    uint32_t b = 2 * j;
-    if (j < v) {
-        uint32_t lq = level_index(j, d);
-        if (tk[lq] == c && (uint32_t)tr[lq] == cr) b += 1;
-    }
-    return b;
+    const uint64_t cc[1] = {c};
+    const uint32_t rr[1] = {cr};
+    uint32_t b[1];
+    classify_n<1>(cc, rr, tk, tr, d, b);
+    return b[0];
 }
 
 // One step of the splitter selection heuristic (section 4.2.2, paragraph

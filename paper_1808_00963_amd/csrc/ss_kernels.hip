@@ -147,8 +147,8 @@ __device__ __forceinline__ uint32_t wave_incl_max(uint32_t x) {
 // kernels declare the one they need; the persistent kernel declares their
 // union, so its LDS footprint is the largest of them.
 struct SmBase {
-    uint64_t K[BASE_CAP];
-    uint64_t A[BASE_CAP];
+    uint64_t K[BASE_CAP];  // packed sort records: hi words
+    uint64_t A[BASE_CAP];  // lo words
     uint32_t dep[BASE_CAP];
     uint32_t lv[BASE_CAP];
     uint32_t aux[BASE_CAP];   // bit 31: tie with the left neighbour; low bits: run start
@@ -259,182 +259,6 @@ __device__ __forceinline__ void dev_root_one(const Work& w, const Params& p, con
 __global__ void k_roots(Work w, Params p, const uint32_t* set_begin, uint32_t num_sets) {
     uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j < num_sets) dev_root_one(w, p, set_begin, num_sets, j);
-}
-
-// ---------------------------------------------------------------------------
-// base case: LDS-resident sort of a small segment with depth refinement
-// ---------------------------------------------------------------------------
-
-// Sort record in LDS: K = key, A = group(16) | r(8) | unused(8) | idx(32).
-// Order: group, then key, then (r, idx).
-__device__ __forceinline__ bool rec_greater(uint64_t ka, uint64_t aa, uint64_t kb, uint64_t ab) {
-    uint32_t ga = (uint32_t)(aa >> 48), gb = (uint32_t)(ab >> 48);
-    if (ga != gb) return ga > gb;
-    if (ka != kb) return ka > kb;
-    return (aa & 0xFFFFFFFFFFFFull) > (ab & 0xFFFFFFFFFFFFull);
-}
-__device__ __forceinline__ uint64_t rec_pack(uint32_t grp, uint32_t r, uint32_t idx) {
-    return ((uint64_t)grp << 48) | ((uint64_t)r << 40) | (uint64_t)idx;
-}
-__device__ __forceinline__ uint32_t rec_grp(uint64_t a) { return (uint32_t)(a >> 48); }
-__device__ __forceinline__ uint32_t rec_r(uint64_t a) { return (uint32_t)(a >> 40) & 0xFFu; }
-
-// In-place bitonic sorting network over P (power of two) LDS records.
-__device__ void bitonic_rec(uint64_t* K, uint64_t* A, uint32_t P) {
-    const uint32_t tid = threadIdx.x;
-    for (uint32_t k = 2; k <= P; k <<= 1) {
-        for (uint32_t j = k >> 1; j > 0; j >>= 1) {
-            for (uint32_t t = tid; t < (P >> 1); t += BLOCK) {
-                uint32_t i = ((t & ~(j - 1)) << 1) | (t & (j - 1));
-                uint32_t l = i | j;
-                bool up = (i & k) == 0;
-                uint64_t ki = K[i], kl = K[l], ai = A[i], al = A[l];
-                if (rec_greater(ki, ai, kl, al) == up) {
-                    K[i] = kl; K[l] = ki; A[i] = al; A[l] = ai;
-                }
-            }
-            __syncthreads();
-        }
-    }
-}
-
-// Sorts a segment of m <= BASE_CAP strings with common prefix h by
-// (key, r, index).  Runs of equal full words are then refined at depth
-// h+8, h+16, ... inside LDS (keys re-gathered for those strings only).
-// LCPs of neighbours separated at depth d are d plus the common bytes of
-// their words at d (the "last compared word"); the role of LCP-insertion
-// sort (Algorithm 4.6) as the paper's base case.
-__device__ void dev_base_wg(const Work& w, const Params& p, int cur, uint32_t item, SmBase& sm) {
-    uint64_t* K = sm.K;
-    uint64_t* A = sm.A;
-    uint32_t* dep = sm.dep;
-    uint32_t* lv = sm.lv;
-    uint32_t* aux = sm.aux;
-    uint32_t* rmin = sm.rmin;
-    uint32_t* wtot = sm.wtot;
-    uint32_t& any = sm.any;
-    constexpr uint32_t PER = BASE_CAP / BLOCK;
-
-    const BaseSeg sg = w.base[CLS_WG][cur][item];
-    const uint32_t tid = threadIdx.x, m = sg.size, h = sg.depth;
-    uint32_t rounds = 0;
-    if (m < 2 || m > BASE_CAP || m > p.base_max || sg.begin > p.n || m > p.n - sg.begin) {  // uniform
-        if (tid == 0) raise_err(w, ERR_BOUNDS);
-        return;
-    }
-    uint32_t P = 2;
-    while (P < m) P <<= 1;
-    const Elem* in = w.buf[cur] + sg.begin;
-    for (uint32_t i = tid; i < P; i += BLOCK) {
-        if (i < m) {
-            Elem e = in[i];
-            K[i] = e.key;
-            A[i] = rec_pack(0, rem8(e.len, h), e.idx);
-        } else {
-            K[i] = ~0ull;
-            A[i] = ~0ull;
-        }
-        dep[i] = h;
-        lv[i] = 0;
-    }
-    __syncthreads();
-
-    for (;;) {
-        if (tid == 0) any = 0;
-        bitonic_rec(K, A, P);
-        // neighbours inside a group: tie (equal full word, refine) or split
-        for (uint32_t i = tid; i < m; i += BLOCK) {
-            uint32_t t = 0;
-            if (i > 0) {
-                uint64_t a1 = A[i], a0 = A[i - 1];
-                if (rec_grp(a1) == rec_grp(a0)) {
-                    uint32_t r1 = rec_r(a1), r0 = rec_r(a0);
-                    uint64_t k1 = K[i], k0 = K[i - 1];
-                    if (k1 == k0 && r1 == r0 && r1 == 8) t = 1;
-                    else lv[i] = dep[i] + lcp_word(k0, r0, k1, r1);
-                }
-            }
-            aux[i] = t << 31;
-            if (t) any = 1;
-        }
-        __syncthreads();
-        if (!any) break;
-        ++rounds;
-        // run starts: inclusive max-scan of (tie ? 0 : position)
-        {
-            const uint32_t base = tid * PER;
-            uint32_t loc[PER];
-            uint32_t run = 0;
-#pragma unroll
-            for (uint32_t e = 0; e < PER; ++e) {
-                uint32_t i = base + e;
-                uint32_t x = (i < m && !(aux[i] >> 31)) ? i : 0u;
-                run = run > x ? run : x;
-                loc[e] = run;
-            }
-            uint32_t incl = wave_incl_max(run);
-            uint32_t excl = __shfl_up(incl, 1, 64);
-            if ((tid & 63) == 0) excl = 0;
-            if ((tid & 63) == 63) wtot[tid >> 6] = incl;
-            __syncthreads();
-            for (uint32_t q = 0; q < (tid >> 6); ++q) excl = excl > wtot[q] ? excl : wtot[q];
-#pragma unroll
-            for (uint32_t e = 0; e < PER; ++e) {
-                uint32_t i = base + e;
-                if (i < m) {
-                    aux[i] = (aux[i] & 0x80000000u) | (excl > loc[e] ? excl : loc[e]);
-                    rmin[i] = ~0u;
-                }
-            }
-        }
-        __syncthreads();
-        // common prefix of each run: every member's LCP with the run's first
-        // string (all members agree on the word at their depth, so the
-        // comparison starts 8 characters further)
-        for (uint32_t i = tid; i < m; i += BLOCK) {
-            const uint32_t ai = aux[i];
-            const bool act = (ai >> 31) || (i + 1 < m && (aux[i + 1] >> 31));
-            const uint32_t rs = ai & 0x7FFFFFFFu;
-            if (act && rs != i) {
-                const uint32_t a = (uint32_t)A[i], b = (uint32_t)A[rs];
-                const uint64_t oa = p.offsets[a], ob = p.offsets[b];
-                const uint32_t la = (uint32_t)(p.offsets[a + 1] - oa), lb = (uint32_t)(p.offsets[b + 1] - ob);
-                atomicMin(&rmin[rs], lcp_from(p.chars, oa, la, ob, lb, dep[i] + W));
-            }
-        }
-        __syncthreads();
-        // strings of a run move on to the run's common prefix
-        for (uint32_t i = tid; i < m; i += BLOCK) {
-            const uint32_t ai = aux[i];
-            const bool act = (ai >> 31) || (i + 1 < m && (aux[i + 1] >> 31));
-            const uint64_t a = A[i];
-            const uint32_t idx = (uint32_t)a;
-            if (act) {
-                const uint32_t rs = ai & 0x7FFFFFFFu;
-                const uint32_t d2 = rmin[rs];
-                dep[i] = d2;
-                const uint64_t o0 = p.offsets[idx], o1 = p.offsets[idx + 1];
-                const uint32_t len = (uint32_t)(o1 - o0);
-                K[i] = gather_key(p.chars, o0, d2, len);
-                A[i] = rec_pack(rs, rem8(len, d2), idx);
-            } else {
-                A[i] = rec_pack(i, rec_r(a), idx);
-            }
-        }
-        __syncthreads();
-    }
-    const uint32_t obase = w.set_base[sg.rid];
-    for (uint32_t i = tid; i < m; i += BLOCK) {
-        p.perm[sg.begin + i] = (uint32_t)A[i] - obase;
-        if (i > 0) p.lcp[sg.begin + i] = lv[i];
-    }
-    if (tid == 0 && w.remaining) atomicSub(&w.remaining[sg.rid], m);
-    if (tid == 0 && rounds) atomicAdd(&w.ctl->base_rounds, rounds);
-}
-
-__global__ __launch_bounds__(BLOCK) void k_base(Work w, Params p, int cur) {
-    __shared__ SmBase sm;
-    dev_base_wg(w, p, cur, blockIdx.x, sm);
 }
 
 // ---------------------------------------------------------------------------
@@ -773,6 +597,197 @@ __global__ __launch_bounds__(BLOCK) void k_base_wave(Work w, Params p, int cur, 
 }
 
 // ---------------------------------------------------------------------------
+// base case: one work group per segment, records in LDS, depth refinement
+// ---------------------------------------------------------------------------
+
+// Sorts NB * 256 packed records held in LDS (hi words H, lo words L): the
+// waves sort blocks of 256 in registers, then a bitonic network merges the
+// blocks, its cross-block stages in LDS, its in-block stages in registers.
+__device__ void lds_block_sort(uint64_t* H, uint64_t* L, uint32_t NB) {
+    constexpr uint32_t E = 4, R = 64 * E;
+    const uint32_t tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    uint64_t K[E], A[E];
+    for (uint32_t b = wv; b < NB; b += WAVES) {  // uniform per wave
+#pragma unroll
+        for (uint32_t r = 0; r < E; ++r) {
+            K[r] = H[b * R + lane * E + r];
+            A[r] = L[b * R + lane * E + r];
+        }
+        wave_bitonic<E>(K, A, lane, NB > 1 ? b * R : 0u);
+#pragma unroll
+        for (uint32_t r = 0; r < E; ++r) {
+            H[b * R + lane * E + r] = K[r];
+            L[b * R + lane * E + r] = A[r];
+        }
+    }
+    __syncthreads();
+    for (uint32_t k = 2 * R; k <= NB * R; k <<= 1) {
+        for (uint32_t j = k >> 1; j >= R; j >>= 1) {
+            for (uint32_t t = tid; t < NB * R / 2; t += BLOCK) {
+                const uint32_t i = ((t & ~(j - 1)) << 1) | (t & (j - 1));
+                const uint32_t l = i | j;
+                const bool up = (i & k) == 0;
+                const uint64_t hi = H[i], hl = H[l], li = L[i], ll = L[l];
+                if (pr_gt(hi, li, hl, ll) == up) {
+                    H[i] = hl; H[l] = hi; L[i] = ll; L[l] = li;
+                }
+            }
+            __syncthreads();
+        }
+        for (uint32_t b = wv; b < NB; b += WAVES) {
+#pragma unroll
+            for (uint32_t r = 0; r < E; ++r) {
+                K[r] = H[b * R + lane * E + r];
+                A[r] = L[b * R + lane * E + r];
+            }
+            wave_merge_tail<E>(K, A, lane, b * R, k);
+#pragma unroll
+            for (uint32_t r = 0; r < E; ++r) {
+                H[b * R + lane * E + r] = K[r];
+                L[b * R + lane * E + r] = A[r];
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// Sorts a segment of m <= BASE_CAP strings with common prefix h by
+// (key, r, index).  Runs of equal full words are then refined at depth
+// h+8, h+16, ... inside LDS (keys re-gathered for those strings only).
+// LCPs of neighbours separated at depth d are d plus the common bytes of
+// their words at d (the "last compared word"); the role of LCP-insertion
+// sort (Algorithm 4.6) as the paper's base case.
+__device__ void dev_base_wg(const Work& w, const Params& p, int cur, uint32_t item, SmBase& sm) {
+    uint64_t* K = sm.K;
+    uint64_t* A = sm.A;
+    uint32_t* dep = sm.dep;
+    uint32_t* lv = sm.lv;
+    uint32_t* aux = sm.aux;
+    uint32_t* rmin = sm.rmin;
+    uint32_t* wtot = sm.wtot;
+    uint32_t& any = sm.any;
+    constexpr uint32_t PER = BASE_CAP / BLOCK;
+
+    const BaseSeg sg = w.base[CLS_WG][cur][item];
+    const uint32_t tid = threadIdx.x, m = sg.size, h = sg.depth;
+    uint32_t rounds = 0;
+    if (m < 2 || m > BASE_CAP || m > p.base_max || sg.begin > p.n || m > p.n - sg.begin) {  // uniform
+        if (tid == 0) raise_err(w, ERR_BOUNDS);
+        return;
+    }
+    uint32_t P = 256;  // whole blocks of the block sort
+    while (P < m) P <<= 1;
+    const Elem* in = w.buf[cur] + sg.begin;
+    for (uint32_t i = tid; i < P; i += BLOCK) {
+        if (i < m) {
+            Elem e = in[i];
+            pr_pack(0, e.key, rem8(e.len, h), e.idx, K[i], A[i]);
+        } else {
+            K[i] = ~0ull;
+            A[i] = ~0ull;
+        }
+        dep[i] = h;
+        lv[i] = 0;
+    }
+    __syncthreads();
+
+    for (;;) {
+        if (tid == 0) any = 0;
+        lds_block_sort(K, A, P / 256);
+        // neighbours inside a group: tie (equal full word, refine) or split
+        for (uint32_t i = tid; i < m; i += BLOCK) {
+            uint32_t t = 0;
+            if (i > 0) {
+                const uint64_t a1 = A[i], a0 = A[i - 1], k1 = K[i], k0 = K[i - 1];
+                if (pr_grp(k1) == pr_grp(k0)) {
+                    const uint32_t r1 = pr_r(a1), r0 = pr_r(a0);
+                    if (k1 == k0 && (a1 >> 32) == (a0 >> 32) && r1 == 8) t = 1;
+                    else lv[i] = dep[i] + lcp_word(pr_key(k0, a0), r0, pr_key(k1, a1), r1);
+                }
+            }
+            aux[i] = t << 31;
+            if (t) any = 1;
+        }
+        __syncthreads();
+        if (!any) break;
+        ++rounds;
+        // run starts: inclusive max-scan of (tie ? 0 : position)
+        {
+            const uint32_t base = tid * PER;
+            uint32_t loc[PER];
+            uint32_t run = 0;
+#pragma unroll
+            for (uint32_t e = 0; e < PER; ++e) {
+                uint32_t i = base + e;
+                uint32_t x = (i < m && !(aux[i] >> 31)) ? i : 0u;
+                run = run > x ? run : x;
+                loc[e] = run;
+            }
+            uint32_t incl = wave_incl_max(run);
+            uint32_t excl = __shfl_up(incl, 1, 64);
+            if ((tid & 63) == 0) excl = 0;
+            if ((tid & 63) == 63) wtot[tid >> 6] = incl;
+            __syncthreads();
+            for (uint32_t q = 0; q < (tid >> 6); ++q) excl = excl > wtot[q] ? excl : wtot[q];
+#pragma unroll
+            for (uint32_t e = 0; e < PER; ++e) {
+                uint32_t i = base + e;
+                if (i < m) {
+                    aux[i] = (aux[i] & 0x80000000u) | (excl > loc[e] ? excl : loc[e]);
+                    rmin[i] = ~0u;
+                }
+            }
+        }
+        __syncthreads();
+        // common prefix of each run: every member's LCP with the run's first
+        // string (all members agree on the word at their depth, so the
+        // comparison starts 8 characters further)
+        for (uint32_t i = tid; i < m; i += BLOCK) {
+            const uint32_t ai = aux[i];
+            const bool act = (ai >> 31) || (i + 1 < m && (aux[i + 1] >> 31));
+            const uint32_t rs = ai & 0x7FFFFFFFu;
+            if (act && rs != i) {
+                const uint32_t a = pr_idx(A[i]), b = pr_idx(A[rs]);
+                const uint64_t oa = p.offsets[a], ob = p.offsets[b];
+                const uint32_t la = (uint32_t)(p.offsets[a + 1] - oa), lb = (uint32_t)(p.offsets[b + 1] - ob);
+                atomicMin(&rmin[rs], lcp_from(p.chars, oa, la, ob, lb, dep[i] + W));
+            }
+        }
+        __syncthreads();
+        // strings of a run move on to the run's common prefix
+        for (uint32_t i = tid; i < m; i += BLOCK) {
+            const uint32_t ai = aux[i];
+            const bool act = (ai >> 31) || (i + 1 < m && (aux[i + 1] >> 31));
+            const uint32_t idx = pr_idx(A[i]);
+            if (act) {
+                const uint32_t rs = ai & 0x7FFFFFFFu;
+                const uint32_t d2 = rmin[rs];
+                dep[i] = d2;
+                const uint64_t o0 = p.offsets[idx], o1 = p.offsets[idx + 1];
+                const uint32_t len = (uint32_t)(o1 - o0);
+                pr_pack(rs, gather_key(p.chars, o0, d2, len), rem8(len, d2), idx, K[i], A[i]);
+            } else {
+                K[i] = pr_regroup(K[i], i);
+            }
+        }
+        __syncthreads();
+    }
+    const uint32_t obase = w.set_base[sg.rid];
+    for (uint32_t i = tid; i < m; i += BLOCK) {
+        p.perm[sg.begin + i] = pr_idx(A[i]) - obase;
+        if (i > 0) p.lcp[sg.begin + i] = lv[i];
+    }
+    if (tid == 0 && w.remaining) atomicSub(&w.remaining[sg.rid], m);
+    if (tid == 0 && rounds) atomicAdd(&w.ctl->base_rounds, rounds);
+}
+
+__global__ __launch_bounds__(BLOCK) void k_base(Work w, Params p, int cur) {
+    __shared__ SmBase sm;
+    dev_base_wg(w, p, cur, blockIdx.x, sm);
+}
+
+
+// ---------------------------------------------------------------------------
 // distribution step: sample + splitter tree
 // ---------------------------------------------------------------------------
 
@@ -962,11 +977,30 @@ __device__ void dev_classify(const Work& w, const Params& p, int cur, uint32_t t
     for (uint32_t b = tid; b < k; b += BLOCK) H[b] = 0;
     __syncthreads();
     const Elem* in = w.buf[cur];
-    for (uint32_t i = start + tid; i < end; i += BLOCK) {
-        Elem e = in[i];
-        uint32_t b = classify(e.key, rem8(e.len, sg.depth), TK, TR, d);
-        w.bkt[i] = (uint16_t)b;
-        atomicAdd(&H[b], 1u);
+    constexpr uint32_t U = 4;  // strings per thread and step, descents interleaved
+    for (uint32_t i0 = start + tid; i0 < end; i0 += U * BLOCK) {
+        uint64_t c[U];
+        uint32_t cr[U], b[U];
+#pragma unroll
+        for (uint32_t u = 0; u < U; ++u) {
+            const uint32_t i = i0 + u * BLOCK;
+            c[u] = 0;
+            cr[u] = 0;
+            if (i < end) {
+                const Elem e = in[i];
+                c[u] = e.key;
+                cr[u] = rem8(e.len, sg.depth);
+            }
+        }
+        classify_n<U>(c, cr, TK, TR, d, b);
+#pragma unroll
+        for (uint32_t u = 0; u < U; ++u) {
+            const uint32_t i = i0 + u * BLOCK;
+            if (i < end) {
+                w.bkt[i] = (uint16_t)b[u];
+                atomicAdd(&H[b[u]], 1u);
+            }
+        }
     }
     __syncthreads();
     uint32_t* c = w.cnt[cur] + sg.cnt_off + ti;
