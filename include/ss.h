@@ -263,6 +263,11 @@ typedef struct {
     double units;
 } ss_kernel_time;
 ss_status ss_set_profiling(ss_ctx* ctx, int enable);
+/* Enables tracing for the one kernel named `kernel` (a name reported by
+ * ss_get_kernel_times); the other launches get no events, so the sort runs
+ * at full speed while that kernel is timed.  SS_INVALID_ARG for an unknown
+ * name. */
+ss_status ss_set_profiling_only(ss_ctx* ctx, const char* kernel);
 ss_status ss_get_kernel_times(const ss_ctx* ctx, ss_kernel_time* out, uint32_t max_entries, uint32_t* n_entries);
 void ss_reset_kernel_times(ss_ctx* ctx);
 

@@ -99,6 +99,7 @@ def lib():
             "ss_server_reset_stats": (None, [vp]),
             "ss_server_destroy": (None, [vp]),
             "ss_set_profiling": (i32, [vp, i32]),
+            "ss_set_profiling_only": (i32, [vp, ctypes.c_char_p]),
             "ss_get_kernel_times": (i32, [vp, ctypes.POINTER(KernelTime), u32, ctypes.POINTER(u32)]),
             "ss_reset_kernel_times": (None, [vp]),
             "ss_hbm_copy": (i32, [vp, vp, ctypes.c_size_t, vp]),
@@ -196,8 +197,12 @@ class Context:
             out[f] = list(v) if isinstance(v, ctypes.Array) else v
         return out
 
-    def set_profiling(self, on: bool = True):
-        _check(lib().ss_set_profiling(self._h, 1 if on else 0), "ss_set_profiling")
+    def set_profiling(self, on: bool = True, only: str | None = None):
+        """Per-kernel HIP-event timing; `only` limits it to one kernel."""
+        if on and only:
+            _check(lib().ss_set_profiling_only(self._h, only.encode()), "ss_set_profiling_only")
+        else:
+            _check(lib().ss_set_profiling(self._h, 1 if on else 0), "ss_set_profiling")
 
     def kernel_times(self) -> dict:
         """{kernel: {"launches", "total_ms", "units", "unit"}} accumulated while profiling."""

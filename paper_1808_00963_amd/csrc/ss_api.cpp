@@ -35,6 +35,7 @@ const char* const KUNIT[K_COUNT] = {"strings", "sets", "strings", "strings", "st
 // Event pairs around kernel launches, resolved at the next host sync.
 struct Profiler {
     bool on = false;
+    uint32_t mask = ~0u;  // kernels (bit per KernelId) that get event pairs
     std::vector<hipEvent_t> ev;  // pairs (start, stop)
     std::vector<int> kid;
     std::vector<double> units;
@@ -179,7 +180,7 @@ ss_status device_error_status(uint32_t err) {
 template <typename F>
 hipError_t timed(ss_ctx* ctx, hipStream_t s, int id, double units, F&& fn) {
     Profiler& P = ctx->prof;
-    if (!P.on) return fn();
+    if (!P.on || !((P.mask >> id) & 1u)) return fn();
     if (P.used * 2 + 2 > P.ev.size()) {
         for (int i = 0; i < 64; ++i) {
             hipEvent_t e;
@@ -657,7 +658,20 @@ ss_status ss_get_stats(const ss_ctx* ctx, ss_stats* st) {
 ss_status ss_set_profiling(ss_ctx* ctx, int enable) {
     if (!ctx) return SS_INVALID_ARG;
     ctx->prof.on = enable != 0;
+    ctx->prof.mask = ~0u;
     return SS_OK;
+}
+
+ss_status ss_set_profiling_only(ss_ctx* ctx, const char* kernel) {
+    if (!ctx || !kernel) return SS_INVALID_ARG;
+    for (int i = 0; i < K_COUNT; ++i) {
+        if (std::strcmp(kernel, KNAME[i]) == 0) {
+            ctx->prof.on = true;
+            ctx->prof.mask = 1u << i;
+            return SS_OK;
+        }
+    }
+    return SS_INVALID_ARG;
 }
 
 ss_status ss_get_kernel_times(const ss_ctx* ctx, ss_kernel_time* out, uint32_t max_entries, uint32_t* n_entries) {
