@@ -1194,9 +1194,165 @@ __device__ void dev_scatter(const Work& w, const Params& p, int cur, uint32_t t,
     }
 }
 
-__global__ __launch_bounds__(BLOCK) void k_scatter(Work w, Params p, int cur, uint32_t n_dist) {
-    __shared__ SmScatter sm;
-    dev_scatter(w, p, cur, xcd_tile(blockIdx.x, gridDim.x), n_dist, sm);
+// Level-by-level form of the scatter: one work group of 1024 threads per
+// tile stages the whole tile in LDS in bucket order before writing, so each
+// bucket's part of the tile leaves as one contiguous run (whole lines
+// instead of scattered 16-byte pieces).  Same output as dev_scatter.
+//   1. every wave loads its 512-record chunk (8 per lane) and bucket ids;
+//   2. ranks inside the wave per bucket (ballot peer masks; order = chunk
+//      order, so the result is stable);
+//   3. per bucket: prefix over the waves and the tile total, block scan of
+//      the totals = the bucket's first slot in the tile;
+//   4. records go to their slots in LDS, then slot j is written to
+//      delta[b] + j where delta[b] = global start of (b, tile) - first slot.
+constexpr uint32_t SC_THREADS = 1024, SC_WAVES = SC_THREADS / 64, SC_PER = TILE / SC_THREADS;
+static_assert(SC_PER * SC_THREADS == TILE && MAX_BUCKETS < 2 * SC_THREADS, "scatter tile shape");
+struct SmScatterTile {
+    union {
+        uint16_t WC[SC_WAVES][MAX_BUCKETS + 1];  // per-wave counts, then per-wave first slots
+        uint4 stage[TILE];                       // the tile's records in bucket order
+    };
+    uint16_t sb[TILE];                  // bucket of each slot
+    uint32_t delta[MAX_BUCKETS + 1];    // tile totals, then global position - slot
+    uint32_t wsum[SC_WAVES];
+};
+
+__global__ __launch_bounds__(SC_THREADS) void k_scatter(Work w, Params p, int cur, uint32_t n_dist) {
+    __shared__ SmScatterTile sm;
+    const uint32_t t = xcd_tile(blockIdx.x, gridDim.x);
+    const uint32_t tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const uint32_t si = w.tile_seg[cur][t];
+    if (si >= n_dist) {
+        if (tid == 0) raise_err(w, ERR_BOUNDS);
+        return;
+    }
+    const Seg sg = w.dist[cur][si];
+    const uint32_t d = sg.logv, v = (1u << d) - 1, k = 2 * v + 1;
+    const uint32_t T = (sg.size + TILE - 1) / TILE;
+    const uint32_t ti = t - sg.tile_off;
+    if (d < 1 || d > MAX_LOGV || ti >= T || sg.begin > p.n || sg.size > p.n - sg.begin) {
+        if (tid == 0) raise_err(w, ERR_BOUNDS);
+        return;
+    }
+    const uint32_t start = sg.begin + ti * TILE;
+    const uint32_t end = min_u32(start + TILE, sg.begin + sg.size);
+    const uint32_t m = end - start;
+    // 1. loads (all issued before any use)
+    static_assert(sizeof(Elem) == sizeof(uint4), "records move as 16-byte words");
+    const uint4* in = (const uint4*)(w.buf[cur] + start);
+    const uint32_t c0 = wv * (TILE / SC_WAVES);  // the wave's chunk in the tile
+    uint4 e[SC_PER];
+    uint32_t bk[SC_PER];
+#pragma unroll
+    for (uint32_t r = 0; r < SC_PER; ++r) {
+        const uint32_t q = c0 + r * 64 + lane;
+        bk[r] = 0xFFFFu;
+        e[r] = make_uint4(0, 0, 0, 0);
+        if (q < m) {
+            e[r] = in[q];
+            bk[r] = w.bkt[start + q];
+        }
+    }
+    for (uint32_t b = tid; b < k; b += SC_THREADS) {
+#pragma unroll
+        for (uint32_t q = 0; q < SC_WAVES; ++q) sm.WC[q][b] = 0;
+    }
+    __syncthreads();
+    // 2. ranks inside the wave
+    uint32_t rank[SC_PER];
+#pragma unroll
+    for (uint32_t r = 0; r < SC_PER; ++r) {
+        const uint32_t b = bk[r];
+        const bool valid = b != 0xFFFFu;
+        uint64_t peers = __ballot(valid);
+#pragma unroll
+        for (uint32_t bit = 0; bit < MAX_LOGV + 1; ++bit) {
+            const uint64_t mk = __ballot((b >> bit) & 1u);
+            peers &= ((b >> bit) & 1u) ? mk : ~mk;
+        }
+        const uint32_t below = __builtin_amdgcn_mbcnt_hi((uint32_t)(peers >> 32),
+                                                         __builtin_amdgcn_mbcnt_lo((uint32_t)peers, 0u));
+        const uint32_t leader = valid ? (uint32_t)__builtin_ctzll(peers) : 0u;
+        uint32_t old = 0;
+        if (valid && lane == leader) {  // one writer per bucket and wave
+            old = sm.WC[wv][b];
+            sm.WC[wv][b] = (uint16_t)(old + (uint32_t)__builtin_popcountll(peers));
+        }
+        old = __shfl(old, (int)leader, 64);
+        rank[r] = old + below;
+    }
+    __syncthreads();
+    // 3. prefix over the waves, tile totals, block scan of the totals
+    for (uint32_t b = tid; b < k; b += SC_THREADS) {
+        uint32_t run = 0;
+#pragma unroll
+        for (uint32_t q = 0; q < SC_WAVES; ++q) {
+            const uint32_t c = sm.WC[q][b];
+            sm.WC[q][b] = (uint16_t)run;
+            run += c;
+        }
+        sm.delta[b] = run;
+    }
+    __syncthreads();
+    const uint32_t b0 = 2 * tid, b1 = 2 * tid + 1;
+    const uint32_t n0 = b0 < k ? sm.delta[b0] : 0u, n1 = b1 < k ? sm.delta[b1] : 0u;
+    const uint32_t incl = wave_incl_sum(n0 + n1);
+    if (lane == 63) sm.wsum[wv] = incl;
+    __syncthreads();
+    uint32_t first0 = incl - n0 - n1;
+    for (uint32_t q = 0; q < wv; ++q) first0 += sm.wsum[q];
+    const uint32_t* sc = w.cnt[cur] + sg.cnt_off;
+    const uint32_t s0 = sc[0];
+    if (b0 < k) {
+        sm.delta[b0] = sg.begin + sc[(size_t)b0 * T + ti] - s0 - first0;
+#pragma unroll
+        for (uint32_t q = 0; q < SC_WAVES; ++q) sm.WC[q][b0] = (uint16_t)(sm.WC[q][b0] + first0);
+    }
+    if (b1 < k) {
+        const uint32_t first1 = first0 + n0;
+        sm.delta[b1] = sg.begin + sc[(size_t)b1 * T + ti] - s0 - first1;
+#pragma unroll
+        for (uint32_t q = 0; q < SC_WAVES; ++q) sm.WC[q][b1] = (uint16_t)(sm.WC[q][b1] + first1);
+    }
+    __syncthreads();
+    // 4. records to their slots, then out in slot order
+    uint32_t slot[SC_PER];
+#pragma unroll
+    for (uint32_t r = 0; r < SC_PER; ++r) slot[r] = bk[r] != 0xFFFFu ? sm.WC[wv][bk[r]] + rank[r] : 0u;
+    __syncthreads();  // WC is overwritten by the staged records
+#pragma unroll
+    for (uint32_t r = 0; r < SC_PER; ++r) {
+        if (bk[r] == 0xFFFFu) continue;
+        if (slot[r] >= m) { raise_err(w, ERR_BOUNDS); continue; }
+        sm.stage[slot[r]] = e[r];
+        sm.sb[slot[r]] = (uint16_t)bk[r];
+    }
+    __syncthreads();
+    uint4* out = (uint4*)w.buf[cur ^ 1];
+    const uint32_t seg_end = sg.begin + sg.size;
+    const uint32_t obase = w.set_base[sg.rid];
+    const uint8_t* gr = w.tree_r[cur] + sg.tree_off;
+#pragma unroll
+    for (uint32_t r = 0; r < SC_PER; ++r) {
+        const uint32_t j = r * SC_THREADS + tid;
+        if (j >= m) break;
+        const uint32_t b = sm.sb[j];
+        uint4 x = sm.stage[j];  // key (x, y), idx (z), len (w)
+        const uint32_t pos = sm.delta[b] + j;
+        if (pos < sg.begin || pos >= seg_end) { raise_err(w, ERR_BOUNDS); continue; }
+        if (b & 1u) {
+            const uint32_t rx = gr[level_index(b >> 1, d) - 1];
+            if (rx < W) {  // identical strings ending inside this word: final
+                p.perm[pos] = x.z - obase;
+                if (pos != sg.begin + sc[(size_t)b * T] - s0) p.lcp[pos] = sg.depth + rx;
+                continue;
+            }
+            const uint64_t key = gather_key(p.chars, p.offsets[x.z], sg.depth + W, x.w);
+            x.x = (uint32_t)key;
+            x.y = (uint32_t)(key >> 32);
+        }
+        out[pos] = x;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1613,7 +1769,7 @@ hipError_t launch_scan(const Work& w, int cur, uint32_t n_cnt, hipStream_t s) {
 }
 hipError_t launch_scatter(const Work& w, const Params& p, int cur, uint32_t n_tiles, uint32_t n_dist,
                           hipStream_t s) {
-    hipLaunchKernelGGL(k_scatter, dim3(n_tiles), dim3(BLOCK), 0, s, w, p, cur, n_dist);
+    hipLaunchKernelGGL(k_scatter, dim3(n_tiles), dim3(SC_THREADS), 0, s, w, p, cur, n_dist);
     return hipGetLastError();
 }
 hipError_t launch_children(const Work& w, const Params& p, int cur, uint32_t n_dist, hipStream_t s) {
