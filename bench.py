@@ -323,10 +323,91 @@ def run_profile(args):
     print(json.dumps({"mode": "profile", "workload": args.workload, "copy_gbs": 2 * nbytes / min(ts) / 1e9}))
 
 
+def run_traffic(args):
+    """Turns two rocprofv3 counter runs of `--mode profile` (FETCH_SIZE, then
+    WRITE_SIZE; KiB per dispatch) into calibrated HBM bytes per launch of
+    every kernel of ONE sort, written to profiles/traffic.json (with the hash
+    of the kernel sources it was taken on) and a text summary.  Calibration:
+    the streaming copy moves exactly 1 GiB each way, so each counter's
+    reading for it gives the factor that turns that counter into bytes."""
+    import csv
+    import numpy as np
+
+    def per_dispatch(path, counter):
+        rows = {}
+        with open(path) as f:
+            for r in csv.DictReader(f):
+                if r["Counter_Name"] != counter:
+                    continue
+                did = int(r["Dispatch_Id"])
+                name = r["Kernel_Name"]
+                rows.setdefault(did, [name, 0.0])
+                rows[did][1] += float(r["Counter_Value"]) * 1024.0  # KiB -> bytes
+        return [rows[k] for k in sorted(rows)]
+
+    fetch = per_dispatch(args.fetch_csv, "FETCH_SIZE")
+    write = per_dispatch(args.write_csv, "WRITE_SIZE")
+    copy_bytes = 1 << 30
+    calib = {}
+    for tag, rows in (("fetch", fetch), ("write", write)):
+        copies = [v for k, v in rows if "k_copy" in k]
+        if not copies:
+            raise SystemExit(f"no copy kernel dispatch in the {tag} run")
+        calib[tag] = copy_bytes / float(np.median(copies))
+
+    def last_sort(rows):
+        starts = [i for i, (k, _) in enumerate(rows) if "k_reset" in k]
+        return rows[starts[-1]:]
+
+    def short(name):
+        base = name.split("(")[0].replace("void ", "").replace("ss::", "")
+        return {"k_base_wave<1>": "k_base_wave1", "k_base_wave<2>": "k_base_wave2",
+                "k_base_wave<4>": "k_base_wave4"}.get(base, base)
+
+    kern = {}
+    for (kf, vf), (kw, vw) in zip(last_sort(fetch), last_sort(write)):
+        if short(kf) != short(kw):
+            raise SystemExit("fetch and write runs dispatched different kernels")
+        d = kern.setdefault(short(kf), {"launches": 0, "fetch": 0.0, "write": 0.0})
+        d["launches"] += 1
+        d["fetch"] += vf * calib["fetch"]
+        d["write"] += vw * calib["write"]
+    out = {"kernel_source_hash": kernel_source_hash(), "workload": args.workload,
+           "calibration": {"copy_bytes_each_way": copy_bytes, "fetch_factor": calib["fetch"],
+                           "write_factor": calib["write"]},
+           "command_fetch": "rocprofv3 --pmc FETCH_SIZE --output-format csv -d <out> -o run -- "
+                            "python3 bench.py --mode profile --steps 1 --warmup 1",
+           "command_write": "rocprofv3 --pmc WRITE_SIZE --output-format csv -d <out> -o run -- "
+                            "python3 bench.py --mode profile --steps 1 --warmup 1",
+           "kernels": {}}
+    for k, d in kern.items():
+        L = d["launches"]
+        out["kernels"][k] = {"launches": L, "fetch_bytes_per_launch": d["fetch"] / L,
+                             "write_bytes_per_launch": d["write"] / L,
+                             "bytes_per_launch": (d["fetch"] + d["write"]) / L}
+    with open(os.path.join(ROOT, "profiles", "traffic.json"), "w") as f:
+        json.dump(out, f, indent=1)
+    lines = [f"# HBM traffic per kernel launch from hardware counters, one full sort of {args.workload}.",
+             "# Commands (from /tmp, TMPDIR=/tmp), one counter per run:",
+             f"#   {out['command_fetch']}", f"#   {out['command_write']}",
+             "# then: python3 bench.py --mode traffic --fetch-csv <fetch csv> --write-csv <write csv>",
+             f"# Calibration: ss_hbm_copy of 1 GiB each way; FETCH_SIZE factor {calib['fetch']:.3f}, "
+             f"WRITE_SIZE factor {calib['write']:.3f} (bytes per counted byte).  Values are calibrated bytes.",
+             "# Columns: kernel | launches per sort | fetch MB/launch | write MB/launch | total MB/launch", ""]
+    for k, v in sorted(out["kernels"].items(), key=lambda kv: -kv[1]["bytes_per_launch"] * kv[1]["launches"]):
+        lines.append(f"{k:14s} | {v['launches']:2d} | {v['fetch_bytes_per_launch'] / 1e6:9.1f} | "
+                     f"{v['write_bytes_per_launch'] / 1e6:9.1f} | {v['bytes_per_launch'] / 1e6:9.1f}")
+    with open(os.path.join(ROOT, "profiles", f"traffic_{args.workload}_pmc.txt"), "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print(json.dumps({"mode": "traffic", "kernels": len(kern)}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--mode", choices=["plain", "batch", "serve", "profile"], default="plain")
+    ap.add_argument("--mode", choices=["plain", "batch", "serve", "profile", "traffic"], default="plain")
+    ap.add_argument("--fetch-csv", help="traffic mode: rocprofv3 counter_collection.csv of the FETCH_SIZE run")
+    ap.add_argument("--write-csv", help="traffic mode: rocprofv3 counter_collection.csv of the WRITE_SIZE run")
     ap.add_argument("--pool", type=int, default=128)
     ap.add_argument("--requests", type=int, default=2000)
     ap.add_argument("--serve-warmup", type=int, default=200)
@@ -351,6 +432,9 @@ def main():
         return
     if args.mode == "profile":
         run_profile(args)
+        return
+    if args.mode == "traffic":
+        run_traffic(args)
         return
 
     import numpy as np

@@ -1366,7 +1366,8 @@ __global__ __launch_bounds__(SC_THREADS) void k_scatter(Work w, Params p, int cu
 // the word at depth h); the value is filled in once the final order is
 // known (figure 4.7).  List slots for the children of the whole segment are
 // reserved with one global atomic per list (two passes over the buckets).
-__device__ void dev_children(const Work& w, const Params& p, int cur, uint32_t item, SmChildren& sm) {
+__device__ void dev_children(const Work& w, const Params& p, int cur, uint32_t item, uint32_t chunk,
+                             uint32_t chunk_buckets, SmChildren& sm) {
     const Seg sg = w.dist[cur][item];
     const uint32_t tid = threadIdx.x, d = sg.logv, v = (1u << d) - 1, k = 2 * v + 1;
     const uint32_t T = (sg.size + TILE - 1) / TILE;
@@ -1375,6 +1376,10 @@ __device__ void dev_children(const Work& w, const Params& p, int cur, uint32_t i
         if (tid == 0) raise_err(w, ERR_BOUNDS);
         return;
     }
+    // this work group's buckets: [lo, hi)
+    const uint32_t lo = chunk * chunk_buckets;
+    if (lo >= k) return;  // uniform
+    const uint32_t hi = min_u32(k, lo + chunk_buckets);
     if (tid < NCLS) { sm.n_cls[tid] = 0; sm.s_cls[tid] = 0; sm.cur_cls[tid] = 0; }
     if (tid == 0) {
         sm.n_pend_l = 0; sm.cur_pend = 0; sm.max_d = 0;
@@ -1384,16 +1389,15 @@ __device__ void dev_children(const Work& w, const Params& p, int cur, uint32_t i
     // bucket starts: the first tile's scanned counter of every bucket
     const uint32_t* sc = w.cnt[cur] + sg.cnt_off;
     const uint32_t s0 = sc[0];
-    for (uint32_t b = tid; b < k; b += BLOCK) sm.ST[b] = sc[(size_t)b * T] - s0;
-    if (tid == 0) sm.ST[k] = sg.size;
+    for (uint32_t b = lo + tid; b <= hi; b += BLOCK) sm.ST[b - lo] = b < k ? sc[(size_t)b * T] - s0 : sg.size;
     __syncthreads();
     const uint8_t* gr = w.tree_r[cur] + sg.tree_off;
     const Elem* out = w.buf[nxt];
     const uint32_t obase = w.set_base[sg.rid];
     // bucket b -> (start, count, child depth); depth == ~0u: no child segment
     auto bucket = [&](uint32_t b, uint32_t& st, uint32_t& cnt, uint32_t& depth) {
-        st = sm.ST[b];
-        const uint32_t en = sm.ST[b + 1];
+        st = sm.ST[b - lo];
+        const uint32_t en = sm.ST[b - lo + 1];
         cnt = en > st ? en - st : 0u;
         if (en > sg.size) { raise_err(w, ERR_BOUNDS); cnt = 0; }
         depth = sg.depth;
@@ -1410,7 +1414,7 @@ __device__ void dev_children(const Work& w, const Params& p, int cur, uint32_t i
         nt = (cnt + TILE - 1) / TILE;
     };
     // pass 1: count per list, finish singletons
-    for (uint32_t b = tid; b < k; b += BLOCK) {
+    for (uint32_t b = lo + tid; b < hi; b += BLOCK) {
         uint32_t st, cnt, depth;
         bucket(b, st, cnt, depth);
         if (cnt == 0) continue;
@@ -1470,7 +1474,7 @@ __device__ void dev_children(const Work& w, const Params& p, int cur, uint32_t i
     }
     __syncthreads();
     // pass 2: write the reserved entries
-    for (uint32_t b = tid; b < k; b += BLOCK) {
+    for (uint32_t b = lo + tid; b < hi; b += BLOCK) {
         uint32_t st, cnt, depth;
         bucket(b, st, cnt, depth);
         if (cnt == 0) continue;
@@ -1497,9 +1501,11 @@ __device__ void dev_children(const Work& w, const Params& p, int cur, uint32_t i
     }
 }
 
+// CHILD_CHUNKS work groups per segment, BLOCK buckets each.
+constexpr uint32_t CHILD_CHUNKS = (MAX_BUCKETS + BLOCK - 1) / BLOCK;
 __global__ __launch_bounds__(BLOCK) void k_children(Work w, Params p, int cur) {
     __shared__ SmChildren sm;
-    dev_children(w, p, cur, blockIdx.x, sm);
+    dev_children(w, p, cur, blockIdx.x / CHILD_CHUNKS, blockIdx.x % CHILD_CHUNKS, BLOCK, sm);
 }
 
 // ---------------------------------------------------------------------------
@@ -1652,7 +1658,7 @@ __global__ __launch_bounds__(BLOCK) void k_persist(Work w, Params p, const uint3
         if (!grid_sync(w, G, gen, &s_ok)) return;
         for (uint32_t q = bid; q < c.n_dist; q += G) {
             __syncthreads();
-            dev_children(w, p, cur, q, sm.children);
+            dev_children(w, p, cur, q, 0, MAX_BUCKETS, sm.children);
         }
         if (!grid_sync(w, G, gen, &s_ok)) return;
         cur ^= 1;
@@ -1773,7 +1779,7 @@ hipError_t launch_scatter(const Work& w, const Params& p, int cur, uint32_t n_ti
     return hipGetLastError();
 }
 hipError_t launch_children(const Work& w, const Params& p, int cur, uint32_t n_dist, hipStream_t s) {
-    hipLaunchKernelGGL(k_children, dim3(n_dist), dim3(BLOCK), 0, s, w, p, cur);
+    hipLaunchKernelGGL(k_children, dim3(n_dist * CHILD_CHUNKS), dim3(BLOCK), 0, s, w, p, cur);
     return hipGetLastError();
 }
 hipError_t launch_lcp_fill(const Work& w, const Params& p, hipStream_t s) {
