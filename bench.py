@@ -51,16 +51,17 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel: str, units_per_launch: float):
+def measured_traffic(kernel: str, workload: str):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if
-    it was taken on the current kernel sources; else None."""
+    it was taken on the current kernel sources and on this workload; else
+    None."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     try:
         with open(path) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
-    if t.get("kernel_source_hash") != kernel_source_hash():
+    if t.get("kernel_source_hash") != kernel_source_hash() or t.get("workload") != workload:
         return None
     k = t.get("kernels", {}).get(kernel)
     if not k:
@@ -495,7 +496,7 @@ def main():
     alg_bytes_per_launch = d["units"] / d["launches"] * bpu[dom]
     avg_ms = d["total_ms"] / d["launches"]
     achieved = alg_bytes_per_launch / (avg_ms * 1e-3) / 1e9
-    traffic = measured_traffic(dom, d["units"] / d["launches"])
+    traffic = measured_traffic(dom, args.workload)
     for k, v in sorted(kt.items(), key=lambda kv: -kv[1]["total_ms"]):
         if v["launches"]:
             per = v["total_ms"] / args.steps
