@@ -294,16 +294,17 @@ template <uint32_t J>
 __device__ __forceinline__ uint32_t xlane32(uint32_t x) {
     static_assert(J == 1 || J == 2 || J == 4 || J == 8 || J == 16 || J == 32, "lane distance");
     const int v = (int)x;
+    // every lane's source lies inside its row, so no lane keeps an old value
     if constexpr (J == 1) {
-        return (uint32_t)__builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, false);  // quad_perm [1,0,3,2]
+        return (uint32_t)__builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, true);  // quad_perm [1,0,3,2]
     } else if constexpr (J == 2) {
-        return (uint32_t)__builtin_amdgcn_update_dpp(0, v, 0x4E, 0xF, 0xF, false);  // quad_perm [2,3,0,1]
+        return (uint32_t)__builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, true);  // quad_perm [2,3,0,1]
     } else if constexpr (J == 4) {
-        const int y = __builtin_amdgcn_update_dpp(0, v, 0x141, 0xF, 0xF, false);    // row_half_mirror
-        return (uint32_t)__builtin_amdgcn_update_dpp(0, y, 0x1B, 0xF, 0xF, false);  // quad_perm [3,2,1,0]
+        const int y = __builtin_amdgcn_mov_dpp(v, 0x141, 0xF, 0xF, true);    // row_half_mirror
+        return (uint32_t)__builtin_amdgcn_mov_dpp(y, 0x1B, 0xF, 0xF, true);  // quad_perm [3,2,1,0]
     } else if constexpr (J == 8) {
-        const int y = __builtin_amdgcn_update_dpp(0, v, 0x140, 0xF, 0xF, false);     // row_mirror
-        return (uint32_t)__builtin_amdgcn_update_dpp(0, y, 0x141, 0xF, 0xF, false);  // row_half_mirror
+        const int y = __builtin_amdgcn_mov_dpp(v, 0x140, 0xF, 0xF, true);     // row_mirror
+        return (uint32_t)__builtin_amdgcn_mov_dpp(y, 0x141, 0xF, 0xF, true);  // row_half_mirror
     } else if constexpr (J == 16) {
         const auto r = __builtin_amdgcn_permlane16_swap(x, x, false, false);
         return (__lane_id() & 16) ? r[0] : r[1];
