@@ -1657,9 +1657,9 @@ __global__ __launch_bounds__(BLOCK) void k_persist(Work w, Params p, const uint3
             dev_scatter(w, p, cur, t, c.n_dist, sm.scatter);
         }
         if (!grid_sync(w, G, gen, &s_ok)) return;
-        for (uint32_t q = bid; q < c.n_dist; q += G) {
+        for (uint32_t q = bid; q < c.n_dist * CHILD_CHUNKS; q += G) {
             __syncthreads();
-            dev_children(w, p, cur, q, 0, MAX_BUCKETS, sm.children);
+            dev_children(w, p, cur, q / CHILD_CHUNKS, q % CHILD_CHUNKS, BLOCK, sm.children);
         }
         if (!grid_sync(w, G, gen, &s_ok)) return;
         cur ^= 1;
