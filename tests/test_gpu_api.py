@@ -1,0 +1,98 @@
+"""Library services on the GPU: statistics, per-kernel timing (all kernels or
+one), the streaming copy, explicit output buffers and streams."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import gen
+from gpu_util import assert_equal_to_oracle, needs_gpu, to_device, to_host
+
+pytestmark = [pytest.mark.gpu, needs_gpu]
+
+
+def note(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def test_stats_account_for_every_string():
+    """Every string ends in exactly one place: a base case, a singleton bucket
+    or an identical-string bucket; the per-class base-case counts add up and
+    the class bounds hold."""
+    import paper_1808_00963_amd as ss
+    note("case stats")
+    c, o = gen.generate("markov", 200000, 3)
+    cd, od = to_device(c, o)
+    ctx = ss.Context()
+    p, l = ctx.sort(cd, od)
+    torch.cuda.synchronize()
+    assert_equal_to_oracle(c, o, to_host(p), to_host(l), full=False)
+    st = ctx.stats()
+    assert st["levels"] >= 2
+    assert sum(st["base_segments_by_class"]) == st["base_segments"]
+    assert sum(st["base_strings_by_class"]) <= len(o) - 1
+    bounds = [64, 128, 256, 1024]
+    for q, (segs, strs) in enumerate(zip(st["base_segments_by_class"], st["base_strings_by_class"])):
+        assert strs <= segs * bounds[q]
+        if q and segs:
+            assert strs > segs * bounds[q - 1]
+    assert st["pending_lcps"] >= st["base_segments"] - st["dist_segments"]
+
+
+def test_profiling_all_and_only_one_kernel():
+    import paper_1808_00963_amd as ss
+    note("case profiling")
+    c, o = gen.generate("markov", 300000, 4)
+    cd, od = to_device(c, o)
+    ctx = ss.Context()
+    ctx.sort(cd, od)
+    ctx.set_profiling(True)
+    ctx.reset_kernel_times()
+    ctx.sort(cd, od)
+    torch.cuda.synchronize()
+    kt = ctx.kernel_times()
+    assert kt["k_init"]["launches"] == 1 and kt["k_init"]["units"] == len(o) - 1
+    assert kt["k_scatter"]["launches"] >= 1 and kt["k_scatter"]["total_ms"] > 0
+    assert kt["k_classify"]["units"] == kt["k_scatter"]["units"]
+    ctx.set_profiling(True, only="k_scatter")
+    ctx.reset_kernel_times()
+    ctx.sort(cd, od)
+    torch.cuda.synchronize()
+    kt1 = ctx.kernel_times()
+    assert kt1["k_scatter"]["launches"] == kt["k_scatter"]["launches"]
+    assert all(v["launches"] == 0 for k, v in kt1.items() if k != "k_scatter")
+    with pytest.raises(ss.SSError):
+        ctx.set_profiling(True, only="no_such_kernel")
+    ctx.set_profiling(False)
+
+
+def test_hbm_copy_moves_bytes_exactly():
+    import paper_1808_00963_amd as ss
+    note("case hbm copy")
+    src = torch.randint(0, 256, (3 << 20,), dtype=torch.uint8, device="cuda")
+    dst = torch.zeros_like(src)
+    ss.hbm_copy(dst, src)
+    torch.cuda.synchronize()
+    assert torch.equal(src, dst)
+    with pytest.raises(ValueError):
+        ss.hbm_copy(dst[:16], src)
+
+
+def test_caller_buffers_and_side_stream():
+    """Outputs written into caller-owned buffers on a caller's stream; the
+    result is ready after that stream is synchronised."""
+    import paper_1808_00963_amd as ss
+    note("case side stream")
+    c, o = gen.generate("urls", 50000, 6)
+    cd, od = to_device(c, o)
+    n = len(o) - 1
+    perm = torch.full((n,), -1, dtype=torch.int32, device="cuda")
+    lcp = torch.full((n,), -1, dtype=torch.int32, device="cuda")
+    s = torch.cuda.Stream()
+    ctx = ss.Context()
+    with torch.cuda.stream(s):
+        ctx.sort(cd, od, perm, lcp, stream=s)
+    s.synchronize()
+    assert_equal_to_oracle(c, o, to_host(perm), to_host(lcp))
