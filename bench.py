@@ -290,6 +290,86 @@ def run_serve(args):
     print(json.dumps(out), flush=True)
 
 
+def run_merge(args):
+    """LCP-aware merge of K sorted runs: the workload's strings are cut into
+    K contiguous runs, sorted by the batched sort (untimed set-up), and the
+    timed step is one ss_merge_runs of the K runs into one sorted sequence
+    with its LCP array."""
+    import numpy as np
+    import torch
+
+    import gen
+    import paper_1808_00963_amd as ss
+
+    model, n, seed = gen.WORKLOADS[args.workload]
+    c, o = gen.generate(model, n, seed)
+    N = int(o[-1])
+    dev = torch.device("cuda:0")
+    chars = torch.from_numpy(c).to(dev)
+    offs = torch.from_numpy(o.view(np.int64)).to(dev)
+    K = max(1, args.runs)
+    rb = [n * r // K for r in range(K + 1)]
+    ctx = ss.Context(0)
+    sb = torch.tensor(rb, dtype=torch.int32, device=dev)
+    p, l = ctx.sort_batch(chars, offs, sb)
+    for r in range(K):  # set-local -> global string indices
+        p[rb[r]:rb[r + 1]] += rb[r]
+    mp = torch.empty(n, dtype=torch.int32, device=dev)
+    ml = torch.empty(n, dtype=torch.int32, device=dev)
+    stream = torch.cuda.current_stream()
+    for _ in range(args.warmup):
+        ctx.merge_runs(chars, offs, p, l, rb, mp, ml, stream=stream)
+    ctx.set_profiling(True)
+    ctx.reset_kernel_times()
+    for _ in range(args.steps):
+        ctx.merge_runs(chars, offs, p, l, rb, mp, ml, stream=stream)
+    torch.cuda.synchronize()
+    ctx.set_profiling(False)
+    kt = ctx.kernel_times()
+    dom = "k_merge_chunks"
+    ctx.set_profiling(True, only=dom)
+    ctx.reset_kernel_times()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ctx.merge_runs(chars, offs, p, l, rb, mp, ml, stream=stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ctx.set_profiling(False)
+    d = ctx.kernel_times()[dom]
+    sec = (t1 - t0) / args.steps
+    # k_merge_chunks moves at least perm + lcp in (8) and out (8) per string
+    # per round; characters are read only where the two heads tie
+    alg = d["units"] / d["launches"] * 16.0
+    avg_ms = d["total_ms"] / d["launches"]
+    achieved = alg / (avg_ms * 1e-3) / 1e9
+    for k, v in sorted(kt.items(), key=lambda kv: -kv[1]["total_ms"]):
+        if v["launches"]:
+            print(f"[bench] {k:14s} {v['total_ms'] / args.steps:8.3f} ms/step  launches/step "
+                  f"{v['launches'] / args.steps:5.1f}", file=sys.stderr)
+    # context: a full sort of the same strings
+    ctx.sort(chars, offs, mp, ml)
+    torch.cuda.synchronize()
+    a = time.perf_counter()
+    for _ in range(args.steps):
+        ctx.sort(chars, offs, mp, ml)
+    torch.cuda.synchronize()
+    sort_ms = (time.perf_counter() - a) / args.steps * 1e3
+    print(f"[bench] merge of {K} runs {sec * 1e3:.3f} ms, full sort {sort_ms:.3f} ms", file=sys.stderr, flush=True)
+    print(json.dumps({
+        "metric": "merged strings/s (LCP-aware merge of K sorted runs, perm + LCP)", "value": n / sec,
+        "unit": "strings/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": sec * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u8", "data": "synthetic",
+        "config": {"workload": args.workload, "model": model, "n_strings": n, "n_chars": N, "runs": K,
+                   "parallelism": "single-gpu"},
+        "chars_per_s": N / sec, "full_sort_ms": sort_ms,
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "alg_bytes_per_launch": alg,
+                     "avg_launch_ms": avg_ms},
+        "kernel_ms_per_step": {k: v["total_ms"] / args.steps for k, v in kt.items() if v["launches"]},
+    }), flush=True)
+
+
 def run_profile(args):
     """Program for hardware-counter runs: 3 streaming copies of 1 GiB (known
     traffic, for calibration) followed by warm-up + timed sorts of the plain
@@ -406,10 +486,11 @@ def run_traffic(args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--mode", choices=["plain", "batch", "serve", "profile", "traffic"], default="plain")
+    ap.add_argument("--mode", choices=["plain", "batch", "serve", "profile", "traffic", "merge"], default="plain")
     ap.add_argument("--fetch-csv", help="traffic mode: rocprofv3 counter_collection.csv of the FETCH_SIZE run")
     ap.add_argument("--write-csv", help="traffic mode: rocprofv3 counter_collection.csv of the WRITE_SIZE run")
     ap.add_argument("--pool", type=int, default=128)
+    ap.add_argument("--runs", type=int, default=2, help="merge mode: number of sorted runs")
     ap.add_argument("--requests", type=int, default=2000)
     ap.add_argument("--serve-warmup", type=int, default=200)
     ap.add_argument("--sets", type=int, default=4096)
@@ -436,6 +517,9 @@ def main():
         return
     if args.mode == "traffic":
         run_traffic(args)
+        return
+    if args.mode == "merge":
+        run_merge(args)
         return
 
     import numpy as np

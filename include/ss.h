@@ -171,6 +171,30 @@ ss_status ss_autotune(ss_ctx* ctx, const uint8_t* chars, const uint64_t* offsets
 /* Forgets every cached autotuning result of the process. */
 void ss_autotune_clear_cache(void);
 
+/* LCP-aware merge of sorted runs (section 4.3.1: binary LCP-merge,
+ * Algorithms 4.2-4.4, Lemma 4.5), done as pairwise GPU rounds.
+ * perm[run_begin[r] .. run_begin[r+1]) is run r: string indices (each below
+ * n_strings) sorted by string, equal strings by index, as ss_sort_ex leaves
+ * them, and lcp[p] is the LCP of the strings at p-1 and p within the run
+ * (the entry at a run's first position is ignored).  The output is the
+ * union of the runs in the same order with its LCP array (lcp_out[0] = 0):
+ * for runs that sort disjoint parts of one set it equals ss_sort_ex of the
+ * whole set.  The same index may appear in several runs (copies stay
+ * adjacent).
+ * chars, offsets: device, as for ss_sort_ex with n_strings strings;
+ * perm, lcp: device, run_begin[num_runs] uint32 each (inputs, unchanged);
+ * run_begin: HOST, num_runs+1 non-decreasing uint64 with run_begin[0] = 0;
+ * perm_out, lcp_out: device, run_begin[num_runs] uint32 each, not
+ * overlapping the inputs or each other.
+ * Errors: SS_INVALID_ARG for bad run boundaries, aliased buffers or a perm
+ * entry >= n_strings (detected on device), SS_LIMIT for more than
+ * 2^32-2 elements or malformed offsets.  Empty runs are allowed.  The merge
+ * workspace (up to four run_begin[num_runs]-entry arrays) is kept by the
+ * context.  Synchronizes `stream` before returning. */
+ss_status ss_merge_runs(ss_ctx* ctx, const uint8_t* chars, const uint64_t* offsets, uint32_t n_strings,
+                        const uint32_t* perm, const uint32_t* lcp, const uint64_t* run_begin, uint32_t num_runs,
+                        uint32_t* perm_out, uint32_t* lcp_out, void* stream);
+
 /* ---- serving: continuous batching under an HBM budget ------------------
  * A server owns one device (its own stream and worker thread) and a fixed
  * device arena sized by `hbm_budget` bytes: character storage plus index

@@ -106,6 +106,7 @@ def lib():
             "ss_autotune": (i32, [vp, vp, vp, u32, vp, u32, vp, vp, vp, u32, i32, ctypes.POINTER(Config),
                                   ctypes.POINTER(ctypes.c_double)]),
             "ss_autotune_clear_cache": (None, []),
+            "ss_merge_runs": (i32, [vp, vp, vp, u32, vp, vp, ctypes.POINTER(u64), u32, vp, vp, vp]),
             "ss_host_key": (u64, [vp, u64, u64, ctypes.POINTER(u32)]),
             "ss_host_level_index": (u32, [u32, u32]),
             "ss_host_inorder_index": (u32, [u32, u32]),
@@ -277,6 +278,35 @@ class Context:
         _check(st, "ss_sort_batch")
         return perm, lcp
 
+    def merge_runs(self, chars, offsets, perm, lcp, run_begin, perm_out=None, lcp_out=None, stream=None):
+        """LCP-aware merge of the sorted runs perm[run_begin[r]:run_begin[r+1]]
+        (with their LCP arrays) into one sorted sequence (ss_merge_runs);
+        run_begin is a host sequence of num_runs+1 ints.  Returns
+        (perm_out, lcp_out) int32 tensors holding uint32."""
+        _check_inputs(chars, offsets)
+        for t in (perm, lcp):
+            if not t.is_cuda or t.dtype not in (torch.int32, torch.uint32) or not t.is_contiguous():
+                raise TypeError("perm and lcp must be contiguous int32/uint32 device tensors")
+        rb = [int(x) for x in run_begin]
+        if len(rb) < 2:
+            raise ValueError("run_begin needs num_runs+1 entries")
+        m = rb[-1]
+        if perm.numel() < m or lcp.numel() < m:
+            raise ValueError("perm/lcp shorter than run_begin[-1]")
+        if perm_out is None:
+            perm_out = torch.empty(m, dtype=torch.int32, device=chars.device)
+        if lcp_out is None:
+            lcp_out = torch.empty(m, dtype=torch.int32, device=chars.device)
+        if perm_out.numel() < m or lcp_out.numel() < m:
+            raise ValueError("outputs shorter than run_begin[-1]")
+        arr = (ctypes.c_uint64 * len(rb))(*rb)
+        st = lib().ss_merge_runs(self._h, ctypes.c_void_p(chars.data_ptr()), ctypes.c_void_p(offsets.data_ptr()),
+                                 offsets.numel() - 1, ctypes.c_void_p(perm.data_ptr()),
+                                 ctypes.c_void_p(lcp.data_ptr()), arr, len(rb) - 1,
+                                 ctypes.c_void_p(perm_out.data_ptr()), ctypes.c_void_p(lcp_out.data_ptr()),
+                                 _stream_ptr(stream))
+        _check(st, "ss_merge_runs")
+        return perm_out, lcp_out
 
     def autotune(self, chars, offsets, set_begin=None, perm=None, lcp=None, reps=3, use_cache=True,
                  stream=None):

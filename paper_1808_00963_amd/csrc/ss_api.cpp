@@ -24,13 +24,14 @@ using namespace ss;
 namespace {
 enum KernelId {
     K_INIT, K_ROOTS, K_BASE_W1, K_BASE_W2, K_BASE_W4, K_BASE, K_SAMPLE, K_CLASSIFY, K_SCAN, K_SCATTER, K_CHILDREN,
-    K_LCP_FILL, K_PERSIST, K_COUNT
+    K_LCP_FILL, K_PERSIST, K_MERGE_SPLIT, K_MERGE, K_COUNT
 };
 const char* const KNAME[K_COUNT] = {"k_init", "k_roots", "k_base_wave1", "k_base_wave2", "k_base_wave4", "k_base",
                                     "k_sample", "k_classify", "k_scan", "k_scatter", "k_children", "k_lcp_fill",
-                                    "k_persist"};
+                                    "k_persist", "k_merge_split", "k_merge_chunks"};
 const char* const KUNIT[K_COUNT] = {"strings", "sets", "strings", "strings", "strings", "strings", "segments",
-                                    "strings", "counters", "strings", "segments", "boundaries", "strings"};
+                                    "strings", "counters", "strings", "segments", "boundaries", "strings",
+                                    "chunks", "strings"};
 
 // Event pairs around kernel launches, resolved at the next host sync.
 struct Profiler {
@@ -59,6 +60,12 @@ struct ss_ctx {
     ss_stats stats{};
     Profiler prof;
     uint32_t persist_blocks = 0;  // co-resident work groups of the persistent kernel
+    // merge workspace (grow-only): device part and pinned staging of the
+    // task tables and the error word
+    void* mws = nullptr;
+    size_t mws_bytes = 0;
+    void* mhost = nullptr;
+    size_t mhost_bytes = 0;
 };
 
 struct ss_graph {
@@ -334,6 +341,125 @@ ss_status sort_checked(ss_ctx* ctx, const uint8_t* chars, const uint64_t* offset
     return st;
 }
 
+// ---- LCP-aware merge of sorted runs ----
+
+// Grows the merge workspace to at least `dev_bytes` device / `host_bytes`
+// pinned host bytes.
+ss_status ensure_merge_ws(ss_ctx* ctx, size_t dev_bytes, size_t host_bytes) {
+    if (ctx->scratch_limit && dev_bytes > ctx->scratch_limit) return SS_OUT_OF_MEMORY;
+    if (dev_bytes > ctx->mws_bytes) {
+        if (ctx->mws) (void)hipFree(ctx->mws);
+        ctx->mws = nullptr;
+        ctx->mws_bytes = 0;
+        if (hipMalloc(&ctx->mws, dev_bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            ctx->mws = nullptr;
+            return SS_OUT_OF_MEMORY;
+        }
+        ctx->mws_bytes = dev_bytes;
+    }
+    if (host_bytes > ctx->mhost_bytes) {
+        if (ctx->mhost) (void)hipHostFree(ctx->mhost);
+        ctx->mhost = nullptr;
+        ctx->mhost_bytes = 0;
+        if (hipHostMalloc(&ctx->mhost, host_bytes, hipHostMallocDefault) != hipSuccess) {
+            (void)hipGetLastError();
+            ctx->mhost = nullptr;
+            return SS_OUT_OF_MEMORY;
+        }
+        ctx->mhost_bytes = host_bytes;
+    }
+    return SS_OK;
+}
+
+ss_status merge_error_status(uint32_t err) {
+    if (err & MERR_INDEX) return SS_INVALID_ARG;
+    if (err & MERR_OFFSETS) return SS_LIMIT;
+    return SS_INTERNAL;
+}
+
+// Pairwise rounds: runs 2t and 2t+1 of a round become run t of the next
+// (an odd last run is carried by a task with an empty B).  Empty runs are
+// dropped first; a single run is one task that copies it.
+ss_status run_merge(ss_ctx* ctx, const uint8_t* chars, const uint64_t* offsets, uint32_t n_strings,
+                    const uint32_t* perm, const uint32_t* lcp, const uint64_t* run_begin, uint32_t num_runs,
+                    uint32_t* perm_out, uint32_t* lcp_out, hipStream_t s) {
+    const uint64_t m = run_begin[num_runs];
+    std::vector<uint32_t> size;
+    for (uint32_t r = 0; r < num_runs; ++r)
+        if (run_begin[r + 1] > run_begin[r]) size.push_back((uint32_t)(run_begin[r + 1] - run_begin[r]));
+    std::vector<std::vector<MergeTask>> rounds;
+    std::vector<uint32_t> chunks;
+    do {
+        std::vector<MergeTask> tasks;
+        std::vector<uint32_t> next;
+        uint32_t a = 0, c0 = 0;
+        for (size_t r = 0; r < size.size(); r += 2) {
+            const uint32_t na = size[r], nb = r + 1 < size.size() ? size[r + 1] : 0u;
+            tasks.push_back(MergeTask{a, na, nb, c0});
+            c0 += (uint32_t)(((uint64_t)na + nb + MERGE_CHUNK - 1) / MERGE_CHUNK);
+            a += na + nb;
+            next.push_back(na + nb);
+        }
+        rounds.push_back(std::move(tasks));
+        chunks.push_back(c0);
+        size.swap(next);
+    } while (size.size() > 1);
+    const size_t R = rounds.size();
+
+    size_t n_tasks = 0, max_chunks = 0;
+    for (size_t r = 0; r < R; ++r) n_tasks += rounds[r].size(), max_chunks = std::max<size_t>(max_chunks, chunks[r]);
+    const size_t tmp_bufs = R >= 3 ? 2 : R - 1;  // ping-pong (perm, lcp) pairs between rounds
+    const size_t arr = align_up(m * sizeof(uint32_t));
+    const size_t off_split = tmp_bufs * 2 * arr;
+    const size_t off_tasks = off_split + align_up(max_chunks * sizeof(uint32_t));
+    const size_t off_err = off_tasks + align_up(n_tasks * sizeof(MergeTask));
+    const size_t dev_bytes = off_err + 256;
+    const size_t host_tasks = align_up(n_tasks * sizeof(MergeTask));
+    ss_status st = ensure_merge_ws(ctx, dev_bytes, host_tasks + 256);
+    if (st != SS_OK) return st;
+
+    char* dws = (char*)ctx->mws;
+    MergeTask* htask = (MergeTask*)ctx->mhost;
+    uint32_t* herr = (uint32_t*)((char*)ctx->mhost + host_tasks);
+    size_t t0 = 0;
+    for (size_t r = 0; r < R; ++r) {
+        std::copy(rounds[r].begin(), rounds[r].end(), htask + t0);
+        t0 += rounds[r].size();
+    }
+    MergeTask* dtask = (MergeTask*)(dws + off_tasks);
+    uint32_t* derr = (uint32_t*)(dws + off_err);
+    SS_TRY(hipMemcpyAsync(dtask, htask, n_tasks * sizeof(MergeTask), hipMemcpyHostToDevice, s));
+    SS_TRY(hipMemsetAsync(derr, 0, sizeof(uint32_t), s));
+
+    uint32_t* tmp_perm[2] = {(uint32_t*)dws, (uint32_t*)(dws + 2 * arr)};
+    uint32_t* tmp_lcp[2] = {(uint32_t*)(dws + arr), (uint32_t*)(dws + 3 * arr)};
+    t0 = 0;
+    for (size_t r = 0; r < R; ++r) {
+        MergeArgs a{};
+        a.chars = chars;
+        a.offsets = offsets;
+        a.n_strings = n_strings;
+        a.src_perm = r == 0 ? perm : tmp_perm[(r - 1) & 1];
+        a.src_lcp = r == 0 ? lcp : tmp_lcp[(r - 1) & 1];
+        a.dst_perm = r + 1 == R ? perm_out : tmp_perm[r & 1];
+        a.dst_lcp = r + 1 == R ? lcp_out : tmp_lcp[r & 1];
+        a.tasks = dtask + t0;
+        a.n_tasks = (uint32_t)rounds[r].size();
+        a.n_chunks = chunks[r];
+        a.split = (uint32_t*)(dws + off_split);
+        a.err = derr;
+        SS_TRY(timed(ctx, s, K_MERGE_SPLIT, a.n_chunks, [&] { return launch_merge_split(a, s); }));
+        SS_TRY(timed(ctx, s, K_MERGE, (double)m, [&] { return launch_merge_chunks(a, s); }));
+        t0 += rounds[r].size();
+    }
+    SS_TRY(hipMemcpyAsync(herr, derr, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    SS_TRY(hipStreamSynchronize(s));
+    if (ctx->prof.used) resolve_timings(ctx);
+    if (*herr) return merge_error_status(*herr);
+    return SS_OK;
+}
+
 std::mutex g_mu;
 std::map<int, std::unique_ptr<ss_ctx, void (*)(ss_ctx*)>>* g_ctx = nullptr;
 
@@ -386,6 +512,8 @@ void ss_ctx_destroy(ss_ctx* ctx) {
     for (hipEvent_t e : ctx->prof.ev) (void)hipEventDestroy(e);
     if (ctx->ws) (void)hipFree(ctx->ws);
     if (ctx->host_ctl) (void)hipHostFree(ctx->host_ctl);
+    if (ctx->mws) (void)hipFree(ctx->mws);
+    if (ctx->mhost) (void)hipHostFree(ctx->mhost);
     (void)hipSetDevice(prev);
     delete ctx;
 }
@@ -688,6 +816,30 @@ void ss_reset_kernel_times(ss_ctx* ctx) {
     Profiler& P = ctx->prof;
     P.used = 0;
     for (int i = 0; i < K_COUNT; ++i) P.ms[i] = P.unit_sum[i] = 0, P.launches[i] = 0;
+}
+
+ss_status ss_merge_runs(ss_ctx* ctx, const uint8_t* chars, const uint64_t* offsets, uint32_t n_strings,
+                        const uint32_t* perm, const uint32_t* lcp, const uint64_t* run_begin, uint32_t num_runs,
+                        uint32_t* perm_out, uint32_t* lcp_out, void* stream) {
+    if (!ctx || !run_begin || num_runs == 0) return SS_INVALID_ARG;
+    if (run_begin[0] != 0) return SS_INVALID_ARG;
+    for (uint32_t r = 0; r < num_runs; ++r)
+        if (run_begin[r + 1] < run_begin[r]) return SS_INVALID_ARG;
+    const uint64_t m = run_begin[num_runs];
+    if (m == 0) return SS_OK;
+    if (m > 0xFFFFFFFEull) return SS_LIMIT;
+    if (!offsets || !perm || !lcp || !perm_out || !lcp_out || n_strings == 0) return SS_INVALID_ARG;
+    if ((const void*)perm_out == (const void*)lcp_out || (const void*)perm_out == (const void*)perm ||
+        (const void*)perm_out == (const void*)lcp || (const void*)lcp_out == (const void*)perm ||
+        (const void*)lcp_out == (const void*)lcp)
+        return SS_INVALID_ARG;
+    int cur_dev = -1;
+    SS_TRY(hipGetDevice(&cur_dev));
+    if (cur_dev != ctx->device) SS_TRY(hipSetDevice(ctx->device));
+    ss_status st = run_merge(ctx, chars, offsets, n_strings, perm, lcp, run_begin, num_runs, perm_out, lcp_out,
+                             (hipStream_t)stream);
+    if (st != SS_OK && st != SS_INVALID_ARG) ctx->sticky = st;
+    return st;
 }
 
 ss_status ss_hbm_copy(void* dst, const void* src, size_t bytes, void* stream) {

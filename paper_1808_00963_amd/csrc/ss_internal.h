@@ -181,6 +181,7 @@ hipError_t launch_reset(const Work& w, hipStream_t s);
 hipError_t launch_init(const Work& w, const Params& p, hipStream_t s);
 hipError_t launch_roots(const Work& w, const Params& p, const uint32_t* set_begin, uint32_t num_sets,
                         hipStream_t s);
+// Zeroes counts slot `which` (no memset: stays capturable).
 hipError_t launch_zero_counts(const Work& w, int which, hipStream_t s);
 hipError_t launch_base(const Work& w, const Params& p, int cur, int cls, uint32_t n_base, hipStream_t s);
 hipError_t launch_sample(const Work& w, const Params& p, int cur, uint32_t n_dist, hipStream_t s);
@@ -207,8 +208,43 @@ hipError_t launch_pend_filter(const Work& w, const Params& p, hipStream_t s);
 hipError_t launch_pend_swap(const Work& w, hipStream_t s);
 // Streaming copy (bandwidth calibration).
 hipError_t launch_copy(void* dst, const void* src, size_t n16, hipStream_t s);
-// Zeroes counts slot `which` (no memset: stays capturable).
 // Largest number of co-resident work groups of the persistent kernel.
 hipError_t persistent_capacity(int device, uint32_t* blocks);
+
+
+// ---- LCP-aware merging of sorted runs (ss_merge.hip) ----
+constexpr uint32_t MERGE_BLOCK = 256;
+constexpr uint32_t MERGE_CHUNK = 32;  // outputs per thread of k_merge_chunks
+
+enum : uint32_t {
+    MERR_INDEX = 1u,     // a perm entry is not below the number of strings
+    MERR_OFFSETS = 2u,   // non-monotone offsets or a string too long
+    MERR_INTERNAL = 4u,  // a split point fell outside its pair of runs
+};
+
+// One pair of adjacent runs A = [a, a+na), B = [a+na, a+na+nb) of the source
+// arrays, merged into [a, a+na+nb) of the destination arrays; its chunks
+// are chunk0, chunk0+1, ... (ceil((na+nb)/MERGE_CHUNK) of them).
+struct MergeTask {
+    uint32_t a, na, nb, chunk0;
+};
+
+struct MergeArgs {
+    const uint8_t* chars;
+    const uint64_t* offsets;
+    uint32_t n_strings;
+    const uint32_t* src_perm;
+    const uint32_t* src_lcp;
+    uint32_t* dst_perm;
+    uint32_t* dst_lcp;
+    const MergeTask* tasks;  // ordered by chunk0
+    uint32_t n_tasks;
+    uint32_t n_chunks;
+    uint32_t* split;  // per chunk: outputs taken from A before it
+    uint32_t* err;
+};
+
+hipError_t launch_merge_split(const MergeArgs& m, hipStream_t s);
+hipError_t launch_merge_chunks(const MergeArgs& m, hipStream_t s);
 
 }  // namespace ss

@@ -11,6 +11,7 @@
 #include <algorithm>
 
 #include "ss_device.h"
+#include "ss_gather.h"
 #include "ss_internal.h"
 
 namespace ss {
@@ -18,45 +19,6 @@ namespace ss {
 // ---------------------------------------------------------------------------
 // helpers
 // ---------------------------------------------------------------------------
-
-__device__ __forceinline__ uint32_t min_u32(uint32_t a, uint32_t b) { return a < b ? a : b; }
-
-// chars_h(s): the 8 characters of a string starting at depth h, big-endian,
-// zero padded past the end (section 4.2.2, "Character Reordering").  Reads
-// the aligned 8-byte word holding the first character and, only when the
-// key straddles a word boundary, the next one (it then holds a character
-// of the string), so no read touches a page without string data.
-__device__ __forceinline__ uint64_t gather_key(const uint8_t* chars, uint64_t off, uint32_t h, uint32_t len) {
-    uint32_t rem = len > h ? len - h : 0u;
-    rem = min_u32(rem, 8u);
-    if (rem == 0) return 0;
-    uintptr_t a = (uintptr_t)(chars + off + h);
-    const uint64_t* p = (const uint64_t*)(a & ~(uintptr_t)7);
-    uint32_t sh = (uint32_t)(a & 7);
-    uint64_t w0 = __builtin_nontemporal_load(p);
-    uint64_t w1 = (sh + rem > 8) ? __builtin_nontemporal_load(p + 1) : 0ull;
-    return key_from_words(w0, w1, sh, rem);
-}
-
-__device__ __forceinline__ uint32_t rem8(uint32_t len, uint32_t h) { return min_u32(len - h, 8u); }
-
-// Length of the common prefix of two strings known to agree on their first
-// `from` characters, by comparing 8-byte words (at most `limit` = the
-// shorter length).
-__device__ __forceinline__ uint32_t lcp_from(const uint8_t* chars, uint64_t oa, uint32_t la, uint64_t ob, uint32_t lb,
-                                             uint32_t from) {
-    const uint32_t limit = la < lb ? la : lb;
-    uint32_t d = from;
-    while (d < limit) {
-        const uint64_t ka = gather_key(chars, oa, d, la), kb = gather_key(chars, ob, d, lb);
-        if (ka != kb) {
-            const uint32_t c = d + common_bytes(ka, kb);
-            return c < limit ? c : limit;
-        }
-        d += W;
-    }
-    return limit;
-}
 
 __device__ __forceinline__ void raise_err(const Work& w, uint32_t bits) { atomicOr(&w.ctl->err, bits); }
 // Two counters in one 64-bit atomic word (low, high); neither half of a
