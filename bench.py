@@ -326,7 +326,7 @@ def run_merge(args):
     torch.cuda.synchronize()
     ctx.set_profiling(False)
     kt = ctx.kernel_times()
-    dom = "k_merge_chunks"
+    dom = "k_merge_tile"
     ctx.set_profiling(True, only=dom)
     ctx.reset_kernel_times()
     torch.cuda.synchronize()
@@ -338,7 +338,7 @@ def run_merge(args):
     ctx.set_profiling(False)
     d = ctx.kernel_times()[dom]
     sec = (t1 - t0) / args.steps
-    # k_merge_chunks moves at least perm + lcp in (8) and out (8) per string
+    # k_merge_tile moves at least perm + lcp in (8) and out (8) per string
     # per round; characters are read only where the two heads tie
     alg = d["units"] / d["launches"] * 16.0
     avg_ms = d["total_ms"] / d["launches"]

@@ -28,10 +28,10 @@ enum KernelId {
 };
 const char* const KNAME[K_COUNT] = {"k_init", "k_roots", "k_base_wave1", "k_base_wave2", "k_base_wave4", "k_base",
                                     "k_sample", "k_classify", "k_scan", "k_scatter", "k_children", "k_lcp_fill",
-                                    "k_persist", "k_merge_split", "k_merge_chunks"};
+                                    "k_persist", "k_merge_split", "k_merge_tile"};
 const char* const KUNIT[K_COUNT] = {"strings", "sets", "strings", "strings", "strings", "strings", "segments",
                                     "strings", "counters", "strings", "segments", "boundaries", "strings",
-                                    "chunks", "strings"};
+                                    "tiles", "strings"};
 
 // Event pairs around kernel launches, resolved at the next host sync.
 struct Profiler {
@@ -389,7 +389,7 @@ ss_status run_merge(ss_ctx* ctx, const uint8_t* chars, const uint64_t* offsets, 
     for (uint32_t r = 0; r < num_runs; ++r)
         if (run_begin[r + 1] > run_begin[r]) size.push_back((uint32_t)(run_begin[r + 1] - run_begin[r]));
     std::vector<std::vector<MergeTask>> rounds;
-    std::vector<uint32_t> chunks;
+    std::vector<uint32_t> tiles;  // per round
     do {
         std::vector<MergeTask> tasks;
         std::vector<uint32_t> next;
@@ -397,22 +397,22 @@ ss_status run_merge(ss_ctx* ctx, const uint8_t* chars, const uint64_t* offsets, 
         for (size_t r = 0; r < size.size(); r += 2) {
             const uint32_t na = size[r], nb = r + 1 < size.size() ? size[r + 1] : 0u;
             tasks.push_back(MergeTask{a, na, nb, c0});
-            c0 += (uint32_t)(((uint64_t)na + nb + MERGE_CHUNK - 1) / MERGE_CHUNK);
+            c0 += (uint32_t)(((uint64_t)na + nb + MERGE_TILE - 1) / MERGE_TILE);
             a += na + nb;
             next.push_back(na + nb);
         }
         rounds.push_back(std::move(tasks));
-        chunks.push_back(c0);
+        tiles.push_back(c0);
         size.swap(next);
     } while (size.size() > 1);
     const size_t R = rounds.size();
 
-    size_t n_tasks = 0, max_chunks = 0;
-    for (size_t r = 0; r < R; ++r) n_tasks += rounds[r].size(), max_chunks = std::max<size_t>(max_chunks, chunks[r]);
+    size_t n_tasks = 0, max_tiles = 0;
+    for (size_t r = 0; r < R; ++r) n_tasks += rounds[r].size(), max_tiles = std::max<size_t>(max_tiles, tiles[r]);
     const size_t tmp_bufs = R >= 3 ? 2 : R - 1;  // ping-pong (perm, lcp) pairs between rounds
     const size_t arr = align_up(m * sizeof(uint32_t));
     const size_t off_split = tmp_bufs * 2 * arr;
-    const size_t off_tasks = off_split + align_up(max_chunks * sizeof(uint32_t));
+    const size_t off_tasks = off_split + align_up(max_tiles * sizeof(uint32_t));
     const size_t off_err = off_tasks + align_up(n_tasks * sizeof(MergeTask));
     const size_t dev_bytes = off_err + 256;
     const size_t host_tasks = align_up(n_tasks * sizeof(MergeTask));
@@ -446,11 +446,11 @@ ss_status run_merge(ss_ctx* ctx, const uint8_t* chars, const uint64_t* offsets, 
         a.dst_lcp = r + 1 == R ? lcp_out : tmp_lcp[r & 1];
         a.tasks = dtask + t0;
         a.n_tasks = (uint32_t)rounds[r].size();
-        a.n_chunks = chunks[r];
+        a.n_tiles = tiles[r];
         a.split = (uint32_t*)(dws + off_split);
         a.err = derr;
-        SS_TRY(timed(ctx, s, K_MERGE_SPLIT, a.n_chunks, [&] { return launch_merge_split(a, s); }));
-        SS_TRY(timed(ctx, s, K_MERGE, (double)m, [&] { return launch_merge_chunks(a, s); }));
+        SS_TRY(timed(ctx, s, K_MERGE_SPLIT, a.n_tiles, [&] { return launch_merge_split(a, s); }));
+        SS_TRY(timed(ctx, s, K_MERGE, (double)m, [&] { return launch_merge_tiles(a, s); }));
         t0 += rounds[r].size();
     }
     SS_TRY(hipMemcpyAsync(herr, derr, sizeof(uint32_t), hipMemcpyDeviceToHost, s));

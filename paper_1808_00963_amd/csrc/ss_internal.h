@@ -214,7 +214,8 @@ hipError_t persistent_capacity(int device, uint32_t* blocks);
 
 // ---- LCP-aware merging of sorted runs (ss_merge.hip) ----
 constexpr uint32_t MERGE_BLOCK = 256;
-constexpr uint32_t MERGE_CHUNK = 32;  // outputs per thread of k_merge_chunks
+constexpr uint32_t MERGE_PER = 8;                          // outputs per thread of k_merge_tile
+constexpr uint32_t MERGE_TILE = MERGE_BLOCK * MERGE_PER;   // outputs per work group
 
 enum : uint32_t {
     MERR_INDEX = 1u,     // a perm entry is not below the number of strings
@@ -223,10 +224,10 @@ enum : uint32_t {
 };
 
 // One pair of adjacent runs A = [a, a+na), B = [a+na, a+na+nb) of the source
-// arrays, merged into [a, a+na+nb) of the destination arrays; its chunks
-// are chunk0, chunk0+1, ... (ceil((na+nb)/MERGE_CHUNK) of them).
+// arrays, merged into [a, a+na+nb) of the destination arrays; its tiles of
+// MERGE_TILE outputs are tile0, tile0+1, ... (ceil((na+nb)/MERGE_TILE)).
 struct MergeTask {
-    uint32_t a, na, nb, chunk0;
+    uint32_t a, na, nb, tile0;
 };
 
 struct MergeArgs {
@@ -237,14 +238,14 @@ struct MergeArgs {
     const uint32_t* src_lcp;
     uint32_t* dst_perm;
     uint32_t* dst_lcp;
-    const MergeTask* tasks;  // ordered by chunk0
+    const MergeTask* tasks;  // ordered by tile0
     uint32_t n_tasks;
-    uint32_t n_chunks;
-    uint32_t* split;  // per chunk: outputs taken from A before it
+    uint32_t n_tiles;
+    uint32_t* split;  // per tile: outputs taken from A before it
     uint32_t* err;
 };
 
 hipError_t launch_merge_split(const MergeArgs& m, hipStream_t s);
-hipError_t launch_merge_chunks(const MergeArgs& m, hipStream_t s);
+hipError_t launch_merge_tiles(const MergeArgs& m, hipStream_t s);
 
 }  // namespace ss

@@ -21,7 +21,7 @@ from gpu_util import assert_equal_to_oracle, needs_gpu, to_device, to_host
 
 pytestmark = [pytest.mark.gpu, needs_gpu]
 
-CHUNK = 32  # outputs per thread of the merge kernel
+TILE = 2048  # outputs per work group of the merge kernel (8 per thread)
 
 
 def note(msg):
@@ -94,7 +94,7 @@ def ctx():
 
 
 @pytest.mark.parametrize("k", [1, 2, 3, 5, 8, 17])
-@pytest.mark.parametrize("n", [1, 2, 31, 32, 33, 1000, 20000])
+@pytest.mark.parametrize("n", [1, 2, 9, 1000, TILE - 1, TILE, TILE + 1, 20000])
 @pytest.mark.parametrize("model", ["random", "binary", "markov", "urls"])
 def test_partition_merge_vs_oracle(ctx, model, n, k):
     note(f"case merge model={model} n={n} k={k}")
@@ -111,7 +111,7 @@ def test_suffix_runs(ctx, n):
 
 def test_contiguous_halves_and_ragged_sizes(ctx):
     c, o = gen.generate("markov", 100003, 21)
-    for cut in (0, 1, 32, 50000, 100002, 100003):
+    for cut in (0, 1, 8, TILE, 50000, 100002, 100003):
         note(f"case merge halves cut={cut}")
         check_merge(ctx, c, o, [np.arange(cut), np.arange(cut, 100003)], f"cut={cut}")
 
