@@ -412,7 +412,8 @@ ss_status run_merge(ss_ctx* ctx, const uint8_t* chars, const uint64_t* offsets, 
     const size_t tmp_bufs = R >= 3 ? 2 : R - 1;  // ping-pong (perm, lcp) pairs between rounds
     const size_t arr = align_up(m * sizeof(uint32_t));
     const size_t off_split = tmp_bufs * 2 * arr;
-    const size_t off_tasks = off_split + align_up(max_tiles * sizeof(uint32_t));
+    const size_t off_cross = off_split + align_up(max_tiles * sizeof(uint32_t));
+    const size_t off_tasks = off_cross + align_up(max_tiles * sizeof(uint32_t));
     const size_t off_err = off_tasks + align_up(n_tasks * sizeof(MergeTask));
     const size_t dev_bytes = off_err + 256;
     const size_t host_tasks = align_up(n_tasks * sizeof(MergeTask));
@@ -448,6 +449,7 @@ ss_status run_merge(ss_ctx* ctx, const uint8_t* chars, const uint64_t* offsets, 
         a.n_tasks = (uint32_t)rounds[r].size();
         a.n_tiles = tiles[r];
         a.split = (uint32_t*)(dws + off_split);
+        a.cross = (uint32_t*)(dws + off_cross);
         a.err = derr;
         SS_TRY(timed(ctx, s, K_MERGE_SPLIT, a.n_tiles, [&] { return launch_merge_split(a, s); }));
         SS_TRY(timed(ctx, s, K_MERGE, (double)m, [&] { return launch_merge_tiles(a, s); }));

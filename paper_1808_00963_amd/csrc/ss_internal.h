@@ -242,6 +242,7 @@ struct MergeArgs {
     uint32_t n_tasks;
     uint32_t n_tiles;
     uint32_t* split;  // per tile: outputs taken from A before it
+    uint32_t* cross;  // per tile: LCP of the first strings of its A and B windows
     uint32_t* err;
 };
 
