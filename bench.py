@@ -370,6 +370,65 @@ def run_merge(args):
     }), flush=True)
 
 
+def run_sa(args):
+    """Suffix array by prefix doubling of a seeded ACGT text with planted
+    1 KiB repeats (the text of the suffix workload), 2^24 characters by
+    default (--sa-n); one step = one complete ss_suffix_array call."""
+    import numpy as np
+    import torch
+
+    import gen
+    import paper_1808_00963_amd as ss
+
+    n = args.sa_n
+    t = gen.text("dna", n, 4)
+    text = torch.from_numpy(t).cuda()
+    sa = torch.empty(n, dtype=torch.int32, device="cuda")
+    isa = torch.empty_like(sa)
+    ctx = ss.Context(0)
+    stream = torch.cuda.current_stream()
+    rounds = 0
+    for _ in range(args.warmup):
+        _, _, rounds = ctx.suffix_array(text, sa, isa, stream=stream)
+    ctx.set_profiling(True)
+    ctx.reset_kernel_times()
+    for _ in range(args.steps):
+        ctx.suffix_array(text, sa, isa, stream=stream)
+    torch.cuda.synchronize()
+    ctx.set_profiling(False)
+    kt = ctx.kernel_times()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        _, _, rounds = ctx.suffix_array(text, sa, isa, stream=stream)
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t0) / args.steps
+    for k, v in sorted(kt.items(), key=lambda kv: -kv[1]["total_ms"]):
+        if v["launches"]:
+            print(f"[bench] {k:14s} {v['total_ms'] / args.steps:8.3f} ms/step  launches/step "
+                  f"{v['launches'] / args.steps:5.1f}", file=sys.stderr)
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        ns = min(n, args.cpu_sample if args.cpu_sample > 0 else 1 << 21)
+        a = time.perf_counter()
+        oracle.suffix_array(t[:ns])
+        dt = time.perf_counter() - a
+        cpu = {"value": ns / dt, "unit": "suffixes/s", "cores": 1, "kind": "oracle",
+               "sample": f"suffix array of the first {ns} characters of the text, qsort of suffixes, 1 thread, "
+                         f"{dt:.2f} s"}
+    print(f"[bench] suffix array n={n}: {sec * 1e3:.3f} ms, {rounds} sorts", file=sys.stderr, flush=True)
+    print(json.dumps({
+        "metric": "suffixes/s (suffix array by prefix doubling on the string sorter)", "value": n / sec,
+        "unit": "suffixes/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": sec * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u8", "data": "synthetic",
+        "config": {"workload": f"dna_text_{n}", "text": "ACGT, planted 1 KiB repeats", "n": n, "rounds": rounds,
+                   "parallelism": "single-gpu"},
+        "cpu_baseline": cpu,
+        "kernel_ms_per_step": {k: v["total_ms"] / args.steps for k, v in kt.items() if v["launches"]},
+    }), flush=True)
+
+
 def run_profile(args):
     """Program for hardware-counter runs: 3 streaming copies of 1 GiB (known
     traffic, for calibration) followed by warm-up + timed sorts of the plain
@@ -486,11 +545,12 @@ def run_traffic(args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--mode", choices=["plain", "batch", "serve", "profile", "traffic", "merge"], default="plain")
+    ap.add_argument("--mode", choices=["plain", "batch", "serve", "profile", "traffic", "merge", "sa"], default="plain")
     ap.add_argument("--fetch-csv", help="traffic mode: rocprofv3 counter_collection.csv of the FETCH_SIZE run")
     ap.add_argument("--write-csv", help="traffic mode: rocprofv3 counter_collection.csv of the WRITE_SIZE run")
     ap.add_argument("--pool", type=int, default=128)
     ap.add_argument("--runs", type=int, default=2, help="merge mode: number of sorted runs")
+    ap.add_argument("--sa-n", type=int, default=1 << 24, help="sa mode: text length")
     ap.add_argument("--requests", type=int, default=2000)
     ap.add_argument("--serve-warmup", type=int, default=200)
     ap.add_argument("--sets", type=int, default=4096)
@@ -520,6 +580,9 @@ def main():
         return
     if args.mode == "merge":
         run_merge(args)
+        return
+    if args.mode == "sa":
+        run_sa(args)
         return
 
     import numpy as np

@@ -281,6 +281,41 @@ int ssgen_chars(int model, uint64_t seed, uint32_t n, const uint64_t* offsets, u
     return 0;
 }
 
+/* Texts for suffix sorting.  Kinds: 0 the ACGT text of the "suffixes" model
+ * (with its planted 1 KiB repeats); 1 bytes uniform over 0..255; 2 a
+ * period of 1..16 random lowercase letters repeated, with one random byte
+ * changed per 4096; 3 lowercase letters with Zipf(1.1) frequencies.
+ * Returns 0 on success. */
+int ssgen_text(int kind, uint64_t seed, uint32_t n, uint8_t* out) {
+    if (kind == 0) {
+        uint8_t* T = suffix_text(seed, n);
+        if (!T) return 1;
+        memcpy(out, T, n);
+        free(T);
+        return 0;
+    }
+    rng_t r = rng_for(seed, 401, (uint64_t)kind);
+    if (kind == 1) {
+        for (uint32_t i = 0; i < n; ++i) out[i] = (uint8_t)rng_below(&r, 256);
+        return 0;
+    }
+    if (kind == 2) {
+        uint8_t per[16];
+        uint32_t p = 1 + rng_below(&r, 16);
+        for (uint32_t k = 0; k < p; ++k) per[k] = (uint8_t)('a' + rng_below(&r, 26));
+        for (uint32_t i = 0; i < n; ++i) out[i] = per[i % p];
+        for (uint32_t i = 0; i + 4096 <= n; i += 4096) out[i + rng_below(&r, 4096)] = (uint8_t)rng_below(&r, 256);
+        return 0;
+    }
+    if (kind == 3) {
+        zipf_t z = zipf_make(26, 1.1);
+        for (uint32_t i = 0; i < n; ++i) out[i] = (uint8_t)('a' + zipf_draw(&z, &r));
+        free(z.cdf);
+        return 0;
+    }
+    return 1;
+}
+
 /* Helper for batched/serving workloads: a value log-uniform in [lo, hi]
  * drawn from stream (seed, 7, j). */
 uint64_t ssgen_log_uniform(uint64_t seed, uint64_t j, double lo, double hi) {

@@ -9,7 +9,9 @@ paper: lexicographic order with a proper prefix smaller, the LCP array H with
 its undefined first entry read as 0), with ties broken by original index so
 the answer is unique.  ``check`` verifies a claimed answer against the same
 definition in linear time; since the answer is unique, passing ``check`` is
-equivalent to equality with ``sort``.  See ``ss_oracle.c``.
+equivalent to equality with ``sort``.  ``suffix_array`` and ``h_names`` are
+the definitions of the suffix array and of the h-names of prefix doubling
+(section 8.2) written out.  See ``ss_oracle.c``.
 """
 from __future__ import annotations
 
@@ -56,6 +58,10 @@ def _bind(lib):
     lib.ss_oracle_lcp.argtypes = [vp, vp, u32, u32]
     lib.ss_oracle_compare.restype = ctypes.c_int
     lib.ss_oracle_compare.argtypes = [vp, vp, u32, u32]
+    lib.ss_oracle_suffix_array.restype = ctypes.c_int
+    lib.ss_oracle_suffix_array.argtypes = [vp, u32, vp]
+    lib.ss_oracle_h_names.restype = ctypes.c_int
+    lib.ss_oracle_h_names.argtypes = [vp, u32, ctypes.c_uint64, vp]
     return lib
 
 
@@ -101,6 +107,31 @@ def lcp_of(chars, offsets, a: int, b: int) -> int:
 def compare(chars, offsets, a: int, b: int) -> int:
     chars, offsets = _prep(chars, offsets)
     return int(load().ss_oracle_compare(chars.ctypes.data, offsets.ctypes.data, a, b))
+
+
+def _text(text):
+    t = np.ascontiguousarray(np.frombuffer(text, dtype=np.uint8) if isinstance(text, (bytes, bytearray))
+                             else text, dtype=np.uint8)
+    return t, (t if t.size else np.zeros(1, dtype=np.uint8))
+
+
+def suffix_array(text, lib=None):
+    """Suffix array (uint32[n]) of a byte text, no sentinel appended."""
+    lib = lib or load()
+    t, buf = _text(text)
+    sa = np.zeros(max(t.size, 1), dtype=np.uint32)
+    lib.ss_oracle_suffix_array(buf.ctypes.data, t.size, sa.ctypes.data)
+    return sa[:t.size]
+
+
+def h_names(text, h: int, lib=None):
+    """Lexicographic h-names (smallest rank in h-order) of all suffixes."""
+    lib = lib or load()
+    t, buf = _text(text)
+    names = np.zeros(max(t.size, 1), dtype=np.uint32)
+    if lib.ss_oracle_h_names(buf.ctypes.data, t.size, h, names.ctypes.data) != 0:
+        raise MemoryError("ss_oracle_h_names")
+    return names[:t.size]
 
 
 def describe_check(code: int, n: int) -> str:

@@ -27,6 +27,16 @@
  *   strictly increasing in (string, index) order, and each lcp entry equals
  *   the brute-force common prefix.  Because the correct output is unique,
  *   passing this check is equivalent to equality with ss_oracle_sort.
+ *
+ * Suffix sorting (section 5.1 definitions; section 8.2 h-order and h-names):
+ * ss_oracle_suffix_array: the suffix array of a text T[0..n) written out --
+ *   qsort of the start positions, comparing the suffixes T[i..n) as strings
+ *   (memcmp, then the shorter one first; suffixes are distinct, so no tie
+ *   rule is needed).  No sentinel is appended.
+ * ss_oracle_h_names: the lexicographic h-name of every suffix, defined as
+ *   the smallest rank among the suffixes equal to it in h-order (the order
+ *   of the suffixes truncated to h characters): a qsort by truncated suffix,
+ *   then the first sorted position of each run of equal truncations.
  */
 #define _GNU_SOURCE
 #include <stdint.h>
@@ -112,4 +122,50 @@ uint32_t ss_oracle_lcp(const uint8_t* chars, const uint64_t* offsets, uint32_t a
 int ss_oracle_compare(const uint8_t* chars, const uint64_t* offsets, uint32_t a, uint32_t b) {
     strset_t S = {chars, offsets};
     return cmp_idx(&S, a, b);
+}
+
+/* ---- suffix sorting --------------------------------------------------- */
+
+typedef struct {
+    const uint8_t* text;
+    uint64_t n;
+    uint64_t h; /* compare at most h characters (UINT64_MAX: whole suffixes) */
+} suftext_t;
+
+/* three-way comparison of the suffixes a and b truncated to h characters */
+static int cmp_suffix(const suftext_t* S, uint32_t a, uint32_t b) {
+    uint64_t la = S->n - a, lb = S->n - b;
+    if (la > S->h) la = S->h;
+    if (lb > S->h) lb = S->h;
+    uint64_t m = la < lb ? la : lb;
+    int c = m ? memcmp(S->text + a, S->text + b, (size_t)m) : 0;
+    if (c) return c < 0 ? -1 : 1;
+    if (la != lb) return la < lb ? -1 : 1; /* proper prefix is smaller */
+    return 0;
+}
+
+static int qsort_suffix(const void* pa, const void* pb, void* ctx) {
+    return cmp_suffix((const suftext_t*)ctx, *(const uint32_t*)pa, *(const uint32_t*)pb);
+}
+
+int ss_oracle_suffix_array(const uint8_t* text, uint32_t n, uint32_t* sa) {
+    suftext_t S = {text, n, UINT64_MAX};
+    for (uint32_t i = 0; i < n; ++i) sa[i] = i;
+    qsort_r(sa, n, sizeof(uint32_t), qsort_suffix, &S);
+    return 0;
+}
+
+int ss_oracle_h_names(const uint8_t* text, uint32_t n, uint64_t h, uint32_t* names) {
+    suftext_t S = {text, n, h};
+    uint32_t* order = (uint32_t*)malloc(sizeof(uint32_t) * (n ? n : 1));
+    if (!order) return -1;
+    for (uint32_t i = 0; i < n; ++i) order[i] = i;
+    qsort_r(order, n, sizeof(uint32_t), qsort_suffix, &S);
+    uint32_t first = 0;
+    for (uint32_t k = 0; k < n; ++k) {
+        if (k > 0 && cmp_suffix(&S, order[k - 1], order[k]) != 0) first = k;
+        names[order[k]] = first;
+    }
+    free(order);
+    return 0;
 }

@@ -107,6 +107,7 @@ def lib():
                                   ctypes.POINTER(ctypes.c_double)]),
             "ss_autotune_clear_cache": (None, []),
             "ss_merge_runs": (i32, [vp, vp, vp, u32, vp, vp, ctypes.POINTER(u64), u32, vp, vp, vp]),
+            "ss_suffix_array": (i32, [vp, vp, u32, vp, vp, ctypes.POINTER(u32), vp]),
             "ss_host_key": (u64, [vp, u64, u64, ctypes.POINTER(u32)]),
             "ss_host_level_index": (u32, [u32, u32]),
             "ss_host_inorder_index": (u32, [u32, u32]),
@@ -307,6 +308,23 @@ class Context:
                                  _stream_ptr(stream))
         _check(st, "ss_merge_runs")
         return perm_out, lcp_out
+
+    def suffix_array(self, text, sa=None, isa=None, stream=None):
+        """Suffix array of a uint8 device text by prefix doubling
+        (ss_suffix_array); returns (sa, isa, rounds) with int32 tensors
+        holding uint32."""
+        if not text.is_cuda or text.dtype != torch.uint8 or not text.is_contiguous():
+            raise TypeError("text must be a contiguous uint8 device tensor")
+        n = text.numel()
+        if sa is None:
+            sa = torch.empty(n, dtype=torch.int32, device=text.device)
+        if isa is None:
+            isa = torch.empty(n, dtype=torch.int32, device=text.device)
+        rounds = ctypes.c_uint32(0)
+        st = lib().ss_suffix_array(self._h, ctypes.c_void_p(text.data_ptr()), n, ctypes.c_void_p(sa.data_ptr()),
+                                   ctypes.c_void_p(isa.data_ptr()), ctypes.byref(rounds), _stream_ptr(stream))
+        _check(st, "ss_suffix_array")
+        return sa, isa, rounds.value
 
     def autotune(self, chars, offsets, set_begin=None, perm=None, lcp=None, reps=3, use_cache=True,
                  stream=None):

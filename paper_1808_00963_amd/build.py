@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libss.so")
-SOURCES = ["ss_kernels.hip", "ss_merge.hip", "ss_api.cpp"]
+SOURCES = ["ss_kernels.hip", "ss_merge.hip", "ss_sa.hip", "ss_api.cpp"]
 ARCH = os.environ.get("SS_OFFLOAD_ARCH", "gfx950")
 
 

@@ -24,14 +24,15 @@ using namespace ss;
 namespace {
 enum KernelId {
     K_INIT, K_ROOTS, K_BASE_W1, K_BASE_W2, K_BASE_W4, K_BASE, K_SAMPLE, K_CLASSIFY, K_SCAN, K_SCATTER, K_CHILDREN,
-    K_LCP_FILL, K_PERSIST, K_MERGE_SPLIT, K_MERGE, K_COUNT
+    K_LCP_FILL, K_PERSIST, K_MERGE_SPLIT, K_MERGE, K_SA_STRINGS, K_SA_RENAME, K_COUNT
 };
 const char* const KNAME[K_COUNT] = {"k_init", "k_roots", "k_base_wave1", "k_base_wave2", "k_base_wave4", "k_base",
                                     "k_sample", "k_classify", "k_scan", "k_scatter", "k_children", "k_lcp_fill",
-                                    "k_persist", "k_merge_split", "k_merge_tile"};
+                                    "k_persist", "k_merge_split", "k_merge_tile", "k_sa_strings",
+                                    "k_sa_rename"};
 const char* const KUNIT[K_COUNT] = {"strings", "sets", "strings", "strings", "strings", "strings", "segments",
                                     "strings", "counters", "strings", "segments", "boundaries", "strings",
-                                    "tiles", "strings"};
+                                    "tiles", "strings", "suffixes", "suffixes"};
 
 // Event pairs around kernel launches, resolved at the next host sync.
 struct Profiler {
@@ -66,6 +67,10 @@ struct ss_ctx {
     size_t mws_bytes = 0;
     void* mhost = nullptr;
     size_t mhost_bytes = 0;
+    // suffix-array workspace (grow-only) and a pinned word for the group count
+    void* saws = nullptr;
+    size_t saws_bytes = 0;
+    uint32_t* sa_host = nullptr;
 };
 
 struct ss_graph {
@@ -462,6 +467,92 @@ ss_status run_merge(ss_ctx* ctx, const uint8_t* chars, const uint64_t* offsets, 
     return SS_OK;
 }
 
+// ---- suffix array by prefix doubling ----
+
+ss_status run_suffix_array(ss_ctx* ctx, const uint8_t* text, uint32_t n, uint32_t* sa, uint32_t* isa_out,
+                           uint32_t* rounds_out, hipStream_t s) {
+    const size_t a4 = align_up((size_t)n * 4);
+    const size_t b_chars = align_up((size_t)n * 8);
+    const size_t b_offs = align_up(((size_t)n + 1) * 8);
+    const size_t b_part = align_up(((size_t)sa_tiles(n) + 1) * 4);
+    // chars, offsets, lcp, perm, idx, two position lists, names, two counter arrays
+    const size_t bytes = b_chars + b_offs + 5 * a4 + (isa_out ? 0 : a4) + 2 * b_part;
+    if (ctx->scratch_limit && bytes > ctx->scratch_limit) return SS_OUT_OF_MEMORY;
+    if (bytes > ctx->saws_bytes) {
+        if (ctx->saws) (void)hipFree(ctx->saws);
+        ctx->saws = nullptr;
+        ctx->saws_bytes = 0;
+        if (hipMalloc(&ctx->saws, bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            ctx->saws = nullptr;
+            return SS_OUT_OF_MEMORY;
+        }
+        ctx->saws_bytes = bytes;
+    }
+    if (!ctx->sa_host) {
+        if (hipHostMalloc((void**)&ctx->sa_host, 256, hipHostMallocDefault) != hipSuccess) {
+            (void)hipGetLastError();
+            ctx->sa_host = nullptr;
+            return SS_OUT_OF_MEMORY;
+        }
+    }
+    char* p = (char*)ctx->saws;
+    auto take = [&](size_t b) { char* q = p; p += b; return q; };
+    uint8_t* chars = (uint8_t*)take(b_chars);
+    uint64_t* offsets = (uint64_t*)take(b_offs);
+    uint32_t* lcp = (uint32_t*)take(a4);
+    uint32_t* perm = (uint32_t*)take(a4);
+    uint32_t* idx = (uint32_t*)take(a4);
+    uint32_t* pos[2] = {(uint32_t*)take(a4), (uint32_t*)take(a4)};
+    uint32_t* names = isa_out ? isa_out : (uint32_t*)take(a4);
+    uint32_t* part_max = (uint32_t*)take(b_part);
+    uint32_t* part_cnt = (uint32_t*)take(b_part);
+
+    SaArgs a{};
+    a.n = n;
+    a.sa = sa;
+    a.names = names;
+    a.part_max = part_max;
+    a.part_cnt = part_cnt;
+    // round 0: every suffix by its first 8 characters, sorted into sa
+    SS_TRY(timed(ctx, s, K_SA_STRINGS, n, [&] { return launch_sa_windows(text, n, chars, offsets, s); }));
+    ss_status st = run_sort(ctx, chars, offsets, n, nullptr, 1, sa, lcp, s);
+    if (st != SS_OK) return st;
+    a.perm = sa;
+    a.lcp = lcp;
+    a.m = n;
+    a.round0 = 1;
+    a.idx = nullptr;
+    a.pos = nullptr;
+    a.next_pos = pos[0];
+    uint32_t rounds = 1, cur = 0;
+    uint64_t h = 8;  // depth the names resolve
+    for (;;) {
+        SS_TRY(timed(ctx, s, K_SA_RENAME, a.m, [&] { return launch_sa_rename(a, s); }));
+        SS_TRY(hipMemcpyAsync(ctx->sa_host, part_cnt + sa_tiles(a.m), sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+        SS_TRY(hipStreamSynchronize(s));
+        if (ctx->prof.used) resolve_timings(ctx);
+        const uint32_t m = *ctx->sa_host;  // suffixes still sharing their group
+        if (m == 0) break;
+        if (h >= n || m > n) return SS_INTERNAL;  // suffixes differ within n characters
+        // next round: the m unfinished suffixes by (name, name at +h)
+        a.round0 = 0;
+        a.m = m;
+        a.pos = pos[cur];
+        a.idx = idx;
+        a.next_pos = pos[cur ^ 1];
+        SS_TRY(timed(ctx, s, K_SA_STRINGS, m, [&] { return launch_sa_pairs(a, (uint32_t)h, chars, offsets, s); }));
+        st = run_sort(ctx, chars, offsets, m, nullptr, 1, perm, lcp, s);
+        if (st != SS_OK) return st;
+        a.perm = perm;
+        cur ^= 1;
+        h *= 2;
+        ++rounds;
+    }
+    if (rounds_out) *rounds_out = rounds;
+    return SS_OK;
+}
+
 std::mutex g_mu;
 std::map<int, std::unique_ptr<ss_ctx, void (*)(ss_ctx*)>>* g_ctx = nullptr;
 
@@ -516,6 +607,8 @@ void ss_ctx_destroy(ss_ctx* ctx) {
     if (ctx->host_ctl) (void)hipHostFree(ctx->host_ctl);
     if (ctx->mws) (void)hipFree(ctx->mws);
     if (ctx->mhost) (void)hipHostFree(ctx->mhost);
+    if (ctx->saws) (void)hipFree(ctx->saws);
+    if (ctx->sa_host) (void)hipHostFree(ctx->sa_host);
     (void)hipSetDevice(prev);
     delete ctx;
 }
@@ -840,6 +933,21 @@ ss_status ss_merge_runs(ss_ctx* ctx, const uint8_t* chars, const uint64_t* offse
     if (cur_dev != ctx->device) SS_TRY(hipSetDevice(ctx->device));
     ss_status st = run_merge(ctx, chars, offsets, n_strings, perm, lcp, run_begin, num_runs, perm_out, lcp_out,
                              (hipStream_t)stream);
+    if (st != SS_OK && st != SS_INVALID_ARG) ctx->sticky = st;
+    return st;
+}
+
+ss_status ss_suffix_array(ss_ctx* ctx, const uint8_t* text, uint32_t n, uint32_t* sa_out, uint32_t* isa_out,
+                          uint32_t* rounds_out, void* stream) {
+    if (rounds_out) *rounds_out = 0;
+    if (!ctx) return SS_INVALID_ARG;
+    if (n == 0) return SS_OK;
+    if (n > 0xFFFFFFFEu) return SS_LIMIT;
+    if (!text || !sa_out || (void*)sa_out == (void*)isa_out) return SS_INVALID_ARG;
+    int cur_dev = -1;
+    SS_TRY(hipGetDevice(&cur_dev));
+    if (cur_dev != ctx->device) SS_TRY(hipSetDevice(ctx->device));
+    ss_status st = run_suffix_array(ctx, text, n, sa_out, isa_out, rounds_out, (hipStream_t)stream);
     if (st != SS_OK && st != SS_INVALID_ARG) ctx->sticky = st;
     return st;
 }

@@ -249,4 +249,35 @@ struct MergeArgs {
 hipError_t launch_merge_split(const MergeArgs& m, hipStream_t s);
 hipError_t launch_merge_tiles(const MergeArgs& m, hipStream_t s);
 
+// ---- suffix array by prefix doubling (ss_sa.hip) ----
+constexpr uint32_t SA_BLOCK = 256;
+constexpr uint32_t SA_PER = 16;                     // sorted positions per thread when renaming
+constexpr uint32_t SA_TILE = SA_BLOCK * SA_PER;
+inline uint32_t sa_tiles(uint32_t n) { return (uint32_t)(((uint64_t)n + SA_TILE - 1) / SA_TILE); }
+
+struct SaArgs {
+    const uint32_t* perm;  // the round's sort: permutation of its m strings
+    const uint32_t* lcp;   // and their LCP array
+    uint32_t n;            // text length
+    uint32_t m;            // strings sorted in this round
+    uint32_t round0;       // 1: all suffixes as 8-character windows, sorted straight into sa
+    uint32_t* idx;         // rounds > 0: suffix of string e
+    const uint32_t* pos;   // rounds > 0: suffix-array position of string e (increasing)
+    uint32_t* next_pos;    // positions that stay unfinished, in order
+    uint32_t* sa;          // suffix array (final entries stay in place)
+    uint32_t* names;       // n: name of every suffix (first position of its group)
+    uint32_t* part_max;    // sa_tiles(m) scratch counters
+    uint32_t* part_cnt;    // sa_tiles(m) + 1; [sa_tiles(m)] receives the count of next_pos
+};
+
+// Round-0 strings: window i = text[i .. i + min(8, n - i)), packed, with
+// their n+1 offsets (chars needs 8n bytes at most).
+hipError_t launch_sa_windows(const uint8_t* text, uint32_t n, uint8_t* chars, uint64_t* offsets, hipStream_t s);
+// Name-pair strings of depth h for the m unfinished suffixes at a.pos (also
+// fills a.idx): 8 bytes per string, offsets 8e.
+hipError_t launch_sa_pairs(const SaArgs& a, uint32_t h, uint8_t* chars, uint64_t* offsets, hipStream_t s);
+// After the round's sort: places the suffixes, renames them and lists the
+// unfinished positions (their count goes to part_cnt[sa_tiles(m)]).
+hipError_t launch_sa_rename(const SaArgs& a, hipStream_t s);
+
 }  // namespace ss

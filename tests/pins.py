@@ -261,8 +261,61 @@ def pin_lemma21_bounds(lib):
     return fails
 
 
+def pin_fig81_names(lib):
+    """Figure 8.1: the h-names at h = 1, 2, 4 and the final suffix array."""
+    g = read_golden("fig81_prefix_doubling.txt")
+    t = g["text"].encode()
+    fails = []
+    for h in (1, 2, 4):
+        got = oracle.h_names(t, h, lib=lib).tolist()
+        if got != [int(x) for x in g[f"isa{h}"].split()]:
+            fails.append(f"figure 8.1 ISA^{h} {got}")
+    sa = oracle.suffix_array(t, lib=lib).tolist()
+    if sa != [int(x) for x in g["sa"].split()]:
+        fails.append(f"figure 8.1 SA {sa}")
+    return fails
+
+
+def pin_fig51_suffix_array(lib):
+    """Figure 5.1 without its sentinel: the empty suffix (first in the
+    figure) is not a suffix of T[0..n)."""
+    g = read_golden("fig51_suffix_array.txt")
+    sa = oracle.suffix_array(g["text"].encode(), lib=lib).tolist()
+    want = [int(x) for x in g["sa"].split()][1:]
+    return [] if sa == want else [f"figure 5.1 SA {sa}"]
+
+
+def pin_suffix_brute(lib, seeds=range(8)):
+    """Tiny texts: the suffix array by Python's sort of the suffix slices and
+    the h-names by counting smaller truncations; at h >= n the names are the
+    inverse suffix array."""
+    fails = []
+    for seed in seeds:
+        rng = random.Random(900 + seed)
+        n = rng.choice([0, 1, 2, 5, 13, 40, 97])
+        alphabet = rng.choice([b"a", b"ab", b"\x00\xff", bytes(range(256)), b"acgt"])
+        t = bytes(rng.choice(alphabet) for _ in range(n))
+        want = sorted(range(n), key=lambda i: t[i:])
+        got = oracle.suffix_array(t, lib=lib).tolist()
+        if got != want:
+            fails.append(f"suffix array seed {seed}: {got} != {want}")
+        for h in (1, 2, 3, 8, max(n, 1)):
+            trunc = [t[i:i + h] for i in range(n)]
+            names = [sum(1 for j in range(n) if trunc[j] < trunc[i]) for i in range(n)]
+            got_n = oracle.h_names(t, h, lib=lib).tolist()
+            if got_n != names:
+                fails.append(f"h-names seed {seed} h={h}")
+        inv = [0] * n
+        for r, i in enumerate(want):
+            inv[i] = r
+        if n and oracle.h_names(t, n, lib=lib).tolist() != inv:
+            fails.append(f"names at h=n are not the inverse suffix array, seed {seed}")
+    return fails
+
+
 ALL_PINS = [pin_lemma21, pin_fig51, pin_library_sort, pin_exhaustive, pin_insertion_sort,
-            pin_truncated_suffixes, pin_lemma21_bounds]
+            pin_truncated_suffixes, pin_lemma21_bounds, pin_fig81_names, pin_fig51_suffix_array,
+            pin_suffix_brute]
 
 
 def run_all(lib):

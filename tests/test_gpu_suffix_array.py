@@ -1,0 +1,128 @@
+"""Parity of the HIP suffix array by prefix doubling (section 8.2,
+Observation 8.1, Algorithm 8.1) with the oracle, on the GPU.
+
+The suffix array of a text is unique, so the HIP result is compared element
+by element with the oracle's (a comparison sort of the suffixes, pinned to
+Figures 5.1 and 8.1).  The inverse array must be its inverse, and the number
+of sorting rounds must be the one prefix doubling needs: round r resolves
+depth 8 * 2^r, and the suffixes are all distinct from depth maxLCP + 1 on.
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import gen
+import oracle
+from gpu_util import needs_gpu, to_host
+from pins import read_golden
+
+pytestmark = [pytest.mark.gpu, needs_gpu]
+
+
+def note(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_1808_00963_amd as ss
+    return ss.Context()
+
+
+def gpu_sa(ctx, text):
+    t = torch.from_numpy(np.ascontiguousarray(text, dtype=np.uint8)).cuda()
+    sa, isa, rounds = ctx.suffix_array(t)
+    torch.cuda.synchronize()
+    return to_host(sa), to_host(isa), rounds
+
+
+def expected_rounds(text, sa):
+    """Rounds prefix doubling needs: the first r with 8 * 2^r > max LCP of
+    suffixes adjacent in the suffix array."""
+    t = bytes(text)
+    m = 0
+    for a, b in zip(sa[:-1], sa[1:]):
+        x, y = t[a:], t[b:]
+        k = 0
+        while k < len(x) and k < len(y) and x[k] == y[k]:
+            k += 1
+        m = max(m, k)
+    r = 0
+    while 8 << r <= m:
+        r += 1
+    return r + 1
+
+
+def check(ctx, text, label, rounds=True):
+    n = len(text)
+    sa, isa, r = gpu_sa(ctx, text)
+    want = oracle.suffix_array(text)
+    bad = np.nonzero(sa != want)[0]
+    assert bad.size == 0, f"{label}: SA differs at {bad[:10]} (of {bad.size})"
+    inv = np.empty(n, dtype=np.uint32)
+    inv[want.astype(np.int64)] = np.arange(n, dtype=np.uint32)
+    assert np.array_equal(isa, inv), f"{label}: ISA is not the inverse suffix array"
+    if rounds:
+        assert r == expected_rounds(text, want), f"{label}: {r} rounds"
+    return r
+
+
+def test_figure_8_1(ctx):
+    g = read_golden("fig81_prefix_doubling.txt")
+    t = np.frombuffer(g["text"].encode(), dtype=np.uint8)
+    sa, isa, r = gpu_sa(ctx, t)
+    assert sa.tolist() == [int(x) for x in g["sa"].split()]
+    assert r == 1  # every suffix is distinct within 8 characters
+
+
+def test_figure_5_1(ctx):
+    g = read_golden("fig51_suffix_array.txt")
+    t = np.frombuffer(g["text"].encode(), dtype=np.uint8)
+    sa, _, _ = gpu_sa(ctx, t)
+    assert sa.tolist() == [int(x) for x in g["sa"].split()][1:]  # the figure's empty suffix is not a suffix here
+
+
+@pytest.mark.parametrize("n", [1, 2, 7, 8, 9, 100, 4095, 4096, 4097, 100003])
+@pytest.mark.parametrize("kind", ["dna", "bytes", "zipf"])
+def test_texts_vs_oracle(ctx, kind, n):
+    note(f"case sa kind={kind} n={n}")
+    t = gen.text(kind, n, 50 + n)
+    check(ctx, t, f"{kind}/{n}", rounds=n <= 4097)
+
+
+@pytest.mark.parametrize("n", [100, 5000, 20000])
+def test_periodic_texts(ctx, n):
+    note(f"case sa periodic n={n}")
+    t = gen.text("periodic", n, n)
+    check(ctx, t, f"periodic/{n}", rounds=n <= 5000)
+
+
+@pytest.mark.parametrize("text", [b"a" * 3000, b"ab" * 1500, b"\x00" * 999, b"\xff\x00" * 700,
+                                  b"abcabcabd" * 300, bytes(range(256)) * 8],
+                         ids=["unary", "ab", "zeros", "ff00", "abcabcabd", "all_bytes"])
+def test_repetitive_texts(ctx, text):
+    note(f"case sa repetitive {text[:8]!r} n={len(text)}")
+    check(ctx, np.frombuffer(text, dtype=np.uint8), repr(text[:8]))
+
+
+def test_full_size_dna_2m(ctx):
+    """A 2 Mi-character ACGT text with planted 1 KiB repeats (the text of the
+    suffix workload), element by element against the oracle."""
+    note("case sa full dna n=2^21")
+    t = gen.text("dna", 1 << 21, 4)
+    check(ctx, t, "dna 2M", rounds=False)
+
+
+def test_empty_text_and_context_reuse(ctx):
+    import paper_1808_00963_amd as ss
+    sa, isa, r = ctx.suffix_array(torch.zeros(0, dtype=torch.uint8, device="cuda"))
+    assert sa.numel() == 0 and r == 0
+    # the same context sorts strings afterwards
+    c, o = gen.generate("markov", 5000, 3)
+    from gpu_util import assert_equal_to_oracle, gpu_sort
+    p, l = gpu_sort(c, o, ctx=ctx)
+    assert_equal_to_oracle(c, o, p, l)
+    assert ctx.last_error() == ss.SS_OK

@@ -66,6 +66,12 @@ MUTATIONS = {
     "lcp_without_perm": ("lcp[k] = lcp_brute(&S, perm[k - 1], perm[k]);", "lcp[k] = lcp_brute(&S, k - 1, k);"),
     "lcp_off_by_one": ("while (k < m && sa[k] == sb[k]) ++k;", "while (k < m && sa[k] == sb[k]) ++k; if (k < m) ++k;"),
     "lcp0_bottom": ("if (n) lcp[0] = 0;", "if (n) lcp[0] = n > 1 ? lcp_brute(&S, perm[0], perm[1]) : 0;"),
+    "suffix_prefix_last": ("if (la != lb) return la < lb ? -1 : 1; /* proper prefix is smaller */",
+                           "if (la != lb) return la > lb ? -1 : 1;"),
+    "h_names_by_position": ("names[order[k]] = first;", "names[order[k]] = k;"),
+    "h_truncation_dropped": ("if (la > S->h) la = S->h;", ""),
+    "suffix_one_char_short": ("int c = m ? memcmp(S->text + a, S->text + b, (size_t)m) : 0;",
+                              "int c = m > 1 ? memcmp(S->text + a, S->text + b, (size_t)(m - 1)) : 0;"),
 }
 
 
