@@ -472,7 +472,7 @@ ss_status run_merge(ss_ctx* ctx, const uint8_t* chars, const uint64_t* offsets, 
 ss_status run_suffix_array(ss_ctx* ctx, const uint8_t* text, uint32_t n, uint32_t* sa, uint32_t* isa_out,
                            uint32_t* rounds_out, hipStream_t s) {
     const size_t a4 = align_up((size_t)n * 4);
-    const size_t b_chars = align_up((size_t)n * 8);
+    const size_t b_chars = align_up((size_t)n * std::max<uint32_t>(SA_W0, 8));
     const size_t b_offs = align_up(((size_t)n + 1) * 8);
     const size_t b_part = align_up(((size_t)sa_tiles(n) + 1) * 4);
     // chars, offsets, lcp, perm, idx, two position lists, names, two counter arrays
@@ -514,7 +514,7 @@ ss_status run_suffix_array(ss_ctx* ctx, const uint8_t* text, uint32_t n, uint32_
     a.names = names;
     a.part_max = part_max;
     a.part_cnt = part_cnt;
-    // round 0: every suffix by its first 8 characters, sorted into sa
+    // round 0: every suffix by its first SA_W0 characters, sorted into sa
     SS_TRY(timed(ctx, s, K_SA_STRINGS, n, [&] { return launch_sa_windows(text, n, chars, offsets, s); }));
     ss_status st = run_sort(ctx, chars, offsets, n, nullptr, 1, sa, lcp, s);
     if (st != SS_OK) return st;
@@ -526,7 +526,7 @@ ss_status run_suffix_array(ss_ctx* ctx, const uint8_t* text, uint32_t n, uint32_
     a.pos = nullptr;
     a.next_pos = pos[0];
     uint32_t rounds = 1, cur = 0;
-    uint64_t h = 8;  // depth the names resolve
+    uint64_t h = SA_W0;  // depth the names resolve
     for (;;) {
         SS_TRY(timed(ctx, s, K_SA_RENAME, a.m, [&] { return launch_sa_rename(a, s); }));
         SS_TRY(hipMemcpyAsync(ctx->sa_host, part_cnt + sa_tiles(a.m), sizeof(uint32_t), hipMemcpyDeviceToHost, s));

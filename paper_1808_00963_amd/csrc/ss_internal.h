@@ -253,6 +253,7 @@ hipError_t launch_merge_tiles(const MergeArgs& m, hipStream_t s);
 constexpr uint32_t SA_BLOCK = 256;
 constexpr uint32_t SA_PER = 16;                     // sorted positions per thread when renaming
 constexpr uint32_t SA_TILE = SA_BLOCK * SA_PER;
+constexpr uint32_t SA_W0 = 32;                      // characters per suffix in the first round
 inline uint32_t sa_tiles(uint32_t n) { return (uint32_t)(((uint64_t)n + SA_TILE - 1) / SA_TILE); }
 
 struct SaArgs {
@@ -260,7 +261,7 @@ struct SaArgs {
     const uint32_t* lcp;   // and their LCP array
     uint32_t n;            // text length
     uint32_t m;            // strings sorted in this round
-    uint32_t round0;       // 1: all suffixes as 8-character windows, sorted straight into sa
+    uint32_t round0;       // 1: all suffixes as SA_W0-character windows, sorted straight into sa
     uint32_t* idx;         // rounds > 0: suffix of string e
     const uint32_t* pos;   // rounds > 0: suffix-array position of string e (increasing)
     uint32_t* next_pos;    // positions that stay unfinished, in order
@@ -270,8 +271,8 @@ struct SaArgs {
     uint32_t* part_cnt;    // sa_tiles(m) + 1; [sa_tiles(m)] receives the count of next_pos
 };
 
-// Round-0 strings: window i = text[i .. i + min(8, n - i)), packed, with
-// their n+1 offsets (chars needs 8n bytes at most).
+// Round-0 strings: window i = text[i .. i + min(SA_W0, n - i)), packed, with
+// their n+1 offsets (chars needs SA_W0 * n bytes at most).
 hipError_t launch_sa_windows(const uint8_t* text, uint32_t n, uint8_t* chars, uint64_t* offsets, hipStream_t s);
 // Name-pair strings of depth h for the m unfinished suffixes at a.pos (also
 // fills a.idx): 8 bytes per string, offsets 8e.

@@ -4,9 +4,11 @@
 //
 // Names are the paper's h-names (section 8.2.1): the smallest rank, i.e. the
 // first suffix-array position, of the group of suffixes equal to depth h.
-// Round 0 sorts all suffixes by their first 8 characters: suffix i becomes
-// the string T[i .. i + min(8, n - i)), so a suffix ending inside the window
-// keeps its proper-prefix order.  Each later round, resolving depth 2h from
+// Round 0 sorts all suffixes by their first SA_W0 characters: suffix i
+// becomes the string T[i .. i + min(SA_W0, n - i)), so a suffix ending inside
+// the window keeps its proper-prefix order (a longer first window costs only
+// its copy when suffixes differ early and saves doubling rounds when they do
+// not).  Each later round, resolving depth 2h from
 // depth h, sorts only the suffixes whose group still holds more than one
 // suffix (the others are final and drop out), as the 8-byte strings
 //     BE32(name(i)) . BE32(i + h < n ? name(i + h) + 1 : 0)
@@ -32,19 +34,19 @@ __device__ __forceinline__ uint32_t min_u32(uint32_t a, uint32_t b) { return a <
 __device__ __forceinline__ uint32_t max_u32(uint32_t a, uint32_t b) { return a > b ? a : b; }
 
 // Offset of suffix window i in the round-0 string array: sum over j < i of
-// min(8, n - j).
+// min(SA_W0, n - j).
 __device__ __forceinline__ uint64_t window_offset(uint64_t i, uint64_t n) {
-    const uint64_t a = n > 8 ? n - 8 : 0;  // windows before a are 8 long
-    if (i <= a) return 8 * i;
-    const uint64_t k = i - a;              // windows a .. i-1 have lengths n-a, n-a-1, ...
-    return 8 * a + k * (n - a) - k * (k - 1) / 2;
+    const uint64_t a = n > SA_W0 ? n - SA_W0 : 0;  // windows before a are SA_W0 long
+    if (i <= a) return SA_W0 * i;
+    const uint64_t k = i - a;  // windows a .. i-1 have lengths n-a, n-a-1, ...
+    return SA_W0 * a + k * (n - a) - k * (k - 1) / 2;
 }
 
 // Sorted element k starts a group: the first one, or its LCP with the
 // previous string is shorter than its own length.
 __device__ __forceinline__ bool starts_group(const SaArgs& a, uint32_t k) {
     if (k == 0) return true;
-    const uint32_t len = a.round0 ? min_u32(8u, a.n - a.perm[k]) : 8u;
+    const uint32_t len = a.round0 ? min_u32(SA_W0, a.n - a.perm[k]) : 8u;
     return a.lcp[k] < len;
 }
 
@@ -105,7 +107,7 @@ __global__ __launch_bounds__(SA_BLOCK) void k_sa_windows(const uint8_t* __restri
     const uint64_t off = window_offset(i, n);
     offsets[i] = off;
     if (i == n) return;
-    const uint32_t len = min_u32(8u, n - i);
+    const uint32_t len = min_u32(SA_W0, n - i);
     for (uint32_t b = 0; b < len; ++b) chars[off + b] = text[i + b];
 }
 

@@ -5,7 +5,8 @@ The suffix array of a text is unique, so the HIP result is compared element
 by element with the oracle's (a comparison sort of the suffixes, pinned to
 Figures 5.1 and 8.1).  The inverse array must be its inverse, and the number
 of sorting rounds must be the one prefix doubling needs: round r resolves
-depth 8 * 2^r, and the suffixes are all distinct from depth maxLCP + 1 on.
+depth W0 * 2^r (W0 = 32 characters in the first round), and the suffixes are
+all distinct from depth maxLCP + 1 on.
 """
 import sys
 
@@ -19,6 +20,8 @@ from gpu_util import needs_gpu, to_host
 from pins import read_golden
 
 pytestmark = [pytest.mark.gpu, needs_gpu]
+
+W0 = 32  # characters per suffix in the first round
 
 
 def note(msg):
@@ -40,7 +43,7 @@ def gpu_sa(ctx, text):
 
 
 def expected_rounds(text, sa):
-    """Rounds prefix doubling needs: the first r with 8 * 2^r > max LCP of
+    """Rounds prefix doubling needs: the first r with W0 * 2^r > max LCP of
     suffixes adjacent in the suffix array."""
     t = bytes(text)
     m = 0
@@ -51,7 +54,7 @@ def expected_rounds(text, sa):
             k += 1
         m = max(m, k)
     r = 0
-    while 8 << r <= m:
+    while W0 << r <= m:
         r += 1
     return r + 1
 
@@ -75,7 +78,7 @@ def test_figure_8_1(ctx):
     t = np.frombuffer(g["text"].encode(), dtype=np.uint8)
     sa, isa, r = gpu_sa(ctx, t)
     assert sa.tolist() == [int(x) for x in g["sa"].split()]
-    assert r == 1  # every suffix is distinct within 8 characters
+    assert r == 1  # every suffix is distinct within the first window
 
 
 def test_figure_5_1(ctx):
