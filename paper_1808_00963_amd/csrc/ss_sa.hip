@@ -42,17 +42,34 @@ __device__ __forceinline__ uint64_t window_offset(uint64_t i, uint64_t n) {
     return SA_W0 * a + k * (n - a) - k * (k - 1) / 2;
 }
 
-// Sorted element k starts a group: the first one, or its LCP with the
-// previous string is shorter than its own length.
-__device__ __forceinline__ bool starts_group(const SaArgs& a, uint32_t k) {
+// One tile's permutation and LCP entries (and the next tile's first),
+// staged in LDS with coalesced loads.
+struct SmSaTile {
+    uint32_t perm[SA_TILE + 1];
+    uint32_t lcp[SA_TILE + 1];
+};
+
+__device__ __forceinline__ void stage_tile(const SaArgs& a, SmSaTile& t) {
+    const uint64_t tile0 = (uint64_t)blockIdx.x * SA_TILE;
+    const uint32_t cnt = (uint32_t)min((uint64_t)SA_TILE + 1, (uint64_t)a.m - tile0);
+    for (uint32_t j = threadIdx.x; j < cnt; j += SA_BLOCK) {
+        t.perm[j] = a.perm[tile0 + j];
+        t.lcp[j] = a.lcp[tile0 + j];
+    }
+    __syncthreads();
+}
+
+// Sorted element k (j inside the tile) starts a group: the first one, or its
+// LCP with the previous string is shorter than its own length.
+__device__ __forceinline__ bool starts_group(const SaArgs& a, const SmSaTile& t, uint64_t k, uint32_t j) {
     if (k == 0) return true;
-    const uint32_t len = a.round0 ? min_u32(SA_W0, a.n - a.perm[k]) : 8u;
-    return a.lcp[k] < len;
+    const uint32_t len = a.round0 ? min_u32(SA_W0, a.n - t.perm[j]) : 8u;
+    return t.lcp[j] < len;
 }
 
 // Element k stays for the next round: its group has another element.
-__device__ __forceinline__ bool keeps(const SaArgs& a, uint32_t k) {
-    return !(starts_group(a, k) && (k + 1 == a.m || starts_group(a, k + 1)));
+__device__ __forceinline__ bool keeps(const SaArgs& a, const SmSaTile& t, uint64_t k, uint32_t j) {
+    return !(starts_group(a, t, k, j) && (k + 1 == a.m || starts_group(a, t, k + 1, j + 1)));
 }
 
 struct Scan2 {
@@ -78,17 +95,19 @@ __device__ __forceinline__ Scan2 block_scan2(Scan2 v, Scan2* buf) {
 }
 
 // This thread's elements and their (max group start, kept count).
-__device__ __forceinline__ Scan2 thread_part(const SaArgs& a, uint64_t base, uint32_t* starts, uint32_t* kept) {
+__device__ __forceinline__ Scan2 thread_part(const SaArgs& a, const SmSaTile& t, uint32_t* starts, uint32_t* kept) {
     Scan2 v{0, 0};
     uint32_t s = 0, kb = 0;
+    const uint32_t j0 = threadIdx.x * SA_PER;
+    const uint64_t base = (uint64_t)blockIdx.x * SA_TILE + j0;
     for (uint32_t r = 0; r < SA_PER; ++r) {
         const uint64_t k = base + r;
         if (k >= a.m) break;
-        if (starts_group(a, (uint32_t)k)) {
+        if (starts_group(a, t, k, j0 + r)) {
             s |= 1u << r;
             v.mx = (uint32_t)k;
         }
-        if (keeps(a, (uint32_t)k)) {
+        if (keeps(a, t, k, j0 + r)) {
             kb |= 1u << r;
             ++v.cnt;
         }
@@ -108,7 +127,24 @@ __global__ __launch_bounds__(SA_BLOCK) void k_sa_windows(const uint8_t* __restri
     offsets[i] = off;
     if (i == n) return;
     const uint32_t len = min_u32(SA_W0, n - i);
-    for (uint32_t b = 0; b < len; ++b) chars[off + b] = text[i + b];
+    if (len < SA_W0) {
+        for (uint32_t b = 0; b < len; ++b) chars[off + b] = text[i + b];
+        return;
+    }
+    // a full window starts at a multiple of 8 (off = SA_W0 * i): funnel the
+    // aligned words that hold its characters into aligned stores; every
+    // word read holds at least one character of the window
+    static_assert(SA_W0 % 8 == 0, "window stores are whole words");
+    const uint64_t* src = (const uint64_t*)((uintptr_t)(text + i) & ~(uintptr_t)7);
+    const uint32_t sh = (uint32_t)((uintptr_t)(text + i) & 7);
+    uint64_t* dst = (uint64_t*)(chars + off);
+    uint64_t w = src[0];
+#pragma unroll
+    for (uint32_t q = 0; q < SA_W0 / 8; ++q) {
+        const uint64_t nx = (sh != 0) ? src[q + 1] : 0ull;  // holds window byte 8q + 8 - sh
+        dst[q] = sh ? (w >> (8 * sh)) | (nx << (64 - 8 * sh)) : w;
+        w = sh ? nx : src[q + 1 < SA_W0 / 8 ? q + 1 : q];
+    }
 }
 
 // Name pairs of the unfinished suffixes: element e is the suffix at
@@ -130,12 +166,14 @@ __global__ __launch_bounds__(SA_BLOCK) void k_sa_pairs(SaArgs a, uint32_t h, uin
 // of kept elements.
 __global__ __launch_bounds__(SA_BLOCK) void k_sa_tiles(SaArgs a) {
     __shared__ Scan2 buf[SA_BLOCK];
+    __shared__ SmSaTile t;
+    stage_tile(a, t);
     uint32_t s, kb;
-    const Scan2 v = thread_part(a, (uint64_t)blockIdx.x * SA_TILE + (uint64_t)threadIdx.x * SA_PER, &s, &kb);
-    const Scan2 t = block_scan2(v, buf);
+    const Scan2 v = thread_part(a, t, &s, &kb);
+    const Scan2 tot = block_scan2(v, buf);
     if (threadIdx.x == SA_BLOCK - 1) {
-        a.part_max[blockIdx.x] = t.mx;
-        a.part_cnt[blockIdx.x] = t.cnt;
+        a.part_max[blockIdx.x] = tot.mx;
+        a.part_cnt[blockIdx.x] = tot.cnt;
     }
 }
 
@@ -166,9 +204,12 @@ __global__ __launch_bounds__(SA_BLOCK) void k_sa_scan(uint32_t* part_max, uint32
 // lists the positions of the suffixes that stay unfinished.
 __global__ __launch_bounds__(SA_BLOCK) void k_sa_apply(SaArgs a) {
     __shared__ Scan2 buf[SA_BLOCK];
-    const uint64_t base = (uint64_t)blockIdx.x * SA_TILE + (uint64_t)threadIdx.x * SA_PER;
+    __shared__ SmSaTile t;
+    stage_tile(a, t);
+    const uint32_t j0 = threadIdx.x * SA_PER;
+    const uint64_t base = (uint64_t)blockIdx.x * SA_TILE + j0;
     uint32_t s, kb;
-    const Scan2 v = thread_part(a, base, &s, &kb);
+    const Scan2 v = thread_part(a, t, &s, &kb);
     (void)block_scan2(v, buf);  // leaves the inclusive scan in buf
     // exclusive prefix of this thread inside the tile
     const Scan2 prev = threadIdx.x > 0 ? buf[threadIdx.x - 1] : Scan2{0, 0};
@@ -178,7 +219,7 @@ __global__ __launch_bounds__(SA_BLOCK) void k_sa_apply(SaArgs a) {
         const uint64_t k = base + r;
         if (k >= a.m) break;
         if ((s >> r) & 1u) start = (uint32_t)k;
-        const uint32_t i = a.idx ? a.idx[a.perm[k]] : a.perm[k];
+        const uint32_t i = a.idx ? a.idx[t.perm[j0 + r]] : t.perm[j0 + r];
         const uint32_t p = a.pos ? a.pos[k] : (uint32_t)k;
         if (a.idx) a.sa[p] = i;  // round 0 sorted straight into the suffix array
         a.names[i] = a.pos ? a.pos[start] : start;
