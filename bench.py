@@ -45,7 +45,7 @@ BYTES_PER_UNIT = {
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("ss_kernels.hip", "ss_device.h", "ss_internal.h"):
+    for f in ("ss_kernels.hip", "ss_device.h", "ss_gather.h", "ss_internal.h"):
         with open(os.path.join(ROOT, "paper_1808_00963_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -338,9 +338,10 @@ def run_merge(args):
     ctx.set_profiling(False)
     d = ctx.kernel_times()[dom]
     sec = (t1 - t0) / args.steps
-    # k_merge_tile moves at least perm + lcp in (8) and out (8) per string
-    # per round; characters are read only where the two heads tie
-    alg = d["units"] / d["launches"] * 16.0
+    # k_merge_tile per string and round: perm + lcp in (8) and out (8), the
+    # string's offset pair (16) and one 8-byte word of its characters (8);
+    # the last two are random accesses (a 64-byte HBM burst each)
+    alg = d["units"] / d["launches"] * 40.0
     avg_ms = d["total_ms"] / d["launches"]
     achieved = alg / (avg_ms * 1e-3) / 1e9
     for k, v in sorted(kt.items(), key=lambda kv: -kv[1]["total_ms"]):
