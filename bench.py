@@ -419,12 +419,25 @@ def run_sa(args):
                "sample": f"suffix array of the first {ns} characters of the text, qsort of suffixes, 1 thread, "
                          f"{dt:.2f} s"}
     print(f"[bench] suffix array n={n}: {sec * 1e3:.3f} ms, {rounds} sorts", file=sys.stderr, flush=True)
+    # roofline of the dominant kernel with known algorithmic bytes (the
+    # sorter's), from the breakdown pass's HIP events
+    roof = None
+    known = [k for k in kt if k in BYTES_PER_UNIT and kt[k]["launches"]]
+    if known:
+        dom = max(known, key=lambda k: kt[k]["total_ms"])
+        d = kt[dom]
+        alg = d["units"] / d["launches"] * BYTES_PER_UNIT[dom]
+        avg_ms = d["total_ms"] / d["launches"]
+        ach = alg / (avg_ms * 1e-3) / 1e9
+        roof = {"bound": "hbm", "kernel": dom, "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": ach / HBM_PEAK_GBS, "traffic": None, "alg_bytes_per_launch": alg, "avg_launch_ms": avg_ms}
     print(json.dumps({
         "metric": "suffixes/s (suffix array by prefix doubling on the string sorter)", "value": n / sec,
         "unit": "suffixes/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": sec * 1e3,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u8", "data": "synthetic",
         "config": {"workload": f"dna_text_{n}", "text": "ACGT, planted 1 KiB repeats", "n": n, "rounds": rounds,
                    "parallelism": "single-gpu"},
+        "roofline": roof,
         "cpu_baseline": cpu,
         "kernel_ms_per_step": {k: v["total_ms"] / args.steps for k, v in kt.items() if v["launches"]},
     }), flush=True)
