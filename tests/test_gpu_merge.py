@@ -181,6 +181,34 @@ def test_merge_of_gpu_sorted_halves_equals_gpu_sort(ctx):
         assert_equal_to_oracle(c, o, to_host(mp), to_host(ml), label=f"e2e/{model}")
 
 
+@pytest.mark.parametrize("seed", range(6))
+def test_random_run_counts(ctx, seed):
+    """K from 2 to 64 runs of random sizes over a random model and size."""
+    rng = np.random.default_rng(700 + seed)
+    model = ["random", "markov", "urls", "binary", "bytes"][seed % 5]
+    n = int(rng.integers(1000, 40000))
+    k = int(rng.integers(2, 65))
+    note(f"case merge random runs seed={seed} model={model} n={n} k={k}")
+    c, o = gen.generate(model, n, 900 + seed)
+    check_merge(ctx, c, o, random_partition(n, k, seed), f"seed {seed}")
+
+
+def test_many_gpu_sorted_runs_equal_gpu_sort(ctx):
+    """End to end with 37 runs: the batched sort sorts 37 contiguous sets,
+    the merge joins them; equals the oracle's sort of the whole set."""
+    c, o = gen.generate("urls", 120000, 23)
+    n = len(o) - 1
+    cd, od = to_device(c, o)
+    rb = [n * r // 37 for r in range(38)]
+    sb = torch.tensor(rb, dtype=torch.int32, device="cuda")
+    p, l = ctx.sort_batch(cd, od, sb)
+    for r in range(37):
+        p[rb[r]:rb[r + 1]] += rb[r]
+    mp, ml = ctx.merge_runs(cd, od, p, l, rb)
+    torch.cuda.synchronize()
+    assert_equal_to_oracle(c, o, to_host(mp), to_host(ml), label="37 runs")
+
+
 def test_full_size_c1_halves(ctx):
     """16M Markov strings: sorted halves merged, verified by the oracle's
     linear-time check (the answer is unique)."""

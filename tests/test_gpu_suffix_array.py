@@ -119,6 +119,29 @@ def test_full_size_dna_2m(ctx):
     check(ctx, t, "dna 2M", rounds=False)
 
 
+@pytest.mark.parametrize("kind,n", [("bytes", 1 << 20), ("zipf", 1 << 20), ("periodic", 100000)])
+def test_large_texts(ctx, kind, n):
+    note(f"case sa large kind={kind} n={n}")
+    check(ctx, gen.text(kind, n, 77), f"{kind}/{n}", rounds=False)
+
+
+def test_isa_may_be_omitted_and_buffers_reused(ctx):
+    """The context's workspace is reused across texts of different sizes;
+    the inverse array can stay internal (NULL from C)."""
+    import ctypes
+
+    import paper_1808_00963_amd as ss
+    for n in (50000, 3000, 70000):
+        t = gen.text("dna", n, n)
+        td = torch.from_numpy(t).cuda()
+        sa = torch.empty(n, dtype=torch.int32, device="cuda")
+        st = ss.lib().ss_suffix_array(ctx._h, ctypes.c_void_p(td.data_ptr()), n, ctypes.c_void_p(sa.data_ptr()),
+                                      None, None, None)
+        assert st == ss.SS_OK
+        torch.cuda.synchronize()
+        assert np.array_equal(to_host(sa), oracle.suffix_array(t)), f"n={n}"
+
+
 def test_empty_text_and_context_reuse(ctx):
     import paper_1808_00963_amd as ss
     sa, isa, r = ctx.suffix_array(torch.zeros(0, dtype=torch.uint8, device="cuda"))
