@@ -198,7 +198,9 @@ ss_status ss_merge_runs(ss_ctx* ctx, const uint8_t* chars, const uint64_t* offse
 /* Suffix array of a byte text by prefix doubling (section 8.2: Observation
  * 8.1, Algorithm 8.1, with the discarding of section 8.2.5), every round
  * being one sort of the context's string sorter.  Round 0 sorts the suffixes
- * by their first 32 characters; each later round sorts, for every suffix
+ * by their first 32 characters (64 or 128 for texts of at most 4 or 2
+ * distinct bytes, whose windows are alphabet compressed); each later round
+ * sorts, for every suffix
  * whose group (suffixes equal to depth h) has other members, the 8-byte
  * string of its name and the name of suffix i + h (names: first suffix-array
  * position of the group), doubling h, until every suffix has its own
@@ -207,7 +209,9 @@ ss_status ss_merge_runs(ss_ctx* ctx, const uint8_t* chars, const uint64_t* offse
  * text: device, n bytes; sa_out: device, n uint32 (the suffix array);
  * isa_out: device, n uint32 (its inverse) or NULL; rounds_out: host, the
  * number of sorts run (may be NULL).  The workspace (about 64 n bytes plus
- * the sort's) is kept by the context.  SS_LIMIT for n > 2^32 - 2.
+ * the sort's) is kept by the context; the sorts use the context's
+ * configuration with a bucket target of at least 256.  SS_LIMIT for
+ * n > 2^32 - 2.
  * Synchronizes `stream` once per round and before returning. */
 ss_status ss_suffix_array(ss_ctx* ctx, const uint8_t* text, uint32_t n, uint32_t* sa_out, uint32_t* isa_out,
                           uint32_t* rounds_out, void* stream);

@@ -472,11 +472,12 @@ ss_status run_merge(ss_ctx* ctx, const uint8_t* chars, const uint64_t* offsets, 
 ss_status run_suffix_array(ss_ctx* ctx, const uint8_t* text, uint32_t n, uint32_t* sa, uint32_t* isa_out,
                            uint32_t* rounds_out, hipStream_t s) {
     const size_t a4 = align_up((size_t)n * 4);
-    const size_t b_chars = align_up((size_t)n * std::max<uint32_t>(SA_W0, 8));
+    const size_t b_chars = align_up((size_t)n * std::max<uint32_t>(std::max(SA_W0, SA_PACKED_LEN), 8));
+    static_assert(SA_PACKED_LEN % 8 == 0, "packed windows are whole words");
     const size_t b_offs = align_up(((size_t)n + 1) * 8);
     const size_t b_part = align_up(((size_t)sa_tiles(n) + 1) * 4);
     // chars, offsets, lcp, perm, idx, two position lists, names, two counter arrays
-    const size_t bytes = b_chars + b_offs + 5 * a4 + (isa_out ? 0 : a4) + 2 * b_part;
+    const size_t bytes = b_chars + b_offs + 5 * a4 + (isa_out ? 0 : a4) + 2 * b_part + 512;
     if (ctx->scratch_limit && bytes > ctx->scratch_limit) return SS_OUT_OF_MEMORY;
     if (bytes > ctx->saws_bytes) {
         if (ctx->saws) (void)hipFree(ctx->saws);
@@ -490,7 +491,8 @@ ss_status run_suffix_array(ss_ctx* ctx, const uint8_t* text, uint32_t n, uint32_
         ctx->saws_bytes = bytes;
     }
     if (!ctx->sa_host) {
-        if (hipHostMalloc((void**)&ctx->sa_host, 256, hipHostMallocDefault) != hipSuccess) {
+        // [0]: group count; [8..16): byte mask; bytes 64..320: rank table
+        if (hipHostMalloc((void**)&ctx->sa_host, 512, hipHostMallocDefault) != hipSuccess) {
             (void)hipGetLastError();
             ctx->sa_host = nullptr;
             return SS_OUT_OF_MEMORY;
@@ -507,6 +509,17 @@ ss_status run_suffix_array(ss_ctx* ctx, const uint8_t* text, uint32_t n, uint32_
     uint32_t* names = isa_out ? isa_out : (uint32_t*)take(a4);
     uint32_t* part_max = (uint32_t*)take(b_part);
     uint32_t* part_cnt = (uint32_t*)take(b_part);
+    uint32_t* mask = (uint32_t*)take(256);  // 8 words of byte presence
+    uint8_t* rank = (uint8_t*)take(256);    // byte -> rank among the bytes present
+
+    // the suffix windows and name pairs split into many small buckets; the
+    // sorts run with a bucket target of at least 256 strings
+    struct CfgGuard {
+        ss_ctx* c;
+        ss_config saved;
+        ~CfgGuard() { c->cfg = saved; }
+    } guard{ctx, ctx->cfg};
+    ctx->cfg.bucket_target = std::max<uint32_t>(ctx->cfg.bucket_target, 256u);
 
     SaArgs a{};
     a.n = n;
@@ -514,19 +527,42 @@ ss_status run_suffix_array(ss_ctx* ctx, const uint8_t* text, uint32_t n, uint32_
     a.names = names;
     a.part_max = part_max;
     a.part_cnt = part_cnt;
-    // round 0: every suffix by its first SA_W0 characters, sorted into sa
-    SS_TRY(timed(ctx, s, K_SA_STRINGS, n, [&] { return launch_sa_windows(text, n, chars, offsets, s); }));
+    // the text's alphabet: at most 16 distinct bytes are packed in round 0
+    SS_TRY(hipMemsetAsync(mask, 0, 8 * sizeof(uint32_t), s));
+    SS_TRY(launch_sa_alphabet(text, n, mask, s));
+    uint32_t* hmask = ctx->sa_host + 8;
+    uint8_t* hrank = (uint8_t*)ctx->sa_host + 64;
+    SS_TRY(hipMemcpyAsync(hmask, mask, 8 * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    SS_TRY(hipStreamSynchronize(s));
+    uint32_t sigma = 0;
+    for (uint32_t v = 0; v < 256; ++v) {
+        hrank[v] = (uint8_t)sigma;
+        if ((hmask[v >> 5] >> (v & 31)) & 1u) ++sigma;
+    }
+    uint32_t bits = 1;  // 1, 2 or 4 bits per character (ranks fit; 64 / bits whole characters per word)
+    while ((1u << bits) < sigma) bits *= 2;
+    const bool packed = bits <= 4;
+    const uint32_t w0 = packed ? 128 / bits : SA_W0;  // characters resolved by round 0
+    // round 0: every suffix by its first w0 characters, sorted into sa
+    SS_TRY(timed(ctx, s, K_SA_STRINGS, n, [&] {
+        if (!packed) return launch_sa_windows(text, n, chars, offsets, s);
+        hipError_t e = hipMemcpyAsync(rank, hrank, 256, hipMemcpyHostToDevice, s);
+        if (e != hipSuccess) return e;
+        // the packed blocks live in the LCP buffer until round 0's sort
+        return launch_sa_windows_packed(text, n, rank, bits, (uint64_t*)lcp, chars, offsets, s);
+    }));
     ss_status st = run_sort(ctx, chars, offsets, n, nullptr, 1, sa, lcp, s);
     if (st != SS_OK) return st;
     a.perm = sa;
     a.lcp = lcp;
     a.m = n;
     a.round0 = 1;
+    a.round0_len = packed ? SA_PACKED_LEN : 0u;
     a.idx = nullptr;
     a.pos = nullptr;
     a.next_pos = pos[0];
     uint32_t rounds = 1, cur = 0;
-    uint64_t h = SA_W0;  // depth the names resolve
+    uint64_t h = w0;  // depth the names resolve
     for (;;) {
         SS_TRY(timed(ctx, s, K_SA_RENAME, a.m, [&] { return launch_sa_rename(a, s); }));
         SS_TRY(hipMemcpyAsync(ctx->sa_host, part_cnt + sa_tiles(a.m), sizeof(uint32_t), hipMemcpyDeviceToHost, s));

@@ -254,6 +254,11 @@ constexpr uint32_t SA_BLOCK = 256;
 constexpr uint32_t SA_PER = 16;                     // sorted positions per thread when renaming
 constexpr uint32_t SA_TILE = SA_BLOCK * SA_PER;
 constexpr uint32_t SA_W0 = 32;                      // characters per suffix in the first round
+constexpr uint32_t SA_PACKED_LEN = 24;              // bytes of an alphabet-compressed first-round window
+static_assert(SA_BLOCK == 256, "the packing kernel stages one rank per thread");
+// Words of packed ranks for a text of n characters at b bits (two extra
+// words of zeros so every window can read three).
+inline uint32_t sa_pack_blocks(uint32_t n, uint32_t b) { return (uint32_t)(((uint64_t)n + 64 / b - 1) / (64 / b) + 2); }
 inline uint32_t sa_tiles(uint32_t n) { return (uint32_t)(((uint64_t)n + SA_TILE - 1) / SA_TILE); }
 
 struct SaArgs {
@@ -261,7 +266,8 @@ struct SaArgs {
     const uint32_t* lcp;   // and their LCP array
     uint32_t n;            // text length
     uint32_t m;            // strings sorted in this round
-    uint32_t round0;       // 1: all suffixes as SA_W0-character windows, sorted straight into sa
+    uint32_t round0;       // 1: all suffixes as first-round windows, sorted straight into sa
+    uint32_t round0_len;   // round 0: string length of a packed window, 0 for plain SA_W0-character windows
     uint32_t* idx;         // rounds > 0: suffix of string e
     const uint32_t* pos;   // rounds > 0: suffix-array position of string e (increasing)
     uint32_t* next_pos;    // positions that stay unfinished, in order
@@ -274,6 +280,16 @@ struct SaArgs {
 // Round-0 strings: window i = text[i .. i + min(SA_W0, n - i)), packed, with
 // their n+1 offsets (chars needs SA_W0 * n bytes at most).
 hipError_t launch_sa_windows(const uint8_t* text, uint32_t n, uint8_t* chars, uint64_t* offsets, hipStream_t s);
+// Byte values present in the text: atomically ORed into mask[8] (zeroed by
+// the caller).
+hipError_t launch_sa_alphabet(const uint8_t* text, uint32_t n, uint32_t* mask, hipStream_t s);
+// Round-0 strings of a text of at most 16 distinct bytes: the ranks
+// (rank[256]) of the 128 / b characters from i on, b in {1, 2, 4} bits
+// each, in 16 bytes, then a word holding the count min(128 / b, n - i)
+// (SA_PACKED_LEN bytes per suffix).  blocks: sa_pack_blocks(n, b) words of
+// scratch.
+hipError_t launch_sa_windows_packed(const uint8_t* text, uint32_t n, const uint8_t* rank, uint32_t b,
+                                    uint64_t* blocks, uint8_t* chars, uint64_t* offsets, hipStream_t s);
 // Name-pair strings of depth h for the m unfinished suffixes at a.pos (also
 // fills a.idx): 8 bytes per string, offsets 8e.
 hipError_t launch_sa_pairs(const SaArgs& a, uint32_t h, uint8_t* chars, uint64_t* offsets, hipStream_t s);

@@ -8,7 +8,15 @@
 // becomes the string T[i .. i + min(SA_W0, n - i)), so a suffix ending inside
 // the window keeps its proper-prefix order (a longer first window costs only
 // its copy when suffixes differ early and saves doubling rounds when they do
-// not).  Each later round, resolving depth 2h from
+// not).  For a text of at most 16 distinct bytes the window is alphabet
+// compressed instead (one of the refinements the paper proposes for string
+// sample sort, §4.6): each byte becomes its rank among the bytes present,
+// b = 1, 2 or 4 bits (the smallest power of two that holds sigma ranks), and
+// 128 / b characters are packed big-endian into 16 bytes, followed by a word
+// holding the window's character count; the packed codes order the windows
+// as the characters do, zero padding makes a shorter window sort first
+// unless its continuation is all rank-0 characters, and the count settles
+// that case.  Each later round, resolving depth 2h from
 // depth h, sorts only the suffixes whose group still holds more than one
 // suffix (the others are final and drop out), as the 8-byte strings
 //     BE32(name(i)) . BE32(i + h < n ? name(i + h) + 1 : 0)
@@ -63,7 +71,7 @@ __device__ __forceinline__ void stage_tile(const SaArgs& a, SmSaTile& t) {
 // LCP with the previous string is shorter than its own length.
 __device__ __forceinline__ bool starts_group(const SaArgs& a, const SmSaTile& t, uint64_t k, uint32_t j) {
     if (k == 0) return true;
-    const uint32_t len = a.round0 ? min_u32(SA_W0, a.n - t.perm[j]) : 8u;
+    const uint32_t len = !a.round0 ? 8u : a.round0_len ? a.round0_len : min_u32(SA_W0, a.n - t.perm[j]);
     return t.lcp[j] < len;
 }
 
@@ -145,6 +153,65 @@ __global__ __launch_bounds__(SA_BLOCK) void k_sa_windows(const uint8_t* __restri
         dst[q] = sh ? (w >> (8 * sh)) | (nx << (64 - 8 * sh)) : w;
         w = sh ? nx : src[q + 1 < SA_W0 / 8 ? q + 1 : q];
     }
+}
+
+// Which byte values occur in the text (bit v of mask[v / 32]).
+__global__ __launch_bounds__(SA_BLOCK) void k_sa_alphabet(const uint8_t* __restrict__ text, uint32_t n,
+                                                         uint32_t* __restrict__ mask) {
+    __shared__ uint32_t seen[8];
+    if (threadIdx.x < 8) seen[threadIdx.x] = 0;
+    __syncthreads();
+    const uint32_t stride = gridDim.x * SA_BLOCK;
+    for (uint32_t i = blockIdx.x * SA_BLOCK + threadIdx.x; i < n; i += stride) {
+        const uint32_t v = text[i];
+        atomicOr(&seen[v >> 5], 1u << (v & 31));
+    }
+    __syncthreads();
+    if (threadIdx.x < 8 && seen[threadIdx.x]) atomicOr(&mask[threadIdx.x], seen[threadIdx.x]);
+}
+
+// Packed ranks of 64 / b consecutive characters per word: block q holds
+// the characters from q * 64 / b on, the first at the top; positions past
+// the text are rank 0.
+__global__ __launch_bounds__(SA_BLOCK) void k_sa_pack_blocks(const uint8_t* __restrict__ text, uint32_t n,
+                                                            const uint8_t* __restrict__ rank, uint32_t b,
+                                                            uint32_t n_blocks, uint64_t* __restrict__ blocks) {
+    __shared__ uint8_t rk[256];
+    rk[threadIdx.x] = rank[threadIdx.x];  // SA_BLOCK == 256
+    __syncthreads();
+    const uint32_t q = blockIdx.x * SA_BLOCK + threadIdx.x;
+    if (q >= n_blocks) return;
+    const uint32_t per = 64 / b;
+    const uint64_t i0 = (uint64_t)q * per;
+    uint64_t w = 0;
+    for (uint32_t c = 0; c < per; ++c) {
+        const uint64_t i = i0 + c;
+        w = (w << b) | (i < n ? rk[text[i]] : 0u);
+    }
+    blocks[q] = w;
+}
+
+// Round-0 strings of a small alphabet: window i = ranks of the 128 / b
+// characters from i on (rank 0 past the end) as 16 big-endian bytes, then
+// the count min(128 / b, n - i) in the top byte of a third word;
+// SA_PACKED_LEN bytes per suffix, every word aligned.
+__global__ __launch_bounds__(SA_BLOCK) void k_sa_windows_packed(const uint64_t* __restrict__ blocks, uint32_t n,
+                                                               uint32_t b, uint64_t* __restrict__ out,
+                                                               uint64_t* __restrict__ offsets) {
+    const uint32_t i = blockIdx.x * SA_BLOCK + threadIdx.x;
+    if (i > n) return;
+    offsets[i] = (uint64_t)SA_PACKED_LEN * i;
+    if (i == n) return;
+    const uint32_t per = 64 / b;
+    const uint32_t q = i / per, sh = (i % per) * b;
+    const uint64_t w0 = blocks[q], w1 = blocks[q + 1], w2 = blocks[q + 2];
+    const uint64_t hi = sh ? (w0 << sh) | (w1 >> (64 - sh)) : w0;
+    const uint64_t lo = sh ? (w1 << sh) | (w2 >> (64 - sh)) : w1;
+    const uint64_t k = min_u32(2 * per, n - i);
+    uint64_t* p = out + (uint64_t)(SA_PACKED_LEN / 8) * i;
+    p[0] = __builtin_bswap64(hi);
+    p[1] = __builtin_bswap64(lo);
+    p[2] = __builtin_bswap64(k << 56);
 }
 
 // Name pairs of the unfinished suffixes: element e is the suffix at
@@ -230,6 +297,24 @@ __global__ __launch_bounds__(SA_BLOCK) void k_sa_apply(SaArgs a) {
 hipError_t launch_sa_windows(const uint8_t* text, uint32_t n, uint8_t* chars, uint64_t* offsets, hipStream_t s) {
     const uint32_t nb = (uint32_t)(((uint64_t)n + 1 + SA_BLOCK - 1) / SA_BLOCK);
     hipLaunchKernelGGL(k_sa_windows, dim3(nb), dim3(SA_BLOCK), 0, s, text, n, chars, offsets);
+    return hipGetLastError();
+}
+
+hipError_t launch_sa_alphabet(const uint8_t* text, uint32_t n, uint32_t* mask, hipStream_t s) {
+    const uint32_t nb = (uint32_t)std::min<uint64_t>(((uint64_t)n + SA_BLOCK - 1) / SA_BLOCK, 2048u);
+    hipLaunchKernelGGL(k_sa_alphabet, dim3(nb ? nb : 1), dim3(SA_BLOCK), 0, s, text, n, mask);
+    return hipGetLastError();
+}
+
+hipError_t launch_sa_windows_packed(const uint8_t* text, uint32_t n, const uint8_t* rank, uint32_t b,
+                                    uint64_t* blocks, uint8_t* chars, uint64_t* offsets, hipStream_t s) {
+    const uint32_t n_blocks = sa_pack_blocks(n, b);
+    hipLaunchKernelGGL(k_sa_pack_blocks, dim3((n_blocks + SA_BLOCK - 1) / SA_BLOCK), dim3(SA_BLOCK), 0, s, text, n,
+                       rank, b, n_blocks, blocks);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const uint32_t nb = (uint32_t)(((uint64_t)n + 1 + SA_BLOCK - 1) / SA_BLOCK);
+    hipLaunchKernelGGL(k_sa_windows_packed, dim3(nb), dim3(SA_BLOCK), 0, s, blocks, n, b, (uint64_t*)chars, offsets);
     return hipGetLastError();
 }
 

@@ -5,8 +5,10 @@ The suffix array of a text is unique, so the HIP result is compared element
 by element with the oracle's (a comparison sort of the suffixes, pinned to
 Figures 5.1 and 8.1).  The inverse array must be its inverse, and the number
 of sorting rounds must be the one prefix doubling needs: round r resolves
-depth W0 * 2^r (W0 = 32 characters in the first round), and the suffixes are
-all distinct from depth maxLCP + 1 on.
+depth W0 * 2^r, and the suffixes are all distinct from depth maxLCP + 1 on.
+W0, the first round's window, is 32 characters, or 128 / b characters for a
+text of sigma <= 16 distinct bytes, b = 1, 2 or 4 bits per character, the
+smallest that holds sigma ranks (alphabet compression).
 """
 import sys
 
@@ -21,7 +23,12 @@ from pins import read_golden
 
 pytestmark = [pytest.mark.gpu, needs_gpu]
 
-W0 = 32  # characters per suffix in the first round
+def first_window(text):
+    sigma = len(set(bytes(text)))
+    b = 1
+    while (1 << b) < sigma:
+        b *= 2
+    return 128 // b if b <= 4 else 32
 
 
 def note(msg):
@@ -46,6 +53,7 @@ def expected_rounds(text, sa):
     """Rounds prefix doubling needs: the first r with W0 * 2^r > max LCP of
     suffixes adjacent in the suffix array."""
     t = bytes(text)
+    w0 = first_window(t)
     m = 0
     for a, b in zip(sa[:-1], sa[1:]):
         x, y = t[a:], t[b:]
@@ -54,7 +62,7 @@ def expected_rounds(text, sa):
             k += 1
         m = max(m, k)
     r = 0
-    while W0 << r <= m:
+    while w0 << r <= m:
         r += 1
     return r + 1
 
@@ -104,8 +112,10 @@ def test_periodic_texts(ctx, n):
 
 
 @pytest.mark.parametrize("text", [b"a" * 3000, b"ab" * 1500, b"\x00" * 999, b"\xff\x00" * 700,
-                                  b"abcabcabd" * 300, bytes(range(256)) * 8],
-                         ids=["unary", "ab", "zeros", "ff00", "abcabcabd", "all_bytes"])
+                                  b"abcabcabd" * 300, bytes(range(256)) * 8, bytes(range(16)) * 300,
+                                  bytes(range(17)) * 300, b"\x00\x01\x00\x00\x01" * 500],
+                         ids=["unary", "ab", "zeros", "ff00", "abcabcabd", "all_bytes", "sigma16", "sigma17",
+                              "zero_ranks"])
 def test_repetitive_texts(ctx, text):
     note(f"case sa repetitive {text[:8]!r} n={len(text)}")
     check(ctx, np.frombuffer(text, dtype=np.uint8), repr(text[:8]))
