@@ -10,7 +10,7 @@
 // its copy when suffixes differ early and saves doubling rounds when they do
 // not).  For a text of at most 16 distinct bytes the window is alphabet
 // compressed instead (one of the refinements the paper proposes for string
-// sample sort, §4.6): each byte becomes its rank among the bytes present,
+// sample sort, §4.6.1): each byte becomes its rank among the bytes present,
 // b = 1, 2 or 4 bits (the smallest power of two that holds sigma ranks), and
 // 128 / b characters are packed big-endian into 16 bytes, followed by a word
 // holding the window's character count; the packed codes order the windows
