@@ -44,10 +44,16 @@ BYTES_PER_UNIT = {
 
 
 def kernel_source_hash() -> str:
+    """Hash of the sort kernels' sources with comments and blank space
+    removed (a comment edit does not change the code the counters saw)."""
+    import re
     h = hashlib.sha256()
     for f in ("ss_kernels.hip", "ss_device.h", "ss_gather.h", "ss_internal.h"):
-        with open(os.path.join(ROOT, "paper_1808_00963_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_1808_00963_amd", "csrc", f)) as fh:
+            src = fh.read()
+        src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
+        src = re.sub(r"//[^\n]*", " ", src)
+        h.update(" ".join(src.split()).encode())
     return h.hexdigest()[:16]
 
 

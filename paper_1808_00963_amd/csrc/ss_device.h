@@ -68,7 +68,7 @@ SS_HD uint32_t inorder_index(uint32_t l, uint32_t d) {
     return (rank << (t + 1)) + (1u << t) - 1;
 }
 
-// Classification (Algorithm 4.1, lines 7-11, with the comparison of line 9
+// Classification (Algorithm 4.1, with the comparison of its descent step
 // taken as "go right when c is greater than the splitter"): descend the
 // level-order tree tk/tr (one-based, v = 2^d - 1 vertices) using only
 // comparisons, giving j = number of splitters smaller than c, then test c

@@ -838,7 +838,7 @@ __device__ __forceinline__ void sample_sort(const Work& w, const Params& p, int 
     }
 }
 
-// Algorithm 4.1 lines 1-5: a regular sample of alpha(v+1)-1 keys (alpha =
+// The sampling step of Algorithm 4.1: a regular sample of alpha(v+1)-1 keys (alpha =
 // 2) is sorted (sample_sort); splitters are chosen by recursive middle selection
 // skipping duplicates (section 4.2.2, "Sampling"), level by level, directly
 // into the level-order tree; an empty sub-range repeats its parent's
@@ -909,7 +909,7 @@ struct TreeView {
     const uint32_t* r;
 };
 
-// Algorithm 4.1 lines 6-14 for one tile (Theorem 4.4: every tile keeps its
+// The classification and counting steps of Algorithm 4.1 for one tile (Theorem 4.4: every tile keeps its
 // own bucket counters): each string's bucket is stored in the oracle array
 // `bkt`, the tile's 2v+1 counts go to the counter pool in bucket-major
 // order (bucket b of tile t of segment s at cnt_off + b*T + t).
@@ -1058,7 +1058,7 @@ __global__ __launch_bounds__(BLOCK) void k_scan_down(uint32_t* x, uint32_t n, co
 // distribution step: stable scatter
 // ---------------------------------------------------------------------------
 
-// Algorithm 4.1 line 16 for one tile, out of place into the other buffer
+// The distribution step of Algorithm 4.1 for one tile, out of place into the other buffer
 // (section 4.2.8, "Out-of-place Redistribution").  Each wave owns a
 // contiguous quarter of the tile; within a wave, strings with the same
 // bucket are ranked by lane order through a ballot-built peer mask, so the
