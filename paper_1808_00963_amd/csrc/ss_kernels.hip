@@ -1158,32 +1158,45 @@ __device__ void dev_scatter(const Work& w, const Params& p, int cur, uint32_t t,
 }
 
 // Level-by-level form of the scatter: one work group of 1024 threads per
-// tile stages the whole tile in LDS in bucket order before writing, so each
-// bucket's part of the tile leaves as one contiguous run (whole lines
-// instead of scattered 16-byte pieces).  Same output as dev_scatter.
-//   1. every wave loads its 512-record chunk (8 per lane) and bucket ids;
+// half of a classification tile (SC_TILE records) stages its records in LDS
+// in bucket order before writing, so each bucket's part leaves as one
+// contiguous run (whole lines instead of scattered 16-byte pieces).  Half
+// tiles let two groups share a compute unit, so one group's loads overlap
+// the other's stores.  Same output as dev_scatter.
+//   1. every wave loads its 256-record chunk (4 per lane) and bucket ids;
+//      the second half also counts the first half's buckets from the
+//      stored bucket ids;
 //   2. ranks inside the wave per bucket (ballot peer masks; order = chunk
 //      order, so the result is stable);
-//   3. per bucket: prefix over the waves and the tile total, block scan of
-//      the totals = the bucket's first slot in the tile;
+//   3. per bucket: prefix over the waves and the half's total, block scan of
+//      the totals = the bucket's first slot in the half;
 //   4. records go to their slots in LDS, then slot j is written to
-//      delta[b] + j where delta[b] = global start of (b, tile) - first slot.
-constexpr uint32_t SC_THREADS = 1024, SC_WAVES = SC_THREADS / 64, SC_PER = TILE / SC_THREADS;
-static_assert(SC_PER * SC_THREADS == TILE && MAX_BUCKETS < 2 * SC_THREADS, "scatter tile shape");
+//      delta[b] + j where delta[b] = global start of (b, tile) + the first
+//      half's count of b (second half only) - first slot.
+constexpr uint32_t SC_TILE = TILE / 2;
+constexpr uint32_t SC_THREADS = 1024, SC_WAVES = SC_THREADS / 64, SC_PER = SC_TILE / SC_THREADS;
+static_assert(SC_PER * SC_THREADS == SC_TILE && MAX_BUCKETS < 2 * SC_THREADS, "scatter tile shape");
+static_assert(SC_TILE >= 2 * (MAX_BUCKETS + 1) && SC_WAVES * 4 <= (MAX_BUCKETS + 1),
+              "first-half counts and wave sums share the slot-bucket array");
 struct SmScatterTile {
     union {
         uint16_t WC[SC_WAVES][MAX_BUCKETS + 1];  // per-wave counts, then per-wave first slots
-        uint4 stage[TILE];                       // the tile's records in bucket order
+        uint4 stage[SC_TILE];                    // the half tile's records in bucket order
     };
-    uint16_t sb[TILE];                  // bucket of each slot
+    // bucket of each slot (staging); before staging, its first 64 bytes
+    // hold the wave sums and its second half the first half's bucket counts
+    // (two 16-bit counts per word)
+    uint16_t sb[SC_TILE];
     uint32_t delta[MAX_BUCKETS + 1];    // tile totals, then global position - slot
-    uint32_t wsum[SC_WAVES];
 };
 
 __global__ __launch_bounds__(SC_THREADS) void k_scatter(Work w, Params p, int cur, uint32_t n_dist) {
     __shared__ SmScatterTile sm;
-    const uint32_t t = xcd_tile(blockIdx.x, gridDim.x);
+    const uint32_t ht = xcd_tile(blockIdx.x, gridDim.x);  // half tile
+    const uint32_t t = ht >> 1, half = ht & 1u;
     const uint32_t tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    uint32_t* const wsum = (uint32_t*)sm.sb;
+    uint32_t* const first_half = (uint32_t*)(sm.sb + (MAX_BUCKETS + 1));
     const uint32_t si = w.tile_seg[cur][t];
     if (si >= n_dist) {
         if (tid == 0) raise_err(w, ERR_BOUNDS);
@@ -1197,13 +1210,16 @@ __global__ __launch_bounds__(SC_THREADS) void k_scatter(Work w, Params p, int cu
         if (tid == 0) raise_err(w, ERR_BOUNDS);
         return;
     }
-    const uint32_t start = sg.begin + ti * TILE;
-    const uint32_t end = min_u32(start + TILE, sg.begin + sg.size);
+    const uint32_t tile_start = sg.begin + ti * TILE;
+    const uint32_t tile_end = min_u32(tile_start + TILE, sg.begin + sg.size);
+    const uint32_t start = min_u32(tile_start + half * SC_TILE, tile_end);
+    const uint32_t end = min_u32(start + SC_TILE, tile_end);
     const uint32_t m = end - start;
+    if (m == 0) return;  // the second half of a tile of at most SC_TILE strings (uniform)
     // 1. loads (all issued before any use)
     static_assert(sizeof(Elem) == sizeof(uint4), "records move as 16-byte words");
     const uint4* in = (const uint4*)(w.buf[cur] + start);
-    const uint32_t c0 = wv * (TILE / SC_WAVES);  // the wave's chunk in the tile
+    const uint32_t c0 = wv * (SC_TILE / SC_WAVES);  // the wave's chunk in the half tile
     uint4 e[SC_PER];
     uint32_t bk[SC_PER];
 #pragma unroll
@@ -1220,7 +1236,14 @@ __global__ __launch_bounds__(SC_THREADS) void k_scatter(Work w, Params p, int cu
 #pragma unroll
         for (uint32_t q = 0; q < SC_WAVES; ++q) sm.WC[q][b] = 0;
     }
+    for (uint32_t b = tid; b < (MAX_BUCKETS + 1) / 2; b += SC_THREADS) first_half[b] = 0;
     __syncthreads();
+    if (half) {  // buckets of the first half, two 16-bit counts per word
+        for (uint32_t q = tid; q < SC_TILE && tile_start + q < tile_end; q += SC_THREADS) {
+            const uint32_t b = w.bkt[tile_start + q];
+            if (b < k) atomicAdd(&first_half[b >> 1], 1u << (16 * (b & 1u)));
+        }
+    }
     // 2. ranks inside the wave
     uint32_t rank[SC_PER];
 #pragma unroll
@@ -1260,20 +1283,22 @@ __global__ __launch_bounds__(SC_THREADS) void k_scatter(Work w, Params p, int cu
     const uint32_t b0 = 2 * tid, b1 = 2 * tid + 1;
     const uint32_t n0 = b0 < k ? sm.delta[b0] : 0u, n1 = b1 < k ? sm.delta[b1] : 0u;
     const uint32_t incl = wave_incl_sum(n0 + n1);
-    if (lane == 63) sm.wsum[wv] = incl;
+    if (lane == 63) wsum[wv] = incl;
     __syncthreads();
     uint32_t first0 = incl - n0 - n1;
-    for (uint32_t q = 0; q < wv; ++q) first0 += sm.wsum[q];
+    for (uint32_t q = 0; q < wv; ++q) first0 += wsum[q];
     const uint32_t* sc = w.cnt[cur] + sg.cnt_off;
     const uint32_t s0 = sc[0];
+    // b0 and b1 share a word of first-half counts (b0 even)
+    const uint32_t fh = first_half[b0 >> 1];
     if (b0 < k) {
-        sm.delta[b0] = sg.begin + sc[(size_t)b0 * T + ti] - s0 - first0;
+        sm.delta[b0] = sg.begin + sc[(size_t)b0 * T + ti] + (fh & 0xFFFFu) - s0 - first0;
 #pragma unroll
         for (uint32_t q = 0; q < SC_WAVES; ++q) sm.WC[q][b0] = (uint16_t)(sm.WC[q][b0] + first0);
     }
     if (b1 < k) {
         const uint32_t first1 = first0 + n0;
-        sm.delta[b1] = sg.begin + sc[(size_t)b1 * T + ti] - s0 - first1;
+        sm.delta[b1] = sg.begin + sc[(size_t)b1 * T + ti] + (fh >> 16) - s0 - first1;
 #pragma unroll
         for (uint32_t q = 0; q < SC_WAVES; ++q) sm.WC[q][b1] = (uint16_t)(sm.WC[q][b1] + first1);
     }
@@ -1738,7 +1763,7 @@ hipError_t launch_scan(const Work& w, int cur, uint32_t n_cnt, hipStream_t s) {
 }
 hipError_t launch_scatter(const Work& w, const Params& p, int cur, uint32_t n_tiles, uint32_t n_dist,
                           hipStream_t s) {
-    hipLaunchKernelGGL(k_scatter, dim3(n_tiles), dim3(SC_THREADS), 0, s, w, p, cur, n_dist);
+    hipLaunchKernelGGL(k_scatter, dim3(2 * n_tiles), dim3(SC_THREADS), 0, s, w, p, cur, n_dist);
     return hipGetLastError();
 }
 hipError_t launch_children(const Work& w, const Params& p, int cur, uint32_t n_dist, hipStream_t s) {
