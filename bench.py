@@ -363,13 +363,25 @@ def run_merge(args):
     torch.cuda.synchronize()
     sort_ms = (time.perf_counter() - a) / args.steps * 1e3
     print(f"[bench] merge of {K} runs {sec * 1e3:.3f} ms, full sort {sort_ms:.3f} ms", file=sys.stderr, flush=True)
+    # CPU baseline: the oracle's answer for a merge is its sort of the union
+    # (the result is unique); timed on a bounded prefix of the workload
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        ns = min(n, args.cpu_sample if args.cpu_sample > 0 else 1 << 21)
+        a = time.perf_counter()
+        oracle.sort(c[: int(o[ns])], o[: ns + 1])
+        dt = time.perf_counter() - a
+        cpu = {"value": ns / dt, "unit": "strings/s", "cores": 1, "kind": "oracle",
+               "sample": f"oracle sort of the first {ns} strings of {args.workload} (the merge's unique result), "
+                         f"qsort+memcmp and brute LCP, 1 thread, {dt:.2f} s"}
     print(json.dumps({
         "metric": "merged strings/s (LCP-aware merge of K sorted runs, perm + LCP)", "value": n / sec,
         "unit": "strings/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": sec * 1e3,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u8", "data": "synthetic",
         "config": {"workload": args.workload, "model": model, "n_strings": n, "n_chars": N, "runs": K,
                    "parallelism": "single-gpu"},
-        "chars_per_s": N / sec, "full_sort_ms": sort_ms,
+        "chars_per_s": N / sec, "full_sort_ms": sort_ms, "cpu_baseline": cpu,
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None, "alg_bytes_per_launch": alg,
                      "avg_launch_ms": avg_ms},
