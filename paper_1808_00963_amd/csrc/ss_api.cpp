@@ -296,7 +296,7 @@ ss_status run_sort(ss_ctx* ctx, const uint8_t* chars, const uint64_t* offsets, u
         if ((st = enqueue_persistent(ctx, w, p, set_begin, nroots, s)) != SS_OK) return st;
         if ((st = read_ctl(ctx, s)) != SS_OK) return st;
         ctx->stats.pending_lcps = ctx->host_ctl->n_pend;
-        ctx->stats.base_rounds = ctx->host_ctl->base_rounds;
+        ctx->stats.base_rounds = base_rounds_of(*ctx->host_ctl);
         if (ctx->host_ctl->err) return device_error_status(ctx->host_ctl->err);
         return SS_OK;
     }
@@ -328,7 +328,7 @@ ss_status run_sort(ss_ctx* ctx, const uint8_t* chars, const uint64_t* offsets, u
     if ((st = read_ctl(ctx, s)) != SS_OK) return st;
     if (ctx->prof.on) ctx->prof.unit_sum[K_LCP_FILL] += ctx->host_ctl->n_pend;
     ctx->stats.pending_lcps = ctx->host_ctl->n_pend;
-    ctx->stats.base_rounds = ctx->host_ctl->base_rounds;
+    ctx->stats.base_rounds = base_rounds_of(*ctx->host_ctl);
     if (ctx->host_ctl->err) return device_error_status(ctx->host_ctl->err);
     return SS_OK;
 }

@@ -94,6 +94,8 @@ inline Counts counts_of(const CountLines& l) {
     return counts_of(v);
 }
 
+constexpr uint32_t ROUND_LINES = 32;  // lines of the base_rounds statistic
+
 // Device-side control block.  Every group of fields that kernels update
 // with atomics sits on its own 128-byte line, so the atomics never share a
 // line with data other waves read.
@@ -104,9 +106,18 @@ struct Ctl {
     uint32_t pad0[30];
     uint32_t err;
     uint32_t pad1[31];
-    uint32_t base_rounds;  // refinement rounds run by base cases (statistics)
-    uint32_t pad2[31];
+    // refinement rounds run by base cases (statistics), spread over lines so
+    // the waves that report them do not queue on one address
+    struct {
+        uint32_t v;
+        uint32_t pad[31];
+    } base_rounds[ROUND_LINES];
 };
+inline uint32_t base_rounds_of(const Ctl& c) {
+    uint32_t t = 0;
+    for (uint32_t i = 0; i < ROUND_LINES; ++i) t += c.base_rounds[i].v;
+    return t;
+}
 
 // Error bits raised on the device.
 enum : uint32_t {

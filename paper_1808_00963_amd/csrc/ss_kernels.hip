@@ -550,7 +550,7 @@ __device__ void dev_base_wave(const Work& w, const Params& p, int cur, int cls, 
         }
     }
     if (lane == 0 && w.remaining) atomicSub(&w.remaining[sg.rid], m);
-    if (lane == 0 && rounds) atomicAdd(&w.ctl->base_rounds, rounds);
+    if (lane == 0 && rounds) atomicAdd(&w.ctl->base_rounds[(group * WAVES + wv) % ROUND_LINES].v, rounds);
 }
 
 template <int E>
@@ -741,7 +741,7 @@ __device__ void dev_base_wg(const Work& w, const Params& p, int cur, uint32_t it
         if (i > 0) p.lcp[sg.begin + i] = lv[i];
     }
     if (tid == 0 && w.remaining) atomicSub(&w.remaining[sg.rid], m);
-    if (tid == 0 && rounds) atomicAdd(&w.ctl->base_rounds, rounds);
+    if (tid == 0 && rounds) atomicAdd(&w.ctl->base_rounds[blockIdx.x % ROUND_LINES].v, rounds);
 }
 
 __global__ __launch_bounds__(BLOCK) void k_base(Work w, Params p, int cur) {
