@@ -247,11 +247,10 @@ __device__ __forceinline__ bool pr_gt(uint64_t ah, uint64_t al, uint64_t bh, uin
     return ah > bh || (ah == bh && al > bl);
 }
 
-// Value of lane (lane ^ J) of a wave, without the LDS crossbar: DPP row
-// permutations for J < 16 (quad_perm for 1 and 2; i^4 = half_mirror then
-// quad reverse; i^8 = row mirror then half mirror) and the gfx950 row-swap
-// permutes for 16 and 32 (after the swap the two results hold the even and
-// the odd rows / halves; each lane picks the one of its partner).
+// Value of lane (lane ^ J) of a wave: DPP quad permutations for 1 and 2, an
+// LDS-crossbar swizzle for 4, 8 and 16, and the gfx950 row-swap permute for
+// 32 (after the swap the two results hold the even and the odd halves; each
+// lane picks the one of its partner).
 template <uint32_t J>
 __device__ __forceinline__ uint32_t xlane32(uint32_t x) {
     static_assert(J == 1 || J == 2 || J == 4 || J == 8 || J == 16 || J == 32, "lane distance");
@@ -261,15 +260,10 @@ __device__ __forceinline__ uint32_t xlane32(uint32_t x) {
         return (uint32_t)__builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, true);  // quad_perm [1,0,3,2]
     } else if constexpr (J == 2) {
         return (uint32_t)__builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, true);  // quad_perm [2,3,0,1]
-    } else if constexpr (J == 4) {
-        const int y = __builtin_amdgcn_mov_dpp(v, 0x141, 0xF, 0xF, true);    // row_half_mirror
-        return (uint32_t)__builtin_amdgcn_mov_dpp(y, 0x1B, 0xF, 0xF, true);  // quad_perm [3,2,1,0]
-    } else if constexpr (J == 8) {
-        const int y = __builtin_amdgcn_mov_dpp(v, 0x140, 0xF, 0xF, true);     // row_mirror
-        return (uint32_t)__builtin_amdgcn_mov_dpp(y, 0x141, 0xF, 0xF, true);  // row_half_mirror
-    } else if constexpr (J == 16) {
-        const auto r = __builtin_amdgcn_permlane16_swap(x, x, false, false);
-        return (__lane_id() & 16) ? r[0] : r[1];
+    } else if constexpr (J == 4 || J == 8 || J == 16) {
+        // LDS crossbar swizzle in bit-mask mode (lane ^ J inside 32 lanes):
+        // one instruction off the vector ALU, which the networks saturate
+        return (uint32_t)__builtin_amdgcn_ds_swizzle(v, (int)((J << 10) | 0x1F));
     } else {
         const auto r = __builtin_amdgcn_permlane32_swap(x, x, false, false);
         return (__lane_id() & 32) ? r[0] : r[1];
