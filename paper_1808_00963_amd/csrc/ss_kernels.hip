@@ -1430,28 +1430,34 @@ __device__ void dev_children(const Work& w, const Params& p, int cur, uint32_t i
         }
     }
     __syncthreads();
-    // one reservation per list for the whole segment
-    if (tid == 0) {
-        CountLines* c = &w.ctl->cl[nxt];
-        for (int q = 0; q < NCLS; ++q) {
-            sm.slot_cls[q] = sm.n_cls[q] ? (uint32_t)atomicAdd(&c->base[q].v, pack2(sm.n_cls[q], sm.s_cls[q])) : 0u;
-            if (sm.slot_cls[q] + sm.n_cls[q] > w.caps.base[q]) raise_err(w, ERR_CAPACITY);
-        }
-        if (sm.max_d) atomicMax(&c->depth.v, (unsigned long long)sm.max_d);
+    // one reservation per list for the whole segment, the lists' atomics
+    // issued by different threads so their round trips overlap
+    CountLines* const cl = &w.ctl->cl[nxt];
+    if (tid < NCLS) {
+        const uint32_t q = tid;
+        sm.slot_cls[q] = sm.n_cls[q] ? (uint32_t)atomicAdd(&cl->base[q].v, pack2(sm.n_cls[q], sm.s_cls[q])) : 0u;
+    } else if (tid == NCLS) {
+        if (sm.max_d) atomicMax(&cl->depth.v, (unsigned long long)sm.max_d);
+    } else if (tid == NCLS + 1) {
         sm.slot_pend = sm.n_pend_l ? atomicAdd(&w.ctl->n_pend, sm.n_pend_l) : 0u;
+    } else if (tid == NCLS + 2) {
+        sm.bd = sm.nd ? (uint32_t)atomicAdd(&cl->dist.v, pack2(sm.nd, sm.sd)) : 0u;
+    } else if (tid == NCLS + 3) {
+        const unsigned long long tt = sm.nd ? atomicAdd(&cl->tree_tiles.v, pack2(sm.ntree, sm.ntile)) : 0ull;
+        sm.btree = (uint32_t)tt;
+        sm.btile = (uint32_t)(tt >> 32);
+    } else if (tid == NCLS + 4) {
+        sm.bcnt = sm.nd ? (uint32_t)atomicAdd(&cl->cnt.v, (unsigned long long)sm.ncnt) : 0u;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        for (int q = 0; q < NCLS; ++q)
+            if (sm.slot_cls[q] + sm.n_cls[q] > w.caps.base[q]) raise_err(w, ERR_CAPACITY);
         if (sm.slot_pend + sm.n_pend_l > w.caps.pend) raise_err(w, ERR_CAPACITY);
-        sm.bd = sm.btree = sm.bcnt = sm.btile = 0;
-        if (sm.nd) {
-            sm.bd = (uint32_t)atomicAdd(&c->dist.v, pack2(sm.nd, sm.sd));
-            const unsigned long long tt = atomicAdd(&c->tree_tiles.v, pack2(sm.ntree, sm.ntile));
-            sm.btree = (uint32_t)tt;
-            sm.btile = (uint32_t)(tt >> 32);
-            sm.bcnt = (uint32_t)atomicAdd(&c->cnt.v, (unsigned long long)sm.ncnt);
-            if (sm.bd + sm.nd > w.caps.dist || sm.btree + sm.ntree > w.caps.tree ||
-                sm.bcnt + sm.ncnt > w.caps.cnt || sm.btile + sm.ntile > w.caps.tiles) {
-                raise_err(w, ERR_CAPACITY);
-                sm.nd = 0;  // write no distribution child
-            }
+        if (sm.nd && (sm.bd + sm.nd > w.caps.dist || sm.btree + sm.ntree > w.caps.tree ||
+                      sm.bcnt + sm.ncnt > w.caps.cnt || sm.btile + sm.ntile > w.caps.tiles)) {
+            raise_err(w, ERR_CAPACITY);
+            sm.nd = 0;  // write no distribution child
         }
     }
     __syncthreads();
