@@ -71,6 +71,10 @@ struct ss_ctx {
     void* saws = nullptr;
     size_t saws_bytes = 0;
     uint32_t* sa_host = nullptr;
+    // second stream (default priority) for the first level's sampling,
+    // which overlaps the key gather; fork/join events
+    hipStream_t side = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
 };
 
 struct ss_graph {
@@ -256,8 +260,10 @@ ss_status enqueue_persistent(ss_ctx* ctx, const Work& w, const Params& p, const 
 // Enqueues one recursion level for the counts `c` of list slot `cur`: the
 // base cases of every class and, if there are distribution segments, their
 // sample/classify/scan/scatter/children steps (children go to slot cur^1,
-// which is zeroed first).
-ss_status enqueue_level(ss_ctx* ctx, const Work& w, const Params& p, int cur, const Counts& c, hipStream_t s) {
+// which is zeroed first).  `sampled`: the level's sampling has already run
+// (first level, on the side stream, joined into `s`).
+ss_status enqueue_level(ss_ctx* ctx, const Work& w, const Params& p, int cur, const Counts& c, bool sampled,
+                        hipStream_t s) {
     for (int cls = 0; cls < NCLS; ++cls) {
         if (!c.n_base[cls]) continue;
         const uint32_t nb = c.n_base[cls];
@@ -265,7 +271,7 @@ ss_status enqueue_level(ss_ctx* ctx, const Work& w, const Params& p, int cur, co
     }
     SS_TRY(launch_zero_counts(w, cur ^ 1, s));
     if (c.n_dist == 0) return SS_OK;
-    SS_TRY(timed(ctx, s, K_SAMPLE, c.n_dist, [&] { return launch_sample(w, p, cur, c.n_dist, s); }));
+    if (!sampled) SS_TRY(timed(ctx, s, K_SAMPLE, c.n_dist, [&] { return launch_sample(w, p, cur, c.n_dist, false, s); }));
     SS_TRY(timed(ctx, s, K_CLASSIFY, c.dist_strings,
                  [&] { return launch_classify(w, p, cur, c.n_tiles, c.n_dist, s); }));
     SS_TRY(timed(ctx, s, K_SCAN, c.n_cnt, [&] { return launch_scan(w, cur, c.n_cnt, s); }));
@@ -300,15 +306,37 @@ ss_status run_sort(ss_ctx* ctx, const uint8_t* chars, const uint64_t* offsets, u
         if (ctx->host_ctl->err) return device_error_status(ctx->host_ctl->err);
         return SS_OK;
     }
+    // The roots are emitted before the key gather: the first level's
+    // sampling reads its keys from the strings, so it runs on a second
+    // stream while the gather fills the buffer, and joins before classifying.
+    // Its grid covers every root that can be a distribution segment (more
+    // than base_max strings); blocks beyond the device's count return.
     SS_TRY(launch_reset(w, s));
-    SS_TRY(timed(ctx, s, K_INIT, n, [&] { return launch_init(w, p, s); }));
     SS_TRY(timed(ctx, s, K_ROOTS, nroots, [&] { return launch_roots(w, p, set_begin, nroots, s); }));
+    if (!ctx->side) {
+        SS_TRY(hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking));
+        SS_TRY(hipEventCreateWithFlags(&ctx->fork, hipEventDisableTiming));
+        SS_TRY(hipEventCreateWithFlags(&ctx->join, hipEventDisableTiming));
+    }
+    // (the gather is enqueued first, so that the host's work for the fork
+    // does not hold it back)
+    const uint32_t root_grid = std::min<uint32_t>(nroots, n / (p.base_max + 1) + 1);
+    SS_TRY(hipEventRecord(ctx->fork, s));
+    SS_TRY(timed(ctx, s, K_INIT, n, [&] { return launch_init(w, p, s); }));
+    SS_TRY(hipStreamWaitEvent(ctx->side, ctx->fork, 0));
+    SS_TRY(timed(ctx, ctx->side, K_SAMPLE, 0.0, [&] { return launch_sample(w, p, 0, root_grid, true, ctx->side); }));
+    SS_TRY(hipEventRecord(ctx->join, ctx->side));
+    SS_TRY(hipStreamWaitEvent(s, ctx->join, 0));
     int cur = 0;
     uint32_t level = 0;
     for (;;) {
         if ((st = read_ctl(ctx, s)) != SS_OK) return st;
         if (ctx->host_ctl->err) return device_error_status(ctx->host_ctl->err);
         const Counts c = counts_of(ctx->host_ctl->cl[cur]);
+        const bool first = level == 0;
+        // the first level's segment count is known on the device only when
+        // its sampling is launched; its units are added here
+        if (first && ctx->prof.on) ctx->prof.unit_sum[K_SAMPLE] += c.n_dist;
         ctx->stats.levels = level + 1;
         ctx->stats.dist_segments += c.n_dist;
         ctx->stats.dist_tiles += c.n_tiles;
@@ -318,7 +346,7 @@ ss_status run_sort(ss_ctx* ctx, const uint8_t* chars, const uint64_t* offsets, u
             ctx->stats.base_strings_by_class[q] += c.base_strings[q];
         }
         ctx->stats.max_depth = std::max(ctx->stats.max_depth, c.max_depth);
-        if ((st = enqueue_level(ctx, w, p, cur, c, s)) != SS_OK) return st;
+        if ((st = enqueue_level(ctx, w, p, cur, c, first, s)) != SS_OK) return st;
         if (c.n_dist == 0) break;
         cur ^= 1;
         if (++level >= MAX_LEVELS) return SS_INTERNAL;
@@ -645,6 +673,9 @@ void ss_ctx_destroy(ss_ctx* ctx) {
     if (ctx->mhost) (void)hipHostFree(ctx->mhost);
     if (ctx->saws) (void)hipFree(ctx->saws);
     if (ctx->sa_host) (void)hipHostFree(ctx->sa_host);
+    if (ctx->fork) (void)hipEventDestroy(ctx->fork);
+    if (ctx->join) (void)hipEventDestroy(ctx->join);
+    if (ctx->side) (void)hipStreamDestroy(ctx->side);
     (void)hipSetDevice(prev);
     delete ctx;
 }
@@ -1279,7 +1310,7 @@ void server_loop(ss_server* S) {
         if (st == SS_OK && ctx->host_ctl->err) st = device_error_status(ctx->host_ctl->err);
         if (st == SS_OK) {
             const Counts c = counts_of(ctx->host_ctl->cl[S->cur]);
-            st = enqueue_level(ctx, S->w, S->p, S->cur, c, S->stream);
+            st = enqueue_level(ctx, S->w, S->p, S->cur, c, false, S->stream);
             S->cur ^= 1;
         }
         // which requests are finished?

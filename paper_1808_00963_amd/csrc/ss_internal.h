@@ -195,7 +195,7 @@ hipError_t launch_roots(const Work& w, const Params& p, const uint32_t* set_begi
 // Zeroes counts slot `which` (no memset: stays capturable).
 hipError_t launch_zero_counts(const Work& w, int which, hipStream_t s);
 hipError_t launch_base(const Work& w, const Params& p, int cur, int cls, uint32_t n_base, hipStream_t s);
-hipError_t launch_sample(const Work& w, const Params& p, int cur, uint32_t n_dist, hipStream_t s);
+hipError_t launch_sample(const Work& w, const Params& p, int cur, uint32_t n_dist, bool root_keys, hipStream_t s);
 hipError_t launch_classify(const Work& w, const Params& p, int cur, uint32_t n_tiles, uint32_t n_dist, hipStream_t s);
 hipError_t launch_scan(const Work& w, int cur, uint32_t n_cnt, hipStream_t s);
 hipError_t launch_scatter(const Work& w, const Params& p, int cur, uint32_t n_tiles, uint32_t n_dist, hipStream_t s);

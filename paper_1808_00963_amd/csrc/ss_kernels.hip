@@ -215,6 +215,11 @@ __device__ __forceinline__ void dev_root_one(const Work& w, const Params& p, con
         }
     }
     if (e > b) p.lcp[b] = 0;
+    if (e - b == 1) {  // final at once; string b (the key gather may not have run yet)
+        p.perm[b] = b - w.set_base[set_begin ? j : 0u];
+        if (w.remaining) atomicSub(&w.remaining[set_begin ? j : 0u], 1u);
+        return;
+    }
     emit_segment(w, p, 0, w.buf[0], b, e - b, 0, set_begin ? j : 0u);
 }
 
@@ -760,7 +765,7 @@ __device__ __forceinline__ bool kr_gt(uint64_t ka, uint32_t ra, uint64_t kb, uin
 // in-block stages run in registers again.
 template <int E>
 __device__ __forceinline__ void sample_sort(const Work& w, const Params& p, int cur, const Seg& sg, uint32_t a,
-                                            uint32_t NB, SmSample& sm) {
+                                            uint32_t NB, bool root_keys, SmSample& sm) {
     constexpr uint32_t R = 64u * E;  // records per block
     const uint32_t tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const Elem* in = w.buf[cur];
@@ -773,8 +778,19 @@ __device__ __forceinline__ void sample_sort(const Work& w, const Params& p, int 
             A[r] = ~0ull;
             if (j < a) {
                 const uint32_t pos = sg.begin + (uint32_t)(((2ull * j + 1) * sg.size) / (2ull * a));
-                const Elem e = in[pos];
-                pr_pack(0, e.key, rem8(e.len, sg.depth), j, K[r], A[r]);
+                uint64_t key;
+                uint32_t len;
+                if (root_keys) {  // a root segment: position = string, depth 0, key read as k_init does
+                    const uint64_t o0 = p.offsets[pos], o1 = p.offsets[pos + 1];
+                    const bool bad = o1 < o0 || o1 - o0 > MAX_LEN || (o1 > o0 && p.chars == nullptr);
+                    len = bad ? 0u : (uint32_t)(o1 - o0);
+                    key = gather_key(p.chars, o0, 0, len);
+                } else {
+                    const Elem e = in[pos];
+                    key = e.key;
+                    len = e.len;
+                }
+                pr_pack(0, key, rem8(len, sg.depth), j, K[r], A[r]);
             }
         }
         wave_bitonic<E>(K, A, lane, NB > 1 ? b * R : 0u);
@@ -836,8 +852,11 @@ __device__ __forceinline__ void sample_sort(const Work& w, const Params& p, int 
 // 2) is sorted (sample_sort); splitters are chosen by recursive middle selection
 // skipping duplicates (section 4.2.2, "Sampling"), level by level, directly
 // into the level-order tree; an empty sub-range repeats its parent's
-// splitter so the in-order splitter sequence stays sorted.
-__device__ void dev_sample(const Work& w, const Params& p, int cur, uint32_t item, SmSample& sm) {
+// splitter so the in-order splitter sequence stays sorted.  With
+// root_keys the segments are roots and their sample keys are read from the
+// strings themselves, so the step need not wait for the key gather.
+__device__ void dev_sample(const Work& w, const Params& p, int cur, uint32_t item, bool root_keys, SmSample& sm) {
+    if (root_keys && item >= (uint32_t)w.ctl->cl[cur].dist.v) return;  // launched for every possible root
     uint64_t* SK = sm.SK;
     uint32_t* SR = sm.SR;
     uint64_t* TK = sm.TK;
@@ -857,7 +876,7 @@ __device__ void dev_sample(const Work& w, const Params& p, int cur, uint32_t ite
         for (uint32_t t = tid; t < T; t += BLOCK) ts[t] = item;
     }
     // blocks of 256 records (the last padded); P <= 2^(MAX_LOGV+1) = 8 blocks
-    sample_sort<4>(w, p, cur, sg, a, P > 256 ? P / 256 : 1u, sm);
+    sample_sort<4>(w, p, cur, sg, a, P > 256 ? P / 256 : 1u, root_keys && sg.depth == 0, sm);
     if (tid == 0) { NL[1] = 0; NH[1] = (uint16_t)a; }
     __syncthreads();
     for (uint32_t L = 0; L < d; ++L) {
@@ -889,9 +908,9 @@ __device__ void dev_sample(const Work& w, const Params& p, int cur, uint32_t ite
     }
 }
 
-__global__ __launch_bounds__(BLOCK) void k_sample(Work w, Params p, int cur) {
+__global__ __launch_bounds__(BLOCK) void k_sample(Work w, Params p, int cur, int root_keys) {
     __shared__ SmSample sm;
-    dev_sample(w, p, cur, blockIdx.x, sm);
+    dev_sample(w, p, cur, blockIdx.x, root_keys != 0, sm);
 }
 
 // ---------------------------------------------------------------------------
@@ -1617,7 +1636,7 @@ __global__ __launch_bounds__(BLOCK) void k_persist(Work w, Params p, const uint3
             else if (it < nb0 + nb1) dev_base_wave<2>(w, p, cur, 1, it - nb0, c.n_base[1], sm.wave);
             else if (it < nb0 + nb1 + nb2) dev_base_wave<4>(w, p, cur, 2, it - nb0 - nb1, c.n_base[2], sm.wave);
             else if (it < nb0 + nb1 + nb2 + nb3) dev_base_wg(w, p, cur, it - nb0 - nb1 - nb2, sm.base);
-            else dev_sample(w, p, cur, it - nb0 - nb1 - nb2 - nb3, sm.sample);
+            else dev_sample(w, p, cur, it - nb0 - nb1 - nb2 - nb3, false, sm.sample);
         }
         if (c.n_dist == 0) break;
         if (!grid_sync(w, G, gen, &s_ok)) return;
@@ -1744,8 +1763,8 @@ hipError_t launch_base(const Work& w, const Params& p, int cur, int cls, uint32_
         hipLaunchKernelGGL(k_base, dim3(n_base), dim3(BLOCK), 0, s, w, p, cur);
     return hipGetLastError();
 }
-hipError_t launch_sample(const Work& w, const Params& p, int cur, uint32_t n_dist, hipStream_t s) {
-    hipLaunchKernelGGL(k_sample, dim3(n_dist), dim3(BLOCK), 0, s, w, p, cur);
+hipError_t launch_sample(const Work& w, const Params& p, int cur, uint32_t n_dist, bool root_keys, hipStream_t s) {
+    hipLaunchKernelGGL(k_sample, dim3(n_dist), dim3(BLOCK), 0, s, w, p, cur, root_keys ? 1 : 0);
     return hipGetLastError();
 }
 hipError_t launch_classify(const Work& w, const Params& p, int cur, uint32_t n_tiles, uint32_t n_dist,
