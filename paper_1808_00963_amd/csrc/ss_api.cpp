@@ -86,6 +86,9 @@ struct ss_graph {
 namespace {
 
 constexpr uint32_t MAX_LEVELS = 1u << 17;
+// Smallest sort whose first-level sampling runs beside the key gather (the
+// gather of 2^21 strings takes about as long as one sampling step).
+constexpr uint32_t FORK_MIN = 1u << 21;
 static_assert(NCLS == 4, "ss_stats reports four base-case classes");
 
 void clamp_config(ss_config* c) {
@@ -261,16 +264,45 @@ ss_status enqueue_persistent(ss_ctx* ctx, const Work& w, const Params& p, const 
 // base cases of every class and, if there are distribution segments, their
 // sample/classify/scan/scatter/children steps (children go to slot cur^1,
 // which is zeroed first).  `sampled`: the level's sampling has already run
-// (first level, on the side stream, joined into `s`).
+// (first level, on the side stream, joined into `s`).  With `overlap`, a
+// level that has both kinds of segments runs its base cases on the side
+// stream: they read and write positions of their own segments only, so they
+// run beside the distribution steps and join `s` at the level's end (the
+// distribution steps are enqueued first, so the host's calls for the side
+// stream do not delay them).  A level of base cases only splits its classes
+// over the two streams (two-per-lane and four-per-lane waves on `s`, one-per-
+// lane waves and work groups beside them), so that one kernel's tail
+// overlaps the other's.
 ss_status enqueue_level(ss_ctx* ctx, const Work& w, const Params& p, int cur, const Counts& c, bool sampled,
-                        hipStream_t s) {
-    for (int cls = 0; cls < NCLS; ++cls) {
-        if (!c.n_base[cls]) continue;
-        const uint32_t nb = c.n_base[cls];
-        SS_TRY(timed(ctx, s, K_BASE_W1 + cls, c.base_strings[cls], [&] { return launch_base(w, p, cur, cls, nb, s); }));
-    }
+                        bool overlap, hipStream_t s) {
+    uint32_t classes = 0;  // bit per non-empty class
+    for (int cls = 0; cls < NCLS; ++cls) classes |= (c.n_base[cls] != 0 ? 1u : 0u) << cls;
+    constexpr uint32_t SIDE_CLASSES = 1u | 1u << 3;  // base-only levels: classes run on the side stream
+    const bool side = overlap && ctx->side &&
+                      (c.n_dist != 0 ? classes != 0 : (classes & SIDE_CLASSES) && (classes & ~SIDE_CLASSES));
+    const uint32_t on_side = !side ? 0u : c.n_dist != 0 ? classes : classes & SIDE_CLASSES;
+    auto bases = [&](hipStream_t bs, uint32_t which) -> ss_status {
+        for (int cls = 0; cls < NCLS; ++cls) {
+            if (!((which >> cls) & 1u)) continue;
+            const uint32_t nb = c.n_base[cls];
+            SS_TRY(timed(ctx, bs, K_BASE_W1 + cls, c.base_strings[cls],
+                         [&] { return launch_base(w, p, cur, cls, nb, bs); }));
+        }
+        return SS_OK;
+    };
+    ss_status st = SS_OK;
+    if (side) SS_TRY(hipEventRecord(ctx->fork, s));
+    if ((st = bases(s, classes & ~on_side)) != SS_OK) return st;
     SS_TRY(launch_zero_counts(w, cur ^ 1, s));
-    if (c.n_dist == 0) return SS_OK;
+    if (c.n_dist == 0) {
+        if (side) {
+            SS_TRY(hipStreamWaitEvent(ctx->side, ctx->fork, 0));
+            if ((st = bases(ctx->side, on_side)) != SS_OK) return st;
+            SS_TRY(hipEventRecord(ctx->join, ctx->side));
+            SS_TRY(hipStreamWaitEvent(s, ctx->join, 0));
+        }
+        return SS_OK;
+    }
     if (!sampled) SS_TRY(timed(ctx, s, K_SAMPLE, c.n_dist, [&] { return launch_sample(w, p, cur, c.n_dist, false, s); }));
     SS_TRY(timed(ctx, s, K_CLASSIFY, c.dist_strings,
                  [&] { return launch_classify(w, p, cur, c.n_tiles, c.n_dist, s); }));
@@ -278,6 +310,12 @@ ss_status enqueue_level(ss_ctx* ctx, const Work& w, const Params& p, int cur, co
     SS_TRY(timed(ctx, s, K_SCATTER, c.dist_strings,
                  [&] { return launch_scatter(w, p, cur, c.n_tiles, c.n_dist, s); }));
     SS_TRY(timed(ctx, s, K_CHILDREN, c.n_dist, [&] { return launch_children(w, p, cur, c.n_dist, s); }));
+    if (side) {
+        SS_TRY(hipStreamWaitEvent(ctx->side, ctx->fork, 0));
+        if ((st = bases(ctx->side, on_side)) != SS_OK) return st;
+        SS_TRY(hipEventRecord(ctx->join, ctx->side));
+        SS_TRY(hipStreamWaitEvent(s, ctx->join, 0));
+    }
     return SS_OK;
 }
 
@@ -308,32 +346,41 @@ ss_status run_sort(ss_ctx* ctx, const uint8_t* chars, const uint64_t* offsets, u
     }
     // The roots are emitted before the key gather: the first level's
     // sampling reads its keys from the strings, so it runs on a second
-    // stream while the gather fills the buffer, and joins before classifying.
-    // Its grid covers every root that can be a distribution segment (more
-    // than base_max strings); blocks beyond the device's count return.
+    // stream while the gather fills the buffer, and joins before classifying
+    // (the gather is enqueued first, so that the host's work for the fork
+    // does not hold it back).  Its grid covers every root that can be a
+    // distribution segment (more than base_max strings); blocks beyond the
+    // device's count return.  Below FORK_MIN strings the gather is shorter
+    // than the sampling and the fork does not pay: the sampling then runs
+    // after the gather, from the gathered keys.
     SS_TRY(launch_reset(w, s));
-    SS_TRY(timed(ctx, s, K_ROOTS, nroots, [&] { return launch_roots(w, p, set_begin, nroots, s); }));
     if (!ctx->side) {
         SS_TRY(hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking));
         SS_TRY(hipEventCreateWithFlags(&ctx->fork, hipEventDisableTiming));
         SS_TRY(hipEventCreateWithFlags(&ctx->join, hipEventDisableTiming));
     }
-    // (the gather is enqueued first, so that the host's work for the fork
-    // does not hold it back)
-    const uint32_t root_grid = std::min<uint32_t>(nroots, n / (p.base_max + 1) + 1);
-    SS_TRY(hipEventRecord(ctx->fork, s));
-    SS_TRY(timed(ctx, s, K_INIT, n, [&] { return launch_init(w, p, s); }));
-    SS_TRY(hipStreamWaitEvent(ctx->side, ctx->fork, 0));
-    SS_TRY(timed(ctx, ctx->side, K_SAMPLE, 0.0, [&] { return launch_sample(w, p, 0, root_grid, true, ctx->side); }));
-    SS_TRY(hipEventRecord(ctx->join, ctx->side));
-    SS_TRY(hipStreamWaitEvent(s, ctx->join, 0));
+    const bool fork0 = n >= FORK_MIN;
+    if (fork0) {
+        SS_TRY(timed(ctx, s, K_ROOTS, nroots, [&] { return launch_roots(w, p, set_begin, nroots, s); }));
+        const uint32_t root_grid = std::min<uint32_t>(nroots, n / (p.base_max + 1) + 1);
+        SS_TRY(hipEventRecord(ctx->fork, s));
+        SS_TRY(timed(ctx, s, K_INIT, n, [&] { return launch_init(w, p, s); }));
+        SS_TRY(hipStreamWaitEvent(ctx->side, ctx->fork, 0));
+        SS_TRY(timed(ctx, ctx->side, K_SAMPLE, 0.0,
+                     [&] { return launch_sample(w, p, 0, root_grid, true, ctx->side); }));
+        SS_TRY(hipEventRecord(ctx->join, ctx->side));
+        SS_TRY(hipStreamWaitEvent(s, ctx->join, 0));
+    } else {
+        SS_TRY(timed(ctx, s, K_INIT, n, [&] { return launch_init(w, p, s); }));
+        SS_TRY(timed(ctx, s, K_ROOTS, nroots, [&] { return launch_roots(w, p, set_begin, nroots, s); }));
+    }
     int cur = 0;
     uint32_t level = 0;
     for (;;) {
         if ((st = read_ctl(ctx, s)) != SS_OK) return st;
         if (ctx->host_ctl->err) return device_error_status(ctx->host_ctl->err);
         const Counts c = counts_of(ctx->host_ctl->cl[cur]);
-        const bool first = level == 0;
+        const bool first = level == 0 && fork0;
         // the first level's segment count is known on the device only when
         // its sampling is launched; its units are added here
         if (first && ctx->prof.on) ctx->prof.unit_sum[K_SAMPLE] += c.n_dist;
@@ -346,7 +393,7 @@ ss_status run_sort(ss_ctx* ctx, const uint8_t* chars, const uint64_t* offsets, u
             ctx->stats.base_strings_by_class[q] += c.base_strings[q];
         }
         ctx->stats.max_depth = std::max(ctx->stats.max_depth, c.max_depth);
-        if ((st = enqueue_level(ctx, w, p, cur, c, first, s)) != SS_OK) return st;
+        if ((st = enqueue_level(ctx, w, p, cur, c, first, true, s)) != SS_OK) return st;
         if (c.n_dist == 0) break;
         cur ^= 1;
         if (++level >= MAX_LEVELS) return SS_INTERNAL;
@@ -1310,7 +1357,7 @@ void server_loop(ss_server* S) {
         if (st == SS_OK && ctx->host_ctl->err) st = device_error_status(ctx->host_ctl->err);
         if (st == SS_OK) {
             const Counts c = counts_of(ctx->host_ctl->cl[S->cur]);
-            st = enqueue_level(ctx, S->w, S->p, S->cur, c, false, S->stream);
+            st = enqueue_level(ctx, S->w, S->p, S->cur, c, false, false, S->stream);
             S->cur ^= 1;
         }
         // which requests are finished?

@@ -198,3 +198,27 @@ def test_autotune_single_set():
     cfg, ms, p, l = ctx.autotune(cd, od, reps=1, use_cache=False)
     torch.cuda.synchronize()
     assert_equal_to_oracle(c, o, to_host(p), to_host(l), label="autotune single")
+
+
+def test_first_level_sampling_beside_the_gather():
+    """From 2^21 strings on, the first level's sampling reads its keys from
+    the strings on a second stream while the key gather runs: sets of every
+    kind around it (empty, one string, base-case sizes, just above the
+    base-case bound, large) and plain sorts on both sides of the bound."""
+    import paper_1808_00963_amd as ss
+    note("case fork batch")
+    n = (1 << 21) + 3000
+    c, o = gen.generate("markov", n, 41)
+    rng = np.random.default_rng(41)
+    sizes = [0, 1, 1, 2, 0, 64, 65, 1024, 1025, 1100, 5000, 70000]
+    sizes += list(rng.integers(0, 3000, 40))
+    sizes.append(n - sum(sizes))
+    sb = np.concatenate([[0], np.cumsum(sizes)]).astype(np.uint32)
+    ctx = ss.Context()
+    p, l = run_batch(c, o, sb, ctx)
+    check_sets(c, o, sb, p, l)
+    for m in ((1 << 21) - 1, 1 << 21):
+        note(f"case fork plain n={m}")
+        cm, om = c[:int(o[m])], o[:m + 1]
+        pm, lm = gpu_sort(cm, om, ctx=ctx)
+        assert_equal_to_oracle(cm, om, pm, lm, label=f"n={m}")
