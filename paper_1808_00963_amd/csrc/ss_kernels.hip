@@ -152,9 +152,12 @@ struct SmChildren {
     uint32_t bd, btree, bcnt, btile;
     uint32_t cd, ctree, ccnt, ctile;
 };
+constexpr uint32_t SCAN_PER_THREAD = 16;
+constexpr uint32_t SCAN_CHUNK = BLOCK * SCAN_PER_THREAD;
 struct SmScan {
     uint32_t wt[16];
     uint32_t carry;
+    uint32_t t[SCAN_CHUNK + SCAN_CHUNK / 32];  // a chunk, one pad word per 32 (conflict-free columns)
 };
 union SmAll {
     SmBase base;
@@ -993,9 +996,6 @@ __global__ __launch_bounds__(BLOCK) void k_classify(Work w, Params p, int cur, u
 // Theorem 4.4)
 // ---------------------------------------------------------------------------
 
-constexpr uint32_t SCAN_PER_THREAD = 16;
-constexpr uint32_t SCAN_CHUNK = BLOCK * SCAN_PER_THREAD;
-
 __device__ void dev_scan_reduce(const uint32_t* x, uint32_t n, uint32_t* partial, uint32_t blk, SmScan& sm) {
     const uint32_t base = blk * SCAN_CHUNK;
     uint32_t s = 0;
@@ -1031,26 +1031,40 @@ __device__ void dev_scan_partials(uint32_t* partial, uint32_t nb, SmScan& sm) {
     (void)nw;
 }
 
+// The chunk moves between HBM and LDS in coalesced rows (thread t holds
+// elements t, t + BLOCK, ...); each thread scans 16 consecutive elements
+// out of LDS.
 __device__ void dev_scan_down(uint32_t* x, uint32_t n, const uint32_t* partial, uint32_t blk, SmScan& sm) {
-    const uint32_t base = blk * SCAN_CHUNK + threadIdx.x * SCAN_PER_THREAD;
+    const uint32_t tid = threadIdx.x, b0 = blk * SCAN_CHUNK;
+    auto at = [](uint32_t i) { return i + (i >> 5); };
+#pragma unroll
+    for (uint32_t e = 0; e < SCAN_PER_THREAD; ++e) {
+        const uint32_t i = e * BLOCK + tid;
+        sm.t[at(i)] = b0 + i < n ? x[b0 + i] : 0u;
+    }
+    __syncthreads();
     uint32_t v[SCAN_PER_THREAD];
     uint32_t s = 0;
 #pragma unroll
     for (uint32_t e = 0; e < SCAN_PER_THREAD; ++e) {
-        uint32_t i = base + e;
-        v[e] = i < n ? x[i] : 0u;
+        v[e] = sm.t[at(tid * SCAN_PER_THREAD + e)];
         s += v[e];
     }
-    uint32_t incl = wave_incl_sum(s);
-    if ((threadIdx.x & 63) == 63) sm.wt[threadIdx.x >> 6] = incl;
+    const uint32_t incl = wave_incl_sum(s);
+    if ((tid & 63) == 63) sm.wt[tid >> 6] = incl;
     __syncthreads();
     uint32_t off = partial[blk] + incl - s;
-    for (uint32_t q = 0; q < (threadIdx.x >> 6); ++q) off += sm.wt[q];
+    for (uint32_t q = 0; q < (tid >> 6); ++q) off += sm.wt[q];
 #pragma unroll
     for (uint32_t e = 0; e < SCAN_PER_THREAD; ++e) {
-        uint32_t i = base + e;
-        if (i < n) x[i] = off;
+        sm.t[at(tid * SCAN_PER_THREAD + e)] = off;
         off += v[e];
+    }
+    __syncthreads();
+#pragma unroll
+    for (uint32_t e = 0; e < SCAN_PER_THREAD; ++e) {
+        const uint32_t i = e * BLOCK + tid;
+        if (b0 + i < n) x[b0 + i] = sm.t[at(i)];
     }
 }
 
