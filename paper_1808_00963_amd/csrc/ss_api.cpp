@@ -139,7 +139,7 @@ size_t layout(uint32_t n, const Caps& k, char* base, Work* w) {
     for (int i = 0; i < 2; ++i) t.tile_seg[i] = (uint32_t*)take(sizeof(uint32_t) * k.tiles);
     for (int i = 0; i < 2; ++i) t.tree_key[i] = (uint64_t*)take(sizeof(uint64_t) * k.tree);
     for (int i = 0; i < 2; ++i) t.tree_r[i] = (uint8_t*)take(k.tree);
-    t.pend = (uint2*)take(sizeof(uint2) * k.pend);
+    t.pend = (Pend*)take(sizeof(Pend) * k.pend);
     t.pend2 = nullptr;
     t.ctl = (Ctl*)take(sizeof(Ctl));
     t.bar = (GridBar*)take(sizeof(GridBar));
@@ -1449,7 +1449,7 @@ ss_status ss_server_create(ss_server** out, int device, size_t hbm_budget, uint3
     // arena bytes per index slot: workspace + offsets + perm + lcp + second pending list
     const uint32_t probe = 1u << 20;
     const size_t ws = layout(probe, caps_for(probe, S->ctx->cfg), nullptr, nullptr);
-    S->slot_bytes = ws / probe + 1 + sizeof(uint64_t) + 2 * sizeof(uint32_t) + sizeof(uint2);
+    S->slot_bytes = ws / probe + 1 + sizeof(uint64_t) + 2 * sizeof(uint32_t) + sizeof(Pend);
     // 1% of the budget is left for the fixed tables and alignment
     const uint64_t cap_n = std::min<uint64_t>((hbm_budget - hbm_budget / 100) / (S->slot_bytes + L), 0xFFFFFFF0ull);
     if (cap_n < 1024) {
@@ -1468,7 +1468,7 @@ ss_status ss_server_create(ss_server** out, int device, size_t hbm_budget, uint3
     const size_t o_off = take(sizeof(uint64_t) * ((size_t)S->cap_n + 1));
     const size_t o_perm = take(sizeof(uint32_t) * (size_t)S->cap_n);
     const size_t o_lcp = take(sizeof(uint32_t) * (size_t)S->cap_n);
-    const size_t o_pend2 = take(sizeof(uint2) * k.pend);
+    const size_t o_pend2 = take(sizeof(Pend) * k.pend);
     const size_t o_chars = take(S->cap_c + 16);
     const size_t o_base = take(sizeof(uint32_t) * max_inflight);
     const size_t o_rem = take(sizeof(uint32_t) * max_inflight);
@@ -1487,7 +1487,7 @@ ss_status ss_server_create(ss_server** out, int device, size_t hbm_budget, uint3
     }
     char* base = (char*)S->mem;
     layout(S->cap_n, k, base, &S->w);
-    S->w.pend2 = (uint2*)(base + o_pend2);
+    S->w.pend2 = (Pend*)(base + o_pend2);
     S->d_set_base = (uint32_t*)(base + o_base);
     S->d_remaining = (uint32_t*)(base + o_rem);
     S->d_done = (uint8_t*)(base + o_done);

@@ -29,6 +29,12 @@ struct Seg {
     uint32_t rid;       // set (batch) or request (serving) the segment belongs to
 };
 
+// A boundary whose LCP is filled in once the final order is known: the
+// strings at pos-1 and pos differ within the word at `depth`.
+struct Pend {
+    uint32_t pos, rid, depth, pad;
+};
+
 // A segment small enough for the in-LDS base case.
 struct BaseSeg {
     uint32_t begin, size, depth, rid;
@@ -138,7 +144,6 @@ struct GridBar {
     uint32_t pad1[31];
 };
 
-constexpr uint32_t PENDING = 0x80000000u;   // lcp entry = PENDING | depth until filled
 constexpr uint32_t MAX_LEN = 0x7FFFFF00u;   // longest accepted string
 constexpr uint32_t BLOCK = 256;             // threads per work group
 constexpr uint32_t WAVES = BLOCK / 64;
@@ -164,8 +169,8 @@ struct Work {
     uint32_t* tile_seg[2];
     uint64_t* tree_key[2];
     uint8_t* tree_r[2];
-    uint2* pend;              // pending boundary LCPs: (position, set/request id)
-    uint2* pend2;             // filter target (serving)
+    Pend* pend;               // pending boundary LCPs
+    Pend* pend2;              // filter target (serving)
     Ctl* ctl;
     GridBar* bar;
     const uint32_t* set_base; // per set/request id: its first position (subtracted from perm entries)

@@ -1434,10 +1434,7 @@ __device__ void dev_children(const Work& w, const Params& p, int cur, uint32_t i
         bucket(b, st, cnt, depth);
         if (cnt == 0) continue;
         const uint32_t pos = sg.begin + st;
-        if (st > 0) {
-            p.lcp[pos] = PENDING | sg.depth;
-            atomicAdd(&sm.n_pend_l, 1u);
-        }
+        if (st > 0) atomicAdd(&sm.n_pend_l, 1u);
         if (depth == ~0u) {  // identical strings: final (written by the scatter)
             if (w.remaining) atomicSub(&w.remaining[sg.rid], cnt);
             continue;
@@ -1502,7 +1499,7 @@ __device__ void dev_children(const Work& w, const Params& p, int cur, uint32_t i
         const uint32_t pos = sg.begin + st;
         if (st > 0) {
             const uint32_t q = sm.slot_pend + atomicAdd(&sm.cur_pend, 1u);
-            if (q < w.caps.pend) w.pend[q] = make_uint2(pos, sg.rid);
+            if (q < w.caps.pend) w.pend[q] = Pend{pos, sg.rid, sg.depth, 0u};
         }
         if (depth == ~0u || cnt == 1) continue;
         if (cnt <= p.base_max) {
@@ -1522,11 +1519,19 @@ __device__ void dev_children(const Work& w, const Params& p, int cur, uint32_t i
     }
 }
 
-// CHILD_CHUNKS work groups per segment, BLOCK buckets each.
+// At most CHILD_CHUNKS work groups per segment, BLOCK buckets each; with
+// many segments fewer, larger chunks, so that the launch stays near one
+// round of resident groups (each group's steps are a chain of dependent
+// global accesses, and a second round would repeat the chain).
 constexpr uint32_t CHILD_CHUNKS = (MAX_BUCKETS + BLOCK - 1) / BLOCK;
-__global__ __launch_bounds__(BLOCK) void k_children(Work w, Params p, int cur) {
+constexpr uint32_t CHILD_GROUPS = 2048;  // about one round: 256 CUs x 8 groups
+__host__ __device__ inline uint32_t child_chunks(uint32_t n_dist) {
+    const uint32_t c = n_dist ? CHILD_GROUPS / n_dist : CHILD_CHUNKS;
+    return c < 1 ? 1u : c > CHILD_CHUNKS ? CHILD_CHUNKS : c;
+}
+__global__ __launch_bounds__(BLOCK) void k_children(Work w, Params p, int cur, uint32_t chunks) {
     __shared__ SmChildren sm;
-    dev_children(w, p, cur, blockIdx.x / CHILD_CHUNKS, blockIdx.x % CHILD_CHUNKS, BLOCK, sm);
+    dev_children(w, p, cur, blockIdx.x / chunks, blockIdx.x % chunks, (MAX_BUCKETS + chunks - 1) / chunks, sm);
 }
 
 // ---------------------------------------------------------------------------
@@ -1536,13 +1541,10 @@ __global__ __launch_bounds__(BLOCK) void k_children(Work w, Params p, int cur) {
 // A pending entry at position q separates two buckets of a segment with
 // common prefix h: the strings now at q-1 and q differ within the word at
 // depth h, so their LCP is h plus the common bytes of those two words.
-// Resolves one pending entry (position q, set/request id rid).
-__device__ __forceinline__ void resolve_pending(const Work& w, const Params& p, uint32_t q, uint32_t rid) {
+__device__ __forceinline__ void resolve_pending(const Work& w, const Params& p, const Pend& pe) {
+    const uint32_t q = pe.pos, h = pe.depth;
     if (q == 0 || q >= p.n) { raise_err(w, ERR_BOUNDS); return; }
-    uint32_t h = p.lcp[q];
-    if (!(h & PENDING)) { raise_err(w, ERR_BOUNDS); return; }
-    h &= ~PENDING;
-    const uint32_t ob = w.set_base[rid];
+    const uint32_t ob = w.set_base[pe.rid];
     const uint32_t a = p.perm[q - 1] + ob, b = p.perm[q] + ob;
     if (a >= p.n || b >= p.n) { raise_err(w, ERR_BOUNDS); return; }
     const uint64_t oa = p.offsets[a], ob0 = p.offsets[b];
@@ -1555,10 +1557,7 @@ __device__ __forceinline__ void resolve_pending(const Work& w, const Params& p, 
 __device__ void dev_lcp_fill(const Work& w, const Params& p, uint32_t first, uint32_t stride) {
     const uint32_t np = min_u32(__hip_atomic_load(&w.ctl->n_pend, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT),
                                 w.caps.pend);
-    for (uint32_t s = first; s < np; s += stride) {
-        const uint2 pe = w.pend[s];
-        resolve_pending(w, p, pe.x, pe.y);
-    }
+    for (uint32_t s = first; s < np; s += stride) resolve_pending(w, p, w.pend[s]);
 }
 
 __global__ __launch_bounds__(BLOCK) void k_lcp_fill(Work w, Params p) {
@@ -1722,9 +1721,9 @@ __global__ void k_admit_root(Work w, Params p, int cur, uint32_t pos, uint32_t m
 __global__ __launch_bounds__(BLOCK) void k_pend_filter(Work w, Params p) {
     const uint32_t np = min_u32(w.ctl->n_pend, w.caps.pend);
     for (uint32_t s = blockIdx.x * BLOCK + threadIdx.x; s < np; s += gridDim.x * BLOCK) {
-        const uint2 pe = w.pend[s];
-        if (w.done[pe.y]) {
-            resolve_pending(w, p, pe.x, pe.y);
+        const Pend pe = w.pend[s];
+        if (w.done[pe.rid]) {
+            resolve_pending(w, p, pe);
         } else {
             const uint32_t q = atomicAdd(&w.ctl->n_pend2, 1u);
             if (q < w.caps.pend) w.pend2[q] = pe;
@@ -1800,7 +1799,8 @@ hipError_t launch_scatter(const Work& w, const Params& p, int cur, uint32_t n_ti
     return hipGetLastError();
 }
 hipError_t launch_children(const Work& w, const Params& p, int cur, uint32_t n_dist, hipStream_t s) {
-    hipLaunchKernelGGL(k_children, dim3(n_dist * CHILD_CHUNKS), dim3(BLOCK), 0, s, w, p, cur);
+    const uint32_t chunks = child_chunks(n_dist);
+    hipLaunchKernelGGL(k_children, dim3(n_dist * chunks), dim3(BLOCK), 0, s, w, p, cur, chunks);
     return hipGetLastError();
 }
 hipError_t launch_lcp_fill(const Work& w, const Params& p, hipStream_t s) {
