@@ -34,7 +34,10 @@
  * Streams and errors.  `stream` is a hipStream_t (NULL = default stream).
  * Calls enqueue work on `stream`; they synchronise with the host between
  * recursion levels (the host reads a few counters per level), and return
- * once the sort has completed on the stream.  Host-detectable errors return
+ * once the sort has completed on the stream.  Inside a sort, independent
+ * steps also run on a second stream that the context owns (default
+ * priority); it is joined into `stream` by events before every host
+ * synchronisation, so the caller sees only `stream`.  Host-detectable errors return
  * immediately without touching the outputs.  Errors detected on the device
  * (non-monotone offsets, a string of 2^31 or more bytes, an internal limit)
  * are returned by the call that detects them and are sticky in the context:
