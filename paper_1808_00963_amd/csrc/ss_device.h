@@ -83,10 +83,21 @@ SS_HD void classify_n(const uint64_t (&c)[N], const uint32_t (&cr)[N], const Key
     uint32_t q[N];
     for (uint32_t u = 0; u < N; ++u) q[u] = 1;
     for (uint32_t l = 0; l < d; ++l) {
+        // the splitters' length codes decide only between equal keys, so
+        // they are read only by a string whose key equals its splitter's
+        uint64_t t[N];
+        uint32_t gt[N];
+        bool any_eq = false;
+        for (uint32_t u = 0; u < N; ++u) t[u] = tk[q[u]];
         for (uint32_t u = 0; u < N; ++u) {
-            const uint32_t gt = kr_greater(c[u], cr[u], tk[q[u]], tr[q[u]]) ? 1u : 0u;
-            q[u] = 2 * q[u] + gt;
+            gt[u] = c[u] > t[u] ? 1u : 0u;
+            any_eq |= c[u] == t[u];
         }
+        if (any_eq) {
+            for (uint32_t u = 0; u < N; ++u)
+                if (c[u] == t[u]) gt[u] = cr[u] > (uint32_t)tr[q[u]] ? 1u : 0u;
+        }
+        for (uint32_t u = 0; u < N; ++u) q[u] = 2 * q[u] + gt[u];
     }
     const uint32_t v = (1u << d) - 1;
     for (uint32_t u = 0; u < N; ++u) {
