@@ -263,7 +263,9 @@ ss_status enqueue_persistent(ss_ctx* ctx, const Work& w, const Params& p, const 
 // Enqueues one recursion level for the counts `c` of list slot `cur`: the
 // base cases of every class and, if there are distribution segments, their
 // sample/classify/scan/scatter/children steps (children go to slot cur^1,
-// which is zeroed first).  `sampled`: the level's sampling has already run
+// which is zeroed first when `zero_next`: a sort's reset has zeroed both
+// slots, so its first level and a level without children skip it).
+// `sampled`: the level's sampling has already run
 // (first level, on the side stream, joined into `s`).  With `overlap`, a
 // level that has both kinds of segments runs its base cases on the side
 // stream: they read and write positions of their own segments only, so they
@@ -274,7 +276,7 @@ ss_status enqueue_persistent(ss_ctx* ctx, const Work& w, const Params& p, const 
 // lane waves and work groups beside them), so that one kernel's tail
 // overlaps the other's.
 ss_status enqueue_level(ss_ctx* ctx, const Work& w, const Params& p, int cur, const Counts& c, bool sampled,
-                        bool overlap, hipStream_t s) {
+                        bool overlap, bool zero_next, hipStream_t s) {
     uint32_t classes = 0;  // bit per non-empty class
     for (int cls = 0; cls < NCLS; ++cls) classes |= (c.n_base[cls] != 0 ? 1u : 0u) << cls;
     constexpr uint32_t SIDE_CLASSES = 1u | 1u << 3;  // base-only levels: classes run on the side stream
@@ -293,7 +295,7 @@ ss_status enqueue_level(ss_ctx* ctx, const Work& w, const Params& p, int cur, co
     ss_status st = SS_OK;
     if (side) SS_TRY(hipEventRecord(ctx->fork, s));
     if ((st = bases(s, classes & ~on_side)) != SS_OK) return st;
-    SS_TRY(launch_zero_counts(w, cur ^ 1, s));
+    if (zero_next) SS_TRY(launch_zero_counts(w, cur ^ 1, s));
     if (c.n_dist == 0) {
         if (side) {
             SS_TRY(hipStreamWaitEvent(ctx->side, ctx->fork, 0));
@@ -393,7 +395,7 @@ ss_status run_sort(ss_ctx* ctx, const uint8_t* chars, const uint64_t* offsets, u
             ctx->stats.base_strings_by_class[q] += c.base_strings[q];
         }
         ctx->stats.max_depth = std::max(ctx->stats.max_depth, c.max_depth);
-        if ((st = enqueue_level(ctx, w, p, cur, c, first, true, s)) != SS_OK) return st;
+        if ((st = enqueue_level(ctx, w, p, cur, c, first, true, level > 0 && c.n_dist > 0, s)) != SS_OK) return st;
         if (c.n_dist == 0) break;
         cur ^= 1;
         if (++level >= MAX_LEVELS) return SS_INTERNAL;
@@ -1357,7 +1359,7 @@ void server_loop(ss_server* S) {
         if (st == SS_OK && ctx->host_ctl->err) st = device_error_status(ctx->host_ctl->err);
         if (st == SS_OK) {
             const Counts c = counts_of(ctx->host_ctl->cl[S->cur]);
-            st = enqueue_level(ctx, S->w, S->p, S->cur, c, false, false, S->stream);
+            st = enqueue_level(ctx, S->w, S->p, S->cur, c, false, false, true, S->stream);
             S->cur ^= 1;
         }
         // which requests are finished?
