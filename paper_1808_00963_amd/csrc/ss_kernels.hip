@@ -1259,10 +1259,12 @@ __global__ __launch_bounds__(SC_THREADS) void k_scatter(Work w, Params p, int cu
             bk[r] = w.bkt[start + q];
         }
     }
-    for (uint32_t b = tid; b < k; b += SC_THREADS) {
-#pragma unroll
-        for (uint32_t q = 0; q < SC_WAVES; ++q) sm.WC[q][b] = 0;
-    }
+    // the per-wave counts are handled two buckets per 32-bit word (16-bit
+    // halves that never carry: every count and sum is at most SC_TILE)
+    static_assert(SC_TILE < 65536 && (MAX_BUCKETS + 1) % 8 == 0, "packed bucket counts");
+    constexpr uint32_t ROW_WORDS = (MAX_BUCKETS + 1) / 2;
+    uint32_t* const WC32 = (uint32_t*)&sm.WC[0][0];
+    for (uint32_t i = tid; i < SC_WAVES * ROW_WORDS / 4; i += SC_THREADS) ((uint4*)WC32)[i] = make_uint4(0, 0, 0, 0);
     for (uint32_t b = tid; b < (MAX_BUCKETS + 1) / 2; b += SC_THREADS) first_half[b] = 0;
     __syncthreads();
     if (half) {  // buckets of the first half, two 16-bit counts per word
@@ -1296,15 +1298,16 @@ __global__ __launch_bounds__(SC_THREADS) void k_scatter(Work w, Params p, int cu
     }
     __syncthreads();
     // 3. prefix over the waves, tile totals, block scan of the totals
-    for (uint32_t b = tid; b < k; b += SC_THREADS) {
+    for (uint32_t pw = tid; 2 * pw < k; pw += SC_THREADS) {  // buckets 2pw, 2pw + 1
         uint32_t run = 0;
 #pragma unroll
         for (uint32_t q = 0; q < SC_WAVES; ++q) {
-            const uint32_t c = sm.WC[q][b];
-            sm.WC[q][b] = (uint16_t)run;
+            const uint32_t c = WC32[q * ROW_WORDS + pw];
+            WC32[q * ROW_WORDS + pw] = run;
             run += c;
         }
-        sm.delta[b] = run;
+        sm.delta[2 * pw] = run & 0xFFFFu;
+        if (2 * pw + 1 < k) sm.delta[2 * pw + 1] = run >> 16;
     }
     __syncthreads();
     const uint32_t b0 = 2 * tid, b1 = 2 * tid + 1;
@@ -1318,16 +1321,14 @@ __global__ __launch_bounds__(SC_THREADS) void k_scatter(Work w, Params p, int cu
     const uint32_t s0 = sc[0];
     // b0 and b1 share a word of first-half counts (b0 even)
     const uint32_t fh = first_half[b0 >> 1];
+    const uint32_t first1 = first0 + n0;
     if (b0 < k) {
         sm.delta[b0] = sg.begin + sc[(size_t)b0 * T + ti] + (fh & 0xFFFFu) - s0 - first0;
+        if (b1 < k) sm.delta[b1] = sg.begin + sc[(size_t)b1 * T + ti] + (fh >> 16) - s0 - first1;
+        // both buckets' first slots at once (bucket k, when b1 == k, has no records)
+        const uint32_t add = first0 | first1 << 16;
 #pragma unroll
-        for (uint32_t q = 0; q < SC_WAVES; ++q) sm.WC[q][b0] = (uint16_t)(sm.WC[q][b0] + first0);
-    }
-    if (b1 < k) {
-        const uint32_t first1 = first0 + n0;
-        sm.delta[b1] = sg.begin + sc[(size_t)b1 * T + ti] + (fh >> 16) - s0 - first1;
-#pragma unroll
-        for (uint32_t q = 0; q < SC_WAVES; ++q) sm.WC[q][b1] = (uint16_t)(sm.WC[q][b1] + first1);
+        for (uint32_t q = 0; q < SC_WAVES; ++q) WC32[q * ROW_WORDS + tid] += add;
     }
     __syncthreads();
     // 4. records to their slots, then out in slot order
