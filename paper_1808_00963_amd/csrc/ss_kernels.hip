@@ -1328,7 +1328,7 @@ __global__ __launch_bounds__(SC_THREADS) void k_scatter(Work w, Params p, int cu
         // both buckets' first slots at once (bucket k, when b1 == k, has no records)
         const uint32_t add = first0 | first1 << 16;
 #pragma unroll
-        for (uint32_t q = 0; q < SC_WAVES; ++q) WC32[q * ROW_WORDS + tid] += add;
+        for (uint32_t q = 0; q < SC_WAVES; ++q) atomicAdd(&WC32[q * ROW_WORDS + tid], add);  // no return: one LDS op
     }
     __syncthreads();
     // 4. records to their slots, then out in slot order
