@@ -71,8 +71,9 @@ struct ss_ctx {
     void* saws = nullptr;
     size_t saws_bytes = 0;
     uint32_t* sa_host = nullptr;
-    // second stream (default priority) for the first level's sampling,
-    // which overlaps the key gather; fork/join events
+    // second stream (default priority) for the steps that overlap others
+    // inside one sort (first-level sampling beside the key gather, base
+    // cases beside the distribution steps); fork/join events
     hipStream_t side = nullptr;
     hipEvent_t fork = nullptr, join = nullptr;
 };
