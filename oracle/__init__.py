@@ -30,7 +30,7 @@ def build(force: bool = True) -> str:
     """Compiles liboracle.so in place with gcc."""
     if force or not os.path.exists(_LIB_PATH):
         tmp = _LIB_PATH + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-fPIC", "-shared", "-std=gnu11",
+        subprocess.check_call(["gcc", "-O2", "-fPIC", "-shared", "-std=gnu11", "-pthread",
                                os.path.join(_HERE, "ss_oracle.c"), "-o", tmp])
         os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
@@ -58,6 +58,8 @@ def _bind(lib):
     lib.ss_oracle_lcp.argtypes = [vp, vp, u32, u32]
     lib.ss_oracle_compare.restype = ctypes.c_int
     lib.ss_oracle_compare.argtypes = [vp, vp, u32, u32]
+    lib.ss_oracle_sort_mt.restype = ctypes.c_int
+    lib.ss_oracle_sort_mt.argtypes = [vp, vp, u32, vp, vp, u32]
     lib.ss_oracle_suffix_array.restype = ctypes.c_int
     lib.ss_oracle_suffix_array.argtypes = [vp, u32, vp]
     lib.ss_oracle_h_names.restype = ctypes.c_int
@@ -84,6 +86,20 @@ def sort(chars, offsets, lib=None):
     return perm[:n], lcp[:n]
 
 
+def sort_mt(chars, offsets, threads: int, lib=None):
+    """Same result as ``sort``, computed on ``threads`` host threads (chunk
+    sorts, pairwise merges, LCPs over disjoint ranges)."""
+    lib = lib or load()
+    chars, offsets = _prep(chars, offsets)
+    n = offsets.size - 1
+    perm = np.zeros(max(n, 1), dtype=np.uint32)
+    lcp = np.zeros(max(n, 1), dtype=np.uint32)
+    if lib.ss_oracle_sort_mt(chars.ctypes.data, offsets.ctypes.data, n, perm.ctypes.data, lcp.ctypes.data,
+                             int(threads)) != 0:
+        raise MemoryError("ss_oracle_sort_mt")
+    return perm[:n], lcp[:n]
+
+
 def check(chars, offsets, perm, lcp, lib=None) -> int:
     """Returns -1 if (perm, lcp) is the correct output, else an error code
     (see ``ss_oracle_check`` in ss_oracle.c)."""
@@ -99,14 +115,45 @@ def check(chars, offsets, perm, lcp, lib=None) -> int:
     return int(lib.ss_oracle_check(chars.ctypes.data, offsets.ctypes.data, n, perm.ctypes.data, lcp.ctypes.data))
 
 
-def lcp_of(chars, offsets, a: int, b: int) -> int:
+def lcp_of(chars, offsets, a: int, b: int, lib=None) -> int:
+    """Longest common prefix of strings a and b (character loop)."""
     chars, offsets = _prep(chars, offsets)
-    return int(load().ss_oracle_lcp(chars.ctypes.data, offsets.ctypes.data, a, b))
+    return int((lib or load()).ss_oracle_lcp(chars.ctypes.data, offsets.ctypes.data, a, b))
 
 
-def compare(chars, offsets, a: int, b: int) -> int:
+def compare(chars, offsets, a: int, b: int, lib=None) -> int:
+    """-1, 0 or 1: strings a and b compared by (bytes, length, index)."""
     chars, offsets = _prep(chars, offsets)
-    return int(load().ss_oracle_compare(chars.ctypes.data, offsets.ctypes.data, a, b))
+    return int((lib or load()).ss_oracle_compare(chars.ctypes.data, offsets.ctypes.data, a, b))
+
+
+def check_sampled(chars, offsets, perm, lcp, positions, lib=None) -> list:
+    """Checks a claimed output at the given sorted positions only (for
+    outputs too large for a full oracle run): each sampled pair
+    (perm[k-1], perm[k]) must be strictly increasing in (string, index)
+    order and lcp[k] must equal their common prefix; lcp[0] must be 0.
+    Returns descriptions of the failures (empty = all sampled positions
+    agree with the definition)."""
+    lib = lib or load()
+    chars, offsets = _prep(chars, offsets)
+    n = offsets.size - 1
+    fails = []
+    for k in positions:
+        k = int(k)
+        if k == 0:
+            if n and int(lcp[0]) != 0:
+                fails.append("lcp[0] != 0")
+            continue
+        a, b = int(perm[k - 1]), int(perm[k])
+        if a >= n or b >= n:
+            fails.append(f"perm entry out of range at {k}")
+            continue
+        if int(lib.ss_oracle_compare(chars.ctypes.data, offsets.ctypes.data, a, b)) >= 0:
+            fails.append(f"order violated at sorted position {k}")
+        want = int(lib.ss_oracle_lcp(chars.ctypes.data, offsets.ctypes.data, a, b))
+        if int(lcp[k]) != want:
+            fails.append(f"lcp at {k}: got {int(lcp[k])}, want {want}")
+    return fails
 
 
 def _text(text):

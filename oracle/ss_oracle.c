@@ -22,6 +22,13 @@
  * ss_oracle_sort: the definition written out -- a library comparison sort
  *   (qsort) of the indices with a memcmp comparator, then a brute-force
  *   character loop for each adjacent LCP.  Single-threaded, unoptimised.
+ * ss_oracle_sort_mt: the same result on several threads, for the CPU
+ *   baseline on all host cores: each thread sorts one contiguous chunk of
+ *   the indices with the same comparator, sorted chunks are merged in
+ *   pairwise rounds (a plain two-way merge per pair, pairs on separate
+ *   threads), and the adjacent LCPs are computed by the same character loop
+ *   over disjoint ranges.  The comparator orders by (string, index), a total
+ *   order, so the merged result is the single correct answer.
  * ss_oracle_check: verifies a claimed (perm, lcp) against the same
  *   definition without sorting: perm is a permutation, each adjacent pair is
  *   strictly increasing in (string, index) order, and each lcp entry equals
@@ -39,6 +46,7 @@
  *   then the first sorted position of each run of equal truncations.
  */
 #define _GNU_SOURCE
+#include <pthread.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -112,16 +120,99 @@ long long ss_oracle_check(const uint8_t* chars, const uint64_t* offsets, uint32_
     return -1;
 }
 
-/* Brute-force LCP of two strings (used by sampled checks). */
+/* Brute-force LCP of two strings (used by sampled checks of outputs too
+ * large for a full oracle run). */
 uint32_t ss_oracle_lcp(const uint8_t* chars, const uint64_t* offsets, uint32_t a, uint32_t b) {
     strset_t S = {chars, offsets};
     return lcp_brute(&S, a, b);
 }
 
-/* Three-way comparison of two strings by (bytes, length, index). */
+/* Three-way comparison of two strings by (bytes, length, index) (used by
+ * sampled checks). */
 int ss_oracle_compare(const uint8_t* chars, const uint64_t* offsets, uint32_t a, uint32_t b) {
     strset_t S = {chars, offsets};
     return cmp_idx(&S, a, b);
+}
+
+/* ---- the same sort on several threads ---------------------------------- */
+
+typedef struct {
+    const strset_t* S;
+    uint32_t* src;
+    uint32_t* dst;
+    uint32_t* lcp;
+    uint32_t lo, mid, hi; /* chunk sort: [lo, hi); merge: [lo, mid) + [mid, hi) */
+} job_t;
+
+static void* job_sort(void* arg) {
+    job_t* j = (job_t*)arg;
+    for (uint32_t i = j->lo; i < j->hi; ++i) j->src[i] = i;
+    qsort_r(j->src + j->lo, j->hi - j->lo, sizeof(uint32_t), qsort_cmp, (void*)j->S);
+    return NULL;
+}
+
+static void* job_merge(void* arg) {
+    job_t* j = (job_t*)arg;
+    uint32_t a = j->lo, b = j->mid, o = j->lo;
+    while (a < j->mid && b < j->hi)
+        j->dst[o++] = cmp_idx(j->S, j->src[a], j->src[b]) < 0 ? j->src[a++] : j->src[b++];
+    while (a < j->mid) j->dst[o++] = j->src[a++];
+    while (b < j->hi) j->dst[o++] = j->src[b++];
+    return NULL;
+}
+
+static void* job_lcp(void* arg) {
+    job_t* j = (job_t*)arg;
+    for (uint32_t k = j->lo; k < j->hi; ++k)
+        j->lcp[k] = k ? lcp_brute(j->S, j->src[k - 1], j->src[k]) : 0;
+    return NULL;
+}
+
+/* runs jobs[0..m) on their own threads (the calling thread takes the last) */
+static int run_jobs(void* (*fn)(void*), job_t* jobs, uint32_t m) {
+    pthread_t* th = (pthread_t*)malloc(sizeof(pthread_t) * (m ? m : 1));
+    if (!th) return -1;
+    uint32_t started = 0;
+    int rc = 0;
+    for (uint32_t t = 0; t + 1 < m; ++t) {
+        if (pthread_create(&th[t], NULL, fn, &jobs[t]) != 0) { rc = -1; break; }
+        ++started;
+    }
+    if (rc == 0 && m) fn(&jobs[m - 1]);
+    for (uint32_t t = 0; t < started; ++t) pthread_join(th[t], NULL);
+    free(th);
+    return rc;
+}
+
+/* Same output as ss_oracle_sort, computed by `threads` threads.  Returns 0,
+ * or -1 if memory or threads are not available. */
+int ss_oracle_sort_mt(const uint8_t* chars, const uint64_t* offsets, uint32_t n, uint32_t* perm, uint32_t* lcp,
+                      uint32_t threads) {
+    strset_t S = {chars, offsets};
+    if (threads < 1) threads = 1;
+    if (threads > n) threads = n ? n : 1;
+    uint32_t* tmp = (uint32_t*)malloc(sizeof(uint32_t) * ((size_t)n + 1));
+    uint32_t* bound = (uint32_t*)malloc(sizeof(uint32_t) * ((size_t)threads + 1));
+    job_t* jobs = (job_t*)calloc(threads, sizeof(job_t));
+    if (!tmp || !bound || !jobs) { free(tmp); free(bound); free(jobs); return -1; }
+    for (uint32_t t = 0; t <= threads; ++t) bound[t] = (uint32_t)((uint64_t)n * t / threads);
+    for (uint32_t t = 0; t < threads; ++t) jobs[t] = (job_t){&S, perm, NULL, NULL, bound[t], 0, bound[t + 1]};
+    int rc = run_jobs(job_sort, jobs, threads);
+    uint32_t *src = perm, *dst = tmp;
+    for (uint32_t w = 1; rc == 0 && w < threads; w *= 2) {
+        uint32_t m = 0;
+        for (uint32_t c = 0; c < threads; c += 2 * w) {
+            uint32_t mid = c + w < threads ? c + w : threads, hi = c + 2 * w < threads ? c + 2 * w : threads;
+            jobs[m++] = (job_t){&S, src, dst, NULL, bound[c], bound[mid], bound[hi]};
+        }
+        rc = run_jobs(job_merge, jobs, m);
+        uint32_t* x = src; src = dst; dst = x;
+    }
+    if (rc == 0 && src != perm) memcpy(perm, src, sizeof(uint32_t) * (size_t)n);
+    for (uint32_t t = 0; rc == 0 && t < threads; ++t) jobs[t] = (job_t){&S, perm, NULL, lcp, bound[t], 0, bound[t + 1]};
+    if (rc == 0) rc = run_jobs(job_lcp, jobs, threads);
+    free(tmp); free(bound); free(jobs);
+    return rc;
 }
 
 /* ---- suffix sorting --------------------------------------------------- */

@@ -313,7 +313,51 @@ def pin_suffix_brute(lib, seeds=range(8)):
     return fails
 
 
-ALL_PINS = [pin_lemma21, pin_fig51, pin_library_sort, pin_exhaustive, pin_insertion_sort,
+def pin_sampled_helpers(lib, seeds=range(4)):
+    """The pairwise helpers used by sampled checks (LCP of two strings,
+    three-way (string, index) comparison) against Python's byte strings."""
+    fails = []
+    for seed in seeds:
+        rng = random.Random(100 + seed)
+        alphabet = rng.choice([b"ab", b"\x00\xff", b"a\x00b\xff", bytes(range(256))])
+        strings = [bytes(rng.choice(alphabet) for _ in range(rng.randint(0, 12))) for _ in range(60)]
+        strings[1] = strings[0]
+        strings[2] = strings[0] + b"\x00"
+        c, o = gen.from_list(strings)
+        for _ in range(400):
+            a, b = rng.randrange(60), rng.randrange(60)
+            if oracle.lcp_of(c, o, a, b, lib=lib) != lcp_py(strings[a], strings[b]):
+                fails.append(f"lcp_of({a},{b}) seed {seed}")
+                break
+            want = ((strings[a], a) > (strings[b], b)) - ((strings[a], a) < (strings[b], b))
+            if oracle.compare(c, o, a, b, lib=lib) != want:
+                fails.append(f"compare({a},{b}) seed {seed}")
+                break
+    return fails
+
+
+def pin_multithreaded(lib, seeds=range(5)):
+    """The all-cores variant of the sort against Python's sort of
+    (bytes, index) pairs, for thread counts that leave ragged chunks."""
+    fails = []
+    for seed in seeds:
+        rng = random.Random(200 + seed)
+        n = rng.choice([0, 1, 2, 7, 300, 2000])
+        alphabet = rng.choice([b"ab", b"\x00\xff", bytes(range(256))])
+        strings = [bytes(rng.choice(alphabet) for _ in range(rng.randint(0, 10))) for _ in range(n)]
+        if n > 4:
+            strings[3] = strings[0]
+            strings[4] = strings[0] + b"\x00"
+        exp = expected_by_library(strings)
+        c, o = gen.from_list(strings)
+        for threads in (1, 2, 3, 5, 8):
+            p, l = oracle.sort_mt(c, o, threads, lib=lib)
+            if (p.tolist(), l.tolist()) != (exp[0], exp[1][:n]):
+                fails.append(f"sort_mt mismatch seed {seed} threads {threads}")
+    return fails
+
+
+ALL_PINS = [pin_sampled_helpers, pin_multithreaded, pin_lemma21, pin_fig51, pin_library_sort, pin_exhaustive, pin_insertion_sort,
             pin_truncated_suffixes, pin_lemma21_bounds, pin_fig81_names, pin_fig51_suffix_array,
             pin_suffix_brute]
 

@@ -70,6 +70,13 @@ MUTATIONS = {
                            "if (la != lb) return la > lb ? -1 : 1;"),
     "h_names_by_position": ("names[order[k]] = first;", "names[order[k]] = k;"),
     "h_truncation_dropped": ("if (la > S->h) la = S->h;", ""),
+    "mt_merge_drops_tail": ("while (b < j->hi) j->dst[o++] = j->src[b++];", ""),
+    "mt_merge_prefers_right": ("cmp_idx(j->S, j->src[a], j->src[b]) < 0 ? j->src[a++] : j->src[b++];",
+                               "cmp_idx(j->S, j->src[a], j->src[b]) > 0 ? j->src[a++] : j->src[b++];"),
+    "mt_lcp_without_perm": ("j->lcp[k] = k ? lcp_brute(j->S, j->src[k - 1], j->src[k]) : 0;",
+                            "j->lcp[k] = k ? lcp_brute(j->S, k - 1, k) : 0;"),
+    "compare_negated": ("    return cmp_idx(&S, a, b);\n}", "    return -cmp_idx(&S, a, b);\n}"),
+    "pair_lcp_off_by_one": ("    return lcp_brute(&S, a, b);\n}", "    return lcp_brute(&S, a, b) + 1;\n}"),
     "suffix_one_char_short": ("int c = m ? memcmp(S->text + a, S->text + b, (size_t)m) : 0;",
                               "int c = m > 1 ? memcmp(S->text + a, S->text + b, (size_t)(m - 1)) : 0;"),
 }
@@ -77,12 +84,21 @@ MUTATIONS = {
 
 @pytest.mark.parametrize("name", sorted(MUTATIONS))
 def test_mutated_oracle_is_caught(tmp_path, name):
+    """The pins run against the mutated build in a child process: a mutation
+    that makes the oracle crash (e.g. a merge that leaves indices
+    uninitialised) counts as caught, like a failed pin."""
+    import sys
     src = open(os.path.join(os.path.dirname(oracle.__file__), "ss_oracle.c")).read()
     old, new = MUTATIONS[name]
     assert old in src, f"mutation anchor missing: {old}"
     mutated = tmp_path / "m.c"
     mutated.write_text(src.replace(old, new))
     so = tmp_path / "libm.so"
-    subprocess.check_call(["gcc", "-O1", "-fPIC", "-shared", "-std=gnu11", str(mutated), "-o", str(so)])
-    lib = oracle.load(str(so))
-    assert pins.run_all(lib) != [], f"mutation {name} was not caught by any pin"
+    subprocess.check_call(["gcc", "-O1", "-fPIC", "-shared", "-std=gnu11", "-pthread", str(mutated), "-o", str(so)])
+    here = os.path.dirname(os.path.abspath(__file__))
+    code = ("import sys; sys.path[:0] = [%r, %r]; import oracle, pins; "
+            "f = pins.run_all(oracle.load(%r)); print(len(f)); sys.exit(0 if f else 3)"
+            % (here, os.path.dirname(here), str(so)))
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
+    assert r.returncode != 3, f"mutation {name} was not caught by any pin"
+    assert r.returncode != 0 or int(r.stdout.strip().splitlines()[-1]) > 0
