@@ -333,6 +333,13 @@ ss_status ss_hbm_copy(void* dst, const void* src, size_t bytes, void* stream);
  * *r_out = min(len - h, 8). */
 uint64_t ss_host_key(const uint8_t* s, uint64_t len, uint64_t h, uint32_t* r_out);
 
+/* The kernels' key gather (chars_h of section 4.2.2) run on the host with
+ * plain loads: the key of string chars[off .. off+len) at depth h, reading
+ * only the aligned 8-byte word(s) that hold characters of the key.  The
+ * caller must make those words readable (the test places strings next to
+ * unreadable pages to show that nothing else is read). */
+uint64_t ss_host_gather_key(const uint8_t* chars, uint64_t off, uint32_t h, uint32_t len);
+
 /* Lemma 4.1 mapping: level-order index of in-order position j (d levels),
  * and its inverse. */
 uint32_t ss_host_level_index(uint32_t j, uint32_t d);

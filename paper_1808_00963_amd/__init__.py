@@ -109,6 +109,7 @@ def lib():
             "ss_merge_runs": (i32, [vp, vp, vp, u32, vp, vp, ctypes.POINTER(u64), u32, vp, vp, vp]),
             "ss_suffix_array": (i32, [vp, vp, u32, vp, vp, ctypes.POINTER(u32), vp]),
             "ss_host_key": (u64, [vp, u64, u64, ctypes.POINTER(u32)]),
+            "ss_host_gather_key": (u64, [vp, u64, u32, u32]),
             "ss_host_level_index": (u32, [u32, u32]),
             "ss_host_inorder_index": (u32, [u32, u32]),
             "ss_host_classify": (i32, [vp, vp, u32, vp, vp, u32, vp]),

@@ -1094,6 +1094,14 @@ uint64_t ss_host_key(const uint8_t* s, uint64_t len, uint64_t h, uint32_t* r_out
     return key_from_words(w0, w1, sh, rem);
 }
 
+uint64_t ss_host_gather_key(const uint8_t* chars, uint64_t off, uint32_t h, uint32_t len) {
+    return gather_key_with(chars, off, h, len, [](const uint64_t* q) {
+        uint64_t w;
+        std::memcpy(&w, q, sizeof(w));
+        return w;
+    });
+}
+
 uint32_t ss_host_level_index(uint32_t j, uint32_t d) { return level_index(j, d); }
 uint32_t ss_host_inorder_index(uint32_t l, uint32_t d) { return inorder_index(l, d); }
 

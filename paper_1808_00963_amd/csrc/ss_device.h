@@ -27,6 +27,26 @@ SS_HD uint64_t key_from_words(uint64_t w0, uint64_t w1, uint32_t sh, uint32_t re
     return be & ~(~0ull >> (8 * rem));
 }
 
+// chars_h(s): the 8 characters of a string starting at depth h, big-endian,
+// zero padded past the end (section 4.2.2, "Character Reordering").  Reads,
+// through `load`, the aligned 8-byte word holding the first character and,
+// only when the key straddles a word boundary, the next one (it then holds a
+// character of the string), so no read touches a word without string data.
+// The address arithmetic is the same on the device (non-temporal loads) and
+// on the host (plain loads, for the exhaustive CPU test).
+template <typename Load>
+SS_HD uint64_t gather_key_with(const uint8_t* chars, uint64_t off, uint32_t h, uint32_t len, Load load) {
+    uint32_t rem = len > h ? len - h : 0u;
+    rem = rem < 8u ? rem : 8u;
+    if (rem == 0) return 0;
+    const uintptr_t a = (uintptr_t)(chars + off + h);
+    const uint64_t* p = (const uint64_t*)(a & ~(uintptr_t)7);
+    const uint32_t sh = (uint32_t)(a & 7);
+    const uint64_t w0 = load(p);
+    const uint64_t w1 = (sh + rem > 8) ? load(p + 1) : 0ull;
+    return key_from_words(w0, w1, sh, rem);
+}
+
 // Number of leading equal bytes of two big-endian keys (8 when equal).
 SS_HD uint32_t common_bytes(uint64_t a, uint64_t b) {
     uint64_t x = a ^ b;

@@ -12,21 +12,10 @@ namespace ss {
 
 __device__ __forceinline__ uint32_t min_u32(uint32_t a, uint32_t b) { return a < b ? a : b; }
 
-// chars_h(s): the 8 characters of a string starting at depth h, big-endian,
-// zero padded past the end (section 4.2.2, "Character Reordering").  Reads
-// the aligned 8-byte word holding the first character and, only when the
-// key straddles a word boundary, the next one (it then holds a character
-// of the string), so no read touches a page without string data.
+// chars_h(s) on the device (gather_key_with in ss_device.h), read with
+// non-temporal loads: string characters are touched once per level.
 __device__ __forceinline__ uint64_t gather_key(const uint8_t* chars, uint64_t off, uint32_t h, uint32_t len) {
-    uint32_t rem = len > h ? len - h : 0u;
-    rem = min_u32(rem, 8u);
-    if (rem == 0) return 0;
-    uintptr_t a = (uintptr_t)(chars + off + h);
-    const uint64_t* p = (const uint64_t*)(a & ~(uintptr_t)7);
-    uint32_t sh = (uint32_t)(a & 7);
-    uint64_t w0 = __builtin_nontemporal_load(p);
-    uint64_t w1 = (sh + rem > 8) ? __builtin_nontemporal_load(p + 1) : 0ull;
-    return key_from_words(w0, w1, sh, rem);
+    return gather_key_with(chars, off, h, len, [](const uint64_t* q) { return __builtin_nontemporal_load(q); });
 }
 
 __device__ __forceinline__ uint32_t rem8(uint32_t len, uint32_t h) { return min_u32(len - h, 8u); }

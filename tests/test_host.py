@@ -115,3 +115,53 @@ def test_workspace_query_grows_with_n():
     assert ss.lib().ss_workspace_query(ctx, 1000, ctypes.byref(b1)) == 0
     assert ss.lib().ss_workspace_query(ctx, 1 << 24, ctypes.byref(b2)) == 0
     assert 0 < b1.value < b2.value < 2 * 1024**3
+
+
+GATHER_CHILD = r"""
+import ctypes, mmap, random, sys
+sys.path.insert(0, sys.argv[1])
+import paper_1808_00963_amd as ss
+lib = ss.lib()
+libc = ctypes.CDLL(None)
+libc.mprotect.argtypes = [ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int]
+PAGE = mmap.PAGESIZE
+buf = mmap.mmap(-1, 3 * PAGE)
+base = ctypes.addressof(ctypes.c_char.from_buffer(buf))
+mid = base + PAGE
+rng = random.Random(7)
+data = bytes(rng.randrange(256) for _ in range(PAGE))
+ctypes.memmove(mid, data, PAGE)
+# the pages before and after the string page become unreadable: a read of
+# any word without string data in it ends this process with SIGSEGV
+assert libc.mprotect(base, PAGE, 0) == 0 and libc.mprotect(mid + PAGE, PAGE, 0) == 0
+checked = 0
+for L in range(0, 25):
+    starts = [s for s in range(16)] + [PAGE - L - e for e in range(16)]
+    for start in starts:
+        s = data[start:start + L]
+        for shift in range(8):  # chars pointer alignment
+            if shift > start:
+                continue
+            chars = mid + start - shift
+            for h in range(0, L + 10):
+                got = lib.ss_host_gather_key(ctypes.c_void_p(chars), shift, h, L)
+                chunk = s[h:h + 8]
+                want = int.from_bytes(chunk + b"\0" * (8 - len(chunk)), "big")
+                if got != want:
+                    print(f"MISMATCH len={L} start={start} shift={shift} h={h}: {got:#x} != {want:#x}")
+                    sys.exit(1)
+                checked += 1
+print(f"ok {checked}")
+"""
+
+
+def test_gather_exhaustive_with_guard_pages():
+    """The kernels' key gather (same address arithmetic, host loads) against
+    the definition of chars_h for every string length up to 24, every depth
+    up to 9 past the end, every alignment of the string and of the chars
+    pointer, with the string placed against an unreadable page on either
+    side: a read of a word without string data would kill the child."""
+    import sys
+    r = subprocess.run([sys.executable, "-c", GATHER_CHILD, ROOT], capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0, f"child exit {r.returncode}: {r.stdout[-500:]} {r.stderr[-500:]}"
+    assert r.stdout.startswith("ok ") and int(r.stdout.split()[1]) > 100000
