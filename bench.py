@@ -128,14 +128,18 @@ def run_batch(args):
                 raise ss.SSError(st, "ss_sort_ex")
 
     results = {}
-    ctx.set_config(persistent=False)
+    ctx.set_config(mode="levels")
     results["per_set_launches"] = timed(per_set, max(1, args.steps // 4))
     outs["per_set_launches"] = (perm.clone(), lcp.clone())
     results["batched_levels"] = timed(lambda: ctx.sort_batch(chars, offs, sbd, perm, lcp, stream), args.steps)
     outs["batched_levels"] = (perm.clone(), lcp.clone())
-    ctx.set_config(persistent=True)
+    ctx.set_config(mode="host_levels")
+    results["batched_host_levels"] = timed(lambda: ctx.sort_batch(chars, offs, sbd, perm, lcp, stream), args.steps)
+    outs["batched_host_levels"] = (perm.clone(), lcp.clone())
+    ctx.set_config(mode="persistent")
     results["batched_persistent"] = timed(lambda: ctx.sort_batch(chars, offs, sbd, perm, lcp, stream), args.steps)
     outs["batched_persistent"] = (perm.clone(), lcp.clone())
+    ctx.set_config(mode="levels")
     g = ctx.graph_batch(chars, offs, sbd, perm, lcp)
 
     def graph_run():
@@ -157,7 +161,7 @@ def run_batch(args):
     identical = all(torch.equal(v[0], ref[0]) and torch.equal(v[1], ref[1]) for v in outs.values())
     for k, v in results.items():
         print(f"[bench] {k:22s} {v * 1e3:9.2f} ms  {N / v / 1e9:8.2f} G chars/s", file=sys.stderr, flush=True)
-    best = min(("batched_levels", "batched_persistent", "batched_graph", "batched_autotuned"),
+    best = min(("batched_levels", "batched_host_levels", "batched_persistent", "batched_graph", "batched_autotuned"),
                key=lambda k: results[k])
     out = {
         "metric": METRIC,
@@ -590,6 +594,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="c1_markov_16m")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--sort-mode", default="levels", choices=["levels", "host_levels", "persistent"],
+                    help="how the recursion levels are driven (ss_config.mode)")
     ap.add_argument("--cpu-sample", type=int, default=0,
                     help="strings for the oracle timing (a prefix of the workload; 0 = all)")
     args = ap.parse_args()
@@ -634,6 +640,7 @@ def main():
     perm = torch.empty(n, dtype=torch.int32, device=dev)
     lcp = torch.empty(n, dtype=torch.int32, device=dev)
     ctx = ss.Context(0)
+    ctx.set_config(mode=args.sort_mode)
     stream = torch.cuda.current_stream()
 
     for _ in range(args.warmup):

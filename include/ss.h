@@ -32,16 +32,22 @@
  * holds a character).
  *
  * Streams and errors.  `stream` is a hipStream_t (NULL = default stream).
- * Calls enqueue work on `stream`; they synchronise with the host between
- * recursion levels (the host reads a few counters per level), and return
- * once the sort has completed on the stream.  Inside a sort, independent
- * steps also run on a second stream that the context owns (default
- * priority); it is joined into `stream` by events before every host
- * synchronisation, so the caller sees only `stream`.  Host-detectable errors return
- * immediately without touching the outputs.  Errors detected on the device
- * (non-monotone offsets, a string of 2^31 or more bytes, an internal limit)
- * are returned by the call that detects them and are sticky in the context:
- * ss_get_last_error reports them until ss_clear_error.
+ * Sort calls are asynchronous and stream-ordered: they enqueue the whole
+ * sort on `stream` and return without waiting for it; the outputs are
+ * complete once `stream` has reached the point where the call was made
+ * (synchronise it, or order later work after it).  The sort starts after
+ * the work enqueued on `stream` before the call and after the context's
+ * previous sort (on whichever stream that ran).  Inside a sort, independent
+ * steps also run on two streams that the context owns (default priority),
+ * forked from and joined back into `stream` by events, so the caller sees
+ * only `stream`; the device-driven form is capturable into a hipGraph.
+ * Host-detectable errors (null pointers, aliased outputs, sizes beyond the
+ * limits) are returned by the call without enqueueing anything.  Errors
+ * detected on the device (non-monotone offsets, a string of 2^31 or more
+ * bytes, bad set boundaries, an internal limit) are recorded on the device
+ * and are sticky: ss_ctx_sync, ss_get_last_error (once the sort has
+ * completed) and ss_get_stats report them until ss_clear_error.  The
+ * outputs of a sort with a device-side error are unspecified.
  *
  * Limits.  n <= 2^32 - 2 strings; each string shorter than 2^31 bytes.
  * n = 0 is a no-op.
@@ -69,6 +75,10 @@ typedef int ss_status;
 
 typedef struct ss_ctx ss_ctx;
 
+#define SS_MODE_LEVELS 0
+#define SS_MODE_PERSISTENT 1
+#define SS_MODE_HOST_LEVELS 2
+
 /* Tunable parameters (performance only; results never depend on them). */
 typedef struct {
     uint32_t max_log_splitters; /* d_max: at most v = 2^d_max - 1 splitters
@@ -78,11 +88,19 @@ typedef struct {
                                    v for a segment, 16..2^20, default 64 */
     uint32_t base_max;          /* segments with at most this many strings go
                                    to the base case, 64..1024, default 1024 */
-    uint32_t persistent;        /* 0: one launch per step of every recursion
-                                   level, the host reads the level's work
-                                   counts in between (default); 1: the whole
-                                   sort in ONE persistent launch that walks the
-                                   levels on the device (no host round trips) */
+    uint32_t mode;              /* how the recursion levels are driven:
+                                   SS_MODE_LEVELS (default): every level is
+                                   enqueued as separate launches whose kernels
+                                   read the level's work counts on the device,
+                                   as many levels as the context's last sort
+                                   needed, then one persistent launch runs any
+                                   levels left; no host synchronisation.
+                                   SS_MODE_PERSISTENT: the whole sort in ONE
+                                   persistent launch that walks the levels on
+                                   the device.  SS_MODE_HOST_LEVELS: the host
+                                   reads each level's counts and enqueues it
+                                   with exact grids (synchronises once per
+                                   level; kept for comparison). */
 } ss_config;
 
 /* Returns a short description of a status code (static storage). */
@@ -91,10 +109,16 @@ const char* ss_status_string(ss_status s);
 /* Library version string (static storage). */
 const char* ss_version(void);
 
-/* Creates a context bound to HIP device `device`.  The context owns a
- * grow-only workspace (freed by ss_ctx_destroy); `scratch_limit` bytes caps
- * it (0 = no cap; a call needing more returns SS_OUT_OF_MEMORY).  One
- * context must not be used by two host threads at once. */
+/* Creates a context bound to HIP device `device`.  The context owns the
+ * sort's working memory: the two ping-pong element arrays of the
+ * out-of-place redistribution (section 4.2.8), the bucket ("oracle") array
+ * and the per-tile bucket counters of the distribution steps (Algorithm
+ * 4.1), the splitter trees (section 4.2.2) and the lists of segments and
+ * pending boundary LCPs (Figure 4.7).  The workspace is grow-only (freed by
+ * ss_ctx_destroy); `scratch_limit` bytes caps it (0 = no cap; a call needing
+ * more returns SS_OUT_OF_MEMORY).  One context must not be used by two host
+ * threads at once; sorts on one context run one after the other on the
+ * device even when issued on different streams. */
 ss_status ss_ctx_create(ss_ctx** ctx, int device, size_t scratch_limit);
 void ss_ctx_destroy(ss_ctx* ctx);
 
@@ -103,8 +127,12 @@ void ss_ctx_destroy(ss_ctx* ctx);
 ss_status ss_get_config(const ss_ctx* ctx, ss_config* cfg);
 ss_status ss_set_config(ss_ctx* ctx, const ss_config* cfg);
 
-/* Bytes of workspace a sort of n strings needs (host function, no device
- * access). */
+/* Bytes of workspace a sort of n strings needs under the context's current
+ * configuration (host function, no device access): the arrays listed at
+ * ss_ctx_create, sized for the worst case of one recursion level -- at most
+ * n strings in flight, n/2 + 2n/bucket_target + 3 n/(base_max+1) bucket
+ * counters (Algorithm 4.1 keeps 2v+1 counters per tile, Theorem 4.4) and
+ * n pending boundary LCPs (Figure 4.7). */
 ss_status ss_workspace_query(const ss_ctx* ctx, uint32_t n, size_t* bytes);
 
 /* Sorts one string set (section 2.1 problem, method of section 4.2:
@@ -120,7 +148,10 @@ ss_status ss_sort(const uint8_t* chars, const uint64_t* offsets, uint32_t n,
                   uint32_t* perm_out, uint32_t* lcp_out, void* stream);
 
 /* Batched form: sorts num_sets independent string sets in one pass of the
- * pipeline (all sets' segments are processed by the same kernel launches).
+ * pipeline (all sets' segments are processed by the same kernel launches):
+ * each set is the section 2.1 problem on its own, and the sets are the
+ * independent jobs that section 4.2.8 runs side by side (every job of any
+ * size shares the processors with the others).
  * The strings of all sets are given as one string array (chars, offsets
  * with offsets[set_begin[num_sets]] characters); set j consists of strings
  * set_begin[j] .. set_begin[j+1]-1.  set_begin: device, num_sets+1
@@ -133,23 +164,32 @@ ss_status ss_sort_batch(ss_ctx* ctx, const uint8_t* chars, const uint64_t* offse
                         const uint32_t* set_begin, uint32_t num_sets,
                         uint32_t* perm_out, uint32_t* lcp_out, void* stream);
 
-/* Graph form of the batched sort: captures the complete batched sort of the
- * given buffers (workspace sized and bound at capture time) as a hipGraph
- * whose only work is a reset kernel and ONE persistent kernel, so repeated
- * launches cost one graph launch each.  The buffers must stay valid and keep
- * their shapes while the graph exists; the contents may change between
- * launches.  Launches of graphs of the same context must not overlap (they
- * share its workspace).  ss_graph_launch enqueues and returns; the result of
- * a launch (device-side errors) is read by ss_ctx_sync. */
+/* Graph form of the batched sort (section 4.2.8, the batched sets as
+ * independent jobs): captures the complete batched sort of the given
+ * buffers as a hipGraph, so repeated launches cost one graph launch each.
+ * Creating the graph runs the batched sort once (synchronously; the outputs
+ * then hold its result) to learn how many recursion levels it needs; the
+ * graph holds that many levels of separate launches whose kernels read the
+ * level's work counts on the device, then ONE persistent launch that runs
+ * any levels left (later contents may need more) and the boundary LCPs.
+ * The graph owns its workspace (allocated here, freed by ss_graph_destroy),
+ * so it is independent of the context's own sorts.  The buffers must stay
+ * valid and keep their shapes while the graph exists; the contents may
+ * change between launches.  Launches of one graph must not overlap each
+ * other.  ss_graph_launch enqueues and returns; device-side errors of a
+ * launch are reported by ss_ctx_sync of the context the graph was created
+ * on.  ss_graph_levels returns the number of level launches in the graph. */
 typedef struct ss_graph ss_graph;
 ss_status ss_graph_create_batch(ss_ctx* ctx, const uint8_t* chars, const uint64_t* offsets, uint32_t n,
                                 const uint32_t* set_begin, uint32_t num_sets, uint32_t* perm_out,
                                 uint32_t* lcp_out, ss_graph** graph_out);
 ss_status ss_graph_launch(ss_graph* graph, void* stream);
 void ss_graph_destroy(ss_graph* graph);
+uint32_t ss_graph_levels(const ss_graph* graph);
 
-/* Waits for `stream` and returns the device-side status of the context's
- * last sort (sticky, as for the other entry points). */
+/* Waits for `stream` and for the context's last sort, and returns the
+ * context's sticky device-side status: SS_OK, or the error of any sort or
+ * graph launch of the context since the last ss_clear_error. */
 ss_status ss_ctx_sync(ss_ctx* ctx, void* stream);
 
 /* Autotuner (variant tuning of section 4.4 / the evaluation's tuned
@@ -276,13 +316,15 @@ void ss_server_reset_stats(ss_server* srv);
 /* Stops the worker after the in-flight and queued requests finish. */
 void ss_server_destroy(ss_server* srv);
 
-/* Sticky device-side error of a context (SS_OK if none). */
-ss_status ss_get_last_error(const ss_ctx* ctx);
+/* Sticky error of a context (SS_OK if none): host-side failures, and the
+ * device-side errors of sorts that have completed (it does not wait).
+ * ss_clear_error waits for the context's last sort and clears both. */
+ss_status ss_get_last_error(ss_ctx* ctx);
 void ss_clear_error(ss_ctx* ctx);
 
-/* Statistics of the last sort on a context (host values, filled after the
- * call returns): recursion levels, distribution steps, base-case segments,
- * pending boundary LCPs. */
+/* Statistics of the last sort on a context, counted on the device level by
+ * level: recursion levels, distribution steps (Algorithm 4.1), base-case
+ * segments, pending boundary LCPs (Figure 4.7).  Waits for the last sort. */
 typedef struct {
     uint32_t levels;
     uint32_t dist_segments;
@@ -295,14 +337,17 @@ typedef struct {
                                            <= 256 and <= base_max strings */
     uint64_t base_strings_by_class[4];  /* strings in those segments */
 } ss_stats;
-ss_status ss_get_stats(const ss_ctx* ctx, ss_stats* st);
+ss_status ss_get_stats(ss_ctx* ctx, ss_stats* st);
 
 /* Per-kernel timing (tracing).  When enabled on a context, every kernel
- * launch of a sort is bracketed by a pair of HIP events on the sort's
- * stream; durations are read at the host synchronisations the sort already
- * performs and accumulated per kernel until ss_reset_kernel_times.  `units`
- * counts the work items the launches processed (strings, segments,
- * counters or boundary entries, see `unit`). */
+ * launch of a sort is bracketed by a pair of HIP events on the stream it is
+ * launched on, and the sort call waits for the sort to finish (tracing makes
+ * sorts synchronous); durations are accumulated per kernel until
+ * ss_reset_kernel_times.  `units` counts the work items the launches
+ * processed (strings, segments, counters or boundary entries, see `unit`),
+ * taken from the level's work counts recorded on the device.  Launches of
+ * a level that turned out to have no work for a kernel count as launches
+ * with zero units. */
 typedef struct {
     const char* name;      /* kernel name (static storage) */
     const char* unit;      /* what `units` counts (static storage) */

@@ -21,6 +21,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libss.so")
 
 SS_OK, SS_INVALID_ARG, SS_OUT_OF_MEMORY, SS_HIP_ERROR, SS_LIMIT, SS_REJECTED, SS_TIMEOUT, SS_INTERNAL = range(8)
+MODE_LEVELS, MODE_PERSISTENT, MODE_HOST_LEVELS = range(3)
+MODES = {"levels": MODE_LEVELS, "persistent": MODE_PERSISTENT, "host_levels": MODE_HOST_LEVELS}
 
 _lib = None
 
@@ -33,7 +35,7 @@ class SSError(RuntimeError):
 
 class Config(ctypes.Structure):
     _fields_ = [("max_log_splitters", ctypes.c_uint32), ("bucket_target", ctypes.c_uint32),
-                ("base_max", ctypes.c_uint32), ("persistent", ctypes.c_uint32)]
+                ("base_max", ctypes.c_uint32), ("mode", ctypes.c_uint32)]
 
 
 class Stats(ctypes.Structure):
@@ -89,6 +91,7 @@ def lib():
             "ss_graph_create_batch": (i32, [vp, vp, vp, u32, vp, u32, vp, vp, ctypes.POINTER(vp)]),
             "ss_graph_launch": (i32, [vp, vp]),
             "ss_graph_destroy": (None, [vp]),
+            "ss_graph_levels": (u32, [vp]),
             "ss_ctx_sync": (i32, [vp, vp]),
             "ss_server_create": (i32, [ctypes.POINTER(vp), i32, ctypes.c_size_t, u32, u32, ctypes.POINTER(Config)]),
             "ss_server_submit": (i32, [vp, ctypes.POINTER(Request), ctypes.POINTER(u64)]),
@@ -179,7 +182,9 @@ class Context:
         _check(lib().ss_get_config(self._h, ctypes.byref(c)), "ss_get_config")
         return c
 
-    def set_config(self, max_log_splitters=None, bucket_target=None, base_max=None, persistent=None):
+    def set_config(self, max_log_splitters=None, bucket_target=None, base_max=None, mode=None):
+        """mode: "levels" (device-driven levels, default), "persistent" or
+        "host_levels" (or the MODE_* constants)."""
         c = self.config
         if max_log_splitters is not None:
             c.max_log_splitters = max_log_splitters
@@ -187,8 +192,8 @@ class Context:
             c.bucket_target = bucket_target
         if base_max is not None:
             c.base_max = base_max
-        if persistent is not None:
-            c.persistent = 1 if persistent else 0
+        if mode is not None:
+            c.mode = MODES[mode] if isinstance(mode, str) else int(mode)
         _check(lib().ss_set_config(self._h, ctypes.byref(c)), "ss_set_config")
 
     def stats(self) -> dict:
@@ -231,7 +236,10 @@ class Context:
         lib().ss_clear_error(self._h)
 
     def sort(self, chars, offsets, perm=None, lcp=None, stream=None):
-        """Sorts one set; returns (perm, lcp) int32 tensors holding uint32."""
+        """Enqueues the sort of one set on `stream` (current stream if None)
+        and returns (perm, lcp) int32 tensors holding uint32, complete once
+        the stream reaches this point.  Device-side errors are raised by
+        sync()."""
         _check_inputs(chars, offsets)
         n = offsets.numel() - 1
         if perm is None:
@@ -245,7 +253,8 @@ class Context:
         return perm, lcp
 
     def sync(self, stream=None):
-        """Waits for the stream; raises on a device-side error of the last sort."""
+        """Waits for the stream and the context's last sort; raises on a
+        (sticky) device-side error of any sort since clear_error()."""
         _check(lib().ss_ctx_sync(self._h, _stream_ptr(stream)), "ss_ctx_sync")
 
     def graph_batch(self, chars, offsets, set_begin, perm, lcp) -> "Graph":
@@ -369,6 +378,11 @@ class Graph:
 
     def launch(self, stream=None):
         _check(lib().ss_graph_launch(self._h, _stream_ptr(stream)), "ss_graph_launch")
+
+    @property
+    def levels(self) -> int:
+        """Level launches in the graph before its persistent tail."""
+        return int(lib().ss_graph_levels(self._h))
 
     def close(self):
         if self._h:

@@ -24,43 +24,66 @@ using namespace ss;
 namespace {
 enum KernelId {
     K_INIT, K_ROOTS, K_BASE_W1, K_BASE_W2, K_BASE_W4, K_BASE, K_SAMPLE, K_CLASSIFY, K_SCAN, K_SCATTER, K_CHILDREN,
-    K_LCP_FILL, K_PERSIST, K_MERGE_SPLIT, K_MERGE, K_SA_STRINGS, K_SA_RENAME, K_COUNT
+    K_LCP_FILL, K_PERSIST, K_LEVEL_BEGIN, K_MERGE_SPLIT, K_MERGE, K_SA_STRINGS, K_SA_RENAME, K_COUNT
 };
 const char* const KNAME[K_COUNT] = {"k_init", "k_roots", "k_base_wave1", "k_base_wave2", "k_base_wave4", "k_base",
                                     "k_sample", "k_classify", "k_scan", "k_scatter", "k_children", "k_lcp_fill",
-                                    "k_persist", "k_merge_split", "k_merge_tile", "k_sa_strings",
+                                    "k_persist", "k_level_begin", "k_merge_split", "k_merge_tile", "k_sa_strings",
                                     "k_sa_rename"};
 const char* const KUNIT[K_COUNT] = {"strings", "sets", "strings", "strings", "strings", "strings", "segments",
-                                    "strings", "counters", "strings", "segments", "boundaries", "strings",
+                                    "strings", "counters", "strings", "segments", "boundaries", "strings", "levels",
                                     "tiles", "strings", "suffixes", "suffixes"};
 
-// Event pairs around kernel launches, resolved at the next host sync.
+// What a timed launch counts (resolved once the sort's control block is on
+// the host): a constant, or a field of the work counts of its level.
+enum UnitField { U_CONST = -1, U_BASE0 = 0, U_DIST = NCLS, U_DIST_STRINGS, U_CNT, U_PEND };
+struct UnitSpec {
+    double units = 0.0;
+    int field = U_CONST;
+    uint32_t level = 0;
+};
+UnitSpec units_const(double u) { return UnitSpec{u, U_CONST, 0}; }
+UnitSpec units_level(int field, uint32_t level) { return UnitSpec{0.0, field, level}; }
+
+// Event pairs around kernel launches, resolved after the sort completes.
 struct Profiler {
     bool on = false;
     uint32_t mask = ~0u;  // kernels (bit per KernelId) that get event pairs
     std::vector<hipEvent_t> ev;  // pairs (start, stop)
     std::vector<int> kid;
-    std::vector<double> units;
+    std::vector<UnitSpec> spec;
     size_t used = 0;
     double ms[K_COUNT] = {};
     double unit_sum[K_COUNT] = {};
     uint32_t launches[K_COUNT] = {};
 };
+
+// A sort workspace: one device allocation laid out as a Work, with the
+// string count and the configuration its pools were sized for.
+struct Ws {
+    void* mem = nullptr;
+    size_t bytes = 0;
+    uint32_t n = 0;
+    uint32_t bucket_target = 0, base_max = 0;
+    Work work{};
+};
 }  // namespace
+
+struct ss_graph;
 
 struct ss_ctx {
     int device = 0;
     size_t scratch_limit = 0;
-    void* ws = nullptr;
-    size_t ws_bytes = 0;
-    uint32_t ws_n = 0;  // largest n the workspace was laid out for
-    Work work{};
-    Ctl* host_ctl = nullptr;  // pinned copy of the device control block
-    ss_config cfg{10, 64, 1024, 0};
+    Ws ws;                    // workspace of the context's own sorts
+    Ctl* host_ctl = nullptr;  // pinned: the control block after the last sort
+    ss_config cfg{10, 64, 1024, SS_MODE_LEVELS};
     ss_status sticky = SS_OK;
     ss_stats stats{};
+    bool pending = false;     // host_ctl of the last sort not yet absorbed
+    uint32_t level_hint = 0;  // levels the last completed sort needed
     Profiler prof;
-    uint32_t persist_blocks = 0;  // co-resident work groups of the persistent kernel
+    KernelCaps kc{};          // resident work groups of each level kernel
+    bool kc_ok = false;
     // merge workspace (grow-only): device part and pinned staging of the
     // task tables and the error word
     void* mws = nullptr;
@@ -71,22 +94,29 @@ struct ss_ctx {
     void* saws = nullptr;
     size_t saws_bytes = 0;
     uint32_t* sa_host = nullptr;
-    // second stream (default priority) for the steps that overlap others
-    // inside one sort (first-level sampling beside the key gather, base
-    // cases beside the distribution steps); fork/join events
-    hipStream_t side = nullptr;
-    hipEvent_t fork = nullptr, join = nullptr;
+    // two library streams (default priority) for the steps of a sort that
+    // overlap others: the first level's sampling beside the key gather, the
+    // base cases of a level beside its distribution steps; fork/join events;
+    // `done` marks the end of the last sort (the workspace is free again)
+    hipStream_t side[2] = {nullptr, nullptr};
+    hipEvent_t fork = nullptr, join[2] = {nullptr, nullptr}, done = nullptr;
+    bool done_recorded = false;
+    std::vector<ss_graph*> graphs;  // live graphs (their errors are read by ss_ctx_sync)
 };
 
 struct ss_graph {
     ss_ctx* ctx = nullptr;
+    Ws ws;  // the graph's own workspace, bound into its kernels
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    uint32_t levels = 0;  // levels enqueued as separate launches before the persistent tail
 };
 
 namespace {
 
 constexpr uint32_t MAX_LEVELS = 1u << 17;
+constexpr uint32_t DEFAULT_LEVELS = 4;   // level launches of a context's first sort
+constexpr uint32_t MAX_LEVEL_LAUNCHES = 32;
 // Smallest sort whose first-level sampling runs beside the key gather (the
 // gather of 2^21 strings takes about as long as one sampling step).
 constexpr uint32_t FORK_MIN = 1u << 21;
@@ -96,27 +126,31 @@ void clamp_config(ss_config* c) {
     c->max_log_splitters = std::min<uint32_t>(std::max<uint32_t>(c->max_log_splitters, 1), MAX_LOGV);
     c->bucket_target = std::min<uint32_t>(std::max<uint32_t>(c->bucket_target, 16), 1u << 20);
     c->base_max = std::min<uint32_t>(std::max<uint32_t>(c->base_max, 64), BASE_CAP);
-    c->persistent = c->persistent ? 1u : 0u;
+    if (c->mode > SS_MODE_HOST_LEVELS) c->mode = SS_MODE_LEVELS;
 }
 
 // Worst-case pool sizes of one recursion level for n strings (the segments
 // of a level are disjoint, so their sizes sum to at most n).
-Caps caps_for(uint32_t n, const ss_config& c) {
+//   counters: a distribution segment of s strings has T = ceil(s / TILE)
+//   tiles and k = 2v+1 <= min(MAX_BUCKETS, max(3, 2 s / bucket_target))
+//   buckets; with several tiles k T < MAX_BUCKETS * 2 s / TILE < s / 2, with
+//   one tile k T <= 3 + 2 s / bucket_target.  Summed: n/2 + 2n/bt + 3 dist.
+//   tree slots: v + 1 <= max(2, s / bucket_target) per segment.
+Caps caps_for(uint32_t n, uint32_t bucket_target, uint32_t base_max) {
     uint64_t N = n;
     Caps k{};
-    uint64_t dist = N / (c.base_max + 1) + 2;
+    uint64_t dist = N / (base_max + 1) + 2;
     k.dist = (uint32_t)dist;
     k.tiles = (uint32_t)(N / TILE + dist + 2);
     k.base[0] = (uint32_t)(N / 2 + 2);
     for (int c = 1; c < NCLS; ++c) k.base[c] = (uint32_t)(N / (CLS_MAX[c - 1] + 1) + 2);
-    // sum of (2v+1) * tiles: at most MAX_BUCKETS per tile of a multi-tile
-    // segment, at most max(3, 2 size / bucket_target) for one-tile segments
-    k.cnt = (uint32_t)std::min<uint64_t>(
-        (uint64_t)MAX_BUCKETS * (N / TILE + dist) + 2 * N / c.bucket_target + 3 * dist + 4096, 0xFFFFFFF0ull);
-    k.tree = (uint32_t)(2 * dist + N / c.bucket_target + 2 * (1u << MAX_LOGV));
+    static_assert(4 * MAX_BUCKETS <= TILE, "multi-tile counter bound");
+    k.cnt = (uint32_t)std::min<uint64_t>(N / 2 + 2 * N / bucket_target + 3 * dist + 4096, 0xFFFFFFF0ull);
+    k.tree = (uint32_t)(2 * dist + N / bucket_target + 2 * (1u << MAX_LOGV));
     k.pend = (uint32_t)(N + 1);
     return k;
 }
+Caps caps_for(uint32_t n, const ss_config& c) { return caps_for(n, c.bucket_target, c.base_max); }
 
 size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -143,6 +177,7 @@ size_t layout(uint32_t n, const Caps& k, char* base, Work* w) {
     t.pend = (Pend*)take(sizeof(Pend) * k.pend);
     t.pend2 = nullptr;
     t.ctl = (Ctl*)take(sizeof(Ctl));
+    t.feed = (FeedLine*)take(sizeof(FeedLine) * FEED_LINES);
     t.bar = (GridBar*)take(sizeof(GridBar));
     t.zero_base = (uint32_t*)take(256);
     t.set_base = t.zero_base;  // a plain sort is one set starting at 0
@@ -161,32 +196,54 @@ ss_status hip_status(hipError_t e) { return e == hipSuccess ? SS_OK : SS_HIP_ERR
         if (e_ != hipSuccess) return SS_HIP_ERROR;    \
     } while (0)
 
-ss_status ensure_workspace(ss_ctx* ctx, uint32_t n) {
-    if (ctx->ws && n <= ctx->ws_n) return SS_OK;
-    uint32_t want = std::max<uint32_t>(n, std::min<uint32_t>(ctx->ws_n ? ctx->ws_n * 2u : n, 0xFFFFFFFEu));
+void ws_free(Ws& ws) {
+    if (ws.mem) (void)hipFree(ws.mem);
+    ws = Ws{};
+}
+
+// Makes `ws` hold a sort of n strings under configuration `c`: a new layout
+// when n is larger than the current one or when c's pools are larger
+// (smaller bucket target or base-case size).  The caller must make sure no
+// sort still uses the old allocation.
+ss_status ws_ensure(Ws& ws, uint32_t n, const ss_config& c, size_t limit, bool* moved = nullptr) {
+    if (moved) *moved = false;
+    const bool fits = ws.mem && n <= ws.n && c.bucket_target >= ws.bucket_target && c.base_max >= ws.base_max;
+    if (fits) return SS_OK;
+    uint32_t want = std::max<uint32_t>(n, std::min<uint32_t>(ws.n ? ws.n * 2u : n, 0xFFFFFFFEu));
     want = std::max(want, n);
-    Caps k = caps_for(want, ctx->cfg);
+    // pools for the smaller of the old and new parameters, so switching back
+    // does not lay out again
+    const uint32_t bt = ws.mem ? std::min(c.bucket_target, ws.bucket_target) : c.bucket_target;
+    const uint32_t bm = ws.mem ? std::min(c.base_max, ws.base_max) : c.base_max;
+    Caps k = caps_for(want, bt, bm);
     size_t bytes = layout(want, k, nullptr, nullptr);
-    if (ctx->scratch_limit && bytes > ctx->scratch_limit) {
+    if (limit && bytes > limit) {
         want = n;
-        k = caps_for(want, ctx->cfg);
+        k = caps_for(want, c);
         bytes = layout(want, k, nullptr, nullptr);
-        if (bytes > ctx->scratch_limit) return SS_OUT_OF_MEMORY;
+        if (bytes > limit) return SS_OUT_OF_MEMORY;
     }
-    if (ctx->ws) {
-        (void)hipFree(ctx->ws);
-        ctx->ws = nullptr;
-        ctx->ws_n = 0;
-    }
+    ws_free(ws);
+    if (moved) *moved = true;
     void* p = nullptr;
     if (hipMalloc(&p, bytes) != hipSuccess) {
         (void)hipGetLastError();
         return SS_OUT_OF_MEMORY;
     }
-    ctx->ws = p;
-    ctx->ws_bytes = bytes;
-    ctx->ws_n = want;
-    layout(want, k, (char*)p, &ctx->work);
+    ws.mem = p;
+    ws.bytes = bytes;
+    ws.n = want;
+    ws.bucket_target = bt;
+    ws.base_max = bm;
+    layout(want, k, (char*)p, &ws.work);
+    // a fresh allocation holds whatever the memory held before; the sticky
+    // error word is kept across resets, so it starts at zero here
+    // (synchronous, before any sort can use the workspace)
+    const Ctl zero{};
+    if (hipMemcpy(ws.work.ctl, &zero, sizeof(Ctl), hipMemcpyHostToDevice) != hipSuccess) {
+        ws_free(ws);
+        return SS_HIP_ERROR;
+    }
     return SS_OK;
 }
 
@@ -198,7 +255,7 @@ ss_status device_error_status(uint32_t err) {
 
 // Launches `fn` and, when profiling, brackets it with an event pair.
 template <typename F>
-hipError_t timed(ss_ctx* ctx, hipStream_t s, int id, double units, F&& fn) {
+hipError_t timed(ss_ctx* ctx, hipStream_t s, int id, UnitSpec u, F&& fn) {
     Profiler& P = ctx->prof;
     if (!P.on || !((P.mask >> id) & 1u)) return fn();
     if (P.used * 2 + 2 > P.ev.size()) {
@@ -216,198 +273,321 @@ hipError_t timed(ss_ctx* ctx, hipStream_t s, int id, double units, F&& fn) {
     if (r != hipSuccess) return r;
     r = hipEventRecord(b, s);
     if (r != hipSuccess) return r;
-    if (P.kid.size() <= P.used) { P.kid.resize(P.used + 1); P.units.resize(P.used + 1); }
+    if (P.kid.size() <= P.used) { P.kid.resize(P.used + 1); P.spec.resize(P.used + 1); }
     P.kid[P.used] = id;
-    P.units[P.used] = units;
+    P.spec[P.used] = u;
     ++P.used;
     return hipSuccess;
 }
 
-// Accumulates the durations of all recorded pairs (stream already synced).
+double spec_units(const UnitSpec& u, const Ctl& c) {
+    if (u.field == U_CONST) return u.units;
+    if (u.field == U_PEND) return c.n_pend;
+    if (u.level >= LEVEL_RECS || u.level >= c.stats.levels) return 0.0;
+    const LevelRec& r = c.lv[u.level];
+    if (u.field >= U_BASE0 && u.field < U_BASE0 + NCLS) return r.base_strings[u.field - U_BASE0];
+    if (u.field == U_DIST) return r.n_dist;
+    if (u.field == U_DIST_STRINGS) return r.dist_strings;
+    if (u.field == U_CNT) return r.n_cnt;
+    return 0.0;
+}
+
+// Accumulates the durations of all recorded pairs (the sort has completed and
+// host_ctl holds its control block).
 void resolve_timings(ss_ctx* ctx) {
     Profiler& P = ctx->prof;
     for (size_t i = 0; i < P.used; ++i) {
         float ms = 0.f;
         if (hipEventElapsedTime(&ms, P.ev[2 * i], P.ev[2 * i + 1]) == hipSuccess) {
             P.ms[P.kid[i]] += ms;
-            P.unit_sum[P.kid[i]] += P.units[i];
+            P.unit_sum[P.kid[i]] += spec_units(P.spec[i], *ctx->host_ctl);
             P.launches[P.kid[i]] += 1;
         }
     }
     P.used = 0;
 }
 
-// Reads the control block into the pinned host copy (synchronous).
-ss_status read_ctl(ss_ctx* ctx, hipStream_t s) {
-    SS_TRY(hipMemcpyAsync(ctx->host_ctl, ctx->work.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
-    SS_TRY(hipStreamSynchronize(s));
+// Takes over the control block of the last sort (its copy in host_ctl is
+// complete): statistics, level hint, device-side errors.
+void absorb(ss_ctx* ctx) {
+    const Ctl& c = *ctx->host_ctl;
+    ss_stats st{};
+    st.levels = c.stats.levels;
+    st.dist_segments = c.stats.dist_segments;
+    st.dist_tiles = c.stats.dist_tiles;
+    st.max_depth = c.stats.max_depth;
+    for (int q = 0; q < NCLS; ++q) {
+        st.base_segments += c.stats.base_segments[q];
+        st.base_segments_by_class[q] = c.stats.base_segments[q];
+        st.base_strings_by_class[q] = c.stats.base_strings[q];
+    }
+    st.pending_lcps = c.n_pend;
+    st.base_rounds = base_rounds_of(c);
+    ctx->stats = st;
+    if (c.stats.levels) ctx->level_hint = c.stats.levels;
+    // the device keeps the errors of every sort since the last clear, so an
+    // error of a sort whose control block was never taken over here (a later
+    // sort was enqueued first) is still seen
+    if (c.err_sticky && ctx->sticky == SS_OK) ctx->sticky = device_error_status(c.err_sticky);
+    ctx->pending = false;
+}
+
+// Waits for the last sort of the context and takes over its control block.
+ss_status finish_pending(ss_ctx* ctx) {
+    if (!ctx->pending) return SS_OK;
+    SS_TRY(hipEventSynchronize(ctx->done));
     if (ctx->prof.used) resolve_timings(ctx);
+    absorb(ctx);
     return SS_OK;
 }
 
-// Reset + the persistent kernel (no host synchronisation; capturable).
-ss_status enqueue_persistent(ss_ctx* ctx, const Work& w, const Params& p, const uint32_t* set_begin,
-                             uint32_t nroots, hipStream_t s) {
-    if (ctx->persist_blocks == 0) {
-        uint32_t b = 0;
-        SS_TRY(persistent_capacity(ctx->device, &b));
-        if (b == 0) return SS_HIP_ERROR;
-        ctx->persist_blocks = b;
+// Reads the control block into the pinned host copy (synchronous; the
+// host-driven level loop and the serving worker).
+ss_status read_ctl(ss_ctx* ctx, const Work& w, hipStream_t s) {
+    SS_TRY(hipMemcpyAsync(ctx->host_ctl, w.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+    SS_TRY(hipStreamSynchronize(s));
+    return SS_OK;
+}
+
+ss_status ensure_streams(ss_ctx* ctx) {
+    if (ctx->done) return SS_OK;
+    for (int i = 0; i < 2; ++i) {
+        SS_TRY(hipStreamCreateWithFlags(&ctx->side[i], hipStreamNonBlocking));
+        SS_TRY(hipEventCreateWithFlags(&ctx->join[i], hipEventDisableTiming));
     }
+    SS_TRY(hipEventCreateWithFlags(&ctx->fork, hipEventDisableTiming));
+    SS_TRY(hipEventCreateWithFlags(&ctx->done, hipEventDisableTiming));
+    return SS_OK;
+}
+
+ss_status ensure_caps(ss_ctx* ctx) {
+    if (ctx->kc_ok) return SS_OK;
+    SS_TRY(kernel_caps(ctx->device, &ctx->kc));
+    ctx->kc_ok = true;
+    return SS_OK;
+}
+
+// What the host knows about a level when it enqueues it: exact counts (the
+// host-driven loop and serving) or nothing (pool capacities bound the work).
+struct LevelPlan {
+    bool exact = false;
+    Counts c{};
+    bool maybe_dist = true;
+    uint32_t maybe_base = (1u << NCLS) - 1;  // classes that may have segments
+    bool sampled = false;                    // sampling already enqueued (first level)
+};
+
+uint32_t clamp_grid(uint32_t resident, uint32_t need) { return std::max<uint32_t>(1, std::min(resident, need)); }
+// Rounds of resident work groups launched for the item kernels: the items
+// of the launched groups are static (the hardware starts a group when
+// another leaves), the rest is taken from the feed.
+constexpr uint32_t ROUNDS_BASE = 16, ROUNDS_TILES = 8;
+// The scatter takes one half tile per work group (see k_scatter); its grid
+// covers up to this many rounds of resident groups.
+constexpr uint32_t ROUNDS_SCATTER = 16;
+
+// Enqueues recursion level `level` on slot `cur` (its counts read on the
+// device): level start, then the base cases on the two library streams
+// (classes 0 and 3 on one, 1 and 2 on the other) beside the distribution
+// steps (sample, classify, scan, scatter, children) on `s`, joined into `s`
+// at the end.  Kernels that the plan shows to have no work are left out.
+ss_status enqueue_level(ss_ctx* ctx, const Work& w, const Params& p, int cur, uint32_t level, const LevelPlan& L,
+                        hipStream_t s) {
+    const KernelCaps& kc = ctx->kc;
+    const Caps& cap = w.caps;
+    uint32_t bases = 0;
+    for (int q = 0; q < NCLS; ++q)
+        if ((L.maybe_base >> q) & 1u && (!L.exact || L.c.n_base[q])) bases |= 1u << q;
+    const bool dist = L.maybe_dist && (!L.exact || L.c.n_dist);
+    SS_TRY(timed(ctx, s, K_LEVEL_BEGIN, units_const(1.0), [&] { return launch_level_begin(w, cur, level, s); }));
+    const uint32_t on[2] = {bases & (1u | 1u << 3), bases & (1u << 1 | 1u << 2)};
+    bool forked[2] = {false, false};
+    if (bases) SS_TRY(hipEventRecord(ctx->fork, s));
+    // the distribution steps are enqueued first, so the host's calls for the
+    // library streams do not hold them back
+    if (dist) {
+        const Counts& c = L.c;
+        const uint32_t n_dist = L.exact ? c.n_dist : cap.dist, n_tiles = L.exact ? c.n_tiles : cap.tiles;
+        const uint32_t n_cnt = L.exact ? c.n_cnt : cap.cnt;
+        if (!L.sampled)
+            SS_TRY(timed(ctx, s, K_SAMPLE, units_level(U_DIST, level),
+                         [&] { return launch_sample(w, p, cur, clamp_grid(kc.sample, n_dist), false, s); }));
+        SS_TRY(timed(ctx, s, K_CLASSIFY, units_level(U_DIST_STRINGS, level), [&] {
+            return launch_classify(w, p, cur, clamp_grid(ROUNDS_TILES * kc.classify, grid_classify(n_tiles)), s);
+        }));
+        SS_TRY(timed(ctx, s, K_SCAN, units_level(U_CNT, level),
+                     [&] { return launch_scan(w, cur, clamp_grid(kc.scan, grid_scan(n_cnt)), s); }));
+        SS_TRY(timed(ctx, s, K_SCATTER, units_level(U_DIST_STRINGS, level), [&] {
+            const uint32_t need = grid_scatter(n_tiles), g = clamp_grid(ROUNDS_SCATTER * kc.scatter, need);
+            return launch_scatter(w, p, cur, g, need > g ? kc.scatter : 0u, s);
+        }));
+        SS_TRY(timed(ctx, s, K_CHILDREN, units_level(U_DIST, level), [&] {
+            return launch_children(w, p, cur, clamp_grid(kc.children, grid_children(n_dist)), s);
+        }));
+    }
+    for (int k = 0; k < 2; ++k) {
+        if (!on[k]) continue;
+        hipStream_t bs = dist || k == 1 ? ctx->side[k] : s;  // without distribution steps, `s` takes one share
+        if (bs != s) {
+            SS_TRY(hipStreamWaitEvent(bs, ctx->fork, 0));
+            forked[k] = true;
+        }
+        for (int q = 0; q < NCLS; ++q) {
+            if (!((on[k] >> q) & 1u)) continue;
+            const uint32_t need = grid_base(q, L.exact ? L.c.n_base[q] : cap.base[q]);
+            SS_TRY(timed(ctx, bs, K_BASE_W1 + q, units_level(U_BASE0 + q, level),
+                         [&] { return launch_base(w, p, cur, q, clamp_grid(ROUNDS_BASE * kc.base[q], need), bs); }));
+        }
+    }
+    for (int k = 0; k < 2; ++k) {
+        if (!forked[k]) continue;
+        SS_TRY(hipEventRecord(ctx->join[k], ctx->side[k]));
+        SS_TRY(hipStreamWaitEvent(s, ctx->join[k], 0));
+    }
+    return SS_OK;
+}
+
+// Start of every sort: reset, roots and key gather.  For 2^21 strings or
+// more the roots are emitted before the gather and the first level's
+// sampling reads its keys from the strings on a library stream while the
+// gather fills the buffer (joined before the first classification); its
+// grid covers every root that can be a distribution segment.  Returns
+// whether the first level's sampling was enqueued.
+ss_status enqueue_start(ss_ctx* ctx, const Work& w, const Params& p, const uint32_t* set_begin, uint32_t nroots,
+                        hipStream_t s, bool* sampled) {
+    const uint32_t n = p.n;
     SS_TRY(launch_reset(w, s));
-    SS_TRY(timed(ctx, s, K_PERSIST, p.n, [&] {
-        return launch_persistent(w, p, set_begin, nroots, ctx->persist_blocks, s);
+    *sampled = n >= FORK_MIN;
+    if (*sampled) {
+        SS_TRY(timed(ctx, s, K_ROOTS, units_const(nroots), [&] { return launch_roots(w, p, set_begin, nroots, s); }));
+        const uint32_t root_grid = clamp_grid(ctx->kc.sample, std::min<uint32_t>(nroots, n / (p.base_max + 1) + 1));
+        SS_TRY(hipEventRecord(ctx->fork, s));
+        SS_TRY(timed(ctx, s, K_INIT, units_const(n), [&] { return launch_init(w, p, s); }));
+        SS_TRY(hipStreamWaitEvent(ctx->side[0], ctx->fork, 0));
+        SS_TRY(timed(ctx, ctx->side[0], K_SAMPLE, units_level(U_DIST, 0),
+                     [&] { return launch_sample(w, p, 0, root_grid, true, ctx->side[0]); }));
+        SS_TRY(hipEventRecord(ctx->join[0], ctx->side[0]));
+        SS_TRY(hipStreamWaitEvent(s, ctx->join[0], 0));
+    } else {
+        SS_TRY(timed(ctx, s, K_INIT, units_const(n), [&] { return launch_init(w, p, s); }));
+        SS_TRY(timed(ctx, s, K_ROOTS, units_const(nroots), [&] { return launch_roots(w, p, set_begin, nroots, s); }));
+    }
+    return SS_OK;
+}
+
+// The device-driven sort: start, `levels` levels enqueued without knowing
+// their counts, then one persistent launch that runs whatever is left and
+// the boundary LCPs.  The last enqueued level gets its base cases only: the
+// last level of a sort has no distribution segments, so when `levels` is
+// what the sort needs, that level is complete and the persistent launch
+// finds nothing to do; otherwise it continues with that level's
+// distribution segments.  No host synchronisation; capturable.
+ss_status enqueue_sort_levels(ss_ctx* ctx, const Work& w, const Params& p, const uint32_t* set_begin,
+                              uint32_t nroots, uint32_t levels, hipStream_t s) {
+    bool sampled = false;
+    ss_status st = enqueue_start(ctx, w, p, set_begin, nroots, s, &sampled);
+    if (st != SS_OK) return st;
+    bool one_root_base = false;
+    if (!set_begin) {  // one root: a distribution segment (two levels at least), a base case or nothing
+        if (p.n > p.base_max) levels = std::max<uint32_t>(levels, 2);
+        else levels = 1, one_root_base = true;
+    }
+    int cur = 0;
+    for (uint32_t level = 0; level < levels; ++level) {
+        LevelPlan L;
+        L.sampled = level == 0 && sampled;
+        L.maybe_dist = level + 1 < levels;
+        if (level == 0 && !set_begin) {
+            L.maybe_base = one_root_base && p.n >= 2 ? 1u << size_class(p.n) : 0u;
+            L.maybe_dist = L.maybe_dist && !one_root_base;
+        }
+        if ((st = enqueue_level(ctx, w, p, cur, level, L, s)) != SS_OK) return st;
+        if (level + 1 < levels) cur ^= 1;
+    }
+    SS_TRY(timed(ctx, s, K_PERSIST, units_const(0.0), [&] {
+        return launch_persistent(w, p, set_begin, nroots, ctx->kc.persist, false, levels - 1, cur, true, s);
     }));
     return SS_OK;
 }
 
-// Enqueues one recursion level for the counts `c` of list slot `cur`: the
-// base cases of every class and, if there are distribution segments, their
-// sample/classify/scan/scatter/children steps (children go to slot cur^1,
-// which is zeroed first when `zero_next`: a sort's reset has zeroed both
-// slots, so its first level and a level without children skip it).
-// `sampled`: the level's sampling has already run
-// (first level, on the side stream, joined into `s`).  With `overlap`, a
-// level that has both kinds of segments runs its base cases on the side
-// stream: they read and write positions of their own segments only, so they
-// run beside the distribution steps and join `s` at the level's end (the
-// distribution steps are enqueued first, so the host's calls for the side
-// stream do not delay them).  A level of base cases only splits its classes
-// over the two streams (two-per-lane and four-per-lane waves on `s`, one-per-
-// lane waves and work groups beside them), so that one kernel's tail
-// overlaps the other's.
-ss_status enqueue_level(ss_ctx* ctx, const Work& w, const Params& p, int cur, const Counts& c, bool sampled,
-                        bool overlap, bool zero_next, hipStream_t s) {
-    uint32_t classes = 0;  // bit per non-empty class
-    for (int cls = 0; cls < NCLS; ++cls) classes |= (c.n_base[cls] != 0 ? 1u : 0u) << cls;
-    constexpr uint32_t SIDE_CLASSES = 1u | 1u << 3;  // base-only levels: classes run on the side stream
-    const bool side = overlap && ctx->side &&
-                      (c.n_dist != 0 ? classes != 0 : (classes & SIDE_CLASSES) && (classes & ~SIDE_CLASSES));
-    const uint32_t on_side = !side ? 0u : c.n_dist != 0 ? classes : classes & SIDE_CLASSES;
-    auto bases = [&](hipStream_t bs, uint32_t which) -> ss_status {
-        for (int cls = 0; cls < NCLS; ++cls) {
-            if (!((which >> cls) & 1u)) continue;
-            const uint32_t nb = c.n_base[cls];
-            SS_TRY(timed(ctx, bs, K_BASE_W1 + cls, c.base_strings[cls],
-                         [&] { return launch_base(w, p, cur, cls, nb, bs); }));
-        }
-        return SS_OK;
-    };
-    ss_status st = SS_OK;
-    if (side) SS_TRY(hipEventRecord(ctx->fork, s));
-    if ((st = bases(s, classes & ~on_side)) != SS_OK) return st;
-    if (zero_next) SS_TRY(launch_zero_counts(w, cur ^ 1, s));
-    if (c.n_dist == 0) {
-        if (side) {
-            SS_TRY(hipStreamWaitEvent(ctx->side, ctx->fork, 0));
-            if ((st = bases(ctx->side, on_side)) != SS_OK) return st;
-            SS_TRY(hipEventRecord(ctx->join, ctx->side));
-            SS_TRY(hipStreamWaitEvent(s, ctx->join, 0));
-        }
-        return SS_OK;
+// The host-driven sort: the host reads each level's counts and enqueues the
+// level with exact grids (synchronises once per level).
+ss_status run_sort_host_levels(ss_ctx* ctx, const Work& w, const Params& p, const uint32_t* set_begin,
+                               uint32_t nroots, hipStream_t s) {
+    bool sampled = false;
+    ss_status st = enqueue_start(ctx, w, p, set_begin, nroots, s, &sampled);
+    if (st != SS_OK) return st;
+    int cur = 0;
+    for (uint32_t level = 0;; ++level) {
+        if ((st = read_ctl(ctx, w, s)) != SS_OK) return st;
+        if (ctx->host_ctl->err) break;
+        LevelPlan L;
+        L.exact = true;
+        L.c = counts_of(ctx->host_ctl->cl[cur]);
+        L.sampled = level == 0 && sampled;
+        bool work = L.c.n_dist != 0;
+        for (int q = 0; q < NCLS; ++q) work |= L.c.n_base[q] != 0;
+        if (!work) break;
+        if ((st = enqueue_level(ctx, w, p, cur, level, L, s)) != SS_OK) return st;
+        if (L.c.n_dist == 0) break;
+        cur ^= 1;
+        if (level + 1 >= MAX_LEVELS) return SS_INTERNAL;
     }
-    if (!sampled) SS_TRY(timed(ctx, s, K_SAMPLE, c.n_dist, [&] { return launch_sample(w, p, cur, c.n_dist, false, s); }));
-    SS_TRY(timed(ctx, s, K_CLASSIFY, c.dist_strings,
-                 [&] { return launch_classify(w, p, cur, c.n_tiles, c.n_dist, s); }));
-    SS_TRY(timed(ctx, s, K_SCAN, c.n_cnt, [&] { return launch_scan(w, cur, c.n_cnt, s); }));
-    SS_TRY(timed(ctx, s, K_SCATTER, c.dist_strings,
-                 [&] { return launch_scatter(w, p, cur, c.n_tiles, c.n_dist, s); }));
-    SS_TRY(timed(ctx, s, K_CHILDREN, c.n_dist, [&] { return launch_children(w, p, cur, c.n_dist, s); }));
-    if (side) {
-        SS_TRY(hipStreamWaitEvent(ctx->side, ctx->fork, 0));
-        if ((st = bases(ctx->side, on_side)) != SS_OK) return st;
-        SS_TRY(hipEventRecord(ctx->join, ctx->side));
-        SS_TRY(hipStreamWaitEvent(s, ctx->join, 0));
-    }
+    SS_TRY(timed(ctx, s, K_LCP_FILL, units_level(U_PEND, 0), [&] { return launch_lcp_fill(w, p, s); }));
     return SS_OK;
 }
 
-// The sort: initial key gather, roots, then one iteration per recursion
-// level over all live segments, then the boundary LCPs.
+// Levels to enqueue as separate launches: what the context's last completed
+// sort needed (the persistent tail covers any more).
+uint32_t level_budget(ss_ctx* ctx) {
+    if (ctx->pending && hipEventQuery(ctx->done) == hipSuccess) absorb(ctx);
+    const uint32_t h = ctx->level_hint ? ctx->level_hint : DEFAULT_LEVELS;
+    return std::min<uint32_t>(std::max<uint32_t>(h, 1), MAX_LEVEL_LAUNCHES);
+}
+
+// One sort on the context's workspace, enqueued on `s`.  The previous sort
+// of the context (on any stream) is waited for on the device; the device-
+// driven form returns without waiting for the sort.
 ss_status run_sort(ss_ctx* ctx, const uint8_t* chars, const uint64_t* offsets, uint32_t n,
                    const uint32_t* set_begin, uint32_t num_sets, uint32_t* perm, uint32_t* lcp,
                    hipStream_t s) {
-    ctx->stats = ss_stats{};
     if (n == 0) return SS_OK;
     int cur_dev = -1;
     SS_TRY(hipGetDevice(&cur_dev));
     if (cur_dev != ctx->device) SS_TRY(hipSetDevice(ctx->device));
-    ss_status st = ensure_workspace(ctx, n);
+    ss_status st = ensure_streams(ctx);
+    if (st == SS_OK) st = ensure_caps(ctx);
     if (st != SS_OK) return st;
-    Work w = ctx->work;
+    const uint32_t levels = level_budget(ctx);
+    {
+        const bool fits = ctx->ws.mem && n <= ctx->ws.n && ctx->cfg.bucket_target >= ctx->ws.bucket_target &&
+                          ctx->cfg.base_max >= ctx->ws.base_max;
+        if (!fits && ctx->done_recorded) SS_TRY(hipEventSynchronize(ctx->done));  // the old workspace is free
+        if ((st = ws_ensure(ctx->ws, n, ctx->cfg, ctx->scratch_limit)) != SS_OK) return st;
+    }
+    // the workspace is free once the context's previous sort (on any stream)
+    // is done; its control block copy may still land in host_ctl before this
+    // sort's, which only drops statistics of an intermediate sort
+    if (ctx->done_recorded) SS_TRY(hipStreamWaitEvent(s, ctx->done, 0));
+    Work w = ctx->ws.work;
     if (set_begin) w.set_base = set_begin;  // perm entries are set-local
     Params p{chars, offsets, n, perm, lcp, ctx->cfg.max_log_splitters, ctx->cfg.bucket_target, ctx->cfg.base_max};
-
     const uint32_t nroots = set_begin ? num_sets : 1;
-    if (ctx->cfg.persistent) {
-        if ((st = enqueue_persistent(ctx, w, p, set_begin, nroots, s)) != SS_OK) return st;
-        if ((st = read_ctl(ctx, s)) != SS_OK) return st;
-        ctx->stats.pending_lcps = ctx->host_ctl->n_pend;
-        ctx->stats.base_rounds = base_rounds_of(*ctx->host_ctl);
-        if (ctx->host_ctl->err) return device_error_status(ctx->host_ctl->err);
-        return SS_OK;
-    }
-    // The roots are emitted before the key gather: the first level's
-    // sampling reads its keys from the strings, so it runs on a second
-    // stream while the gather fills the buffer, and joins before classifying
-    // (the gather is enqueued first, so that the host's work for the fork
-    // does not hold it back).  Its grid covers every root that can be a
-    // distribution segment (more than base_max strings); blocks beyond the
-    // device's count return.  Below FORK_MIN strings the gather is shorter
-    // than the sampling and the fork does not pay: the sampling then runs
-    // after the gather, from the gathered keys.
-    SS_TRY(launch_reset(w, s));
-    if (!ctx->side) {
-        SS_TRY(hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking));
-        SS_TRY(hipEventCreateWithFlags(&ctx->fork, hipEventDisableTiming));
-        SS_TRY(hipEventCreateWithFlags(&ctx->join, hipEventDisableTiming));
-    }
-    const bool fork0 = n >= FORK_MIN;
-    if (fork0) {
-        SS_TRY(timed(ctx, s, K_ROOTS, nroots, [&] { return launch_roots(w, p, set_begin, nroots, s); }));
-        const uint32_t root_grid = std::min<uint32_t>(nroots, n / (p.base_max + 1) + 1);
-        SS_TRY(hipEventRecord(ctx->fork, s));
-        SS_TRY(timed(ctx, s, K_INIT, n, [&] { return launch_init(w, p, s); }));
-        SS_TRY(hipStreamWaitEvent(ctx->side, ctx->fork, 0));
-        SS_TRY(timed(ctx, ctx->side, K_SAMPLE, 0.0,
-                     [&] { return launch_sample(w, p, 0, root_grid, true, ctx->side); }));
-        SS_TRY(hipEventRecord(ctx->join, ctx->side));
-        SS_TRY(hipStreamWaitEvent(s, ctx->join, 0));
+    if (ctx->cfg.mode == SS_MODE_PERSISTENT) {
+        SS_TRY(launch_reset(w, s));
+        SS_TRY(timed(ctx, s, K_PERSIST, units_const(n), [&] {
+            return launch_persistent(w, p, set_begin, nroots, ctx->kc.persist, true, 0, 0, false, s);
+        }));
+    } else if (ctx->cfg.mode == SS_MODE_HOST_LEVELS) {
+        if ((st = run_sort_host_levels(ctx, w, p, set_begin, nroots, s)) != SS_OK) return st;
     } else {
-        SS_TRY(timed(ctx, s, K_INIT, n, [&] { return launch_init(w, p, s); }));
-        SS_TRY(timed(ctx, s, K_ROOTS, nroots, [&] { return launch_roots(w, p, set_begin, nroots, s); }));
+        if ((st = enqueue_sort_levels(ctx, w, p, set_begin, nroots, levels, s)) != SS_OK) return st;
     }
-    int cur = 0;
-    uint32_t level = 0;
-    for (;;) {
-        if ((st = read_ctl(ctx, s)) != SS_OK) return st;
-        if (ctx->host_ctl->err) return device_error_status(ctx->host_ctl->err);
-        const Counts c = counts_of(ctx->host_ctl->cl[cur]);
-        const bool first = level == 0 && fork0;
-        // the first level's segment count is known on the device only when
-        // its sampling is launched; its units are added here
-        if (first && ctx->prof.on) ctx->prof.unit_sum[K_SAMPLE] += c.n_dist;
-        ctx->stats.levels = level + 1;
-        ctx->stats.dist_segments += c.n_dist;
-        ctx->stats.dist_tiles += c.n_tiles;
-        for (int q = 0; q < NCLS; ++q) {
-            ctx->stats.base_segments += c.n_base[q];
-            ctx->stats.base_segments_by_class[q] += c.n_base[q];
-            ctx->stats.base_strings_by_class[q] += c.base_strings[q];
-        }
-        ctx->stats.max_depth = std::max(ctx->stats.max_depth, c.max_depth);
-        if ((st = enqueue_level(ctx, w, p, cur, c, first, true, level > 0 && c.n_dist > 0, s)) != SS_OK) return st;
-        if (c.n_dist == 0) break;
-        cur ^= 1;
-        if (++level >= MAX_LEVELS) return SS_INTERNAL;
-    }
-    // the pending count is known on the device only; units are added below
-    SS_TRY(timed(ctx, s, K_LCP_FILL, 0.0, [&] { return launch_lcp_fill(w, p, s); }));
-    if ((st = read_ctl(ctx, s)) != SS_OK) return st;
-    if (ctx->prof.on) ctx->prof.unit_sum[K_LCP_FILL] += ctx->host_ctl->n_pend;
-    ctx->stats.pending_lcps = ctx->host_ctl->n_pend;
-    ctx->stats.base_rounds = base_rounds_of(*ctx->host_ctl);
-    if (ctx->host_ctl->err) return device_error_status(ctx->host_ctl->err);
+    SS_TRY(hipMemcpyAsync(ctx->host_ctl, w.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+    SS_TRY(hipEventRecord(ctx->done, s));
+    ctx->done_recorded = true;
+    ctx->pending = true;
+    if (ctx->prof.on) return finish_pending(ctx);  // timings need the sort to have run
     return SS_OK;
 }
 
@@ -534,8 +714,8 @@ ss_status run_merge(ss_ctx* ctx, const uint8_t* chars, const uint64_t* offsets, 
         a.split = (uint32_t*)(dws + off_split);
         a.cross = (uint32_t*)(dws + off_cross);
         a.err = derr;
-        SS_TRY(timed(ctx, s, K_MERGE_SPLIT, a.n_tiles, [&] { return launch_merge_split(a, s); }));
-        SS_TRY(timed(ctx, s, K_MERGE, (double)m, [&] { return launch_merge_tiles(a, s); }));
+        SS_TRY(timed(ctx, s, K_MERGE_SPLIT, units_const(a.n_tiles), [&] { return launch_merge_split(a, s); }));
+        SS_TRY(timed(ctx, s, K_MERGE, units_const((double)m), [&] { return launch_merge_tiles(a, s); }));
         t0 += rounds[r].size();
     }
     SS_TRY(hipMemcpyAsync(herr, derr, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
@@ -622,7 +802,7 @@ ss_status run_suffix_array(ss_ctx* ctx, const uint8_t* text, uint32_t n, uint32_
     const bool packed = bits <= 4;
     const uint32_t w0 = packed ? 128 / bits : SA_W0;  // characters resolved by round 0
     // round 0: every suffix by its first w0 characters, sorted into sa
-    SS_TRY(timed(ctx, s, K_SA_STRINGS, n, [&] {
+    SS_TRY(timed(ctx, s, K_SA_STRINGS, units_const(n), [&] {
         if (!packed) return launch_sa_windows(text, n, chars, offsets, s);
         hipError_t e = hipMemcpyAsync(rank, hrank, 256, hipMemcpyHostToDevice, s);
         if (e != hipSuccess) return e;
@@ -642,9 +822,12 @@ ss_status run_suffix_array(ss_ctx* ctx, const uint8_t* text, uint32_t n, uint32_
     uint32_t rounds = 1, cur = 0;
     uint64_t h = w0;  // depth the names resolve
     for (;;) {
-        SS_TRY(timed(ctx, s, K_SA_RENAME, a.m, [&] { return launch_sa_rename(a, s); }));
+        SS_TRY(timed(ctx, s, K_SA_RENAME, units_const(a.m), [&] { return launch_sa_rename(a, s); }));
         SS_TRY(hipMemcpyAsync(ctx->sa_host, part_cnt + sa_tiles(a.m), sizeof(uint32_t), hipMemcpyDeviceToHost, s));
         SS_TRY(hipStreamSynchronize(s));
+        // the round's sort has completed: its device-side errors
+        if ((st = finish_pending(ctx)) != SS_OK) return st;
+        if (ctx->host_ctl->err) return device_error_status(ctx->host_ctl->err);
         if (ctx->prof.used) resolve_timings(ctx);
         const uint32_t m = *ctx->sa_host;  // suffixes still sharing their group
         if (m == 0) break;
@@ -655,7 +838,7 @@ ss_status run_suffix_array(ss_ctx* ctx, const uint8_t* text, uint32_t n, uint32_
         a.pos = pos[cur];
         a.idx = idx;
         a.next_pos = pos[cur ^ 1];
-        SS_TRY(timed(ctx, s, K_SA_STRINGS, m, [&] { return launch_sa_pairs(a, (uint32_t)h, chars, offsets, s); }));
+        SS_TRY(timed(ctx, s, K_SA_STRINGS, units_const(m), [&] { return launch_sa_pairs(a, (uint32_t)h, chars, offsets, s); }));
         st = run_sort(ctx, chars, offsets, m, nullptr, 1, perm, lcp, s);
         if (st != SS_OK) return st;
         a.perm = perm;
@@ -716,16 +899,21 @@ void ss_ctx_destroy(ss_ctx* ctx) {
     int prev = 0;
     (void)hipGetDevice(&prev);
     (void)hipSetDevice(ctx->device);
+    if (ctx->done_recorded) (void)hipEventSynchronize(ctx->done);
+    for (ss_graph* g : ctx->graphs) g->ctx = nullptr;  // graphs own their workspaces
     for (hipEvent_t e : ctx->prof.ev) (void)hipEventDestroy(e);
-    if (ctx->ws) (void)hipFree(ctx->ws);
+    ws_free(ctx->ws);
     if (ctx->host_ctl) (void)hipHostFree(ctx->host_ctl);
     if (ctx->mws) (void)hipFree(ctx->mws);
     if (ctx->mhost) (void)hipHostFree(ctx->mhost);
     if (ctx->saws) (void)hipFree(ctx->saws);
     if (ctx->sa_host) (void)hipHostFree(ctx->sa_host);
     if (ctx->fork) (void)hipEventDestroy(ctx->fork);
-    if (ctx->join) (void)hipEventDestroy(ctx->join);
-    if (ctx->side) (void)hipStreamDestroy(ctx->side);
+    if (ctx->done) (void)hipEventDestroy(ctx->done);
+    for (int i = 0; i < 2; ++i) {
+        if (ctx->join[i]) (void)hipEventDestroy(ctx->join[i]);
+        if (ctx->side[i]) (void)hipStreamDestroy(ctx->side[i]);
+    }
     (void)hipSetDevice(prev);
     delete ctx;
 }
@@ -740,19 +928,13 @@ ss_status ss_set_config(ss_ctx* ctx, const ss_config* cfg) {
     if (!ctx || !cfg) return SS_INVALID_ARG;
     ss_config c = *cfg;
     clamp_config(&c);
-    bool relayout = c.base_max != ctx->cfg.base_max || c.bucket_target != ctx->cfg.bucket_target;
-    ctx->cfg = c;
-    if (relayout && ctx->ws) {
-        (void)hipFree(ctx->ws);
-        ctx->ws = nullptr;
-        ctx->ws_n = 0;
-    }
+    ctx->cfg = c;  // the next sort lays the workspace out again if its pools are too small
     return SS_OK;
 }
 
 ss_status ss_workspace_query(const ss_ctx* ctx, uint32_t n, size_t* bytes) {
     if (!bytes) return SS_INVALID_ARG;
-    ss_config c = ctx ? ctx->cfg : ss_config{10, 64, 1024, 0};
+    ss_config c = ctx ? ctx->cfg : ss_config{10, 64, 1024, SS_MODE_LEVELS};
     *bytes = layout(n, caps_for(n, c), nullptr, nullptr);
     return SS_OK;
 }
@@ -797,41 +979,56 @@ ss_status ss_graph_create_batch(ss_ctx* ctx, const uint8_t* chars, const uint64_
     int cur_dev = -1;
     SS_TRY(hipGetDevice(&cur_dev));
     if (cur_dev != ctx->device) SS_TRY(hipSetDevice(ctx->device));
-    ss_status st = ensure_workspace(ctx, n);  // no allocation may happen during capture
+    ss_status st = ensure_streams(ctx);
+    if (st == SS_OK) st = ensure_caps(ctx);
+    if (st == SS_OK) st = finish_pending(ctx);  // host_ctl is used by the sizing run below
     if (st != SS_OK) return st;
+    std::unique_ptr<ss_graph> gr(new ss_graph());
+    gr->ctx = ctx;
+    if ((st = ws_ensure(gr->ws, n, ctx->cfg, ctx->scratch_limit)) != SS_OK) return st;
+    Params p{chars, offsets, n, perm_out, lcp_out, ctx->cfg.max_log_splitters, ctx->cfg.bucket_target,
+             ctx->cfg.base_max};
+    Work w = gr->ws.work;
+    w.set_base = set_begin;
     hipStream_t cs = nullptr;
     SS_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
     const bool prof = ctx->prof.on;
     ctx->prof.on = false;  // no event records inside the graph
-    Params p{chars, offsets, n, perm_out, lcp_out, ctx->cfg.max_log_splitters, ctx->cfg.bucket_target,
-             ctx->cfg.base_max};
-    Work w = ctx->work;
-    w.set_base = set_begin;
+    // sizing run: the batched sort once, level by level from the host, on
+    // the graph's workspace; the graph enqueues as many level launches as it
+    // needed (a persistent tail runs any further levels of later contents)
+    st = run_sort_host_levels(ctx, w, p, set_begin, num_sets, cs);
+    if (st == SS_OK) st = read_ctl(ctx, w, cs);
+    if (st == SS_OK && ctx->host_ctl->err) st = device_error_status(ctx->host_ctl->err);
     hipGraph_t g = nullptr;
-    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
-    if (e == hipSuccess) {
-        st = enqueue_persistent(ctx, w, p, set_begin, num_sets, cs);
-        hipError_t e2 = hipStreamEndCapture(cs, &g);
-        if (st == SS_OK && e2 != hipSuccess) st = SS_HIP_ERROR;
-    } else {
-        st = SS_HIP_ERROR;
+    if (st == SS_OK) {
+        gr->levels = std::min<uint32_t>(std::max<uint32_t>(ctx->host_ctl->stats.levels, 1), MAX_LEVEL_LAUNCHES);
+        hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) {
+            st = enqueue_sort_levels(ctx, w, p, set_begin, num_sets, gr->levels, cs);
+            hipError_t e2 = hipStreamEndCapture(cs, &g);
+            if (st == SS_OK && e2 != hipSuccess) st = SS_HIP_ERROR;
+        } else {
+            st = SS_HIP_ERROR;
+        }
     }
     ctx->prof.on = prof;
     (void)hipStreamDestroy(cs);
     if (st != SS_OK) {
         if (g) (void)hipGraphDestroy(g);
+        ws_free(gr->ws);
         return st;
     }
     hipGraphExec_t ex = nullptr;
     if (hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) != hipSuccess) {
         (void)hipGraphDestroy(g);
+        ws_free(gr->ws);
         return SS_HIP_ERROR;
     }
-    auto* gr = new ss_graph();
-    gr->ctx = ctx;
     gr->graph = g;
     gr->exec = ex;
-    *graph_out = gr;
+    ctx->graphs.push_back(gr.get());
+    *graph_out = gr.release();
     return SS_OK;
 }
 
@@ -842,21 +1039,32 @@ ss_status ss_graph_launch(ss_graph* graph, void* stream) {
 
 void ss_graph_destroy(ss_graph* graph) {
     if (!graph) return;
+    if (graph->ctx) {
+        auto& v = graph->ctx->graphs;
+        v.erase(std::remove(v.begin(), v.end(), graph), v.end());
+    }
     if (graph->exec) (void)hipGraphExecDestroy(graph->exec);
     if (graph->graph) (void)hipGraphDestroy(graph->graph);
+    ws_free(graph->ws);
     delete graph;
 }
 
+uint32_t ss_graph_levels(const ss_graph* graph) { return graph ? graph->levels : 0u; }
+
 ss_status ss_ctx_sync(ss_ctx* ctx, void* stream) {
     if (!ctx) return SS_INVALID_ARG;
-    ss_status st = read_ctl(ctx, (hipStream_t)stream);
+    int cur_dev = -1;
+    SS_TRY(hipGetDevice(&cur_dev));
+    if (cur_dev != ctx->device) SS_TRY(hipSetDevice(ctx->device));
+    SS_TRY(hipStreamSynchronize((hipStream_t)stream));
+    ss_status st = finish_pending(ctx);
     if (st != SS_OK) return st;
-    if (ctx->host_ctl->err) {
-        st = device_error_status(ctx->host_ctl->err);
-        ctx->sticky = st;
-        return st;
+    for (ss_graph* g : ctx->graphs) {
+        uint32_t err = 0;
+        SS_TRY(hipMemcpy(&err, &g->ws.work.ctl->err_sticky, sizeof(err), hipMemcpyDeviceToHost));
+        if (err && ctx->sticky == SS_OK) ctx->sticky = device_error_status(err);
     }
-    return SS_OK;
+    return ctx->sticky;
 }
 
 namespace {
@@ -942,7 +1150,7 @@ ss_status ss_autotune(ss_ctx* ctx, const uint8_t* chars, const uint64_t* offsets
     auto consider = [&](const ss_config& c) {
         double ms = time_config(ctx, c, chars, offsets, n, set_begin, num_sets, perm_out, lcp_out, s, reps, e0, e1);
         if (ms < 0) {
-            ctx->sticky = SS_OK;  // a failed candidate (e.g. workspace cap) is skipped
+            ss_clear_error(ctx);  // a failed candidate (e.g. workspace cap) is skipped
             return;
         }
         if (top_ms < 0 || ms < top_ms) {
@@ -955,11 +1163,13 @@ ss_status ss_autotune(ss_ctx* ctx, const uint8_t* chars, const uint64_t* offsets
     // parameters
     for (uint32_t d : {8u, 9u, 10u})
         for (uint32_t bt : {32u, 64u, 128u})
-            for (uint32_t bm : {512u, 1024u}) consider(ss_config{d, bt, bm, 0});
+            for (uint32_t bm : {512u, 1024u}) consider(ss_config{d, bt, bm, SS_MODE_LEVELS});
     if (top_ms >= 0) {
-        ss_config pc = top;
-        pc.persistent = 1;
-        consider(pc);
+        for (uint32_t m : {SS_MODE_HOST_LEVELS, SS_MODE_PERSISTENT}) {
+            ss_config pc = top;
+            pc.mode = m;
+            consider(pc);
+        }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
@@ -983,14 +1193,34 @@ void ss_autotune_clear_cache(void) {
     g_tune.clear();
 }
 
-ss_status ss_get_last_error(const ss_ctx* ctx) { return ctx ? ctx->sticky : SS_INVALID_ARG; }
-
-void ss_clear_error(ss_ctx* ctx) {
-    if (ctx) ctx->sticky = SS_OK;
+ss_status ss_get_last_error(ss_ctx* ctx) {
+    if (!ctx) return SS_INVALID_ARG;
+    if (ctx->pending && hipEventQuery(ctx->done) == hipSuccess) {
+        if (ctx->prof.used) resolve_timings(ctx);
+        absorb(ctx);
+    }
+    return ctx->sticky;
 }
 
-ss_status ss_get_stats(const ss_ctx* ctx, ss_stats* st) {
+void ss_clear_error(ss_ctx* ctx) {
+    if (!ctx) return;
+    int prev = 0;
+    (void)hipGetDevice(&prev);
+    (void)hipSetDevice(ctx->device);
+    if (ctx->done_recorded) (void)hipEventSynchronize(ctx->done);
+    ctx->pending = false;
+    const uint32_t zero = 0;
+    if (ctx->ws.mem) (void)hipMemcpy(&ctx->ws.work.ctl->err_sticky, &zero, sizeof(zero), hipMemcpyHostToDevice);
+    for (ss_graph* g : ctx->graphs)
+        (void)hipMemcpy(&g->ws.work.ctl->err_sticky, &zero, sizeof(zero), hipMemcpyHostToDevice);
+    ctx->sticky = SS_OK;
+    (void)hipSetDevice(prev);
+}
+
+ss_status ss_get_stats(ss_ctx* ctx, ss_stats* st) {
     if (!ctx || !st) return SS_INVALID_ARG;
+    ss_status r = finish_pending(ctx);
+    if (r != SS_OK) return r;
     *st = ctx->stats;
     return SS_OK;
 }
@@ -1025,6 +1255,7 @@ ss_status ss_get_kernel_times(const ss_ctx* ctx, ss_kernel_time* out, uint32_t m
 
 void ss_reset_kernel_times(ss_ctx* ctx) {
     if (!ctx) return;
+    (void)finish_pending(ctx);
     Profiler& P = ctx->prof;
     P.used = 0;
     for (int i = 0; i < K_COUNT; ++i) P.ms[i] = P.unit_sum[i] = 0, P.launches[i] = 0;
@@ -1254,6 +1485,7 @@ struct ss_server {
     uint64_t next_ticket = 1;
     hipStream_t stream = nullptr;
     int cur = 0;
+    uint32_t level = 0;  // levels run (numbers the level records)
     // statistics
     ss_server_stats st{};
     std::vector<double> lat_us;
@@ -1364,12 +1596,15 @@ void server_loop(ss_server* S) {
         ss_status st = SS_OK;
         for (Req* r : admitted)
             if ((st = stage_request(S, r)) != SS_OK) break;
-        if (st == SS_OK) st = read_ctl(ctx, S->stream);
+        if (st == SS_OK) st = read_ctl(ctx, S->w, S->stream);
         if (st == SS_OK && ctx->host_ctl->err) st = device_error_status(ctx->host_ctl->err);
         if (st == SS_OK) {
-            const Counts c = counts_of(ctx->host_ctl->cl[S->cur]);
-            st = enqueue_level(ctx, S->w, S->p, S->cur, c, false, false, true, S->stream);
+            LevelPlan L;
+            L.exact = true;
+            L.c = counts_of(ctx->host_ctl->cl[S->cur]);
+            st = enqueue_level(ctx, S->w, S->p, S->cur, S->level, L, S->stream);
             S->cur ^= 1;
+            ++S->level;
         }
         // which requests are finished?
         std::vector<Req*> finished;
@@ -1406,7 +1641,7 @@ void server_loop(ss_server* S) {
             if (e == hipSuccess) e = hipMemcpyAsync(S->d_done, S->h_done, S->max_inflight, hipMemcpyHostToDevice, S->stream);
             if (e != hipSuccess) st = SS_HIP_ERROR;
             if (st == SS_OK && ctx->host_ctl->err == 0) {
-                if (read_ctl(ctx, S->stream) != SS_OK) st = SS_HIP_ERROR;
+                if (read_ctl(ctx, S->w, S->stream) != SS_OK) st = SS_HIP_ERROR;
                 else if (ctx->host_ctl->err) st = device_error_status(ctx->host_ctl->err);
             }
         }
@@ -1419,6 +1654,7 @@ void server_loop(ss_server* S) {
                 (void)launch_reset(S->w, S->stream);
                 (void)hipStreamSynchronize(S->stream);
                 S->cur = 0;
+                S->level = 0;
             } else {
                 for (Req* r : finished) {
                     finish_locked(S, r, SS_OK);
@@ -1450,7 +1686,7 @@ ss_status ss_server_create(ss_server** out, int device, size_t hbm_budget, uint3
     }
     if (cfg) {
         ss_config c = *cfg;
-        c.persistent = 0;
+        c.mode = SS_MODE_HOST_LEVELS;  // the worker reads every level's counts
         clamp_config(&c);
         S->ctx->cfg = c;
     }
@@ -1460,6 +1696,11 @@ ss_status ss_server_create(ss_server** out, int device, size_t hbm_budget, uint3
     // arena bytes per index slot: workspace + offsets + perm + lcp + second pending list
     const uint32_t probe = 1u << 20;
     const size_t ws = layout(probe, caps_for(probe, S->ctx->cfg), nullptr, nullptr);
+    if (ensure_streams(S->ctx) != SS_OK || ensure_caps(S->ctx) != SS_OK) {
+        ss_ctx_destroy(S->ctx);
+        delete S;
+        return SS_HIP_ERROR;
+    }
     S->slot_bytes = ws / probe + 1 + sizeof(uint64_t) + 2 * sizeof(uint32_t) + sizeof(Pend);
     // 1% of the budget is left for the fixed tables and alignment
     const uint64_t cap_n = std::min<uint64_t>((hbm_budget - hbm_budget / 100) / (S->slot_bytes + L), 0xFFFFFFF0ull);
@@ -1505,7 +1746,6 @@ ss_status ss_server_create(ss_server** out, int device, size_t hbm_budget, uint3
     S->w.set_base = S->d_set_base;
     S->w.remaining = S->d_remaining;
     S->w.done = S->d_done;
-    S->ctx->work = S->w;
     const ss_config& c = S->ctx->cfg;
     S->p = Params{(const uint8_t*)(base + o_chars), (const uint64_t*)(base + o_off), S->cap_n,
                   (uint32_t*)(base + o_perm), (uint32_t*)(base + o_lcp), c.max_log_splitters, c.bucket_target,
@@ -1641,10 +1881,7 @@ void ss_server_destroy(ss_server* S) {
     if (S->h_slot) (void)hipHostFree(S->h_slot);
     if (S->h_done) (void)hipHostFree(S->h_done);
     for (auto& kv : S->reqs) delete kv.second;
-    if (S->ctx) {
-        S->ctx->ws = nullptr;  // the server's arena is freed above
-        ss_ctx_destroy(S->ctx);
-    }
+    if (S->ctx) ss_ctx_destroy(S->ctx);
     delete S;
 }
 

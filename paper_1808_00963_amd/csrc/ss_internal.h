@@ -101,6 +101,25 @@ inline Counts counts_of(const CountLines& l) {
 }
 
 constexpr uint32_t ROUND_LINES = 32;  // lines of the base_rounds statistic
+constexpr uint32_t LEVEL_RECS = 64;    // levels whose work counts are kept for the profiler
+
+// Work counts of one recursion level as recorded when the level starts
+// (statistics and per-launch units of the profiler).
+struct LevelRec {
+    uint32_t n_dist, n_tiles, n_cnt, dist_strings;
+    uint32_t n_base[NCLS], base_strings[NCLS];
+};
+
+// Statistics of one sort, accumulated on the device level by level.
+struct DevStats {
+    uint32_t levels;          // levels that had work
+    uint32_t dist_segments;
+    uint32_t dist_tiles;
+    uint32_t max_depth;
+    uint32_t base_segments[NCLS];
+    uint64_t base_strings[NCLS];
+    uint64_t dist_strings;
+};
 
 // Device-side control block.  Every group of fields that kernels update
 // with atomics sits on its own 128-byte line, so the atomics never share a
@@ -110,20 +129,39 @@ struct Ctl {
     uint32_t n_pend;
     uint32_t n_pend2;      // survivors of a pending-list filter (serving)
     uint32_t pad0[30];
-    uint32_t err;
-    uint32_t pad1[31];
+    uint32_t err;          // errors of this sort (zeroed when a sort starts)
+    uint32_t err_sticky;   // errors of every sort on this workspace until cleared by the host
+    uint32_t pad1[30];
     // refinement rounds run by base cases (statistics), spread over lines so
     // the waves that report them do not queue on one address
     struct {
         uint32_t v;
         uint32_t pad[31];
     } base_rounds[ROUND_LINES];
+    DevStats stats;
+    LevelRec lv[LEVEL_RECS];
 };
 inline uint32_t base_rounds_of(const Ctl& c) {
     uint32_t t = 0;
     for (uint32_t i = 0; i < ROUND_LINES; ++i) t += c.base_rounds[i].v;
     return t;
 }
+
+// Dynamic distribution of a launch's items over its workers (work groups or
+// waves): the items are cut into FEED_PARTS contiguous parts, one per XCD
+// (work groups are dispatched to the XCDs round robin), and a worker takes
+// chunks of its part through an atomic counter on the part's own line, so
+// workers that finish early take more and neighbouring items stay on one
+// XCD.  Each kernel kind of a level has its own FEED_PARTS lines; the
+// counters of the two level slots alternate and are zeroed when a level
+// starts.
+constexpr uint32_t FEED_PARTS = 8;
+enum FeedKind : uint32_t { FEED_BASE = 0, FEED_CLASSIFY = NCLS, FEED_SCATTER, FEED_KINDS };
+struct alignas(128) FeedLine {
+    uint32_t next;
+    uint32_t pad[31];
+};
+constexpr uint32_t FEED_LINES = 2 * FEED_KINDS * FEED_PARTS;
 
 // Error bits raised on the device.
 enum : uint32_t {
@@ -172,6 +210,7 @@ struct Work {
     Pend* pend;               // pending boundary LCPs
     Pend* pend2;              // filter target (serving)
     Ctl* ctl;
+    FeedLine* feed;           // FEED_LINES work-distribution counters
     GridBar* bar;
     const uint32_t* set_base; // per set/request id: its first position (subtracted from perm entries)
     uint32_t* zero_base;      // one zero word on its own line: set base of a plain sort
@@ -193,24 +232,52 @@ struct Params {
 };
 
 // ---- launchers (ss_kernels.hip) ----
+// Every kernel of a recursion level reads its work counts from the control
+// block (slot `cur`), so a level can be enqueued before the previous one has
+// run.  `grid` is the number of work groups to launch: any value >= 1 gives
+// the same result (workers take items until none are left); the host picks
+// it from what it knows (exact counts, or the pool capacities and the
+// device's resident capacity).
 hipError_t launch_reset(const Work& w, hipStream_t s);
 hipError_t launch_init(const Work& w, const Params& p, hipStream_t s);
 hipError_t launch_roots(const Work& w, const Params& p, const uint32_t* set_begin, uint32_t num_sets,
                         hipStream_t s);
-// Zeroes counts slot `which` (no memset: stays capturable).
-hipError_t launch_zero_counts(const Work& w, int which, hipStream_t s);
-hipError_t launch_base(const Work& w, const Params& p, int cur, int cls, uint32_t n_base, hipStream_t s);
-hipError_t launch_sample(const Work& w, const Params& p, int cur, uint32_t n_dist, bool root_keys, hipStream_t s);
-hipError_t launch_classify(const Work& w, const Params& p, int cur, uint32_t n_tiles, uint32_t n_dist, hipStream_t s);
-hipError_t launch_scan(const Work& w, int cur, uint32_t n_cnt, hipStream_t s);
-hipError_t launch_scatter(const Work& w, const Params& p, int cur, uint32_t n_tiles, uint32_t n_dist, hipStream_t s);
-hipError_t launch_children(const Work& w, const Params& p, int cur, uint32_t n_dist, hipStream_t s);
+// Starts level `level` on slot `cur`: records its counts (statistics),
+// zeroes the next slot's counts and this slot's feed counters (no memset:
+// stays capturable).
+hipError_t launch_level_begin(const Work& w, int cur, uint32_t level, hipStream_t s);
+hipError_t launch_base(const Work& w, const Params& p, int cur, int cls, uint32_t grid, hipStream_t s);
+// root_keys: the first level's sampling, reading keys from the strings.
+hipError_t launch_sample(const Work& w, const Params& p, int cur, uint32_t grid, bool root_keys, hipStream_t s);
+hipError_t launch_classify(const Work& w, const Params& p, int cur, uint32_t grid, hipStream_t s);
+hipError_t launch_scan(const Work& w, int cur, uint32_t grid, hipStream_t s);
+// One half tile per work group of `grid`; with more_grid != 0 a second
+// launch of more_grid groups takes the half tiles beyond `grid` (none when
+// the level has at most `grid` of them).
+hipError_t launch_scatter(const Work& w, const Params& p, int cur, uint32_t grid, uint32_t more_grid,
+                          hipStream_t s);
+hipError_t launch_children(const Work& w, const Params& p, int cur, uint32_t grid, hipStream_t s);
 hipError_t launch_lcp_fill(const Work& w, const Params& p, hipStream_t s);
-// The whole sort (init, roots, every level, boundary LCPs) in one launch of
-// `blocks` work groups that must all be resident; levels are separated by
-// grid barriers.  launch_reset must precede it on the stream.
+// Resident capacity (work groups) of each level kernel on `device`.
+struct KernelCaps {
+    uint32_t base[NCLS], sample, classify, scan, scatter, children, persist;
+};
+hipError_t kernel_caps(int device, KernelCaps* k);
+// Work groups of a level kernel that suffice for the given work counts.
+uint32_t grid_base(int cls, uint32_t n_base);
+uint32_t grid_classify(uint32_t n_tiles);
+uint32_t grid_scan(uint32_t n_cnt);
+uint32_t grid_scatter(uint32_t n_tiles);
+uint32_t grid_children(uint32_t n_dist);
+// The sort's levels in ONE persistent launch of `blocks` work groups that
+// must all be resident, separated by grid barriers.  full: starts with the
+// key gather and the roots (after launch_reset); otherwise continues from
+// slot `cur` at level `level` (the levels before were enqueued as separate
+// launches; with bases_done, so were the base cases of `level` itself, and
+// only its distribution segments are left).  Ends with the boundary LCPs
+// either way.
 hipError_t launch_persistent(const Work& w, const Params& p, const uint32_t* set_begin, uint32_t num_sets,
-                             uint32_t blocks, hipStream_t s);
+                             uint32_t blocks, bool full, uint32_t level, int cur, bool bases_done, hipStream_t s);
 // Serving: gathers keys at depth 0 for positions [pos, pos+m) into buffer
 // `cur` and makes them one root segment of request `rid` in the lists of
 // `cur`.
@@ -224,8 +291,6 @@ hipError_t launch_pend_filter(const Work& w, const Params& p, hipStream_t s);
 hipError_t launch_pend_swap(const Work& w, hipStream_t s);
 // Streaming copy (bandwidth calibration).
 hipError_t launch_copy(void* dst, const void* src, size_t n16, hipStream_t s);
-// Largest number of co-resident work groups of the persistent kernel.
-hipError_t persistent_capacity(int device, uint32_t* blocks);
 
 
 // ---- LCP-aware merging of sorted runs (ss_merge.hip) ----

@@ -20,21 +20,123 @@ namespace ss {
 // helpers
 // ---------------------------------------------------------------------------
 
-__device__ __forceinline__ void raise_err(const Work& w, uint32_t bits) { atomicOr(&w.ctl->err, bits); }
+__device__ __forceinline__ void raise_err(const Work& w, uint32_t bits) {
+    atomicOr(&w.ctl->err, bits);
+    atomicOr(&w.ctl->err_sticky, bits);
+}
 // Two counters in one 64-bit atomic word (low, high); neither half of a
 // level's counters reaches 2^32, so no carry crosses.
 __device__ __forceinline__ unsigned long long pack2(uint32_t lo, uint32_t hi) {
     return (unsigned long long)lo | ((unsigned long long)hi << 32);
 }
 
-// Block -> tile mapping that keeps consecutive tiles on the same XCD (work
-// groups are dispatched to the 8 XCDs round robin): the tiles of XCD x are a
-// contiguous range, so concurrently running neighbours write adjacent parts
-// of the same buckets through the same L2.
-__device__ __forceinline__ uint32_t xcd_tile(uint32_t b, uint32_t nt) {
-    constexpr uint32_t X = 8;
+// A level's work counter, written by earlier launches (or, in the
+// persistent kernel, before the last grid barrier).
+__device__ __forceinline__ unsigned long long load_count(const CLine& l) {
+    return __hip_atomic_load(&l.v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// Counts clamped to the pool capacities: after a capacity error (raised by
+// whoever overflowed a pool) the entries past the capacity were never
+// written, so no kernel may index them.
+__device__ __forceinline__ void clamp_counts(Counts& c, const Caps& k) {
+    c.n_dist = min_u32(c.n_dist, k.dist);
+    c.n_tiles = min_u32(c.n_tiles, k.tiles);
+    c.n_cnt = min_u32(c.n_cnt, k.cnt);
+    c.n_tree = min_u32(c.n_tree, k.tree);
+    for (int q = 0; q < NCLS; ++q) c.n_base[q] = min_u32(c.n_base[q], k.base[q]);
+}
+__device__ __forceinline__ uint32_t n_dist_of(const Work& w, int cur) {
+    return min_u32((uint32_t)load_count(w.ctl->cl[cur].dist), w.caps.dist);
+}
+__device__ __forceinline__ uint32_t n_tiles_of(const Work& w, int cur) {
+    return min_u32((uint32_t)(load_count(w.ctl->cl[cur].tree_tiles) >> 32), w.caps.tiles);
+}
+__device__ __forceinline__ uint32_t n_cnt_of(const Work& w, int cur) {
+    return min_u32((uint32_t)load_count(w.ctl->cl[cur].cnt), w.caps.cnt);
+}
+__device__ __forceinline__ uint32_t n_base_of(const Work& w, int cur, int cls) {
+    return min_u32((uint32_t)load_count(w.ctl->cl[cur].base[cls]), w.caps.base[cls]);
+}
+__device__ __forceinline__ Counts load_counts(const Work& w, int cur) {
+    unsigned long long v[COUNT_LINES];
+    const CLine* L = &w.ctl->cl[cur].dist;
+    for (uint32_t i = 0; i < COUNT_LINES; ++i) v[i] = load_count(L[i]);
+    return counts_of(v);
+}
+
+__device__ __forceinline__ FeedLine* feed_of(const Work& w, int cur, uint32_t kind) {
+    return w.feed + ((uint32_t)cur * FEED_KINDS + kind) * FEED_PARTS;
+}
+
+// Next chunk [*lo, *hi) of part `part` of the items [first, n) (see
+// FeedLine); false once the part is used up.  The parts are contiguous, so
+// a part's items are neighbours (for tiles: adjacent parts of the same
+// buckets, written through the same L2).
+__device__ __forceinline__ bool feed_take(FeedLine* f, uint32_t first, uint32_t n, uint32_t part, uint32_t chunk,
+                                          uint32_t* lo, uint32_t* hi) {
+    if (first >= n) return false;
+    const uint32_t len = (n - first + FEED_PARTS - 1) / FEED_PARTS;
+    const uint32_t b = first + part * len;
+    const uint32_t e = min_u32(b + len, n);
+    if (b >= e) return false;
+    const uint32_t i = atomicAdd(&f[part].next, chunk);
+    if (i >= e - b) return false;
+    *lo = b + i;
+    *hi = min_u32(b + i + chunk, e);
+    return true;
+}
+
+// Static first items of a launch's work groups, keeping consecutive items on
+// the same XCD (work groups are dispatched to the 8 XCDs round robin): the
+// items of XCD x are a contiguous range, so concurrently running
+// neighbouring tiles write adjacent parts of the same buckets through the
+// same L2.  A bijection on [0, nt).
+__device__ __forceinline__ uint32_t xcd_item(uint32_t b, uint32_t nt) {
+    constexpr uint32_t X = FEED_PARTS;
     const uint32_t x = b % X, i = b / X, q = nt / X, r = nt % X;
     return x * q + (x < r ? x : r) + i;
+}
+
+// A value every lane of the wave holds alike (read back from an LDS
+// mailbox), marked uniform so that what is derived from it (segment fields,
+// addresses) stays in scalar registers.
+__device__ __forceinline__ uint32_t uniform(uint32_t x) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)x); }
+
+// One item of the dynamic part [first, n) for a work group (n when none is
+// left).
+__device__ __forceinline__ uint32_t feed_one(FeedLine* f, uint32_t first, uint32_t n, uint32_t part) {
+    uint32_t lo = 0, hi = 0;
+    return feed_take(f, first, n, part, 1, &lo, &hi) ? lo : n;
+}
+
+// Records a level's work counts when it starts (statistics; the profiler's
+// per-launch units).  One thread.
+__device__ void note_level(const Work& w, const Counts& c, uint32_t level) {
+    bool work = c.n_dist != 0;
+    for (int q = 0; q < NCLS; ++q) work |= c.n_base[q] != 0;
+    if (!work) return;
+    DevStats& st = w.ctl->stats;
+    st.levels = level + 1;
+    st.dist_segments += c.n_dist;
+    st.dist_tiles += c.n_tiles;
+    st.dist_strings += c.dist_strings;
+    if (c.max_depth > st.max_depth) st.max_depth = c.max_depth;
+    for (int q = 0; q < NCLS; ++q) {
+        st.base_segments[q] += c.n_base[q];
+        st.base_strings[q] += c.base_strings[q];
+    }
+    if (level < LEVEL_RECS) {
+        LevelRec r;
+        r.n_dist = c.n_dist;
+        r.n_tiles = c.n_tiles;
+        r.n_cnt = c.n_cnt;
+        r.dist_strings = c.dist_strings;
+        for (int q = 0; q < NCLS; ++q) {
+            r.n_base[q] = c.n_base[q];
+            r.base_strings[q] = c.base_strings[q];
+        }
+        w.ctl->lv[level] = r;
+    }
 }
 
 
@@ -175,15 +277,21 @@ union SmAll {
 
 __global__ void k_reset(Work w) {
     uint32_t* p = (uint32_t*)w.ctl;
-    for (uint32_t i = threadIdx.x; i < sizeof(Ctl) / 4; i += blockDim.x) p[i] = 0;
+    constexpr uint32_t keep = offsetof(Ctl, err_sticky) / 4;  // survives the reset
+    for (uint32_t i = threadIdx.x; i < sizeof(Ctl) / 4; i += blockDim.x)
+        if (i != keep) p[i] = 0;
     if (threadIdx.x == 0) w.zero_base[0] = 0;
     uint32_t* b = (uint32_t*)w.bar;
     for (uint32_t i = threadIdx.x; i < sizeof(GridBar) / 4; i += blockDim.x) b[i] = 0;
+    for (uint32_t i = threadIdx.x; i < FEED_LINES; i += blockDim.x) w.feed[i].next = 0;
 }
 
-__global__ void k_zero_counts(Work w, int which) {
-    CLine* L = &w.ctl->cl[which].dist;
+__global__ void k_level_begin(Work w, int cur, uint32_t level) {
+    if (threadIdx.x == 0) note_level(w, load_counts(w, cur), level);
+    CLine* L = &w.ctl->cl[cur ^ 1].dist;
     for (uint32_t i = threadIdx.x; i < COUNT_LINES; i += blockDim.x) L[i].v = 0;
+    FeedLine* f = feed_of(w, cur, 0);
+    for (uint32_t i = threadIdx.x; i < FEED_KINDS * FEED_PARTS; i += blockDim.x) f[i].next = 0;
 }
 
 // Key gather at depth 0 for every string (Algorithm 4.1's chars_h with
@@ -410,12 +518,11 @@ __device__ __forceinline__ void wave_oddeven_step(uint64_t (&K)[E], uint64_t (&A
 // the depth where they separate.  Depth and LCP are kept per position
 // (a run never moves), keys and records move.
 template <int E>
-__device__ void dev_base_wave(const Work& w, const Params& p, int cur, int cls, uint32_t group, uint32_t nseg,
+__device__ void dev_base_wave(const Work& w, const Params& p, int cur, int cls, uint32_t si, uint32_t nseg,
                               SmWave& sm) {
     auto& LIDX = sm.LIDX;
     auto& RMIN = sm.RMIN;
     const uint32_t lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const uint32_t si = group * WAVES + wv;
     if (si >= nseg) return;  // uniform per wave
     const BaseSeg sg = w.base[cls][cur][si];
     const uint32_t m = sg.size, h = sg.depth;
@@ -552,13 +659,41 @@ __device__ void dev_base_wave(const Work& w, const Params& p, int cur, int cls, 
         }
     }
     if (lane == 0 && w.remaining) atomicSub(&w.remaining[sg.rid], m);
-    if (lane == 0 && rounds) atomicAdd(&w.ctl->base_rounds[(group * WAVES + wv) % ROUND_LINES].v, rounds);
+    if (lane == 0 && rounds) atomicAdd(&w.ctl->base_rounds[si % ROUND_LINES].v, rounds);
 }
 
+// Waves take segments: wave g of the launch takes segment g, then chunks
+// of its XCD's part of the rest.
+constexpr uint32_t BASE_WAVE_CHUNK = 2;
+// The item loops of the level kernels keep values of the loop around that a
+// one-item kernel would recompute; each kernel's register budget is pinned
+// to the occupancy its one-item body reaches (the waves that hide the
+// latency of its global loads matter more than the recomputation).
 template <int E>
-__global__ __launch_bounds__(BLOCK) void k_base_wave(Work w, Params p, int cur, int cls, uint32_t nseg) {
+constexpr int base_wave_occupancy() { return E == 1 ? 7 : E == 2 ? 6 : 4; }
+template <int E>
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(base_wave_occupancy<E>())))
+void k_base_wave(Work w, Params p, int cur, int cls) {
     __shared__ SmWave sm;
-    dev_base_wave<E>(w, p, cur, cls, blockIdx.x, nseg, sm);
+    const uint32_t n = n_base_of(w, cur, cls);
+    const uint32_t lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const uint32_t G = gridDim.x * WAVES, g = blockIdx.x * WAVES + wv;
+    const uint32_t s0 = min_u32(G, n);
+    if (g >= s0) return;  // no static segment: nothing is left for this wave either
+    FeedLine* f = feed_of(w, cur, FEED_BASE + cls);
+    const uint32_t part = blockIdx.x % FEED_PARTS;
+    uint32_t lo = g, hi = g + 1;
+    for (;;) {
+        // the next chunk's atomic is issued before this chunk is sorted, so
+        // its round trip overlaps the work
+        uint32_t nlo = 0, nhi = 0, ok = 0;
+        if (lane == 0) ok = feed_take(f, s0, n, part, BASE_WAVE_CHUNK, &nlo, &nhi) ? 1u : 0u;
+        for (uint32_t si = lo; si < hi; ++si) dev_base_wave<E>(w, p, cur, cls, si, n, sm);
+        ok = (uint32_t)__builtin_amdgcn_readfirstlane((int)ok);
+        if (!ok) break;
+        lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)nlo);
+        hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)nhi);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -622,7 +757,7 @@ __device__ void lds_block_sort(uint64_t* H, uint64_t* L, uint32_t NB) {
 // LCPs of neighbours separated at depth d are d plus the common bytes of
 // their words at d (the "last compared word"); the role of LCP-insertion
 // sort (Algorithm 4.6) as the paper's base case.
-__device__ void dev_base_wg(const Work& w, const Params& p, int cur, uint32_t item, SmBase& sm) {
+__device__ void dev_base_wg(const Work& w, const Params& p, int cur, uint32_t item, uint32_t nseg, SmBase& sm) {
     uint64_t* K = sm.K;
     uint64_t* A = sm.A;
     uint32_t* dep = sm.dep;
@@ -633,6 +768,7 @@ __device__ void dev_base_wg(const Work& w, const Params& p, int cur, uint32_t it
     uint32_t& any = sm.any;
     constexpr uint32_t PER = BASE_CAP / BLOCK;
 
+    if (item >= nseg) return;  // uniform
     const BaseSeg sg = w.base[CLS_WG][cur][item];
     const uint32_t tid = threadIdx.x, m = sg.size, h = sg.depth;
     uint32_t rounds = 0;
@@ -743,12 +879,27 @@ __device__ void dev_base_wg(const Work& w, const Params& p, int cur, uint32_t it
         if (i > 0) p.lcp[sg.begin + i] = lv[i];
     }
     if (tid == 0 && w.remaining) atomicSub(&w.remaining[sg.rid], m);
-    if (tid == 0 && rounds) atomicAdd(&w.ctl->base_rounds[blockIdx.x % ROUND_LINES].v, rounds);
+    if (tid == 0 && rounds) atomicAdd(&w.ctl->base_rounds[item % ROUND_LINES].v, rounds);
 }
 
-__global__ __launch_bounds__(BLOCK) void k_base(Work w, Params p, int cur) {
+// Work groups take segments: group b takes segment b, then segments of its
+// XCD's part of the rest.
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void k_base(Work w, Params p, int cur) {
     __shared__ SmBase sm;
-    dev_base_wg(w, p, cur, blockIdx.x, sm);
+    uint32_t& s_item = sm.wtot[0];  // item mailbox: wtot is first written after the body's first barrier
+    const uint32_t n = n_base_of(w, cur, CLS_WG);
+    const uint32_t s0 = min_u32(gridDim.x, n);
+    FeedLine* f = feed_of(w, cur, FEED_BASE + CLS_WG);
+    uint32_t item = blockIdx.x < s0 ? blockIdx.x : n;
+    while (item < n) {
+        uint32_t nxt = n;
+        if (threadIdx.x == 0) nxt = feed_one(f, s0, n, blockIdx.x % FEED_PARTS);  // overlaps the work
+        dev_base_wg(w, p, cur, item, n, sm);
+        __syncthreads();
+        if (threadIdx.x == 0) s_item = nxt;
+        __syncthreads();
+        item = uniform(s_item);
+    }
 }
 
 
@@ -859,7 +1010,6 @@ __device__ __forceinline__ void sample_sort(const Work& w, const Params& p, int 
 // root_keys the segments are roots and their sample keys are read from the
 // strings themselves, so the step need not wait for the key gather.
 __device__ void dev_sample(const Work& w, const Params& p, int cur, uint32_t item, bool root_keys, SmSample& sm) {
-    if (root_keys && item >= (uint32_t)w.ctl->cl[cur].dist.v) return;  // launched for every possible root
     uint64_t* SK = sm.SK;
     uint32_t* SR = sm.SR;
     uint64_t* TK = sm.TK;
@@ -911,9 +1061,13 @@ __device__ void dev_sample(const Work& w, const Params& p, int cur, uint32_t ite
     }
 }
 
-__global__ __launch_bounds__(BLOCK) void k_sample(Work w, Params p, int cur, int root_keys) {
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void k_sample(Work w, Params p, int cur, int root_keys) {
     __shared__ SmSample sm;
-    dev_sample(w, p, cur, blockIdx.x, root_keys != 0, sm);
+    const uint32_t n = n_dist_of(w, cur);
+    for (uint32_t item = blockIdx.x; item < n; item += gridDim.x) {
+        __syncthreads();
+        dev_sample(w, p, cur, item, root_keys != 0, sm);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -986,9 +1140,24 @@ __device__ void dev_classify(const Work& w, const Params& p, int cur, uint32_t t
     for (uint32_t b = tid; b < k; b += BLOCK) c[(size_t)b * T] = H[b];
 }
 
-__global__ __launch_bounds__(BLOCK) void k_classify(Work w, Params p, int cur, uint32_t n_dist) {
+// Work groups take tiles from their XCD's part of the level's tiles.
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(8))) void k_classify(Work w, Params p, int cur) {
     __shared__ SmClassify sm;
-    dev_classify(w, p, cur, xcd_tile(blockIdx.x, gridDim.x), n_dist, sm);
+    uint32_t& s_t = sm.TR[0];  // tile mailbox: the tree is one-based, TR[0] is never used
+    const uint32_t n_dist = n_dist_of(w, cur);
+    const uint32_t n_tiles = n_tiles_of(w, cur);
+    FeedLine* f = feed_of(w, cur, FEED_CLASSIFY);
+    const uint32_t s0 = min_u32(gridDim.x, n_tiles);
+    uint32_t t = blockIdx.x < s0 ? xcd_item(blockIdx.x, s0) : n_tiles;
+    while (t < n_tiles) {
+        uint32_t nxt = n_tiles;
+        if (threadIdx.x == 0) nxt = feed_one(f, s0, n_tiles, blockIdx.x % FEED_PARTS);  // overlaps the work
+        dev_classify(w, p, cur, t, n_dist, sm);
+        __syncthreads();
+        if (threadIdx.x == 0) s_t = nxt;
+        __syncthreads();
+        t = uniform(s_t);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1068,17 +1237,26 @@ __device__ void dev_scan_down(uint32_t* x, uint32_t n, const uint32_t* partial, 
     }
 }
 
-__global__ __launch_bounds__(BLOCK) void k_scan_reduce(const uint32_t* x, uint32_t n, uint32_t* partial) {
+__global__ __launch_bounds__(BLOCK) void k_scan_reduce(Work w, int cur) {
     __shared__ SmScan sm;
-    dev_scan_reduce(x, n, partial, blockIdx.x, sm);
+    const uint32_t n = n_cnt_of(w, cur), nb = (n + SCAN_CHUNK - 1) / SCAN_CHUNK;
+    for (uint32_t b = blockIdx.x; b < nb; b += gridDim.x) {
+        __syncthreads();
+        dev_scan_reduce(w.cnt[cur], n, w.partial, b, sm);
+    }
 }
-__global__ __launch_bounds__(1024) void k_scan_partials(uint32_t* partial, uint32_t nb) {
+__global__ __launch_bounds__(1024) void k_scan_partials(Work w, int cur) {
     __shared__ SmScan sm;
-    dev_scan_partials(partial, nb, sm);
+    const uint32_t n = n_cnt_of(w, cur);
+    if (n) dev_scan_partials(w.partial, (n + SCAN_CHUNK - 1) / SCAN_CHUNK, sm);
 }
-__global__ __launch_bounds__(BLOCK) void k_scan_down(uint32_t* x, uint32_t n, const uint32_t* partial) {
+__global__ __launch_bounds__(BLOCK) void k_scan_down(Work w, int cur) {
     __shared__ SmScan sm;
-    dev_scan_down(x, n, partial, blockIdx.x, sm);
+    const uint32_t n = n_cnt_of(w, cur), nb = (n + SCAN_CHUNK - 1) / SCAN_CHUNK;
+    for (uint32_t b = blockIdx.x; b < nb; b += gridDim.x) {
+        __syncthreads();
+        dev_scan_down(w.cnt[cur], n, w.partial, b, sm);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1217,9 +1395,8 @@ struct SmScatterTile {
     uint32_t delta[MAX_BUCKETS + 1];    // tile totals, then global position - slot
 };
 
-__global__ __launch_bounds__(SC_THREADS) void k_scatter(Work w, Params p, int cur, uint32_t n_dist) {
-    __shared__ SmScatterTile sm;
-    const uint32_t ht = xcd_tile(blockIdx.x, gridDim.x);  // half tile
+__device__ void dev_scatter_half(const Work& w, const Params& p, int cur, uint32_t ht, uint32_t n_dist,
+                                 SmScatterTile& sm) {
     const uint32_t t = ht >> 1, half = ht & 1u;
     const uint32_t tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     uint32_t* const wsum = (uint32_t*)sm.sb;
@@ -1368,6 +1545,49 @@ __global__ __launch_bounds__(SC_THREADS) void k_scatter(Work w, Params p, int cu
             x.y = (uint32_t)(key >> 32);
         }
         out[pos] = x;
+    }
+}
+
+// One half tile per work group: group b takes half tile xcd_item(b, m) of the
+// first m = min(groups, half tiles) half tiles, so neighbouring tiles, whose
+// runs of a bucket are adjacent in the output, are written through the same
+// L2.  A loop over several items here would cost the body two of its four
+// waves per SIMD (values of the loop would be held in registers), so the
+// half tiles beyond the grid are left to k_scatter_more.
+__global__ __launch_bounds__(SC_THREADS) void k_scatter(Work w, Params p, int cur) {
+    __shared__ SmScatterTile sm;
+    const uint32_t n_half = 2 * n_tiles_of(w, cur);
+    const uint32_t m = min_u32(gridDim.x, n_half);
+    if (blockIdx.x >= m) return;
+    dev_scatter_half(w, p, cur, xcd_item(blockIdx.x, m), n_dist_of(w, cur), sm);
+}
+
+// The half tiles from `first` on (first = k_scatter's grid), taken from the
+// feed by the work groups of its XCD; nothing to do in the common case of a
+// level with at most `first` half tiles.
+__global__ __launch_bounds__(SC_THREADS) __attribute__((amdgpu_waves_per_eu(8)))
+void k_scatter_more(Work w, Params p, int cur, uint32_t first) {
+    __shared__ SmScatterTile sm;
+    // half-tile mailbox (a separate word would take the LDS past 80 KB, and
+    // two groups would no longer fit a compute unit): delta is first written
+    // after the body's first barrier
+    uint32_t& s_ht = sm.delta[0];
+    const uint32_t n_half = 2 * n_tiles_of(w, cur);
+    if (first >= n_half) return;
+    const uint32_t n_dist = n_dist_of(w, cur);
+    FeedLine* f = feed_of(w, cur, FEED_SCATTER);
+    const uint32_t part = blockIdx.x % FEED_PARTS;
+    if (threadIdx.x == 0) s_ht = feed_one(f, first, n_half, part);
+    __syncthreads();
+    uint32_t ht = uniform(s_ht);
+    while (ht < n_half) {
+        uint32_t nxt = n_half;
+        if (threadIdx.x == 0) nxt = feed_one(f, first, n_half, part);  // overlaps the work
+        dev_scatter_half(w, p, cur, ht, n_dist, sm);
+        __syncthreads();
+        if (threadIdx.x == 0) s_ht = nxt;
+        __syncthreads();
+        ht = uniform(s_ht);
     }
 }
 
@@ -1530,9 +1750,14 @@ __host__ __device__ inline uint32_t child_chunks(uint32_t n_dist) {
     const uint32_t c = n_dist ? CHILD_GROUPS / n_dist : CHILD_CHUNKS;
     return c < 1 ? 1u : c > CHILD_CHUNKS ? CHILD_CHUNKS : c;
 }
-__global__ __launch_bounds__(BLOCK) void k_children(Work w, Params p, int cur, uint32_t chunks) {
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(8))) void k_children(Work w, Params p, int cur) {
     __shared__ SmChildren sm;
-    dev_children(w, p, cur, blockIdx.x / chunks, blockIdx.x % chunks, (MAX_BUCKETS + chunks - 1) / chunks, sm);
+    const uint32_t n_dist = n_dist_of(w, cur);
+    const uint32_t chunks = child_chunks(n_dist), items = n_dist * chunks;
+    for (uint32_t q = blockIdx.x; q < items; q += gridDim.x) {
+        __syncthreads();
+        dev_children(w, p, cur, q / chunks, q % chunks, (MAX_BUCKETS + chunks - 1) / chunks, sm);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1597,7 +1822,7 @@ __device__ bool grid_sync(const Work& w, uint32_t nblocks, uint32_t& gen, uint32
                 __builtin_amdgcn_s_sleep(2);
                 if (wall_clock64() - t0 > BARRIER_TIMEOUT_TICKS) {
                     good = 0;
-                    atomicOr(&w.ctl->err, (uint32_t)ERR_BARRIER);
+                    raise_err(w, ERR_BARRIER);
                     break;
                 }
             }
@@ -1610,49 +1835,72 @@ __device__ bool grid_sync(const Work& w, uint32_t nblocks, uint32_t& gen, uint32
     return *s_ok != 0;
 }
 
-__global__ __launch_bounds__(BLOCK) void k_persist(Work w, Params p, const uint32_t* set_begin, uint32_t num_sets) {
+__global__ __launch_bounds__(BLOCK) void k_persist(Work w, Params p, const uint32_t* set_begin, uint32_t num_sets,
+                                                   int full, uint32_t level0, int cur0, int bases_done) {
     __shared__ SmAll sm;
     __shared__ uint32_t s_ok, s_err;
     __shared__ unsigned long long sc[COUNT_LINES];
-    const uint32_t G = gridDim.x, bid = blockIdx.x, tid = threadIdx.x;
+    const uint32_t G = gridDim.x, bid = blockIdx.x, tid = threadIdx.x, wv = tid >> 6;
     uint32_t gen = 0;
 
-    for (uint32_t i = bid * BLOCK + tid; i < p.n; i += G * BLOCK) dev_init_one(w, p, i);
-    if (!grid_sync(w, G, gen, &s_ok)) return;
-    const uint32_t nroots = set_begin ? num_sets : 1u;
-    for (uint32_t j = bid * BLOCK + tid; j < nroots; j += G * BLOCK) dev_root_one(w, p, set_begin, nroots, j);
-    if (!grid_sync(w, G, gen, &s_ok)) return;
-
-    int cur = 0;
-    uint32_t level = 0;
-    for (;; ++level) {
-        // every block reads the level's counts before any block changes them
-        if (tid < COUNT_LINES)
-            sc[tid] = __hip_atomic_load(&(&w.ctl->cl[cur].dist)[tid].v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (tid == 0) s_err = __hip_atomic_load(&w.ctl->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (full) {
+        for (uint32_t i = bid * BLOCK + tid; i < p.n; i += G * BLOCK) dev_init_one(w, p, i);
         if (!grid_sync(w, G, gen, &s_ok)) return;
-        const Counts c = counts_of(sc);
-        if (s_err) break;
-        if (level >= MAX_LEVELS_DEV) {
-            if (bid == 0 && tid == 0) atomicOr(&w.ctl->err, (uint32_t)ERR_LEVELS);
+        const uint32_t nroots = set_begin ? num_sets : 1u;
+        for (uint32_t j = bid * BLOCK + tid; j < nroots; j += G * BLOCK) dev_root_one(w, p, set_begin, nroots, j);
+        if (!grid_sync(w, G, gen, &s_ok)) return;
+    }
+
+    int cur = cur0;
+    uint32_t level = level0;
+    for (;; ++level) {
+        if (tid < COUNT_LINES) sc[tid] = load_count((&w.ctl->cl[cur].dist)[tid]);
+        if (tid == 0) s_err = __hip_atomic_load(&w.ctl->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        // Every block reads the counts (and error bits) before any block
+        // changes them.  The first level of a continuation needs no barrier:
+        // no block of this launch has written anything yet, so all read the
+        // same counts; its error bits are not consulted (errors of earlier
+        // launches are reported at the end all the same, and every loop here
+        // is bounded by the counts).
+        const bool first_cont = !full && level == level0;
+        if (first_cont) {
+            __syncthreads();
+        } else if (!grid_sync(w, G, gen, &s_ok)) {
+            return;
+        }
+        Counts c = counts_of(sc);
+        clamp_counts(c, w.caps);
+        if (!first_cont && s_err) break;
+        if (level - level0 >= MAX_LEVELS_DEV) {
+            if (bid == 0 && tid == 0) raise_err(w, ERR_LEVELS);
             break;
         }
-        const uint32_t nb0 = (c.n_base[0] + WAVES - 1) / WAVES, nb1 = (c.n_base[1] + WAVES - 1) / WAVES;
-        const uint32_t nb2 = (c.n_base[2] + WAVES - 1) / WAVES, nb3 = c.n_base[3];
+        // a continuation whose first level's base cases ran as separate
+        // launches (that level was enqueued without its distribution steps)
+        // takes only that level's distribution segments
+        const bool skip = first_cont && bases_done;
+        const uint32_t nb0 = skip ? 0u : (c.n_base[0] + WAVES - 1) / WAVES;
+        const uint32_t nb1 = skip ? 0u : (c.n_base[1] + WAVES - 1) / WAVES;
+        const uint32_t nb2 = skip ? 0u : (c.n_base[2] + WAVES - 1) / WAVES, nb3 = skip ? 0u : c.n_base[3];
         const uint32_t nitems = nb0 + nb1 + nb2 + nb3 + c.n_dist;
         if (nitems == 0) break;
+        if (bid == 0 && tid == 0 && !skip) note_level(w, c, level);
         if (bid == 0 && tid < COUNT_LINES)
             __hip_atomic_store(&(&w.ctl->cl[cur ^ 1].dist)[tid].v, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         // base cases of every class and the splitter trees of the level
         for (uint32_t it = bid; it < nitems; it += G) {
             __syncthreads();
-            if (it < nb0) dev_base_wave<1>(w, p, cur, 0, it, c.n_base[0], sm.wave);
-            else if (it < nb0 + nb1) dev_base_wave<2>(w, p, cur, 1, it - nb0, c.n_base[1], sm.wave);
-            else if (it < nb0 + nb1 + nb2) dev_base_wave<4>(w, p, cur, 2, it - nb0 - nb1, c.n_base[2], sm.wave);
-            else if (it < nb0 + nb1 + nb2 + nb3) dev_base_wg(w, p, cur, it - nb0 - nb1 - nb2, sm.base);
+            if (it < nb0) dev_base_wave<1>(w, p, cur, 0, it * WAVES + wv, c.n_base[0], sm.wave);
+            else if (it < nb0 + nb1) dev_base_wave<2>(w, p, cur, 1, (it - nb0) * WAVES + wv, c.n_base[1], sm.wave);
+            else if (it < nb0 + nb1 + nb2)
+                dev_base_wave<4>(w, p, cur, 2, (it - nb0 - nb1) * WAVES + wv, c.n_base[2], sm.wave);
+            else if (it < nb0 + nb1 + nb2 + nb3) dev_base_wg(w, p, cur, it - nb0 - nb1 - nb2, c.n_base[3], sm.base);
             else dev_sample(w, p, cur, it - nb0 - nb1 - nb2 - nb3, false, sm.sample);
         }
-        if (c.n_dist == 0) break;
+        if (c.n_dist == 0) {
+            ++level;
+            break;
+        }
         if (!grid_sync(w, G, gen, &s_ok)) return;
         for (uint32_t t = bid; t < c.n_tiles; t += G) {
             __syncthreads();
@@ -1681,10 +1929,12 @@ __global__ __launch_bounds__(BLOCK) void k_persist(Work w, Params p, const uint3
             __syncthreads();
             dev_children(w, p, cur, q / CHILD_CHUNKS, q % CHILD_CHUNKS, BLOCK, sm.children);
         }
-        if (!grid_sync(w, G, gen, &s_ok)) return;
+        if (!grid_sync(w, G, gen, &s_ok)) return;  // the next level's counts are complete
         cur ^= 1;
     }
-    if (!grid_sync(w, G, gen, &s_ok)) return;
+    // the boundary LCPs need every level's output; nothing to wait for when
+    // a continuation found no level left
+    if ((full || level > level0) && !grid_sync(w, G, gen, &s_ok)) return;
     dev_lcp_fill(w, p, bid * BLOCK + tid, G * BLOCK);
 }
 
@@ -1747,11 +1997,11 @@ __global__ void k_pend_swap(Work w) {
 static inline uint32_t blocks_for(uint64_t n, uint32_t per) { return (uint32_t)((n + per - 1) / per); }
 
 hipError_t launch_reset(const Work& w, hipStream_t s) {
-    hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, s, w);
+    hipLaunchKernelGGL(k_reset, dim3(1), dim3(BLOCK), 0, s, w);
     return hipGetLastError();
 }
-hipError_t launch_zero_counts(const Work& w, int which, hipStream_t s) {
-    hipLaunchKernelGGL(k_zero_counts, dim3(1), dim3(64), 0, s, w, which);
+hipError_t launch_level_begin(const Work& w, int cur, uint32_t level, hipStream_t s) {
+    hipLaunchKernelGGL(k_level_begin, dim3(1), dim3(BLOCK), 0, s, w, cur, level);
     return hipGetLastError();
 }
 hipError_t launch_init(const Work& w, const Params& p, hipStream_t s) {
@@ -1765,43 +2015,41 @@ hipError_t launch_roots(const Work& w, const Params& p, const uint32_t* set_begi
     hipLaunchKernelGGL(k_roots, dim3(blocks_for(num_sets, 64)), dim3(64), 0, s, w, p, set_begin, num_sets);
     return hipGetLastError();
 }
-hipError_t launch_base(const Work& w, const Params& p, int cur, int cls, uint32_t n_base, hipStream_t s) {
-    if (n_base == 0) return hipSuccess;
+static inline dim3 grid_of(uint32_t g) { return dim3(g ? g : 1u); }
+hipError_t launch_base(const Work& w, const Params& p, int cur, int cls, uint32_t grid, hipStream_t s) {
     if (cls == 0)
-        hipLaunchKernelGGL(k_base_wave<1>, dim3(blocks_for(n_base, WAVES)), dim3(BLOCK), 0, s, w, p, cur, 0, n_base);
+        hipLaunchKernelGGL(k_base_wave<1>, grid_of(grid), dim3(BLOCK), 0, s, w, p, cur, 0);
     else if (cls == 1)
-        hipLaunchKernelGGL(k_base_wave<2>, dim3(blocks_for(n_base, WAVES)), dim3(BLOCK), 0, s, w, p, cur, 1, n_base);
+        hipLaunchKernelGGL(k_base_wave<2>, grid_of(grid), dim3(BLOCK), 0, s, w, p, cur, 1);
     else if (cls == 2)
-        hipLaunchKernelGGL(k_base_wave<4>, dim3(blocks_for(n_base, WAVES)), dim3(BLOCK), 0, s, w, p, cur, 2, n_base);
+        hipLaunchKernelGGL(k_base_wave<4>, grid_of(grid), dim3(BLOCK), 0, s, w, p, cur, 2);
     else
-        hipLaunchKernelGGL(k_base, dim3(n_base), dim3(BLOCK), 0, s, w, p, cur);
+        hipLaunchKernelGGL(k_base, grid_of(grid), dim3(BLOCK), 0, s, w, p, cur);
     return hipGetLastError();
 }
-hipError_t launch_sample(const Work& w, const Params& p, int cur, uint32_t n_dist, bool root_keys, hipStream_t s) {
-    hipLaunchKernelGGL(k_sample, dim3(n_dist), dim3(BLOCK), 0, s, w, p, cur, root_keys ? 1 : 0);
+hipError_t launch_sample(const Work& w, const Params& p, int cur, uint32_t grid, bool root_keys, hipStream_t s) {
+    hipLaunchKernelGGL(k_sample, grid_of(grid), dim3(BLOCK), 0, s, w, p, cur, root_keys ? 1 : 0);
     return hipGetLastError();
 }
-hipError_t launch_classify(const Work& w, const Params& p, int cur, uint32_t n_tiles, uint32_t n_dist,
-                           hipStream_t s) {
-    hipLaunchKernelGGL(k_classify, dim3(n_tiles), dim3(BLOCK), 0, s, w, p, cur, n_dist);
+hipError_t launch_classify(const Work& w, const Params& p, int cur, uint32_t grid, hipStream_t s) {
+    hipLaunchKernelGGL(k_classify, grid_of(grid), dim3(BLOCK), 0, s, w, p, cur);
     return hipGetLastError();
 }
-hipError_t launch_scan(const Work& w, int cur, uint32_t n_cnt, hipStream_t s) {
-    if (n_cnt == 0) return hipSuccess;
-    uint32_t nb = blocks_for(n_cnt, SCAN_CHUNK);
-    hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(BLOCK), 0, s, w.cnt[cur], n_cnt, w.partial);
-    hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(1024), 0, s, w.partial, nb);
-    hipLaunchKernelGGL(k_scan_down, dim3(nb), dim3(BLOCK), 0, s, w.cnt[cur], n_cnt, (const uint32_t*)w.partial);
+hipError_t launch_scan(const Work& w, int cur, uint32_t grid, hipStream_t s) {
+    hipLaunchKernelGGL(k_scan_reduce, grid_of(grid), dim3(BLOCK), 0, s, w, cur);
+    hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(1024), 0, s, w, cur);
+    hipLaunchKernelGGL(k_scan_down, grid_of(grid), dim3(BLOCK), 0, s, w, cur);
     return hipGetLastError();
 }
-hipError_t launch_scatter(const Work& w, const Params& p, int cur, uint32_t n_tiles, uint32_t n_dist,
+hipError_t launch_scatter(const Work& w, const Params& p, int cur, uint32_t grid, uint32_t more_grid,
                           hipStream_t s) {
-    hipLaunchKernelGGL(k_scatter, dim3(2 * n_tiles), dim3(SC_THREADS), 0, s, w, p, cur, n_dist);
+    hipLaunchKernelGGL(k_scatter, grid_of(grid), dim3(SC_THREADS), 0, s, w, p, cur);
+    if (more_grid)
+        hipLaunchKernelGGL(k_scatter_more, grid_of(more_grid), dim3(SC_THREADS), 0, s, w, p, cur, grid_of(grid).x);
     return hipGetLastError();
 }
-hipError_t launch_children(const Work& w, const Params& p, int cur, uint32_t n_dist, hipStream_t s) {
-    const uint32_t chunks = child_chunks(n_dist);
-    hipLaunchKernelGGL(k_children, dim3(n_dist * chunks), dim3(BLOCK), 0, s, w, p, cur, chunks);
+hipError_t launch_children(const Work& w, const Params& p, int cur, uint32_t grid, hipStream_t s) {
+    hipLaunchKernelGGL(k_children, grid_of(grid), dim3(BLOCK), 0, s, w, p, cur);
     return hipGetLastError();
 }
 hipError_t launch_lcp_fill(const Work& w, const Params& p, hipStream_t s) {
@@ -1812,20 +2060,42 @@ hipError_t launch_lcp_fill(const Work& w, const Params& p, hipStream_t s) {
     return hipGetLastError();
 }
 
+uint32_t grid_base(int cls, uint32_t n_base) { return cls == CLS_WG ? n_base : blocks_for(n_base, WAVES); }
+uint32_t grid_classify(uint32_t n_tiles) { return n_tiles; }
+uint32_t grid_scan(uint32_t n_cnt) { return blocks_for(n_cnt, SCAN_CHUNK); }
+uint32_t grid_scatter(uint32_t n_tiles) { return 2 * n_tiles; }
+uint32_t grid_children(uint32_t n_dist) { return n_dist * child_chunks(n_dist); }
+
 hipError_t launch_persistent(const Work& w, const Params& p, const uint32_t* set_begin, uint32_t num_sets,
-                             uint32_t blocks, hipStream_t s) {
-    hipLaunchKernelGGL(k_persist, dim3(blocks), dim3(BLOCK), 0, s, w, p, set_begin, num_sets);
+                             uint32_t blocks, bool full, uint32_t level, int cur, bool bases_done, hipStream_t s) {
+    hipLaunchKernelGGL(k_persist, dim3(blocks), dim3(BLOCK), 0, s, w, p, set_begin, num_sets, full ? 1 : 0, level,
+                       cur, bases_done ? 1 : 0);
     return hipGetLastError();
 }
 
-hipError_t persistent_capacity(int device, uint32_t* blocks) {
-    int per_cu = 0, cus = 0;
-    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_persist, BLOCK, 0);
+template <typename K>
+static hipError_t resident(K kernel, int threads, int cus, uint32_t* out) {
+    int per_cu = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0);
     if (e != hipSuccess) return e;
-    e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
-    if (e != hipSuccess) return e;
-    *blocks = (uint32_t)(per_cu * cus);
+    *out = (uint32_t)std::max(1, per_cu * cus);
     return hipSuccess;
+}
+
+hipError_t kernel_caps(int device, KernelCaps* k) {
+    int cus = 0;
+    hipError_t e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
+    if (e == hipSuccess) e = resident(k_base_wave<1>, BLOCK, cus, &k->base[0]);
+    if (e == hipSuccess) e = resident(k_base_wave<2>, BLOCK, cus, &k->base[1]);
+    if (e == hipSuccess) e = resident(k_base_wave<4>, BLOCK, cus, &k->base[2]);
+    if (e == hipSuccess) e = resident(k_base, BLOCK, cus, &k->base[3]);
+    if (e == hipSuccess) e = resident(k_sample, BLOCK, cus, &k->sample);
+    if (e == hipSuccess) e = resident(k_classify, BLOCK, cus, &k->classify);
+    if (e == hipSuccess) e = resident(k_scan_reduce, BLOCK, cus, &k->scan);
+    if (e == hipSuccess) e = resident(k_scatter, SC_THREADS, cus, &k->scatter);
+    if (e == hipSuccess) e = resident(k_children, BLOCK, cus, &k->children);
+    if (e == hipSuccess) e = resident(k_persist, BLOCK, cus, &k->persist);
+    return e;
 }
 
 hipError_t launch_admit(const Work& w, const Params& p, int cur, uint32_t pos, uint32_t m, uint32_t rid,

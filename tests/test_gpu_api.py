@@ -96,3 +96,51 @@ def test_caller_buffers_and_side_stream():
         ctx.sort(cd, od, perm, lcp, stream=s)
     s.synchronize()
     assert_equal_to_oracle(c, o, to_host(perm), to_host(lcp))
+
+
+def test_sorts_are_stream_ordered_and_asynchronous():
+    """The sort call only enqueues: work enqueued after it on the same stream
+    (here a copy of the outputs) sees the finished outputs, and two sorts of
+    one context issued on different streams run one after the other (they
+    share the context's workspace); everything is checked only after the
+    device is synchronised."""
+    import paper_1808_00963_amd as ss
+    note("case async ordering")
+    c1, o1 = gen.generate("markov", 300000, 8)
+    c2, o2 = gen.generate("urls", 200000, 9)
+    d1, d2 = to_device(c1, o1), to_device(c2, o2)
+    torch.cuda.synchronize()
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    ctx = ss.Context()
+    with torch.cuda.stream(s1):
+        p1, l1 = ctx.sort(*d1, stream=s1)
+        p1c, l1c = p1.clone(), l1.clone()
+    with torch.cuda.stream(s2):
+        p2, l2 = ctx.sort(*d2, stream=s2)
+        p2c, l2c = p2.clone(), l2.clone()
+    torch.cuda.synchronize()
+    ctx.sync()
+    assert_equal_to_oracle(c1, o1, to_host(p1c), to_host(l1c), label="stream 1")
+    assert_equal_to_oracle(c2, o2, to_host(p2c), to_host(l2c), label="stream 2")
+
+
+def test_level_budget_and_persistent_tail():
+    """A fresh context enqueues a few level launches; a sort that needs more
+    levels finishes them in the persistent tail, and the next sort on the
+    context enqueues as many level launches as the last one needed.  Both
+    results equal the oracle."""
+    import paper_1808_00963_amd as ss
+    note("case level budget")
+    n, L = 30000, 150
+    rng = np.random.default_rng(12)
+    rows = rng.integers(ord("a"), ord("d"), (n, L), dtype=np.uint8)
+    rows[:, :100] = ord("k")  # a shared prefix: one equality bucket per 8 characters
+    c = rows.reshape(-1)
+    o = np.arange(n + 1, dtype=np.uint64) * L
+    cd, od = to_device(c, o)
+    ctx = ss.Context()
+    for rep in range(2):
+        p, l = ctx.sort(cd, od)
+        torch.cuda.synchronize()
+        assert_equal_to_oracle(c, o, to_host(p), to_host(l), label=f"rep {rep}")
+        assert ctx.stats()["levels"] > 10

@@ -1,5 +1,6 @@
-"""Batched form and persistent (single-launch, graph-capturable) form on the
-GPU: every set's result equals the oracle's result for that set alone."""
+"""Batched form in every mode (device-driven levels, one persistent launch,
+host-driven levels) and its hipGraph on the GPU: every set's result equals
+the oracle's result for that set alone."""
 import sys
 
 import numpy as np
@@ -43,21 +44,24 @@ def small_batch(num_sets=64, seed=11, scale=0.02):
     return gen.batch_sets(num_sets=num_sets, seed=seed, scale=scale)
 
 
-@pytest.mark.parametrize("persistent", [False, True])
-def test_batch_vs_oracle(persistent):
+MODES = ["levels", "persistent", "host_levels"]
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_batch_vs_oracle(mode):
     import paper_1808_00963_amd as ss
-    note(f"case batch persistent={persistent}")
+    note(f"case batch mode={mode}")
     c, o, sb = small_batch()
     ctx = ss.Context()
-    ctx.set_config(persistent=persistent)
+    ctx.set_config(mode=mode)
     p, l = run_batch(c, o, sb, ctx)
     check_sets(c, o, sb, p, l)
 
 
-@pytest.mark.parametrize("persistent", [False, True])
-def test_batch_edge_sets(persistent):
+@pytest.mark.parametrize("mode", MODES)
+def test_batch_edge_sets(mode):
     import paper_1808_00963_amd as ss
-    note(f"case batch edges persistent={persistent}")
+    note(f"case batch edges mode={mode}")
     sets = [[], [b"x"], [b"b", b"a"], [b""] * 5, [b"ab", b"ab", b"a"], [bytes([255, 0])] * 3 + [b""],
             [b"q" * k for k in range(300)]]
     strings, sb = [], [0]
@@ -67,7 +71,7 @@ def test_batch_edge_sets(persistent):
     c, o = gen.from_list(strings)
     sb = np.array(sb, dtype=np.uint32)
     ctx = ss.Context()
-    ctx.set_config(persistent=persistent)
+    ctx.set_config(mode=mode)
     p, l = run_batch(c, o, sb, ctx)
     check_sets(c, o, sb, p, l)
 
@@ -78,7 +82,7 @@ def test_persistent_single_vs_oracle(model, n):
     import paper_1808_00963_amd as ss
     note(f"case persistent model={model} n={n}")
     ctx = ss.Context()
-    ctx.set_config(persistent=True)
+    ctx.set_config(mode="persistent")
     c, o = gen.generate(model, n, 500 + n)
     p, l = gpu_sort(c, o, ctx=ctx)
     assert_equal_to_oracle(c, o, p, l, label=f"persistent {model}/{n}")
@@ -88,7 +92,7 @@ def test_persistent_full_size_markov():
     import paper_1808_00963_amd as ss
     note("case persistent full c1")
     ctx = ss.Context()
-    ctx.set_config(persistent=True)
+    ctx.set_config(mode="persistent")
     c, o = gen.workload("c1_markov_16m")
     p, l = gpu_sort(c, o, ctx=ctx)
     assert_equal_to_oracle(c, o, p, l, full=False, label="persistent c1")
@@ -107,6 +111,7 @@ def test_graph_replays_match_eager():
     perm = torch.full((n,), -1, dtype=torch.int32, device="cuda")
     lcp = torch.full((n,), -1, dtype=torch.int32, device="cuda")
     g = ctx.graph_batch(cd, od, sbd, perm, lcp)
+    assert g.levels >= 1
     stream = torch.cuda.current_stream()
     for rep in range(3):
         perm.fill_(-1)
@@ -150,19 +155,20 @@ def test_bad_set_boundaries():
     cd, od = to_device(c, o)
     ctx = ss.Context()
     bad = torch.tensor([0, 600, 500, 1000], dtype=torch.int32, device="cuda")
+    ctx.sort_batch(cd, od, bad)
     with pytest.raises(ss.SSError) as e:
-        ctx.sort_batch(cd, od, bad)
+        ctx.sync()
     assert e.value.status == ss.SS_INVALID_ARG
 
 
-@pytest.mark.parametrize("persistent", [False, True])
-def test_full_batched_workload(persistent):
+@pytest.mark.parametrize("mode", MODES)
+def test_full_batched_workload(mode):
     """4096 sets, character budgets log-uniform in [1e3, 1e6]."""
     import paper_1808_00963_amd as ss
-    note(f"case full batched persistent={persistent}")
+    note(f"case full batched mode={mode}")
     c, o, sb = gen.batch_sets()
     ctx = ss.Context()
-    ctx.set_config(persistent=persistent)
+    ctx.set_config(mode=mode)
     p, l = run_batch(c, o, sb, ctx)
     check_sets(c, o, sb, p, l, full=False)
 
@@ -222,3 +228,58 @@ def test_first_level_sampling_beside_the_gather():
         cm, om = c[:int(o[m])], o[:m + 1]
         pm, lm = gpu_sort(cm, om, ctx=ctx)
         assert_equal_to_oracle(cm, om, pm, lm, label=f"n={m}")
+
+
+def test_full_batched_graph():
+    """The 4096-set workload as one graph: level launches plus the
+    persistent tail; two replays each equal the oracle on every set."""
+    import paper_1808_00963_amd as ss
+    note("case full batched graph")
+    c, o, sb = gen.batch_sets()
+    cd, od = to_device(c, o)
+    sbd = torch.from_numpy(sb.astype(np.int32)).cuda()
+    n = len(o) - 1
+    perm = torch.empty(n, dtype=torch.int32, device="cuda")
+    lcp = torch.empty_like(perm)
+    ctx = ss.Context()
+    g = ctx.graph_batch(cd, od, sbd, perm, lcp)
+    for rep in range(2):
+        perm.fill_(-1)
+        lcp.fill_(-1)
+        g.launch()
+        ctx.sync()
+        check_sets(c, o, sb, to_host(perm), to_host(lcp), full=False)
+    g.close()
+
+
+def test_graph_tail_runs_deeper_contents():
+    """A graph sized on shallow contents replayed on contents that need more
+    levels: the persistent tail runs the extra levels."""
+    import paper_1808_00963_amd as ss
+    note("case graph deeper contents")
+    n = 20000
+    rng = np.random.default_rng(5)
+    # shallow: random letters; deep: one shared 200-byte prefix, then random
+    L = 220
+    shallow = rng.integers(ord("a"), ord("z") + 1, n * L, dtype=np.uint8)
+    deep = shallow.copy().reshape(n, L)
+    deep[:, :200] = ord("p")
+    deep = deep.reshape(-1)
+    o = np.arange(n + 1, dtype=np.uint64) * L
+    sb = np.array([0, n // 2, n], dtype=np.uint32)
+    cd, od = to_device(shallow, o)
+    sbd = torch.from_numpy(sb.astype(np.int32)).cuda()
+    perm = torch.empty(n, dtype=torch.int32, device="cuda")
+    lcp = torch.empty_like(perm)
+    ctx = ss.Context()
+    g = ctx.graph_batch(cd, od, sbd, perm, lcp)
+    few = g.levels
+    cd.copy_(torch.from_numpy(deep).cuda())
+    g.launch()
+    ctx.sync()
+    check_sets(deep, o, sb, to_host(perm), to_host(lcp))
+    eager = ss.Context()
+    eager.sort_batch(cd, od, sbd)
+    torch.cuda.synchronize()
+    assert eager.stats()["levels"] > few
+    g.close()

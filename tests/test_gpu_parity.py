@@ -104,11 +104,16 @@ def test_bad_offsets_is_an_error_and_context_recovers():
     bad[100], bad[101] = bad[101], bad[100]   # not monotone
     from gpu_util import to_device
     cd, od = to_device(c, bad)
+    ctx.sort(cd, od)  # asynchronous: the device-side error surfaces at sync
     with pytest.raises(ss.SSError) as e:
-        ctx.sort(cd, od)
+        ctx.sync()
     assert e.value.status == ss.SS_LIMIT
     assert ctx.last_error() == ss.SS_LIMIT
+    # sticky until cleared, also across later sorts
+    p, l = gpu_sort(c, o, ctx=ctx)
+    assert ctx.last_error() == ss.SS_LIMIT
     ctx.clear_error()
+    assert ctx.last_error() == ss.SS_OK
     p, l = gpu_sort(c, o, ctx=ctx)
     assert_equal_to_oracle(c, o, p, l)
 
