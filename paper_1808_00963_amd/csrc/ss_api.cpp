@@ -255,9 +255,9 @@ ss_status device_error_status(uint32_t err) {
 
 // Launches `fn` and, when profiling, brackets it with an event pair.
 template <typename F>
-hipError_t timed(ss_ctx* ctx, hipStream_t s, int id, UnitSpec u, F&& fn) {
-    Profiler& P = ctx->prof;
-    if (!P.on || !((P.mask >> id) & 1u)) return fn();
+hipError_t timed(Profiler* prof, hipStream_t s, int id, UnitSpec u, F&& fn) {
+    if (!prof || !prof->on || !((prof->mask >> id) & 1u)) return fn();
+    Profiler& P = *prof;
     if (P.used * 2 + 2 > P.ev.size()) {
         for (int i = 0; i < 64; ++i) {
             hipEvent_t e;
@@ -367,6 +367,27 @@ ss_status ensure_caps(ss_ctx* ctx) {
     return SS_OK;
 }
 
+// What a sort's launches run with: the kernels' resident capacities, the
+// profiler (null: no timing) and the library streams for the steps that
+// overlap others (null: everything on the sort's stream).
+struct Engine {
+    const KernelCaps* kc = nullptr;
+    Profiler* prof = nullptr;
+    hipStream_t side[2] = {nullptr, nullptr};
+    hipEvent_t fork = nullptr, join[2] = {nullptr, nullptr};
+};
+Engine engine_of(ss_ctx* ctx) {
+    Engine e;
+    e.kc = &ctx->kc;
+    e.prof = &ctx->prof;
+    for (int i = 0; i < 2; ++i) {
+        e.side[i] = ctx->side[i];
+        e.join[i] = ctx->join[i];
+    }
+    e.fork = ctx->fork;
+    return e;
+}
+
 // What the host knows about a level when it enqueues it: exact counts (the
 // host-driven loop and serving) or nothing (pool capacities bound the work).
 struct LevelPlan {
@@ -387,22 +408,25 @@ constexpr uint32_t ROUNDS_BASE = 16, ROUNDS_TILES = 8;
 constexpr uint32_t ROUNDS_SCATTER = 16;
 
 // Enqueues recursion level `level` on slot `cur` (its counts read on the
-// device): level start, then the base cases on the two library streams
-// (classes 0 and 3 on one, 1 and 2 on the other) beside the distribution
-// steps (sample, classify, scan, scatter, children) on `s`, joined into `s`
-// at the end.  Kernels that the plan shows to have no work are left out.
-ss_status enqueue_level(ss_ctx* ctx, const Work& w, const Params& p, int cur, uint32_t level, const LevelPlan& L,
+// device): level start, then the distribution steps (sample, classify, scan,
+// scatter, children) on `s` and the base cases on the two library streams
+// (classes 0 and 3 on one, 1 and 2 on the other), forked from `s` after the
+// level start and joined into `s` at the end.  Without library streams
+// everything runs on `s`.  Kernels that the plan shows to have no work are
+// left out.
+ss_status enqueue_level(const Engine& e, const Work& w, const Params& p, int cur, uint32_t level, const LevelPlan& L,
                         hipStream_t s) {
-    const KernelCaps& kc = ctx->kc;
+    const KernelCaps& kc = *e.kc;
     const Caps& cap = w.caps;
     uint32_t bases = 0;
     for (int q = 0; q < NCLS; ++q)
         if ((L.maybe_base >> q) & 1u && (!L.exact || L.c.n_base[q])) bases |= 1u << q;
     const bool dist = L.maybe_dist && (!L.exact || L.c.n_dist);
-    SS_TRY(timed(ctx, s, K_LEVEL_BEGIN, units_const(1.0), [&] { return launch_level_begin(w, cur, level, s); }));
+    SS_TRY(timed(e.prof, s, K_LEVEL_BEGIN, units_const(1.0), [&] { return launch_level_begin(w, cur, level, s); }));
     const uint32_t on[2] = {bases & (1u | 1u << 3), bases & (1u << 1 | 1u << 2)};
+    const bool sides = e.side[0] && e.side[1];
     bool forked[2] = {false, false};
-    if (bases) SS_TRY(hipEventRecord(ctx->fork, s));
+    if (bases && sides) SS_TRY(hipEventRecord(e.fork, s));
     // the distribution steps are enqueued first, so the host's calls for the
     // library streams do not hold them back
     if (dist) {
@@ -410,67 +434,68 @@ ss_status enqueue_level(ss_ctx* ctx, const Work& w, const Params& p, int cur, ui
         const uint32_t n_dist = L.exact ? c.n_dist : cap.dist, n_tiles = L.exact ? c.n_tiles : cap.tiles;
         const uint32_t n_cnt = L.exact ? c.n_cnt : cap.cnt;
         if (!L.sampled)
-            SS_TRY(timed(ctx, s, K_SAMPLE, units_level(U_DIST, level),
+            SS_TRY(timed(e.prof, s, K_SAMPLE, units_level(U_DIST, level),
                          [&] { return launch_sample(w, p, cur, clamp_grid(kc.sample, n_dist), false, s); }));
-        SS_TRY(timed(ctx, s, K_CLASSIFY, units_level(U_DIST_STRINGS, level), [&] {
+        SS_TRY(timed(e.prof, s, K_CLASSIFY, units_level(U_DIST_STRINGS, level), [&] {
             return launch_classify(w, p, cur, clamp_grid(ROUNDS_TILES * kc.classify, grid_classify(n_tiles)), s);
         }));
-        SS_TRY(timed(ctx, s, K_SCAN, units_level(U_CNT, level),
+        SS_TRY(timed(e.prof, s, K_SCAN, units_level(U_CNT, level),
                      [&] { return launch_scan(w, cur, clamp_grid(kc.scan, grid_scan(n_cnt)), s); }));
-        SS_TRY(timed(ctx, s, K_SCATTER, units_level(U_DIST_STRINGS, level), [&] {
+        SS_TRY(timed(e.prof, s, K_SCATTER, units_level(U_DIST_STRINGS, level), [&] {
             const uint32_t need = grid_scatter(n_tiles), g = clamp_grid(ROUNDS_SCATTER * kc.scatter, need);
             return launch_scatter(w, p, cur, g, need > g ? kc.scatter : 0u, s);
         }));
-        SS_TRY(timed(ctx, s, K_CHILDREN, units_level(U_DIST, level), [&] {
+        SS_TRY(timed(e.prof, s, K_CHILDREN, units_level(U_DIST, level), [&] {
             return launch_children(w, p, cur, clamp_grid(kc.children, grid_children(n_dist)), s);
         }));
     }
     for (int k = 0; k < 2; ++k) {
         if (!on[k]) continue;
-        hipStream_t bs = dist || k == 1 ? ctx->side[k] : s;  // without distribution steps, `s` takes one share
+        // without distribution steps, `s` takes one share
+        hipStream_t bs = sides && (dist || k == 1) ? e.side[k] : s;
         if (bs != s) {
-            SS_TRY(hipStreamWaitEvent(bs, ctx->fork, 0));
+            SS_TRY(hipStreamWaitEvent(bs, e.fork, 0));
             forked[k] = true;
         }
         for (int q = 0; q < NCLS; ++q) {
             if (!((on[k] >> q) & 1u)) continue;
             const uint32_t need = grid_base(q, L.exact ? L.c.n_base[q] : cap.base[q]);
-            SS_TRY(timed(ctx, bs, K_BASE_W1 + q, units_level(U_BASE0 + q, level),
+            SS_TRY(timed(e.prof, bs, K_BASE_W1 + q, units_level(U_BASE0 + q, level),
                          [&] { return launch_base(w, p, cur, q, clamp_grid(ROUNDS_BASE * kc.base[q], need), bs); }));
         }
     }
     for (int k = 0; k < 2; ++k) {
         if (!forked[k]) continue;
-        SS_TRY(hipEventRecord(ctx->join[k], ctx->side[k]));
-        SS_TRY(hipStreamWaitEvent(s, ctx->join[k], 0));
+        SS_TRY(hipEventRecord(e.join[k], e.side[k]));
+        SS_TRY(hipStreamWaitEvent(s, e.join[k], 0));
     }
     return SS_OK;
 }
 
 // Start of every sort: reset, roots and key gather.  For 2^21 strings or
-// more the roots are emitted before the gather and the first level's
-// sampling reads its keys from the strings on a library stream while the
-// gather fills the buffer (joined before the first classification); its
-// grid covers every root that can be a distribution segment.  Returns
-// whether the first level's sampling was enqueued.
-ss_status enqueue_start(ss_ctx* ctx, const Work& w, const Params& p, const uint32_t* set_begin, uint32_t nroots,
+// more (and with library streams) the roots are emitted before the gather
+// and the first level's sampling reads its keys from the strings on a
+// library stream while the gather fills the buffer (joined before the first
+// classification); its grid covers every root that can be a distribution
+// segment.  Returns whether the first level's sampling was enqueued.
+ss_status enqueue_start(const Engine& e, const Work& w, const Params& p, const uint32_t* set_begin, uint32_t nroots,
                         hipStream_t s, bool* sampled) {
     const uint32_t n = p.n;
     SS_TRY(launch_reset(w, s));
-    *sampled = n >= FORK_MIN;
+    *sampled = n >= FORK_MIN && e.side[0];
     if (*sampled) {
-        SS_TRY(timed(ctx, s, K_ROOTS, units_const(nroots), [&] { return launch_roots(w, p, set_begin, nroots, s); }));
-        const uint32_t root_grid = clamp_grid(ctx->kc.sample, std::min<uint32_t>(nroots, n / (p.base_max + 1) + 1));
-        SS_TRY(hipEventRecord(ctx->fork, s));
-        SS_TRY(timed(ctx, s, K_INIT, units_const(n), [&] { return launch_init(w, p, s); }));
-        SS_TRY(hipStreamWaitEvent(ctx->side[0], ctx->fork, 0));
-        SS_TRY(timed(ctx, ctx->side[0], K_SAMPLE, units_level(U_DIST, 0),
-                     [&] { return launch_sample(w, p, 0, root_grid, true, ctx->side[0]); }));
-        SS_TRY(hipEventRecord(ctx->join[0], ctx->side[0]));
-        SS_TRY(hipStreamWaitEvent(s, ctx->join[0], 0));
+        SS_TRY(timed(e.prof, s, K_ROOTS, units_const(nroots), [&] { return launch_roots(w, p, set_begin, nroots, s); }));
+        const uint32_t root_grid = clamp_grid(e.kc->sample, std::min<uint32_t>(nroots, n / (p.base_max + 1) + 1));
+        SS_TRY(hipEventRecord(e.fork, s));
+        SS_TRY(timed(e.prof, s, K_INIT, units_const(n), [&] { return launch_init(w, p, s); }));
+        SS_TRY(hipStreamWaitEvent(e.side[0], e.fork, 0));
+        SS_TRY(timed(e.prof, e.side[0], K_SAMPLE, units_level(U_DIST, 0),
+                     [&] { return launch_sample(w, p, 0, root_grid, true, e.side[0]); }));
+        SS_TRY(hipEventRecord(e.join[0], e.side[0]));
+        SS_TRY(hipStreamWaitEvent(s, e.join[0], 0));
     } else {
-        SS_TRY(timed(ctx, s, K_INIT, units_const(n), [&] { return launch_init(w, p, s); }));
-        SS_TRY(timed(ctx, s, K_ROOTS, units_const(nroots), [&] { return launch_roots(w, p, set_begin, nroots, s); }));
+        SS_TRY(timed(e.prof, s, K_INIT, units_const(n), [&] { return launch_init(w, p, s); }));
+        SS_TRY(timed(e.prof, s, K_ROOTS, units_const(nroots), [&] { return launch_roots(w, p, set_begin, nroots, s); }));
     }
     return SS_OK;
 }
@@ -482,10 +507,10 @@ ss_status enqueue_start(ss_ctx* ctx, const Work& w, const Params& p, const uint3
 // what the sort needs, that level is complete and the persistent launch
 // finds nothing to do; otherwise it continues with that level's
 // distribution segments.  No host synchronisation; capturable.
-ss_status enqueue_sort_levels(ss_ctx* ctx, const Work& w, const Params& p, const uint32_t* set_begin,
+ss_status enqueue_sort_levels(const Engine& e, const Work& w, const Params& p, const uint32_t* set_begin,
                               uint32_t nroots, uint32_t levels, hipStream_t s) {
     bool sampled = false;
-    ss_status st = enqueue_start(ctx, w, p, set_begin, nroots, s, &sampled);
+    ss_status st = enqueue_start(e, w, p, set_begin, nroots, s, &sampled);
     if (st != SS_OK) return st;
     bool one_root_base = false;
     if (!set_begin) {  // one root: a distribution segment (two levels at least), a base case or nothing
@@ -501,11 +526,11 @@ ss_status enqueue_sort_levels(ss_ctx* ctx, const Work& w, const Params& p, const
             L.maybe_base = one_root_base && p.n >= 2 ? 1u << size_class(p.n) : 0u;
             L.maybe_dist = L.maybe_dist && !one_root_base;
         }
-        if ((st = enqueue_level(ctx, w, p, cur, level, L, s)) != SS_OK) return st;
+        if ((st = enqueue_level(e, w, p, cur, level, L, s)) != SS_OK) return st;
         if (level + 1 < levels) cur ^= 1;
     }
-    SS_TRY(timed(ctx, s, K_PERSIST, units_const(0.0), [&] {
-        return launch_persistent(w, p, set_begin, nroots, ctx->kc.persist, false, levels - 1, cur, true, s);
+    SS_TRY(timed(e.prof, s, K_PERSIST, units_const(0.0), [&] {
+        return launch_persistent(w, p, set_begin, nroots, e.kc->persist, false, levels - 1, cur, true, s);
     }));
     return SS_OK;
 }
@@ -514,8 +539,9 @@ ss_status enqueue_sort_levels(ss_ctx* ctx, const Work& w, const Params& p, const
 // level with exact grids (synchronises once per level).
 ss_status run_sort_host_levels(ss_ctx* ctx, const Work& w, const Params& p, const uint32_t* set_begin,
                                uint32_t nroots, hipStream_t s) {
+    const Engine e = engine_of(ctx);
     bool sampled = false;
-    ss_status st = enqueue_start(ctx, w, p, set_begin, nroots, s, &sampled);
+    ss_status st = enqueue_start(e, w, p, set_begin, nroots, s, &sampled);
     if (st != SS_OK) return st;
     int cur = 0;
     for (uint32_t level = 0;; ++level) {
@@ -528,12 +554,12 @@ ss_status run_sort_host_levels(ss_ctx* ctx, const Work& w, const Params& p, cons
         bool work = L.c.n_dist != 0;
         for (int q = 0; q < NCLS; ++q) work |= L.c.n_base[q] != 0;
         if (!work) break;
-        if ((st = enqueue_level(ctx, w, p, cur, level, L, s)) != SS_OK) return st;
+        if ((st = enqueue_level(e, w, p, cur, level, L, s)) != SS_OK) return st;
         if (L.c.n_dist == 0) break;
         cur ^= 1;
         if (level + 1 >= MAX_LEVELS) return SS_INTERNAL;
     }
-    SS_TRY(timed(ctx, s, K_LCP_FILL, units_level(U_PEND, 0), [&] { return launch_lcp_fill(w, p, s); }));
+    SS_TRY(timed(&ctx->prof, s, K_LCP_FILL, units_level(U_PEND, 0), [&] { return launch_lcp_fill(w, p, s); }));
     return SS_OK;
 }
 
@@ -575,13 +601,13 @@ ss_status run_sort(ss_ctx* ctx, const uint8_t* chars, const uint64_t* offsets, u
     const uint32_t nroots = set_begin ? num_sets : 1;
     if (ctx->cfg.mode == SS_MODE_PERSISTENT) {
         SS_TRY(launch_reset(w, s));
-        SS_TRY(timed(ctx, s, K_PERSIST, units_const(n), [&] {
+        SS_TRY(timed(&ctx->prof, s, K_PERSIST, units_const(n), [&] {
             return launch_persistent(w, p, set_begin, nroots, ctx->kc.persist, true, 0, 0, false, s);
         }));
     } else if (ctx->cfg.mode == SS_MODE_HOST_LEVELS) {
         if ((st = run_sort_host_levels(ctx, w, p, set_begin, nroots, s)) != SS_OK) return st;
     } else {
-        if ((st = enqueue_sort_levels(ctx, w, p, set_begin, nroots, levels, s)) != SS_OK) return st;
+        if ((st = enqueue_sort_levels(engine_of(ctx), w, p, set_begin, nroots, levels, s)) != SS_OK) return st;
     }
     SS_TRY(hipMemcpyAsync(ctx->host_ctl, w.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
     SS_TRY(hipEventRecord(ctx->done, s));
@@ -714,8 +740,8 @@ ss_status run_merge(ss_ctx* ctx, const uint8_t* chars, const uint64_t* offsets, 
         a.split = (uint32_t*)(dws + off_split);
         a.cross = (uint32_t*)(dws + off_cross);
         a.err = derr;
-        SS_TRY(timed(ctx, s, K_MERGE_SPLIT, units_const(a.n_tiles), [&] { return launch_merge_split(a, s); }));
-        SS_TRY(timed(ctx, s, K_MERGE, units_const((double)m), [&] { return launch_merge_tiles(a, s); }));
+        SS_TRY(timed(&ctx->prof, s, K_MERGE_SPLIT, units_const(a.n_tiles), [&] { return launch_merge_split(a, s); }));
+        SS_TRY(timed(&ctx->prof, s, K_MERGE, units_const((double)m), [&] { return launch_merge_tiles(a, s); }));
         t0 += rounds[r].size();
     }
     SS_TRY(hipMemcpyAsync(herr, derr, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
@@ -802,7 +828,7 @@ ss_status run_suffix_array(ss_ctx* ctx, const uint8_t* text, uint32_t n, uint32_
     const bool packed = bits <= 4;
     const uint32_t w0 = packed ? 128 / bits : SA_W0;  // characters resolved by round 0
     // round 0: every suffix by its first w0 characters, sorted into sa
-    SS_TRY(timed(ctx, s, K_SA_STRINGS, units_const(n), [&] {
+    SS_TRY(timed(&ctx->prof, s, K_SA_STRINGS, units_const(n), [&] {
         if (!packed) return launch_sa_windows(text, n, chars, offsets, s);
         hipError_t e = hipMemcpyAsync(rank, hrank, 256, hipMemcpyHostToDevice, s);
         if (e != hipSuccess) return e;
@@ -822,7 +848,7 @@ ss_status run_suffix_array(ss_ctx* ctx, const uint8_t* text, uint32_t n, uint32_
     uint32_t rounds = 1, cur = 0;
     uint64_t h = w0;  // depth the names resolve
     for (;;) {
-        SS_TRY(timed(ctx, s, K_SA_RENAME, units_const(a.m), [&] { return launch_sa_rename(a, s); }));
+        SS_TRY(timed(&ctx->prof, s, K_SA_RENAME, units_const(a.m), [&] { return launch_sa_rename(a, s); }));
         SS_TRY(hipMemcpyAsync(ctx->sa_host, part_cnt + sa_tiles(a.m), sizeof(uint32_t), hipMemcpyDeviceToHost, s));
         SS_TRY(hipStreamSynchronize(s));
         // the round's sort has completed: its device-side errors
@@ -838,7 +864,7 @@ ss_status run_suffix_array(ss_ctx* ctx, const uint8_t* text, uint32_t n, uint32_
         a.pos = pos[cur];
         a.idx = idx;
         a.next_pos = pos[cur ^ 1];
-        SS_TRY(timed(ctx, s, K_SA_STRINGS, units_const(m), [&] { return launch_sa_pairs(a, (uint32_t)h, chars, offsets, s); }));
+        SS_TRY(timed(&ctx->prof, s, K_SA_STRINGS, units_const(m), [&] { return launch_sa_pairs(a, (uint32_t)h, chars, offsets, s); }));
         st = run_sort(ctx, chars, offsets, m, nullptr, 1, perm, lcp, s);
         if (st != SS_OK) return st;
         a.perm = perm;
@@ -1005,7 +1031,7 @@ ss_status ss_graph_create_batch(ss_ctx* ctx, const uint8_t* chars, const uint64_
         gr->levels = std::min<uint32_t>(std::max<uint32_t>(ctx->host_ctl->stats.levels, 1), MAX_LEVEL_LAUNCHES);
         hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
         if (e == hipSuccess) {
-            st = enqueue_sort_levels(ctx, w, p, set_begin, num_sets, gr->levels, cs);
+            st = enqueue_sort_levels(engine_of(ctx), w, p, set_begin, num_sets, gr->levels, cs);
             hipError_t e2 = hipStreamEndCapture(cs, &g);
             if (st == SS_OK && e2 != hipSuccess) st = SS_HIP_ERROR;
         } else {
@@ -1602,7 +1628,7 @@ void server_loop(ss_server* S) {
             LevelPlan L;
             L.exact = true;
             L.c = counts_of(ctx->host_ctl->cl[S->cur]);
-            st = enqueue_level(ctx, S->w, S->p, S->cur, S->level, L, S->stream);
+            st = enqueue_level(engine_of(ctx), S->w, S->p, S->cur, S->level, L, S->stream);
             S->cur ^= 1;
             ++S->level;
         }

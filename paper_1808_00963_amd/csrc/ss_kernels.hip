@@ -287,7 +287,16 @@ __global__ void k_reset(Work w) {
 }
 
 __global__ void k_level_begin(Work w, int cur, uint32_t level) {
-    if (threadIdx.x == 0) note_level(w, load_counts(w, cur), level);
+    // A sort with an error stops here: the level's counts are dropped, so no
+    // kernel of this or a later level finds work (malformed offsets are
+    // found by the key gather, before any string is read past its first
+    // word).
+    if (__hip_atomic_load(&w.ctl->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+        CLine* C = &w.ctl->cl[cur].dist;
+        for (uint32_t i = threadIdx.x; i < COUNT_LINES; i += blockDim.x) C[i].v = 0;
+    } else if (threadIdx.x == 0) {
+        note_level(w, load_counts(w, cur), level);
+    }
     CLine* L = &w.ctl->cl[cur ^ 1].dist;
     for (uint32_t i = threadIdx.x; i < COUNT_LINES; i += blockDim.x) L[i].v = 0;
     FeedLine* f = feed_of(w, cur, 0);
