@@ -147,6 +147,26 @@ ss_status ss_sort_ex(ss_ctx* ctx, const uint8_t* chars, const uint64_t* offsets,
 ss_status ss_sort(const uint8_t* chars, const uint64_t* offsets, uint32_t n,
                   uint32_t* perm_out, uint32_t* lcp_out, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the sort
+ * of ss_sort, with its workspace in a fixed array of the library instead of
+ * a context's allocation.  It calls no allocating routine; every launch goes
+ * to `stream` (asynchronous, stream-ordered, capturable).  The array (72 MiB,
+ * workspace for SS_NOALLOC_MAX_STRINGS strings) is allocated on each device
+ * when the library is loaded there and held until the process ends; all
+ * calls on one device share it, so calls on one device must not overlap
+ * (order them on one stream, or synchronise between them): overlapping calls
+ * race on the shared workspace.  Each call starts by clearing the control
+ * data it relies on.  chars, offsets, perm_out, lcp_out: as for ss_sort_ex.
+ * err_out: device pointer to one uint32 (or NULL) that receives the sort's
+ * device-side error bits when it has run (0 = success; nonzero = offsets not
+ * monotone, a string too long, or an internal limit; the outputs are then
+ * unspecified).  Returns SS_LIMIT for n > SS_NOALLOC_MAX_STRINGS,
+ * SS_INVALID_ARG for null or aliased pointers; n = 0 is a no-op. */
+#define SS_NOALLOC_MAX_STRINGS (1u << 20)
+ss_status ss_sort_noalloc(const uint8_t* chars, const uint64_t* offsets, uint32_t n, uint32_t* perm_out,
+                          uint32_t* lcp_out, uint32_t* err_out, void* stream);
+
 /* Batched form: sorts num_sets independent string sets in one pass of the
  * pipeline (all sets' segments are processed by the same kernel launches):
  * each set is the section 2.1 problem on its own, and the sets are the

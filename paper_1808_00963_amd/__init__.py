@@ -84,6 +84,7 @@ def lib():
             "ss_workspace_query": (i32, [vp, u32, ctypes.POINTER(ctypes.c_size_t)]),
             "ss_sort_ex": (i32, [vp, vp, vp, u32, vp, vp, vp]),
             "ss_sort": (i32, [vp, vp, u32, vp, vp, vp]),
+            "ss_sort_noalloc": (i32, [vp, vp, u32, vp, vp, vp, vp]),
             "ss_sort_batch": (i32, [vp, vp, vp, u32, vp, u32, vp, vp, vp]),
             "ss_get_last_error": (i32, [vp]),
             "ss_clear_error": (None, [vp]),
@@ -471,6 +472,25 @@ def sort(chars, offsets, stream=None):
     st = lib().ss_sort(ctypes.c_void_p(chars.data_ptr()), ctypes.c_void_p(offsets.data_ptr()), n,
                        ctypes.c_void_p(perm.data_ptr()), ctypes.c_void_p(lcp.data_ptr()), _stream_ptr(stream))
     _check(st, "ss_sort")
+    return perm, lcp
+
+
+NOALLOC_MAX_STRINGS = 1 << 20
+
+
+def sort_noalloc(chars, offsets, perm, lcp, err=None, stream=None):
+    """ss_sort_noalloc: the sort with the library's fixed workspace (at most
+    NOALLOC_MAX_STRINGS strings, no allocation); perm/lcp (and err, one
+    int32 device word receiving the device-side error bits) are
+    caller-provided device tensors."""
+    _check_inputs(chars, offsets)
+    n = offsets.numel() - 1
+    if perm.numel() < n or lcp.numel() < n:
+        raise ValueError("outputs shorter than n")
+    st = lib().ss_sort_noalloc(ctypes.c_void_p(chars.data_ptr()), ctypes.c_void_p(offsets.data_ptr()), n,
+                               ctypes.c_void_p(perm.data_ptr()), ctypes.c_void_p(lcp.data_ptr()),
+                               ctypes.c_void_p(err.data_ptr()) if err is not None else None, _stream_ptr(stream))
+    _check(st, "ss_sort_noalloc")
     return perm, lcp
 
 

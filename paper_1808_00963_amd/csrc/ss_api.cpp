@@ -879,6 +879,57 @@ ss_status run_suffix_array(ss_ctx* ctx, const uint8_t* text, uint32_t n, uint32_
 std::mutex g_mu;
 std::map<int, std::unique_ptr<ss_ctx, void (*)(ss_ctx*)>>* g_ctx = nullptr;
 
+// ---- sorting without allocation ----
+//
+// The workspace of ss_sort_noalloc is this array: one copy per device,
+// allocated when the library's code object is loaded there and held until
+// the process ends.  Host code never uses the array's name as an address:
+// set-up takes each device's address with hipGetSymbolAddress (with that
+// device current) and the kernels get that address.
+constexpr uint32_t NOALLOC_MAX_N = SS_NOALLOC_MAX_STRINGS;
+constexpr size_t NOALLOC_BYTES = (size_t)72 << 20;
+constexpr uint32_t NOALLOC_LEVELS = 4;  // level launches before the persistent tail
+static __device__ __align__(256) uint8_t scratch[NOALLOC_BYTES];
+
+constexpr int NOALLOC_DEVICES = 64;
+struct NoAllocDevice {
+    bool ready = false;
+    ss_status status = SS_OK;  // of the set-up
+    Work work{};
+    KernelCaps kc{};
+};
+std::mutex g_na_mu;
+NoAllocDevice g_na[NOALLOC_DEVICES];
+
+// Set-up on device `dev` (current): the array's address on this device, the
+// workspace laid out in it for NOALLOC_MAX_N strings, the kernels' resident
+// capacities.  Runs once per device.
+const NoAllocDevice* noalloc_device(int dev) {
+    if (dev < 0 || dev >= NOALLOC_DEVICES) return nullptr;
+    std::lock_guard<std::mutex> lock(g_na_mu);
+    NoAllocDevice& d = g_na[dev];
+    if (d.ready) return &d;
+    d.ready = true;
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) {
+        (void)hipGetLastError();
+        d.status = SS_HIP_ERROR;
+        return &d;
+    }
+    const ss_config c{10, 64, 1024, SS_MODE_LEVELS};
+    const Caps k = caps_for(NOALLOC_MAX_N, c);
+    if (layout(NOALLOC_MAX_N, k, nullptr, nullptr) > NOALLOC_BYTES) {
+        d.status = SS_INTERNAL;
+        return &d;
+    }
+    layout(NOALLOC_MAX_N, k, (char*)ptr, &d.work);
+    if (kernel_caps(dev, &d.kc) != hipSuccess) {
+        (void)hipGetLastError();
+        d.status = SS_HIP_ERROR;
+    }
+    return &d;
+}
+
 }  // namespace
 
 extern "C" {
@@ -984,6 +1035,25 @@ ss_status ss_sort(const uint8_t* chars, const uint64_t* offsets, uint32_t n, uin
         it = g_ctx->emplace(dev, std::unique_ptr<ss_ctx, void (*)(ss_ctx*)>(c, ss_ctx_destroy)).first;
     }
     return sort_checked(it->second.get(), chars, offsets, n, nullptr, 1, perm_out, lcp_out, stream);
+}
+
+ss_status ss_sort_noalloc(const uint8_t* chars, const uint64_t* offsets, uint32_t n, uint32_t* perm_out,
+                          uint32_t* lcp_out, uint32_t* err_out, void* stream) {
+    if (n == 0) return SS_OK;
+    if (n > NOALLOC_MAX_N) return SS_LIMIT;
+    if (!offsets || !perm_out || !lcp_out || (void*)perm_out == (void*)lcp_out) return SS_INVALID_ARG;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return SS_HIP_ERROR;
+    const NoAllocDevice* d = noalloc_device(dev);
+    if (!d) return SS_INVALID_ARG;
+    if (d->status != SS_OK) return d->status;
+    hipStream_t s = (hipStream_t)stream;
+    Engine e;
+    e.kc = &d->kc;  // no profiler, no library streams: every launch goes to `stream`
+    const Params p{chars, offsets, n, perm_out, lcp_out, 10, 64, 1024};
+    ss_status st = enqueue_sort_levels(e, d->work, p, nullptr, 1, NOALLOC_LEVELS, s);
+    if (st == SS_OK && err_out) st = hip_status(launch_report(d->work, err_out, s));
+    return st;
 }
 
 ss_status ss_sort_batch(ss_ctx* ctx, const uint8_t* chars, const uint64_t* offsets, uint32_t n,

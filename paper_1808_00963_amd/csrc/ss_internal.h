@@ -246,6 +246,8 @@ hipError_t launch_roots(const Work& w, const Params& p, const uint32_t* set_begi
 // zeroes the next slot's counts and this slot's feed counters (no memset:
 // stays capturable).
 hipError_t launch_level_begin(const Work& w, int cur, uint32_t level, hipStream_t s);
+// out[0] = the sort's error bits (a device word of the caller).
+hipError_t launch_report(const Work& w, uint32_t* out, hipStream_t s);
 hipError_t launch_base(const Work& w, const Params& p, int cur, int cls, uint32_t grid, hipStream_t s);
 // root_keys: the first level's sampling, reading keys from the strings.
 hipError_t launch_sample(const Work& w, const Params& p, int cur, uint32_t grid, bool root_keys, hipStream_t s);

@@ -2009,6 +2009,13 @@ hipError_t launch_reset(const Work& w, hipStream_t s) {
     hipLaunchKernelGGL(k_reset, dim3(1), dim3(BLOCK), 0, s, w);
     return hipGetLastError();
 }
+__global__ void k_report(Work w, uint32_t* out) {
+    if (threadIdx.x == 0) out[0] = w.ctl->err;
+}
+hipError_t launch_report(const Work& w, uint32_t* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_report, dim3(1), dim3(64), 0, s, w, out);
+    return hipGetLastError();
+}
 hipError_t launch_level_begin(const Work& w, int cur, uint32_t level, hipStream_t s) {
     hipLaunchKernelGGL(k_level_begin, dim3(1), dim3(BLOCK), 0, s, w, cur, level);
     return hipGetLastError();
