@@ -25,22 +25,31 @@ HBM_PEAK_GBS = 8000.0
 
 # Algorithmic bytes per work unit of each kernel (what the kernel must move
 # by its definition, not what the hardware ends up fetching).
-#   k_init      per string: offset (8) + first word (<= 8, measured) + element write (16)
-#   k_classify  per string: element read (16) + bucket id write (2)
-#   k_scatter   per string: bucket id (2) + element read (16) + element write (16)
-#   k_base      per string: element read (16) + perm and lcp writes (4 + 4)
+#   k_init      per string: offset (8) + first word (<= 8, measured) + record write (13)
+#   k_classify  per string: key and r read (9) + bucket id write (2)
+#   k_scatter   per string and distribution pass: 2 x 13 (read + write of
+#               idx u32, key u64, r u8), the byte model of one distribution pass
+#   k_base      per string: record read (13) + perm and lcp writes (4 + 4)
 #   k_scan      per counter: reduce read (4) + scan read (4) + write (4)
 #   k_lcp_fill  per boundary: entry (8) + lcp (4+4) + perm (8) + offsets (32) + two words (16)
+# The implementation's records are 16 bytes (key, idx, len) and the scatter
+# also reads the 2-byte bucket id, 34 bytes per string; that figure is
+# reported beside the model's 26.
 BYTES_PER_UNIT = {
-    "k_classify": 18.0,
-    "k_scatter": 34.0,
-    "k_base": 24.0,
-    "k_base_wave1": 24.0,
-    "k_base_wave2": 24.0,
-    "k_base_wave4": 24.0,
+    "k_classify": 11.0,
+    "k_scatter": 26.0,
+    "k_base": 21.0,
+    "k_base_wave1": 21.0,
+    "k_base_wave2": 21.0,
+    "k_base_wave4": 21.0,
     "k_scan": 12.0,
     "k_lcp_fill": 72.0,
 }
+SCATTER_IMPL_BYTES = 34.0
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def kernel_source_hash() -> str:
@@ -75,12 +84,49 @@ def measured_traffic(kernel: str, workload: str):
     return k.get("bytes_per_launch")
 
 
-def run_batch(args):
-    """Batched workload: 4096 independent sets (character budgets
+def event_ms(fn, reps, stream):
+    """Median milliseconds of fn() over reps runs, HIP events on `stream`
+    around each run (one warm-up run first)."""
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        fn()
+        b.record(stream)
+        b.synchronize()
+        ts.append(a.elapsed_time(b))
+    ts.sort()
+    return ts[len(ts) // 2]
+
+
+def wall_ms(fn, reps):
+    """Median wall milliseconds of fn() with the device synchronised around
+    each run (one warm-up run first)."""
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        ts.append((time.perf_counter() - a) * 1e3)
+    ts.sort()
+    return ts[len(ts) // 2]
+
+
+def batch_measure(steps, sets=4096, autotune=False):
+    """Batched workload: `sets` independent sets (character budgets
     log-uniform in [1e3, 1e6], model per set uniform over the four
-    generators).  Compares a loop of per-set ss_sort calls on one stream with
-    the batched forms (host-driven levels, one persistent launch, hipGraph of
-    the persistent launch).  All forms must give identical outputs."""
+    generators).  Times a loop of per-set ss_sort_ex calls on one stream
+    against the batched forms (device-driven levels, host-driven levels, one
+    persistent launch, the hipGraph); all forms must give identical
+    outputs.  Wall time with the device synchronised around each run."""
     import ctypes
 
     import numpy as np
@@ -90,9 +136,9 @@ def run_batch(args):
     import paper_1808_00963_amd as ss
 
     t0 = time.perf_counter()
-    c, o, sb = gen.batch_sets(num_sets=args.sets)
+    c, o, sb = gen.batch_sets(num_sets=sets)
     n, N, S = len(o) - 1, int(o[-1]), len(sb) - 1
-    print(f"[bench] batched workload: {S} sets, n={n} N={N} ({time.perf_counter() - t0:.1f}s)", file=sys.stderr, flush=True)
+    log(f"batched workload: {S} sets, n={n} N={N} ({time.perf_counter() - t0:.1f}s)")
     dev = torch.device("cuda:0")
     chars = torch.from_numpy(c).to(dev)
     offs = torch.from_numpy(o.view(np.int64)).to(dev)
@@ -102,19 +148,6 @@ def run_batch(args):
     ctx = ss.Context(0)
     lib = ss.lib()
     outs = {}
-
-    def timed(fn, reps):
-        fn()
-        torch.cuda.synchronize()
-        ts = []
-        for _ in range(reps):
-            torch.cuda.synchronize()
-            a = time.perf_counter()
-            fn()
-            torch.cuda.synchronize()
-            ts.append(time.perf_counter() - a)
-        return float(np.median(ts))
-
     perm = torch.empty(n, dtype=torch.int32, device=dev)
     lcp = torch.empty(n, dtype=torch.int32, device=dev)
     cp, op, pp, lp = chars.data_ptr(), offs.data_ptr(), perm.data_ptr(), lcp.data_ptr()
@@ -127,71 +160,73 @@ def run_batch(args):
             if st:
                 raise ss.SSError(st, "ss_sort_ex")
 
-    results = {}
+    ms = {}
     ctx.set_config(mode="levels")
-    results["per_set_launches"] = timed(per_set, max(1, args.steps // 4))
+    ms["per_set_launches"] = wall_ms(per_set, 1)
     outs["per_set_launches"] = (perm.clone(), lcp.clone())
-    results["batched_levels"] = timed(lambda: ctx.sort_batch(chars, offs, sbd, perm, lcp, stream), args.steps)
-    outs["batched_levels"] = (perm.clone(), lcp.clone())
-    ctx.set_config(mode="host_levels")
-    results["batched_host_levels"] = timed(lambda: ctx.sort_batch(chars, offs, sbd, perm, lcp, stream), args.steps)
-    outs["batched_host_levels"] = (perm.clone(), lcp.clone())
-    ctx.set_config(mode="persistent")
-    results["batched_persistent"] = timed(lambda: ctx.sort_batch(chars, offs, sbd, perm, lcp, stream), args.steps)
-    outs["batched_persistent"] = (perm.clone(), lcp.clone())
+    for form, mode in (("batched_levels", "levels"), ("batched_host_levels", "host_levels"),
+                       ("batched_persistent", "persistent")):
+        ctx.set_config(mode=mode)
+        ms[form] = wall_ms(lambda: ctx.sort_batch(chars, offs, sbd, perm, lcp, stream), steps)
+        outs[form] = (perm.clone(), lcp.clone())
     ctx.set_config(mode="levels")
     g = ctx.graph_batch(chars, offs, sbd, perm, lcp)
 
     def graph_run():
         g.launch(stream)
-        ctx.sync(stream)
 
-    results["batched_graph"] = timed(graph_run, args.steps)
+    ms["batched_graph"] = wall_ms(graph_run, steps)
+    ctx.sync(stream)
     outs["batched_graph"] = (perm.clone(), lcp.clone())
+    graph_levels = g.levels
     g.close()
-    # autotuned batched form: the tuner times its grid on this batch, then
-    # the chosen configuration is timed like the others
-    tctx = ss.Context(0)
-    t_a = time.perf_counter()
-    tuned_cfg, tuned_ms, _, _ = tctx.autotune(chars, offs, sbd, perm, lcp, reps=2, stream=stream)
-    tune_s = time.perf_counter() - t_a
-    results["batched_autotuned"] = timed(lambda: tctx.sort_batch(chars, offs, sbd, perm, lcp, stream), args.steps)
-    outs["batched_autotuned"] = (perm.clone(), lcp.clone())
+    tune = None
+    if autotune:
+        tctx = ss.Context(0)
+        t_a = time.perf_counter()
+        tuned_cfg, tuned_ms, _, _ = tctx.autotune(chars, offs, sbd, perm, lcp, reps=2, stream=stream)
+        tune_s = time.perf_counter() - t_a
+        ms["batched_autotuned"] = wall_ms(lambda: tctx.sort_batch(chars, offs, sbd, perm, lcp, stream), steps)
+        outs["batched_autotuned"] = (perm.clone(), lcp.clone())
+        tune = {"config": tuned_cfg, "tuner_median_ms": tuned_ms, "tuning_s": tune_s}
     ref = outs["per_set_launches"]
     identical = all(torch.equal(v[0], ref[0]) and torch.equal(v[1], ref[1]) for v in outs.values())
-    for k, v in results.items():
-        print(f"[bench] {k:22s} {v * 1e3:9.2f} ms  {N / v / 1e9:8.2f} G chars/s", file=sys.stderr, flush=True)
-    best = min(("batched_levels", "batched_host_levels", "batched_persistent", "batched_graph", "batched_autotuned"),
-               key=lambda k: results[k])
+    for k, v in ms.items():
+        log(f"{k:22s} {v:9.3f} ms  {N / v / 1e6:8.2f} G chars/s")
+    forms = [k for k in ms if k != "per_set_launches"]
+    best = min(forms, key=lambda k: ms[k])
+    del chars, offs, sbd, perm, lcp, outs
+    torch.cuda.empty_cache()
+    return {"sets": S, "n_strings": n, "n_chars": N, "ms": ms, "best_form": best,
+            "graph_level_launches": graph_levels,
+            "graph_vs_per_set": ms["per_set_launches"] / ms["batched_graph"],
+            "best_vs_per_set": ms["per_set_launches"] / ms[best],
+            "outputs_identical": identical, "autotune": tune}
+
+
+def run_batch(args):
+    r = batch_measure(args.steps, sets=args.sets, autotune=True)
+    best = r["best_form"]
     out = {
-        "metric": METRIC,
-        "value": N / results[best],
-        "unit": "chars/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": 1,
-        "ms_per_step": results[best] * 1e3,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "u8",
-        "data": "synthetic",
-        "config": {"workload": "batched_4096_sets", "sets": S, "n_strings": n, "n_chars": N, "form": best},
-        "batched_vs_per_set": results["per_set_launches"] / results[best],
-        "ms": {k: v * 1e3 for k, v in results.items()},
-        "outputs_identical": identical,
-        "autotune": {"config": tuned_cfg, "tuner_median_ms": tuned_ms, "tuning_s": tune_s},
+        "metric": METRIC, "value": r["n_chars"] / (r["ms"][best] * 1e-3), "unit": "chars/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": 1, "ms_per_step": r["ms"][best], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u8", "data": "synthetic",
+        "config": {"workload": "batched_4096_sets", "sets": r["sets"], "n_strings": r["n_strings"],
+                   "n_chars": r["n_chars"], "form": best},
+        "batched_vs_per_set": r["best_vs_per_set"], **r,
     }
     print(json.dumps(out), flush=True)
 
 
-def run_serve(args):
-    """Serving workload: a Poisson stream of sort requests, sizes log-uniform
-    in [1e3, 1e6] strings from the Markov generator, admitted by an 8 GB HBM
-    budget.  Saturation throughput mu is measured closed-loop first; the
-    open-loop runs at 0.5 mu and 0.8 mu report p50/p99 latency (submit ->
-    outputs on the host) and chars/s.  Requests cycle through a pool of
-    distinct pre-generated requests held in pinned host memory."""
+def serve_measure(pool_size=128, requests=2000, warmup=200, check=8):
+    """Serving workload: a Poisson stream of sort requests, sizes
+    log-uniform in [1e3, 1e6] strings from the Markov generator, admitted by
+    an 8 GB HBM budget.  Saturation throughput mu is measured closed-loop
+    first; open-loop runs at 0.5 mu and 0.8 mu report p50/p99 latency
+    (submit -> outputs on the host) and chars/s.  Requests cycle through a
+    pool of distinct pre-generated requests in pinned host memory.  After
+    the timed runs, `check` completed requests of the pool are verified
+    against the oracle (outside the timed region)."""
     import threading
 
     import numpy as np
@@ -200,7 +235,7 @@ def run_serve(args):
     import gen
     import paper_1808_00963_amd as ss
 
-    seed, P = 6, args.pool
+    seed, P = 6, pool_size
     t0 = time.perf_counter()
     pool = []
     for j in range(P):
@@ -213,24 +248,21 @@ def run_serve(args):
         pool.append((cp, op))
     sizes = np.array([len(o) - 1 for _, o in pool])
     chars_of = np.array([int(o[-1]) for _, o in pool])
-    print(f"[bench] serving pool: {P} requests, mean {sizes.mean():.0f} strings / {chars_of.mean() / 1e6:.2f} MB "
-          f"({time.perf_counter() - t0:.1f}s)", file=sys.stderr, flush=True)
+    log(f"serving pool: {P} requests, mean {sizes.mean():.0f} strings / {chars_of.mean() / 1e6:.2f} MB "
+        f"({time.perf_counter() - t0:.1f}s)")
     srv = ss.Server(8 << 30, max_inflight=4096)
-
-    # closed loop: keep the queue full, measure completions per second
     for j in range(min(P, 32)):
         srv.wait(srv.submit(*pool[j]))
     srv.reset_stats()
-    K = args.requests
     a = time.perf_counter()
-    tickets = [srv.submit(*pool[j % P]) for j in range(min(K, 600))]
+    tickets = [srv.submit(*pool[j % P]) for j in range(min(requests, 600))]
     for t in tickets:
         srv.wait(t)
     dt = time.perf_counter() - a
     mu = len(tickets) / dt
     sat = srv.stats()
-    print(f"[bench] saturation: {mu:.1f} req/s, {sat['chars_completed'] / dt / 1e9:.2f} G chars/s, "
-          f"inflight_max {sat['inflight_max']}", file=sys.stderr, flush=True)
+    log(f"saturation: {mu:.1f} req/s, {sat['chars_completed'] / dt / 1e9:.2f} G chars/s, "
+        f"inflight_max {sat['inflight_max']}")
 
     def open_loop(rate, n_req, warm):
         srv.reset_stats()
@@ -270,32 +302,38 @@ def run_serve(args):
 
     res = {}
     for frac in (0.5, 0.8):
-        r = open_loop(frac * mu, K + args.serve_warmup, args.serve_warmup)
+        r = open_loop(frac * mu, requests + warmup, warmup)
         res[str(frac)] = r
-        print(f"[bench] rate {frac:.1f} mu = {r['rate_req_s']:.1f} req/s: p50 {r['p50_ms']:.2f} ms, p99 "
-              f"{r['p99_ms']:.2f} ms, {r['chars_per_s'] / 1e9:.2f} G chars/s, inflight_max {r['inflight_max']}",
-              file=sys.stderr, flush=True)
+        log(f"rate {frac:.1f} mu = {r['rate_req_s']:.1f} req/s: p50 {r['p50_ms']:.2f} ms, p99 "
+            f"{r['p99_ms']:.2f} ms, {r['chars_per_s'] / 1e9:.2f} G chars/s, inflight_max {r['inflight_max']}")
+    # results checked outside the timed runs: a spread of pool requests,
+    # submitted together, each against the oracle's definition
+    import oracle
+    idx = sorted(range(P), key=lambda j: sizes[j])[:: max(1, P // check)][:check]
+    tk = [srv.submit(*pool[j]) for j in idx]
+    fails = []
+    for j, t in zip(idx, tk):
+        p, l, _ = srv.wait(t)
+        code = oracle.check(pool[j][0], pool[j][1], p, l)
+        if code != -1:
+            fails.append(f"request {j}: {oracle.describe_check(code, int(sizes[j]))}")
     srv.close()
-    main_r = res["0.8"]
+    log(f"serving results checked against the oracle: {len(idx)} requests, {len(fails)} failures")
+    return {"saturation_req_s": mu, "saturation_chars_per_s": sat["chars_completed"] / dt,
+            "open_loop": res, "pool": P, "mean_strings": float(sizes.mean()),
+            "checked_requests": len(idx), "check_failures": fails}
+
+
+def run_serve(args):
+    r = serve_measure(args.pool, args.requests, args.serve_warmup)
+    main_r = r["open_loop"]["0.8"]
     out = {
-        "metric": METRIC,
-        "value": main_r["chars_per_s"],
-        "unit": "chars/s",
-        "n_gpus": 1,
-        "steps": main_r["requests"],
-        "warmup": args.serve_warmup,
-        "ms_per_step": main_r["mean_ms"],
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "u8",
-        "data": "synthetic",
-        "config": {"workload": "serving_poisson_markov", "budget_bytes": 8 << 30, "pool": P,
+        "metric": METRIC, "value": main_r["chars_per_s"], "unit": "chars/s", "n_gpus": 1,
+        "steps": main_r["requests"], "warmup": args.serve_warmup, "ms_per_step": main_r["mean_ms"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u8", "data": "synthetic",
+        "config": {"workload": "serving_poisson_markov", "budget_bytes": 8 << 30, "pool": args.pool,
                    "sizes": "log-uniform 1e3..1e6 strings", "rate": "0.8 x saturation"},
-        "saturation_req_s": mu,
-        "p50_ms": main_r["p50_ms"],
-        "p99_ms": main_r["p99_ms"],
-        "open_loop": res,
+        "p50_ms": main_r["p50_ms"], "p99_ms": main_r["p99_ms"], **r,
     }
     print(json.dumps(out), flush=True)
 
@@ -561,6 +599,11 @@ def run_traffic(args):
         out["kernels"][k] = {"launches": L, "fetch_bytes_per_launch": d["fetch"] / L,
                              "write_bytes_per_launch": d["write"] / L,
                              "bytes_per_launch": (d["fetch"] + d["write"]) / L}
+    # the whole sort as one entry (every kernel of one sort)
+    tf = sum(d["fetch"] for d in kern.values())
+    tw = sum(d["write"] for d in kern.values())
+    out["kernels"]["__sort__"] = {"launches": 1, "fetch_bytes_per_launch": tf, "write_bytes_per_launch": tw,
+                                  "bytes_per_launch": tf + tw}
     with open(os.path.join(ROOT, "profiles", "traffic.json"), "w") as f:
         json.dump(out, f, indent=1)
     lines = [f"# HBM traffic per kernel launch from hardware counters, one full sort of {args.workload}.",
@@ -594,6 +637,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="c1_markov_16m")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="plain mode: only the headline workload")
     ap.add_argument("--sort-mode", default="levels", choices=["levels", "host_levels", "persistent"],
                     help="how the recursion levels are driven (ss_config.mode)")
     ap.add_argument("--cpu-sample", type=int, default=0,
@@ -623,93 +667,179 @@ def main():
         run_sa(args)
         return
 
+    run_plain(args)
+
+
+def alg_bytes(o, perm, lcp, dist_strings):
+    """The byte model of the method for one sort (algorithmic bytes, not the
+    traffic a kernel ends up causing):
+      B_min = 8 (n+1) offsets + sum_i 8 ceil(max(d_i, 1) / 8) distinguishing
+              prefix words + 8 n perm and LCP writes, with d_i = min(|s_i|,
+              max(lcp_i, lcp_{i+1}) + 1) from the output;
+      B_alg = B_min + 26 per string and distribution pass (idx u32, key u64,
+              r u8 read and written).
+    Re-gathers of equality buckets and base-case refinements are not
+    counted, so B_alg is a lower bound."""
+    import numpy as np
+    n = len(perm)
+    lens = np.diff(o.astype(np.int64))[perm.astype(np.int64)]
+    L = lcp.astype(np.int64)
+    nxt = np.append(L[1:], 0)
+    d = np.minimum(lens, np.maximum(L, nxt) + 1)
+    words = (np.maximum(d, 1) + 7) // 8
+    b_min = 8 * (n + 1) + 8 * int(words.sum()) + 8 * n
+    return b_min, b_min + 26 * int(dist_strings)
+
+
+def copy_bandwidth(nbytes=2 << 30, reps=5):
+    """Achievable HBM bandwidth: the library's streaming copy of `nbytes`,
+    read + write bytes over the median event time."""
+    import torch
+
+    import paper_1808_00963_amd as ss
+    src = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    src.fill_(1)
+    stream = torch.cuda.current_stream()
+    ms = event_ms(lambda: ss.hbm_copy(dst, src, stream), reps, stream)
+    ok = bool(torch.equal(dst[:: 1 << 20], src[:: 1 << 20]))
+    del src, dst
+    torch.cuda.empty_cache()
+    return {"bytes_each_way": nbytes, "ms": ms, "gbs": 2 * nbytes / (ms * 1e-3) / 1e9, "copied": ok}
+
+
+def sort_measure(workload, steps, warmup, mode="levels", breakdown=True, timed_kernel=None, cpu=False):
+    """One named workload: generation, warm-up sorts, a breakdown pass with
+    HIP events around every kernel launch (untimed), then the timed region
+    of `steps` complete sorts with events (on the sort's stream) only around
+    the launches of one kernel.  Returns timing, per-kernel breakdown,
+    statistics and the host copy of the output."""
     import numpy as np
     import torch
 
     import gen
     import paper_1808_00963_amd as ss
 
-    model, n, seed = gen.WORKLOADS[args.workload]
+    model, n, seed = gen.WORKLOADS[workload]
     t0 = time.perf_counter()
     c, o = gen.generate(model, n, seed)
     N = int(o[-1])
-    print(f"[bench] generated {args.workload}: n={n} N={N} in {time.perf_counter() - t0:.1f}s", file=sys.stderr, flush=True)
+    log(f"generated {workload}: n={n} N={N} in {time.perf_counter() - t0:.1f}s")
     dev = torch.device("cuda:0")
     chars = torch.from_numpy(c).to(dev)
     offs = torch.from_numpy(o.view(np.int64)).to(dev)
     perm = torch.empty(n, dtype=torch.int32, device=dev)
     lcp = torch.empty(n, dtype=torch.int32, device=dev)
     ctx = ss.Context(0)
-    ctx.set_config(mode=args.sort_mode)
+    ctx.set_config(mode=mode)
     stream = torch.cuda.current_stream()
-
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         ctx.sort(chars, offs, perm, lcp, stream=stream)
-    torch.cuda.synchronize()
+    ctx.sync(stream)
     stats = ctx.stats()
-
-    # breakdown pass (untimed): HIP events around every kernel launch
-    ctx.set_profiling(True)
-    ctx.reset_kernel_times()
-    for _ in range(args.steps):
-        ctx.sort(chars, offs, perm, lcp, stream=stream)
-    torch.cuda.synchronize()
-    ctx.set_profiling(False)
-    kt = ctx.kernel_times()
-    bpu = dict(BYTES_PER_UNIT)
-    L = np.diff(o)
-    bpu["k_init"] = 8.0 + float(np.minimum(L, 8).mean()) + 16.0
-    dom = max((k for k in kt if k in bpu and kt[k]["launches"]), key=lambda k: kt[k]["total_ms"])
-
-    # timed region: K complete sorts; HIP events (on the sort's stream) only
-    # around the launches of the dominant kernel
-    ctx.set_profiling(True, only=dom)
-    ctx.reset_kernel_times()
+    kt = {}
+    if breakdown:
+        ctx.set_profiling(True)
+        ctx.reset_kernel_times()
+        for _ in range(steps):
+            ctx.sort(chars, offs, perm, lcp, stream=stream)
+        torch.cuda.synchronize()
+        ctx.set_profiling(False)
+        kt = ctx.kernel_times()
+    if timed_kernel:
+        ctx.set_profiling(True, only=timed_kernel)
+        ctx.reset_kernel_times()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for _ in range(steps):
         ctx.sort(chars, offs, perm, lcp, stream=stream)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    ctx.set_profiling(False)
-    d = ctx.kernel_times()[dom]
+    ctx.sync(stream)
+    dk = None
+    if timed_kernel:
+        ctx.set_profiling(False)
+        dk = ctx.kernel_times()[timed_kernel]
+    sec = (t1 - t0) / steps
+    ph, lh = perm.cpu().numpy().view(np.uint32), lcp.cpu().numpy().view(np.uint32)
+    del chars, offs, perm, lcp, ctx
+    torch.cuda.empty_cache()
+    return {"workload": workload, "model": model, "seed": seed, "n": n, "N": N, "sec": sec, "stats": stats,
+            "kt": kt, "timed_kernel": dk, "chars": c, "offsets": o, "perm": ph, "lcp": lh}
 
-    sec = (t1 - t0) / args.steps
-    value = N / sec
-    strings_per_s = n / sec
 
-    # roofline of the dominant kernel, from the timed region's events
-    alg_bytes_per_launch = d["units"] / d["launches"] * bpu[dom]
-    avg_ms = d["total_ms"] / d["launches"]
-    achieved = alg_bytes_per_launch / (avg_ms * 1e-3) / 1e9
-    traffic = measured_traffic(dom, args.workload)
+def cpu_baselines(c, o, label):
+    """The oracle timed on the host: all cores (chunk sorts + pairwise
+    merges, the threads this process may use) and one thread, on the whole
+    workload.  Both results are checked against each other."""
+    import numpy as np
+
+    import oracle
+    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    if os.environ.get("OMP_NUM_THREADS", "").isdigit():
+        cores = min(cores, int(os.environ["OMP_NUM_THREADS"]))
+    N, n = int(o[-1]), len(o) - 1
+    t0 = time.perf_counter()
+    pm, lm = oracle.sort_mt(c, o, cores)
+    dt_mt = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    p1, l1 = oracle.sort(c, o)
+    dt_1 = time.perf_counter() - t0
+    same = bool(np.array_equal(pm, p1) and np.array_equal(lm, l1))
+    log(f"oracle: {cores} threads {dt_mt:.2f} s, 1 thread {dt_1:.2f} s, identical {same}")
+    mt = {"value": N / dt_mt, "unit": "chars/s", "cores": cores, "kind": "oracle",
+          "sample": f"all {n} strings ({N} chars) of {label}, chunk qsort+memcmp sorts on {cores} threads, "
+                    f"pairwise merges, brute LCP, {dt_mt:.2f} s", "strings_per_s": n / dt_mt}
+    one = {"value": N / dt_1, "unit": "chars/s", "cores": 1, "kind": "oracle",
+           "sample": f"all {n} strings of {label}, qsort+memcmp and brute LCP, 1 thread, {dt_1:.2f} s",
+           "strings_per_s": n / dt_1, "identical_to_all_cores": same}
+    return mt, one
+
+
+def run_plain(args):
+    """Default: the 16M-string Markov workload (the headline), plus the
+    other workloads as extra keys unless --no-extras."""
+    import numpy as np
+
+    bpu = dict(BYTES_PER_UNIT)
+    r = sort_measure(args.workload, args.steps, args.warmup, mode=args.sort_mode, timed_kernel="k_scatter")
+    n, N, sec, kt, stats = r["n"], r["N"], r["sec"], r["kt"], r["stats"]
+    L = np.diff(r["offsets"].astype(np.int64))
+    bpu["k_init"] = 8.0 + float(np.minimum(L, 8).mean()) + 13.0
     for k, v in sorted(kt.items(), key=lambda kv: -kv[1]["total_ms"]):
         if v["launches"]:
             per = v["total_ms"] / args.steps
             gbs = (v["units"] * bpu[k] / (v["total_ms"] * 1e-3) / 1e9) if k in bpu and v["total_ms"] else float("nan")
-            print(f"[bench] {k:12s} {per:8.3f} ms/step  launches/step {v['launches'] / args.steps:6.1f}  "
-                  f"{v['units'] / args.steps:12.0f} {v['unit']}/step  {gbs:8.1f} GB/s alg", file=sys.stderr)
+            log(f"{k:14s} {per:8.3f} ms/step  launches/step {v['launches'] / args.steps:6.1f}  "
+                f"{v['units'] / args.steps:12.0f} {v['unit']}/step  {gbs:8.1f} GB/s alg")
     kernel_ms = sum(v["total_ms"] for v in kt.values()) / args.steps
-    print(f"[bench] step {sec * 1e3:.3f} ms, kernels {kernel_ms:.3f} ms, stats {stats}", file=sys.stderr, flush=True)
-
-    # CPU baseline: the oracle as it is, single thread, on the host cores
-    cpu = None
+    log(f"step {sec * 1e3:.3f} ms, kernels {kernel_ms:.3f} ms, stats {stats}")
+    # roofline of the dominant kernel from the timed region's events
+    dom = "k_scatter"
+    d = r["timed_kernel"]
+    avg_ms = d["total_ms"] / d["launches"]
+    units_per_launch = d["units"] / d["launches"]
+    alg_per_launch = units_per_launch * bpu[dom]
+    achieved = alg_per_launch / (avg_ms * 1e-3) / 1e9
+    impl_achieved = units_per_launch * SCATTER_IMPL_BYTES / (avg_ms * 1e-3) / 1e9
+    traffic = measured_traffic(dom, args.workload)
+    # whole sort: the method's byte model and, when the committed counter
+    # summary matches these kernels, the counted bytes
+    dist_strings = kt.get("k_scatter", {}).get("units", 0.0) / max(1, args.steps)
+    b_min, b_alg = alg_bytes(r["offsets"], r["perm"], r["lcp"], dist_strings)
+    counted = measured_traffic("__sort__", args.workload)
+    whole = {"b_min": b_min, "b_alg": b_alg, "alg_frac": b_alg / sec / (HBM_PEAK_GBS * 1e9),
+             "counted_bytes": counted, "counted_frac": counted / sec / (HBM_PEAK_GBS * 1e9) if counted else None,
+             "amplification": counted / b_alg if counted else None,
+             "distribution_strings_per_sort": dist_strings}
+    copy = copy_bandwidth()
+    log(f"copy {copy['gbs']:.0f} GB/s; whole sort: B_alg {b_alg / 1e9:.3f} GB = {whole['alg_frac']:.3f} of peak")
+    cpu = cpu1 = None
     if not args.no_cpu_baseline:
-        import oracle
-        ns = n if args.cpu_sample <= 0 else min(n, args.cpu_sample)
-        oc = c[: int(o[ns])]
-        oo = o[: ns + 1]
-        t0 = time.perf_counter()
-        oracle.sort(oc, oo)
-        dt = time.perf_counter() - t0
-        cpu = {"value": int(oo[-1]) / dt, "unit": "chars/s", "cores": 1, "kind": "oracle",
-               "sample": f"first {ns} strings ({int(oo[-1])} chars) of {args.workload}, qsort+memcmp and brute LCP, "
-                         f"1 thread, {dt:.2f} s"}
-        print(f"[bench] oracle {dt:.2f}s on {ns} strings", file=sys.stderr, flush=True)
-
+        cpu, cpu1 = cpu_baselines(r["chars"], r["offsets"], args.workload)
     out = {
         "metric": METRIC,
-        "value": value,
+        "value": N / sec,
         "unit": "chars/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -720,19 +850,37 @@ def main():
         "vs_baseline": None,
         "dtype": "u8",
         "data": "synthetic",
-        "config": {"workload": args.workload, "model": model, "seed": seed, "n_strings": n, "n_chars": N,
-                   "parallelism": "single-gpu"},
-        "strings_per_s": strings_per_s,
-        "hbm_frac_alg_whole_sort": None,
+        "config": {"workload": args.workload, "model": r["model"], "seed": r["seed"], "n_strings": n, "n_chars": N,
+                   "parallelism": "single-gpu", "mode": args.sort_mode},
+        "strings_per_s": n / sec,
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "alg_bytes_per_launch": alg_bytes_per_launch, "avg_launch_ms": avg_ms},
+                     "alg_bytes_per_launch": alg_per_launch, "bytes_per_string": bpu[dom],
+                     "avg_launch_ms": avg_ms, "launches": d["launches"],
+                     "frac_impl_bytes": impl_achieved / HBM_PEAK_GBS, "impl_bytes_per_string": SCATTER_IMPL_BYTES},
+        "hbm_whole_sort": whole,
+        "copy_calibration": copy,
         "cpu_baseline": cpu,
+        "cpu_baseline_1thread": cpu1,
+        "stats": stats,
         "kernel_ms_per_step": {k: v["total_ms"] / args.steps for k, v in kt.items() if v["launches"]},
     }
-    # whole-sort algorithmic bytes over the step time
-    alg_total = sum(v["units"] * bpu[k] for k, v in kt.items() if k in bpu) / args.steps
-    out["hbm_frac_alg_whole_sort"] = alg_total / sec / (HBM_PEAK_GBS * 1e9)
+    del r
+    if not args.no_extras:
+        extras = {}
+        for w in ("c2a_urls_8m", "c2b_suffixes_2m", "c0_random_128k"):
+            e = sort_measure(w, args.steps, 2, mode=args.sort_mode, breakdown=True)
+            top = sorted(((k, v["total_ms"] / args.steps) for k, v in e["kt"].items() if v["launches"]),
+                         key=lambda kv: -kv[1])[:4]
+            extras[w] = {"ms_per_sort": e["sec"] * 1e3, "chars_per_s": e["N"] / e["sec"],
+                         "strings_per_s": e["n"] / e["sec"], "n_strings": e["n"], "n_chars": e["N"],
+                         "levels": e["stats"]["levels"], "top_kernels_ms": dict(top)}
+            log(f"{w}: {e['sec'] * 1e3:.3f} ms, {e['N'] / e['sec'] / 1e9:.1f} G chars/s, levels "
+                f"{e['stats']['levels']}, top {top}")
+            del e
+        extras["batched_4096_sets"] = batch_measure(max(4, args.steps // 2))
+        extras["serving"] = serve_measure(args.pool, args.requests, args.serve_warmup)
+        out["extras"] = extras
     print(json.dumps(out), flush=True)
 
 

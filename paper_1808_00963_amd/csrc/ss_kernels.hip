@@ -2133,15 +2133,33 @@ hipError_t launch_pend_swap(const Work& w, hipStream_t s) {
     return hipGetLastError();
 }
 
-// Plain streaming copy, 16 bytes per lane per iteration.
+// Plain streaming copy: every lane moves COPY_U 16-byte words per
+// iteration (all loads issued before the stores), grid-stride over the
+// buffer; the reference for the achievable HBM bandwidth and the kernel of
+// known traffic for counter calibration.
+constexpr uint32_t COPY_U = 4;
 __global__ __launch_bounds__(BLOCK) void k_copy(uint4* __restrict__ dst, const uint4* __restrict__ src, size_t n16) {
-    const size_t stride = (size_t)gridDim.x * BLOCK;
-    for (size_t i = (size_t)blockIdx.x * BLOCK + threadIdx.x; i < n16; i += stride) dst[i] = src[i];
+    const size_t stride = (size_t)gridDim.x * BLOCK * COPY_U;
+    for (size_t i0 = (size_t)blockIdx.x * BLOCK * COPY_U + threadIdx.x; i0 < n16; i0 += stride) {
+        uint4 v[COPY_U];
+#pragma unroll
+        for (uint32_t u = 0; u < COPY_U; ++u) {
+            const size_t i = i0 + (size_t)u * BLOCK;
+            if (i < n16) v[u] = src[i];
+        }
+#pragma unroll
+        for (uint32_t u = 0; u < COPY_U; ++u) {
+            const size_t i = i0 + (size_t)u * BLOCK;
+            if (i < n16) dst[i] = v[u];
+        }
+    }
 }
 
 hipError_t launch_copy(void* dst, const void* src, size_t n16, hipStream_t s) {
     if (n16 == 0) return hipSuccess;
-    const uint32_t nb = (uint32_t)std::min<size_t>((n16 + BLOCK - 1) / BLOCK, 256u * 32u);
+    // 16 groups of 256 lanes per compute unit at most: every lane then keeps
+    // four 16-byte loads in flight
+    const uint32_t nb = (uint32_t)std::min<size_t>((n16 + BLOCK * COPY_U - 1) / (BLOCK * COPY_U), 256u * 16u);
     hipLaunchKernelGGL(k_copy, dim3(nb), dim3(BLOCK), 0, s, (uint4*)dst, (const uint4*)src, n16);
     return hipGetLastError();
 }

@@ -157,3 +157,38 @@ def test_cancel_queued_request():
     st = srv.stats()
     assert st["cancelled"] == (1 if cancelled else 0)
     srv.close()
+
+
+def test_serving_workload_sizes_8gb_budget():
+    """Requests of the serving workload's sizes: Markov requests of 2e5 to
+    1e6 strings (the upper part of its log-uniform range) under its 8 GB
+    budget, submitted at once from three threads so that several are on the
+    device together, then again one at a time; every result equals the
+    oracle's check of that request, alone and in the mix identically, and
+    the admitted footprint never exceeds the budget."""
+    import paper_1808_00963_amd as ss
+    note("case serve workload sizes")
+    reqs = request_pool(10, seed=61, lo=2e5, hi=1e6)
+    reqs.append(gen.generate("markov", 1000000, gen.mix(61, 99)))  # the largest size exactly
+    srv = ss.Server(8 << 30, max_inflight=64)
+    tickets = [None] * len(reqs)
+
+    def submit(idx):
+        for i in idx:
+            tickets[i] = srv.submit(*reqs[i])
+    th = [threading.Thread(target=submit, args=(range(k, len(reqs), 3),)) for k in (0, 1, 2)]
+    [t.start() for t in th]
+    [t.join() for t in th]
+    mix = [srv.wait(t)[:2] for t in tickets]
+    st = srv.stats()
+    assert st["footprint_max"] <= 8 << 30
+    assert st["inflight_max"] >= 2
+    for i, (r, (p, l)) in enumerate(zip(reqs, mix)):
+        n = len(r[1]) - 1
+        assert 2e5 <= n <= 1e6
+        code = oracle.check(r[0], r[1], p, l)
+        assert code == -1, f"request {i} (n={n}) in the mix: {oracle.describe_check(code, n)}"
+    for i, r in enumerate(reqs[:4]):
+        p, l, _ = srv.wait(srv.submit(*r))
+        assert np.array_equal(p, mix[i][0]) and np.array_equal(l, mix[i][1]), f"request {i} alone vs mix"
+    srv.close()
