@@ -164,7 +164,11 @@ size_t layout(uint32_t n, const Caps& k, char* base, Work* w) {
     };
     size_t N = std::max<uint32_t>(n, 1);
     Work t{};
-    for (int i = 0; i < 2; ++i) t.buf[i] = (Elem*)take(sizeof(Elem) * N);
+    t.wide = N >= NARROW_MAX_N ? 1u : 0u;
+    for (int i = 0; i < 2; ++i) {
+        t.rec[i] = (Rec*)take(sizeof(Rec) * N);
+        t.rw[i] = t.wide ? (uint8_t*)take(N) : nullptr;
+    }
     t.bkt = (uint16_t*)take(sizeof(uint16_t) * N);
     for (int i = 0; i < 2; ++i) t.cnt[i] = (uint32_t*)take(sizeof(uint32_t) * k.cnt);
     t.partial = (uint32_t*)take(sizeof(uint32_t) * (k.cnt / 4096 + 4));

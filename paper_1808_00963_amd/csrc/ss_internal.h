@@ -6,14 +6,24 @@
 
 namespace ss {
 
-// One string in flight: its 8-byte key at the segment's depth, its index in
-// the input (global over a batch) and its length.  16 bytes, so loads and
-// stores are single dwordx4 accesses.
-struct alignas(16) Elem {
-    uint64_t key;
-    uint32_t idx;
-    uint32_t len;
+// A string in flight, one ping-pong buffer per recursion level parity
+// (section 4.2.8, "Out-of-place Redistribution"): its 8-byte key at the
+// segment's depth h (big-endian, zero padded), its index in the input
+// (global over a batch) and r = min(len - h, 8), the characters of the
+// string inside the key (0 is a character, so r tells a string that ends
+// inside the word from one with zero bytes there).  12 bytes, moved as one
+// 3-dword access: with fewer than 2^28 strings r sits in the top 4 bits of
+// the index word; wider sorts keep the whole index there and r in a side
+// byte array.  The length itself is re-read from the offsets where a key is
+// gathered again deeper.
+struct Rec {
+    uint32_t klo, khi;  // key
+    uint32_t ix;        // index | r << IX_BITS (narrow), index (wide)
 };
+static_assert(sizeof(Rec) == 12, "12-byte records");
+constexpr uint32_t IX_BITS = 28;
+constexpr uint32_t IX_MASK = (1u << IX_BITS) - 1;
+constexpr uint32_t NARROW_MAX_N = 1u << IX_BITS;  // sorts of fewer strings are narrow
 
 // A segment of the ping-pong element array that still needs a distribution
 // step (sample, classify, scatter; Algorithm 4.1).  All its strings share a
@@ -198,7 +208,9 @@ struct Caps {
 
 // Pointers to the workspace of one sort.
 struct Work {
-    Elem* buf[2];
+    Rec* rec[2];
+    uint8_t* rw[2];      // wide layout: r of each position (else null)
+    uint32_t wide;       // 1: the index word holds the whole index
     uint16_t* bkt;
     uint32_t* cnt[2];
     uint32_t* partial;

@@ -24,6 +24,35 @@ __device__ __forceinline__ void raise_err(const Work& w, uint32_t bits) {
     atomicOr(&w.ctl->err, bits);
     atomicOr(&w.ctl->err_sticky, bits);
 }
+// Record fields (Rec: narrow records keep r in the top bits of the index
+// word, wide ones in the side array rw).
+__device__ __forceinline__ uint64_t rec_key(const Rec& x) { return (uint64_t)x.klo | (uint64_t)x.khi << 32; }
+__device__ __forceinline__ uint32_t rec_idx(const Work& w, const Rec& x) { return w.wide ? x.ix : x.ix & IX_MASK; }
+__device__ __forceinline__ uint32_t rec_r(const Work& w, const Rec& x, int buf, uint32_t i) {
+    return w.wide ? (uint32_t)w.rw[buf][i] : x.ix >> IX_BITS;
+}
+__device__ __forceinline__ Rec rec_make(const Work& w, uint64_t key, uint32_t idx, uint32_t r) {
+    Rec x;
+    x.klo = (uint32_t)key;
+    x.khi = (uint32_t)(key >> 32);
+    x.ix = w.wide ? idx : idx | r << IX_BITS;
+    return x;
+}
+__device__ __forceinline__ void rec_put(const Work& w, int buf, uint32_t i, uint64_t key, uint32_t idx, uint32_t r) {
+    w.rec[buf][i] = rec_make(w, key, idx, r);
+    if (w.wide) w.rw[buf][i] = (uint8_t)r;
+}
+
+// A string of an equality bucket moves on to depth h: its key there and the
+// number of its characters inside that key, from its offsets (the length is
+// not carried with the record).
+__device__ __forceinline__ void regather(const Params& p, uint32_t idx, uint32_t h, uint64_t& key, uint32_t& r) {
+    const uint64_t o0 = p.offsets[idx], o1 = p.offsets[idx + 1];
+    const uint32_t len = (uint32_t)(o1 - o0);
+    key = gather_key(p.chars, o0, h, len);
+    r = len > h ? min_u32(len - h, W) : 0u;
+}
+
 // Two counters in one 64-bit atomic word (low, high); neither half of a
 // level's counters reaches 2^32, so no carry crosses.
 __device__ __forceinline__ unsigned long long pack2(uint32_t lo, uint32_t hi) {
@@ -145,11 +174,11 @@ __device__ void note_level(const Work& w, const Counts& c, uint32_t level) {
 // `nxt`: a single string is final at once, small segments go to the base
 // case, larger ones get a distribution step with its tree, counters and
 // tiles reserved here.
-__device__ void emit_segment(const Work& w, const Params& p, int nxt, const Elem* buf, uint32_t begin,
+__device__ void emit_segment(const Work& w, const Params& p, int nxt, int buf, uint32_t begin,
                              uint32_t size, uint32_t depth, uint32_t rid) {
     if (size == 0) return;
     if (size == 1) {
-        p.perm[begin] = buf[begin].idx - w.set_base[rid];
+        p.perm[begin] = rec_idx(w, w.rec[buf][begin]) - w.set_base[rid];
         if (w.remaining) atomicSub(&w.remaining[rid], 1u);
         return;
     }
@@ -310,11 +339,7 @@ __device__ __forceinline__ void dev_init_one(const Work& w, const Params& p, uin
     uint32_t len = 0;
     if (o1 < o0 || o1 - o0 > MAX_LEN || (o1 > o0 && p.chars == nullptr)) raise_err(w, ERR_OFFSETS);
     else len = (uint32_t)(o1 - o0);
-    Elem e;
-    e.key = gather_key(p.chars, o0, 0, len);
-    e.idx = i;
-    e.len = len;
-    w.buf[0][i] = e;
+    rec_put(w, 0, i, gather_key(p.chars, o0, 0, len), i, min_u32(len, W));
 }
 
 __global__ __launch_bounds__(BLOCK) void k_init(Work w, Params p) {
@@ -340,7 +365,7 @@ __device__ __forceinline__ void dev_root_one(const Work& w, const Params& p, con
         if (w.remaining) atomicSub(&w.remaining[set_begin ? j : 0u], 1u);
         return;
     }
-    emit_segment(w, p, 0, w.buf[0], b, e - b, 0, set_begin ? j : 0u);
+    emit_segment(w, p, 0, 0, b, e - b, 0, set_begin ? j : 0u);
 }
 
 __global__ void k_roots(Work w, Params p, const uint32_t* set_begin, uint32_t num_sets) {
@@ -540,15 +565,15 @@ __device__ void dev_base_wave(const Work& w, const Params& p, int cur, int cls, 
         if (lane == 0) raise_err(w, ERR_BOUNDS);
         return;
     }
-    const Elem* in = w.buf[cur] + sg.begin;
+    const Rec* in = w.rec[cur] + sg.begin;
     uint64_t K[E], A[E];
     uint32_t D[E], LV[E];
 #pragma unroll
     for (uint32_t r = 0; r < (uint32_t)E; ++r) {
         const uint32_t e = lane * E + r;
         if (e < m) {
-            Elem x = in[e];
-            pr_pack(0, x.key, rem8(x.len, h), x.idx, K[r], A[r]);
+            const Rec x = in[e];
+            pr_pack(0, rec_key(x), rec_r(w, x, cur, sg.begin + e), rec_idx(w, x), K[r], A[r]);
         } else {
             K[r] = ~0ull;
             A[r] = ~0ull;
@@ -787,11 +812,11 @@ __device__ void dev_base_wg(const Work& w, const Params& p, int cur, uint32_t it
     }
     uint32_t P = 256;  // whole blocks of the block sort
     while (P < m) P <<= 1;
-    const Elem* in = w.buf[cur] + sg.begin;
+    const Rec* in = w.rec[cur] + sg.begin;
     for (uint32_t i = tid; i < P; i += BLOCK) {
         if (i < m) {
-            Elem e = in[i];
-            pr_pack(0, e.key, rem8(e.len, h), e.idx, K[i], A[i]);
+            const Rec x = in[i];
+            pr_pack(0, rec_key(x), rec_r(w, x, cur, sg.begin + i), rec_idx(w, x), K[i], A[i]);
         } else {
             K[i] = ~0ull;
             A[i] = ~0ull;
@@ -931,7 +956,7 @@ __device__ __forceinline__ void sample_sort(const Work& w, const Params& p, int 
                                             uint32_t NB, bool root_keys, SmSample& sm) {
     constexpr uint32_t R = 64u * E;  // records per block
     const uint32_t tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const Elem* in = w.buf[cur];
+    const Rec* in = w.rec[cur];
     uint64_t K[E], A[E];
     for (uint32_t b = wv; b < NB; b += WAVES) {  // uniform per wave
 #pragma unroll
@@ -942,18 +967,19 @@ __device__ __forceinline__ void sample_sort(const Work& w, const Params& p, int 
             if (j < a) {
                 const uint32_t pos = sg.begin + (uint32_t)(((2ull * j + 1) * sg.size) / (2ull * a));
                 uint64_t key;
-                uint32_t len;
+                uint32_t rr;
                 if (root_keys) {  // a root segment: position = string, depth 0, key read as k_init does
                     const uint64_t o0 = p.offsets[pos], o1 = p.offsets[pos + 1];
                     const bool bad = o1 < o0 || o1 - o0 > MAX_LEN || (o1 > o0 && p.chars == nullptr);
-                    len = bad ? 0u : (uint32_t)(o1 - o0);
+                    const uint32_t len = bad ? 0u : (uint32_t)(o1 - o0);
                     key = gather_key(p.chars, o0, 0, len);
+                    rr = min_u32(len, W);
                 } else {
-                    const Elem e = in[pos];
-                    key = e.key;
-                    len = e.len;
+                    const Rec x = in[pos];
+                    key = rec_key(x);
+                    rr = rec_r(w, x, cur, pos);
                 }
-                pr_pack(0, key, rem8(len, sg.depth), j, K[r], A[r]);
+                pr_pack(0, key, rr, j, K[r], A[r]);
             }
         }
         wave_bitonic<E>(K, A, lane, NB > 1 ? b * R : 0u);
@@ -1118,7 +1144,7 @@ __device__ void dev_classify(const Work& w, const Params& p, int cur, uint32_t t
     for (uint32_t q = 1 + tid; q <= v; q += BLOCK) { TK[q] = gk[q - 1]; TR[q] = gr[q - 1]; }
     for (uint32_t b = tid; b < k; b += BLOCK) H[b] = 0;
     __syncthreads();
-    const Elem* in = w.buf[cur];
+    const Rec* in = w.rec[cur];
     constexpr uint32_t U = 4;  // strings per thread and step, descents interleaved
     for (uint32_t i0 = start + tid; i0 < end; i0 += U * BLOCK) {
         uint64_t c[U];
@@ -1129,9 +1155,9 @@ __device__ void dev_classify(const Work& w, const Params& p, int cur, uint32_t t
             c[u] = 0;
             cr[u] = 0;
             if (i < end) {
-                const Elem e = in[i];
-                c[u] = e.key;
-                cr[u] = rem8(e.len, sg.depth);
+                const Rec x = in[i];
+                c[u] = rec_key(x);
+                cr[u] = rec_r(w, x, cur, i);
             }
         }
         classify_n<U>(c, cr, TK, TR, d, b);
@@ -1346,28 +1372,30 @@ __device__ void dev_scatter(const Work& w, const Params& p, int cur, uint32_t t,
     }
     __syncthreads();
     // phase 3: move
-    const Elem* in = w.buf[cur];
-    Elem* out = w.buf[cur ^ 1];
+    const Rec* in = w.rec[cur];
     const uint32_t seg_end = sg.begin + sg.size;
     const uint32_t obase = w.set_base[sg.rid];
 #pragma unroll 4
     for (uint32_t it = 0; it < IPT; ++it) {
         const uint32_t i = cbeg + it * 64 + lane;
         if (i >= end) continue;
-        Elem e = in[i];
+        const Rec x = in[i];
+        uint64_t key = rec_key(x);
+        const uint32_t idx = rec_idx(w, x);
+        uint32_t rr = rec_r(w, x, cur, i);
         const uint32_t b = w.bkt[i], rank = (rank2[it >> 1] >> (16 * (it & 1))) & 0xFFFFu;
         const uint32_t pos = WC[wv][b] + rank;
         if (pos < sg.begin || pos >= seg_end) { raise_err(w, ERR_BOUNDS); continue; }
         if (b & 1u) {
             const uint32_t rx = gr[level_index(b >> 1, d) - 1];
             if (rx < W) {  // identical strings ending inside this word: final
-                p.perm[pos] = e.idx - obase;
+                p.perm[pos] = idx - obase;
                 if (pos != sg.begin + sc[(size_t)b * T] - s0) p.lcp[pos] = sg.depth + rx;
                 continue;
             }
-            e.key = gather_key(p.chars, p.offsets[e.idx], sg.depth + W, e.len);
+            regather(p, idx, sg.depth + W, key, rr);
         }
-        out[pos] = e;
+        rec_put(w, cur ^ 1, pos, key, idx, rr);
     }
 }
 
@@ -1388,6 +1416,8 @@ __device__ void dev_scatter(const Work& w, const Params& p, int cur, uint32_t t,
 //      delta[b] + j where delta[b] = global start of (b, tile) + the first
 //      half's count of b (second half only) - first slot.
 constexpr uint32_t SC_TILE = TILE / 2;
+constexpr uint32_t SB_R = 12;  // r sits above the 11 bits of a bucket id in a staged slot
+static_assert(2 * MAX_BUCKETS < (1u << SB_R) && (W << SB_R) < (1u << 16), "slot word layout");
 constexpr uint32_t SC_THREADS = 1024, SC_WAVES = SC_THREADS / 64, SC_PER = SC_TILE / SC_THREADS;
 static_assert(SC_PER * SC_THREADS == SC_TILE && MAX_BUCKETS < 2 * SC_THREADS, "scatter tile shape");
 static_assert(SC_TILE >= 2 * (MAX_BUCKETS + 1) && SC_WAVES * 4 <= (MAX_BUCKETS + 1),
@@ -1395,11 +1425,12 @@ static_assert(SC_TILE >= 2 * (MAX_BUCKETS + 1) && SC_WAVES * 4 <= (MAX_BUCKETS +
 struct SmScatterTile {
     union {
         uint16_t WC[SC_WAVES][MAX_BUCKETS + 1];  // per-wave counts, then per-wave first slots
-        uint4 stage[SC_TILE];                    // the half tile's records in bucket order
+        Rec stage[SC_TILE];                      // the half tile's records in bucket order
     };
-    // bucket of each slot (staging); before staging, its first 64 bytes
-    // hold the wave sums and its second half the first half's bucket counts
-    // (two 16-bit counts per word)
+    // bucket | r << SB_R of each slot (staging; r is needed there by wide
+    // records only); before staging, its first 64 bytes hold the wave sums
+    // and its second half the first half's bucket counts (two 16-bit counts
+    // per word)
     uint16_t sb[SC_TILE];
     uint32_t delta[MAX_BUCKETS + 1];    // tile totals, then global position - slot
 };
@@ -1430,19 +1461,19 @@ __device__ void dev_scatter_half(const Work& w, const Params& p, int cur, uint32
     const uint32_t m = end - start;
     if (m == 0) return;  // the second half of a tile of at most SC_TILE strings (uniform)
     // 1. loads (all issued before any use)
-    static_assert(sizeof(Elem) == sizeof(uint4), "records move as 16-byte words");
-    const uint4* in = (const uint4*)(w.buf[cur] + start);
+    const Rec* in = w.rec[cur] + start;
     const uint32_t c0 = wv * (SC_TILE / SC_WAVES);  // the wave's chunk in the half tile
-    uint4 e[SC_PER];
-    uint32_t bk[SC_PER];
+    Rec e[SC_PER];
+    uint32_t bk[SC_PER];  // bucket id in bits 0..15 (0xFFFF: no record), r above
 #pragma unroll
     for (uint32_t r = 0; r < SC_PER; ++r) {
         const uint32_t q = c0 + r * 64 + lane;
         bk[r] = 0xFFFFu;
-        e[r] = make_uint4(0, 0, 0, 0);
+        e[r] = Rec{0, 0, 0};
         if (q < m) {
             e[r] = in[q];
-            bk[r] = w.bkt[start + q];
+            bk[r] = (uint32_t)w.bkt[start + q];
+            if (w.wide) bk[r] |= (uint32_t)w.rw[cur][start + q] << 16;
         }
     }
     // the per-wave counts are handled two buckets per 32-bit word (16-bit
@@ -1463,7 +1494,7 @@ __device__ void dev_scatter_half(const Work& w, const Params& p, int cur, uint32
     uint32_t rank[SC_PER];
 #pragma unroll
     for (uint32_t r = 0; r < SC_PER; ++r) {
-        const uint32_t b = bk[r];
+        const uint32_t b = bk[r] & 0xFFFFu;
         const bool valid = b != 0xFFFFu;
         uint64_t peers = __ballot(valid);
 #pragma unroll
@@ -1520,17 +1551,18 @@ __device__ void dev_scatter_half(const Work& w, const Params& p, int cur, uint32
     // 4. records to their slots, then out in slot order
     uint32_t slot[SC_PER];
 #pragma unroll
-    for (uint32_t r = 0; r < SC_PER; ++r) slot[r] = bk[r] != 0xFFFFu ? sm.WC[wv][bk[r]] + rank[r] : 0u;
+    for (uint32_t r = 0; r < SC_PER; ++r)
+        slot[r] = (bk[r] & 0xFFFFu) != 0xFFFFu ? sm.WC[wv][bk[r] & 0xFFFFu] + rank[r] : 0u;
     __syncthreads();  // WC is overwritten by the staged records
 #pragma unroll
     for (uint32_t r = 0; r < SC_PER; ++r) {
-        if (bk[r] == 0xFFFFu) continue;
+        if ((bk[r] & 0xFFFFu) == 0xFFFFu) continue;
         if (slot[r] >= m) { raise_err(w, ERR_BOUNDS); continue; }
         sm.stage[slot[r]] = e[r];
-        sm.sb[slot[r]] = (uint16_t)bk[r];
+        sm.sb[slot[r]] = (uint16_t)((bk[r] & 0xFFFFu) | (bk[r] >> 16) << SB_R);
     }
     __syncthreads();
-    uint4* out = (uint4*)w.buf[cur ^ 1];
+    Rec* out = w.rec[cur ^ 1];
     const uint32_t seg_end = sg.begin + sg.size;
     const uint32_t obase = w.set_base[sg.rid];
     const uint8_t* gr = w.tree_r[cur] + sg.tree_off;
@@ -1538,20 +1570,26 @@ __device__ void dev_scatter_half(const Work& w, const Params& p, int cur, uint32
     for (uint32_t r = 0; r < SC_PER; ++r) {
         const uint32_t j = r * SC_THREADS + tid;
         if (j >= m) break;
-        const uint32_t b = sm.sb[j];
-        uint4 x = sm.stage[j];  // key (x, y), idx (z), len (w)
+        const uint32_t sbw = sm.sb[j];
+        const uint32_t b = sbw & ((1u << SB_R) - 1);
+        Rec x = sm.stage[j];
         const uint32_t pos = sm.delta[b] + j;
         if (pos < sg.begin || pos >= seg_end) { raise_err(w, ERR_BOUNDS); continue; }
         if (b & 1u) {
             const uint32_t rx = gr[level_index(b >> 1, d) - 1];
+            const uint32_t idx = rec_idx(w, x);
             if (rx < W) {  // identical strings ending inside this word: final
-                p.perm[pos] = x.z - obase;
+                p.perm[pos] = idx - obase;
                 if (pos != sg.begin + sc[(size_t)b * T] - s0) p.lcp[pos] = sg.depth + rx;
                 continue;
             }
-            const uint64_t key = gather_key(p.chars, p.offsets[x.z], sg.depth + W, x.w);
-            x.x = (uint32_t)key;
-            x.y = (uint32_t)(key >> 32);
+            uint64_t key;
+            uint32_t rr;
+            regather(p, idx, sg.depth + W, key, rr);
+            x = rec_make(w, key, idx, rr);
+            if (w.wide) w.rw[cur ^ 1][pos] = (uint8_t)rr;
+        } else if (w.wide) {
+            w.rw[cur ^ 1][pos] = (uint8_t)(sbw >> SB_R);
         }
         out[pos] = x;
     }
@@ -1563,7 +1601,7 @@ __device__ void dev_scatter_half(const Work& w, const Params& p, int cur, uint32
 // L2.  A loop over several items here would cost the body two of its four
 // waves per SIMD (values of the loop would be held in registers), so the
 // half tiles beyond the grid are left to k_scatter_more.
-__global__ __launch_bounds__(SC_THREADS) void k_scatter(Work w, Params p, int cur) {
+__global__ __launch_bounds__(SC_THREADS) __attribute__((amdgpu_waves_per_eu(8))) void k_scatter(Work w, Params p, int cur) {
     __shared__ SmScatterTile sm;
     const uint32_t n_half = 2 * n_tiles_of(w, cur);
     const uint32_t m = min_u32(gridDim.x, n_half);
@@ -1637,7 +1675,7 @@ __device__ void dev_children(const Work& w, const Params& p, int cur, uint32_t i
     for (uint32_t b = lo + tid; b <= hi; b += BLOCK) sm.ST[b - lo] = b < k ? sc[(size_t)b * T] - s0 : sg.size;
     __syncthreads();
     const uint8_t* gr = w.tree_r[cur] + sg.tree_off;
-    const Elem* out = w.buf[nxt];
+    const Rec* out = w.rec[nxt];
     const uint32_t obase = w.set_base[sg.rid];
     // bucket b -> (start, count, child depth); depth == ~0u: no child segment
     auto bucket = [&](uint32_t b, uint32_t& st, uint32_t& cnt, uint32_t& depth) {
@@ -1670,7 +1708,7 @@ __device__ void dev_children(const Work& w, const Params& p, int cur, uint32_t i
             continue;
         }
         if (cnt == 1) {
-            p.perm[pos] = out[pos].idx - obase;
+            p.perm[pos] = rec_idx(w, out[pos]) - obase;
             if (w.remaining) atomicSub(&w.remaining[sg.rid], 1u);
             continue;
         }
@@ -1965,17 +2003,13 @@ __global__ __launch_bounds__(BLOCK) void k_admit_init(Work w, Params p, int cur,
     uint32_t len = 0;
     if (o1 < o0 || o1 - o0 > MAX_LEN) raise_err(w, ERR_OFFSETS);
     else len = (uint32_t)(o1 - o0);
-    Elem e;
-    e.key = gather_key(p.chars, o0, 0, len);
-    e.idx = g;
-    e.len = len;
-    w.buf[cur][g] = e;
+    rec_put(w, cur, g, gather_key(p.chars, o0, 0, len), g, min_u32(len, W));
 }
 
 __global__ void k_admit_root(Work w, Params p, int cur, uint32_t pos, uint32_t m, uint32_t rid) {
     if (threadIdx.x != 0) return;
     if (m) p.lcp[pos] = 0;
-    emit_segment(w, p, cur, w.buf[cur], pos, m, 0, rid);
+    emit_segment(w, p, cur, cur, pos, m, 0, rid);
 }
 
 __global__ __launch_bounds__(BLOCK) void k_pend_filter(Work w, Params p) {
