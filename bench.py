@@ -621,12 +621,67 @@ def run_traffic(args):
     print(json.dumps({"mode": "traffic", "kernels": len(kern)}))
 
 
+def run_counters(args):
+    """Per-kernel sums of hardware counters over the last sort of a
+    `--mode profile` run (rocprofv3 --pmc ... --output-format csv), one or
+    more counter CSVs, written to profiles/counters_<workload>.txt with the
+    per-wave figures (counter / SQ_WAVES) where SQ_WAVES was collected."""
+    import csv
+
+    per = {}   # dispatch id -> (kernel, {counter: value})
+    for path in args.csv:
+        with open(path) as f:
+            for r in csv.DictReader(f):
+                did = (path, int(r["Dispatch_Id"]))
+                e = per.setdefault(did, [r["Kernel_Name"], {}])
+                e[1][r["Counter_Name"]] = e[1].get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+    kern = {}
+    counters = []
+    for path in args.csv:
+        rows = [per[k] for k in sorted(k for k in per if k[0] == path)]
+        starts = [i for i, (name, _) in enumerate(rows) if "k_reset" in name]
+        for name, vals in rows[starts[-1]:] if starts else rows:
+            base = name.split("(")[0].replace("void ", "").replace("ss::", "")
+            d = kern.setdefault(base, {})
+            for c, v in vals.items():
+                if c not in counters:
+                    counters.append(c)
+                d[c] = d.get(c, 0.0) + v
+    lines = [f"# Hardware counters summed per kernel over one sort of {args.workload}.",
+             "# Commands (from /tmp, TMPDIR=/tmp), one counter group per run:"]
+    lines += [f"#   rocprofv3 --pmc {g} --output-format csv -d <out> -o run -- "
+              "python3 bench.py --mode profile --steps 1 --warmup 1" for g in args.groups or []]
+    lines += ["# then: python3 bench.py --mode counters --csv <csv> [--csv <csv> ...]",
+              "# Rows: kernel; columns: counter totals (and per wave, /w, where SQ_WAVES was collected)", ""]
+    hdr = f"{'kernel':16s}" + "".join(f" {c[:22]:>22s}" for c in counters)
+    lines.append(hdr)
+    order = sorted(kern, key=lambda k: -kern[k].get("SQ_WAVES", 0.0))
+    for k in order:
+        d = kern[k]
+        cells = []
+        for c in counters:
+            v = d.get(c)
+            if v is None:
+                cells.append(f" {'-':>22s}")
+            elif "SQ_WAVES" in d and c != "SQ_WAVES" and d["SQ_WAVES"] > 0:
+                cells.append(f" {v:12.4g} {v / d['SQ_WAVES']:7.1f}/w")
+            else:
+                cells.append(f" {v:22.4g}")
+        lines.append(f"{k[:16]:16s}" + "".join(cells))
+    out = os.path.join(ROOT, "profiles", f"counters_{args.workload}.txt")
+    with open(out, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--mode", choices=["plain", "batch", "serve", "profile", "traffic", "merge", "sa"], default="plain")
+    ap.add_argument("--mode", choices=["plain", "batch", "serve", "profile", "traffic", "counters", "merge", "sa"], default="plain")
     ap.add_argument("--fetch-csv", help="traffic mode: rocprofv3 counter_collection.csv of the FETCH_SIZE run")
     ap.add_argument("--write-csv", help="traffic mode: rocprofv3 counter_collection.csv of the WRITE_SIZE run")
+    ap.add_argument("--csv", action="append", help="counters mode: a rocprofv3 counter_collection.csv")
+    ap.add_argument("--groups", action="append", help="counters mode: the --pmc counter list of each run")
     ap.add_argument("--pool", type=int, default=128)
     ap.add_argument("--runs", type=int, default=2, help="merge mode: number of sorted runs")
     ap.add_argument("--sa-n", type=int, default=1 << 24, help="sa mode: text length")
@@ -659,6 +714,9 @@ def main():
         return
     if args.mode == "traffic":
         run_traffic(args)
+        return
+    if args.mode == "counters":
+        run_counters(args)
         return
     if args.mode == "merge":
         run_merge(args)

@@ -494,6 +494,79 @@ __device__ __forceinline__ void wave_merge_tail(uint64_t (&K)[E], uint64_t (&A)[
     for (uint32_t j = 32u * E; j > 0; j >>= 1) wave_stage<E>(K, A, lane, base, k, j);
 }
 
+// The same network on records packed into one 64-bit word: one compare and
+// half the exchanges of the two-word form.
+template <int E>
+__device__ __forceinline__ void wave_stage1(uint64_t (&K)[E], uint32_t lane, uint32_t base, uint32_t k, uint32_t j) {
+    if (j < (uint32_t)E) {
+#pragma unroll
+        for (uint32_t r = 0; r < (uint32_t)E; ++r) {
+            if ((r & j) == 0) {
+                const uint32_t r2 = r | j;
+                const uint32_t e = base + lane * E + r;
+                const bool up = (e & k) == 0;
+                const uint64_t a = K[r], b = K[r2];
+                if ((a > b) == up) { K[r] = b; K[r2] = a; }
+            }
+        }
+    } else {
+        const uint32_t lj = j / E;
+#pragma unroll
+        for (uint32_t r = 0; r < (uint32_t)E; ++r) {
+            const uint32_t e = base + lane * E + r;
+            const uint64_t pk = xlane(K[r], lj);
+            const bool keep_min = ((e & j) == 0) == ((e & k) == 0);
+            if ((K[r] > pk) == keep_min) K[r] = pk;
+        }
+    }
+}
+template <int E>
+__device__ __forceinline__ void wave_bitonic1(uint64_t (&K)[E], uint32_t lane, uint32_t base = 0) {
+#pragma unroll
+    for (uint32_t k = 2; k <= 64u * E; k <<= 1) {
+#pragma unroll
+        for (uint32_t j = k >> 1; j > 0; j >>= 1) wave_stage1<E>(K, lane, base, k, j);
+    }
+}
+template <int E>
+__device__ __forceinline__ void wave_merge_tail1(uint64_t (&K)[E], uint32_t lane, uint32_t base, uint32_t k) {
+#pragma unroll
+    for (uint32_t j = 32u * E; j > 0; j >>= 1) wave_stage1<E>(K, lane, base, k, j);
+}
+
+// Bitwise OR over the 64 lanes of a wave (every lane gets the result).
+__device__ __forceinline__ uint64_t wave_or64(uint64_t x) {
+    x |= xlane64<1>(x);
+    x |= xlane64<2>(x);
+    x |= xlane64<4>(x);
+    x |= xlane64<8>(x);
+    x |= xlane64<16>(x);
+    x |= xlane64<32>(x);
+    return x;
+}
+__device__ __forceinline__ uint64_t uniform64(uint64_t x) {
+    return (uint64_t)uniform((uint32_t)x) | (uint64_t)uniform((uint32_t)(x >> 32)) << 32;
+}
+
+// One-word sort records of a base case whose keys share their first c >= 2
+// bytes: the key bits below the shared bytes, then r (4 bits), then the
+// record's position in the segment (PB bits).  Keys that are equal with
+// equal r are identical strings (r < 8) or a tie to refine (r = 8); either
+// way the position orders them as the index does, because every
+// distribution pass keeps the input order inside a bucket, and the input
+// order of a segment's records is ascending in index.
+__device__ __forceinline__ uint64_t shl_key(uint64_t x, uint32_t s) { return s < 64 ? x << s : 0ull; }
+__device__ __forceinline__ uint64_t shr_key(uint64_t x, uint32_t s) { return s < 64 ? x >> s : 0ull; }
+__device__ __forceinline__ uint64_t p1_pack(uint64_t key, uint32_t r, uint32_t pos, uint32_t sh, uint32_t pb) {
+    return shl_key(key, sh) | (uint64_t)r << pb | pos;
+}
+// key (with the shared bytes `pre` restored), r and position of a record
+__device__ __forceinline__ uint64_t p1_key(uint64_t x, uint64_t pre, uint32_t sh) {
+    return pre | shr_key(x & ~0xFFFFull, sh);  // sh >= 16: the low 16 bits hold r and position
+}
+__device__ __forceinline__ uint32_t p1_r(uint64_t x, uint32_t pb) { return (uint32_t)(x >> pb) & 0xFu; }
+__device__ __forceinline__ uint32_t p1_pos(uint64_t x, uint32_t pb) { return (uint32_t)x & ((1u << pb) - 1); }
+
 // One step of odd-even transposition sort over the blocked 64*E records:
 // pairs (2i, 2i+1) on even steps, (2i+1, 2i+2) on odd steps, each put in
 // order.  Records of different groups are already in order (groups are
@@ -573,7 +646,8 @@ __device__ void dev_base_wave(const Work& w, const Params& p, int cur, int cls, 
         const uint32_t e = lane * E + r;
         if (e < m) {
             const Rec x = in[e];
-            pr_pack(0, rec_key(x), rec_r(w, x, cur, sg.begin + e), rec_idx(w, x), K[r], A[r]);
+            K[r] = rec_key(x);
+            A[r] = (uint64_t)rec_r(w, x, cur, sg.begin + e) << 32 | rec_idx(w, x);
         } else {
             K[r] = ~0ull;
             A[r] = ~0ull;
@@ -581,9 +655,58 @@ __device__ void dev_base_wave(const Work& w, const Params& p, int cur, int cls, 
         D[r] = h;
         LV[r] = 0;
     }
+    // bytes shared by all keys of the segment
+    const uint64_t k0 = uniform64(K[0]);
+    uint64_t dx = 0;
+#pragma unroll
+    for (uint32_t r = 0; r < (uint32_t)E; ++r)
+        if (lane * E + r < m) dx |= K[r] ^ k0;
+    const uint32_t c = uniform(common_bytes(wave_or64(dx), 0));
+    bool presorted = false;
+    if (c >= 2) {
+        // one-word records; the indices wait in LDS, found by position
+        constexpr uint32_t PB = E == 1 ? 6 : E == 2 ? 7 : 8;
+        const uint32_t sh = 8 * c;
+        uint64_t P[E];
+#pragma unroll
+        for (uint32_t r = 0; r < (uint32_t)E; ++r) {
+            const uint32_t e = lane * E + r;
+            P[r] = ~0ull;
+            if (e < m) {
+                LIDX[wv][e] = (uint32_t)A[r];
+                P[r] = p1_pack(K[r], (uint32_t)(A[r] >> 32), e, sh, PB);
+            }
+        }
+        wave_bitonic1<E>(P, lane);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const uint64_t pre = k0 & ~shr_key(~0ull, sh);
+#pragma unroll
+        for (uint32_t r = 0; r < (uint32_t)E; ++r) {
+            const uint32_t e = lane * E + r;
+            if (e < m) {
+                pr_pack(0, p1_key(P[r], pre, sh), p1_r(P[r], PB), LIDX[wv][p1_pos(P[r], PB)], K[r], A[r]);
+            } else {
+                K[r] = ~0ull;
+                A[r] = ~0ull;
+            }
+        }
+        // LIDX is rewritten by the refinement below
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        presorted = true;
+    } else {
+#pragma unroll
+        for (uint32_t r = 0; r < (uint32_t)E; ++r)
+            if (lane * E + r < m) pr_pack(0, K[r], (uint32_t)(A[r] >> 32), (uint32_t)A[r], K[r], A[r]);
+    }
     uint32_t span = ~0u;
     for (;;) {
-        if (span <= (E == 1 ? 12u : 32u)) {
+        if (presorted) {
+            presorted = false;
+        } else if (span <= (E == 1 ? 12u : 32u)) {
             for (uint32_t st = 0; st < span; ++st) wave_oddeven_step<E>(K, A, lane, (st & 1u) != 0);
         } else {
             wave_bitonic<E>(K, A, lane);
@@ -785,6 +908,41 @@ __device__ void lds_block_sort(uint64_t* H, uint64_t* L, uint32_t NB) {
     }
 }
 
+// lds_block_sort on one-word records.
+__device__ void lds_block_sort1(uint64_t* H, uint32_t NB) {
+    constexpr uint32_t E = 4, R = 64 * E;
+    const uint32_t tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    uint64_t K[E];
+    for (uint32_t b = wv; b < NB; b += WAVES) {  // uniform per wave
+#pragma unroll
+        for (uint32_t r = 0; r < E; ++r) K[r] = H[b * R + lane * E + r];
+        wave_bitonic1<E>(K, lane, NB > 1 ? b * R : 0u);
+#pragma unroll
+        for (uint32_t r = 0; r < E; ++r) H[b * R + lane * E + r] = K[r];
+    }
+    __syncthreads();
+    for (uint32_t k = 2 * R; k <= NB * R; k <<= 1) {
+        for (uint32_t j = k >> 1; j >= R; j >>= 1) {
+            for (uint32_t t = tid; t < NB * R / 2; t += BLOCK) {
+                const uint32_t i = ((t & ~(j - 1)) << 1) | (t & (j - 1));
+                const uint32_t l = i | j;
+                const bool up = (i & k) == 0;
+                const uint64_t a = H[i], b = H[l];
+                if ((a > b) == up) { H[i] = b; H[l] = a; }
+            }
+            __syncthreads();
+        }
+        for (uint32_t b = wv; b < NB; b += WAVES) {
+#pragma unroll
+            for (uint32_t r = 0; r < E; ++r) K[r] = H[b * R + lane * E + r];
+            wave_merge_tail1<E>(K, lane, b * R, k);
+#pragma unroll
+            for (uint32_t r = 0; r < E; ++r) H[b * R + lane * E + r] = K[r];
+        }
+        __syncthreads();
+    }
+}
+
 // Sorts a segment of m <= BASE_CAP strings with common prefix h by
 // (key, r, index).  Runs of equal full words are then refined at depth
 // h+8, h+16, ... inside LDS (keys re-gathered for those strings only).
@@ -813,10 +971,15 @@ __device__ void dev_base_wg(const Work& w, const Params& p, int cur, uint32_t it
     uint32_t P = 256;  // whole blocks of the block sort
     while (P < m) P <<= 1;
     const Rec* in = w.rec[cur] + sg.begin;
+    // keys and (r, index) first; the bytes all keys share decide the record form
+    const uint64_t k0 = rec_key(in[0]);
+    uint64_t dx = 0;
     for (uint32_t i = tid; i < P; i += BLOCK) {
         if (i < m) {
             const Rec x = in[i];
-            pr_pack(0, rec_key(x), rec_r(w, x, cur, sg.begin + i), rec_idx(w, x), K[i], A[i]);
+            K[i] = rec_key(x);
+            A[i] = (uint64_t)rec_r(w, x, cur, sg.begin + i) << 32 | rec_idx(w, x);
+            dx |= K[i] ^ k0;
         } else {
             K[i] = ~0ull;
             A[i] = ~0ull;
@@ -824,11 +987,44 @@ __device__ void dev_base_wg(const Work& w, const Params& p, int cur, uint32_t it
         dep[i] = h;
         lv[i] = 0;
     }
+    dx = wave_or64(dx);
+    if ((tid & 63) == 0) {  // rmin is free until the refinement
+        rmin[2 * (tid >> 6)] = (uint32_t)dx;
+        rmin[2 * (tid >> 6) + 1] = (uint32_t)(dx >> 32);
+    }
+    __syncthreads();
+    dx = 0;
+#pragma unroll
+    for (uint32_t q = 0; q < WAVES; ++q) dx |= (uint64_t)rmin[2 * q] | (uint64_t)rmin[2 * q + 1] << 32;
+    const uint32_t c = common_bytes(dx, 0);
+    bool presorted = false;
+    if (c >= 2) {
+        // one-word records; the indices wait in aux, found by position
+        constexpr uint32_t PB = 10;
+        static_assert(BASE_CAP <= (1u << PB) && PB + 4 <= 16, "one-word base records");
+        const uint32_t sh = 8 * c;
+        for (uint32_t i = tid; i < m; i += BLOCK) {
+            aux[i] = (uint32_t)A[i];
+            K[i] = p1_pack(K[i], (uint32_t)(A[i] >> 32), i, sh, PB);
+        }
+        __syncthreads();
+        lds_block_sort1(K, P / 256);
+        const uint64_t pre = k0 & ~shr_key(~0ull, sh);
+        for (uint32_t i = tid; i < m; i += BLOCK) {
+            const uint64_t x = K[i];
+            pr_pack(0, p1_key(x, pre, sh), p1_r(x, PB), aux[p1_pos(x, PB)], K[i], A[i]);
+        }
+        presorted = true;
+    } else {
+        for (uint32_t i = tid; i < m; i += BLOCK)
+            pr_pack(0, K[i], (uint32_t)(A[i] >> 32), (uint32_t)A[i], K[i], A[i]);
+    }
     __syncthreads();
 
     for (;;) {
         if (tid == 0) any = 0;
-        lds_block_sort(K, A, P / 256);
+        if (presorted) presorted = false;
+        else lds_block_sort(K, A, P / 256);
         // neighbours inside a group: tie (equal full word, refine) or split
         for (uint32_t i = tid; i < m; i += BLOCK) {
             uint32_t t = 0;
