@@ -434,6 +434,26 @@ __device__ __forceinline__ uint64_t xlane(uint64_t x, uint32_t lj) {
     }
 }
 
+// Lanes of a wave whose record (global index base + lane*E + r of a
+// blocked layout) has the bit `bit` (a power of two) set: a constant lane
+// pattern when the bit falls on the lane number, all or none otherwise.
+// Used through inverse ballots, the compare-exchange directions cost no
+// vector instructions.
+template <int E>
+__device__ __forceinline__ uint64_t lanes_with_bit(uint32_t bit, uint32_t r, uint32_t base) {
+    if (bit < (uint32_t)E) return (r & bit) ? ~0ull : 0ull;
+    if (bit >= 64u * E) return (base & bit) ? ~0ull : 0ull;
+    switch (bit / E) {
+    case 1: return 0xAAAAAAAAAAAAAAAAull;
+    case 2: return 0xCCCCCCCCCCCCCCCCull;
+    case 4: return 0xF0F0F0F0F0F0F0F0ull;
+    case 8: return 0xFF00FF00FF00FF00ull;
+    case 16: return 0xFFFF0000FFFF0000ull;
+    default: return 0xFFFFFFFF00000000ull;
+    }
+}
+__device__ __forceinline__ bool lane_in(uint64_t lanes) { return __builtin_amdgcn_inverse_ballot_w64(lanes); }
+
 // One compare-exchange stage (k, j) of a bitonic network over records in
 // blocked layout (lane holds records lane*E .. lane*E+E-1 of a block whose
 // first record has global index `base`): partners inside a lane are
@@ -448,8 +468,7 @@ __device__ __forceinline__ void wave_stage(uint64_t (&K)[E], uint64_t (&A)[E], u
         for (uint32_t r = 0; r < (uint32_t)E; ++r) {
             if ((r & j) == 0) {
                 const uint32_t r2 = r | j;
-                const uint32_t e = base + lane * E + r;
-                const bool up = (e & k) == 0;
+                const bool up = lane_in(~lanes_with_bit<E>(k, r, base));
                 if (pr_gt(K[r], A[r], K[r2], A[r2]) == up) {
                     uint64_t tk = K[r]; K[r] = K[r2]; K[r2] = tk;
                     uint64_t ta = A[r]; A[r] = A[r2]; A[r2] = ta;
@@ -460,12 +479,10 @@ __device__ __forceinline__ void wave_stage(uint64_t (&K)[E], uint64_t (&A)[E], u
         const uint32_t lj = j / E;
 #pragma unroll
         for (uint32_t r = 0; r < (uint32_t)E; ++r) {
-            const uint32_t e = base + lane * E + r;
             const uint64_t pk = xlane(K[r], lj);
             const uint64_t pa = xlane(A[r], lj);
-            const bool lower = (e & j) == 0;
-            const bool up = (e & k) == 0;
-            const bool keep_min = lower == up;
+            // keep the smaller when the bits j and k of the index agree
+            const bool keep_min = lane_in(~(lanes_with_bit<E>(j, r, base) ^ lanes_with_bit<E>(k, r, base)));
             const bool self_gt = pr_gt(K[r], A[r], pk, pa);
             if (self_gt == keep_min) { K[r] = pk; A[r] = pa; }
         }
@@ -503,8 +520,7 @@ __device__ __forceinline__ void wave_stage1(uint64_t (&K)[E], uint32_t lane, uin
         for (uint32_t r = 0; r < (uint32_t)E; ++r) {
             if ((r & j) == 0) {
                 const uint32_t r2 = r | j;
-                const uint32_t e = base + lane * E + r;
-                const bool up = (e & k) == 0;
+                const bool up = lane_in(~lanes_with_bit<E>(k, r, base));
                 const uint64_t a = K[r], b = K[r2];
                 if ((a > b) == up) { K[r] = b; K[r2] = a; }
             }
@@ -513,9 +529,9 @@ __device__ __forceinline__ void wave_stage1(uint64_t (&K)[E], uint32_t lane, uin
         const uint32_t lj = j / E;
 #pragma unroll
         for (uint32_t r = 0; r < (uint32_t)E; ++r) {
-            const uint32_t e = base + lane * E + r;
             const uint64_t pk = xlane(K[r], lj);
-            const bool keep_min = ((e & j) == 0) == ((e & k) == 0);
+            // keep the smaller when the bits j and k of the index agree
+            const bool keep_min = lane_in(~(lanes_with_bit<E>(j, r, base) ^ lanes_with_bit<E>(k, r, base)));
             if ((K[r] > pk) == keep_min) K[r] = pk;
         }
     }
@@ -565,6 +581,14 @@ __device__ __forceinline__ uint64_t p1_key(uint64_t x, uint64_t pre, uint32_t sh
     return pre | shr_key(x & ~0xFFFFull, sh);  // sh >= 16: the low 16 bits hold r and position
 }
 __device__ __forceinline__ uint32_t p1_r(uint64_t x, uint32_t pb) { return (uint32_t)(x >> pb) & 0xFu; }
+// LCP contribution of the words of two one-word records (their r values
+// r1, r0) whose keys share c leading bytes, as lcp_word gives it
+__device__ __forceinline__ uint32_t p1_lcp(uint64_t x1, uint32_t r1, uint64_t x0, uint32_t r0, uint32_t c) {
+    uint32_t cb = c + common_bytes(x1 & ~0xFFFFull, x0 & ~0xFFFFull);
+    cb = cb < W ? cb : W;
+    cb = cb < r0 ? cb : r0;
+    return cb < r1 ? cb : r1;
+}
 __device__ __forceinline__ uint32_t p1_pos(uint64_t x, uint32_t pb) { return (uint32_t)x & ((1u << pb) - 1); }
 
 // One step of odd-even transposition sort over the blocked 64*E records:
@@ -619,33 +643,64 @@ __device__ __forceinline__ void wave_oddeven_step(uint64_t (&K)[E], uint64_t (&A
     }
 }
 
+// A base segment's descriptor and its set's first index, in scalar
+// registers, loaded before the segment is sorted (so a wave loads the next
+// segment's descriptor while it sorts one).
+struct BaseDesc {
+    BaseSeg sg;
+    uint32_t obase;
+    bool ok;
+};
+template <int E>
+__device__ __forceinline__ BaseDesc base_wave_desc(const Work& w, const Params& p, int cur, int cls, uint32_t si,
+                                                   uint32_t nseg) {
+    const uint32_t lane = threadIdx.x & 63;
+    BaseDesc d{};
+    if (si >= nseg) return d;  // uniform per wave
+    const BaseSeg sg = w.base[cls][cur][si];
+    d.sg = BaseSeg{uniform(sg.begin), uniform(sg.size), uniform(sg.depth), uniform(sg.rid)};
+    const uint32_t m = d.sg.size;
+    if (m < 2 || m > 64u * E || d.sg.begin > p.n || m > p.n - d.sg.begin) {
+        if (lane == 0) raise_err(w, ERR_BOUNDS);
+        return d;
+    }
+    d.ok = true;
+    d.obase = uniform(w.set_base[d.sg.rid]);
+    return d;
+}
+template <int E>
+__device__ __forceinline__ void base_wave_recs(const Work& w, int cur, const BaseDesc& d, Rec (&x)[E]) {
+    const uint32_t lane = threadIdx.x & 63;
+    const Rec* src = w.rec[cur] + d.sg.begin;
+#pragma unroll
+    for (uint32_t r = 0; r < (uint32_t)E; ++r) {
+        const uint32_t e = lane * E + r;
+        x[r] = d.ok && e < d.sg.size ? src[e] : Rec{0, 0, 0};
+    }
+}
+
 // Same job as k_base for a segment of at most 64*E strings: sort by
 // (key, r, index), refine runs of equal full words at depth + 8 (keys
 // re-gathered only for those strings), LCP of neighbours from the word at
 // the depth where they separate.  Depth and LCP are kept per position
 // (a run never moves), keys and records move.
 template <int E>
-__device__ void dev_base_wave(const Work& w, const Params& p, int cur, int cls, uint32_t si, uint32_t nseg,
-                              SmWave& sm) {
+__device__ void dev_base_wave_run(const Work& w, const Params& p, int cur, const BaseDesc& in, const Rec (&X)[E],
+                                  uint32_t si, SmWave& sm) {
     auto& LIDX = sm.LIDX;
     auto& RMIN = sm.RMIN;
     const uint32_t lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    if (si >= nseg) return;  // uniform per wave
-    const BaseSeg sg = w.base[cls][cur][si];
+    if (!in.ok) return;  // uniform per wave
+    const BaseSeg& sg = in.sg;
     const uint32_t m = sg.size, h = sg.depth;
     uint32_t rounds = 0;
-    if (m < 2 || m > 64u * E || sg.begin > p.n || m > p.n - sg.begin) {
-        if (lane == 0) raise_err(w, ERR_BOUNDS);
-        return;
-    }
-    const Rec* in = w.rec[cur] + sg.begin;
     uint64_t K[E], A[E];
     uint32_t D[E], LV[E];
 #pragma unroll
     for (uint32_t r = 0; r < (uint32_t)E; ++r) {
         const uint32_t e = lane * E + r;
         if (e < m) {
-            const Rec x = in[e];
+            const Rec& x = X[r];
             K[r] = rec_key(x);
             A[r] = (uint64_t)rec_r(w, x, cur, sg.begin + e) << 32 | rec_idx(w, x);
         } else {
@@ -681,6 +736,32 @@ __device__ void dev_base_wave(const Work& w, const Params& p, int cur, int cls, 
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        // neighbours: equal words with r = 8 tie, else the LCP is final
+        const uint64_t pl = __shfl_up(P[E - 1], 1, 64);
+        uint32_t tb = 0;
+#pragma unroll
+        for (uint32_t r = 0; r < (uint32_t)E; ++r) {
+            const uint32_t e = lane * E + r;
+            const uint64_t q = r == 0 ? pl : P[r - 1];
+            if (e > 0 && e < m) {
+                const uint32_t r1 = p1_r(P[r], PB), r0 = p1_r(q, PB);
+                if (((P[r] ^ q) >> PB) == 0 && r1 == W) tb |= 1u << r;
+                else LV[r] = h + p1_lcp(P[r], r1, q, r0, c);
+            }
+        }
+        if (__ballot(tb != 0) == 0) {  // no ties: order and LCPs are final
+            const uint32_t obase = in.obase;
+#pragma unroll
+            for (uint32_t r = 0; r < (uint32_t)E; ++r) {
+                const uint32_t e = lane * E + r;
+                if (e < m) {
+                    p.perm[sg.begin + e] = LIDX[wv][p1_pos(P[r], PB)] - obase;
+                    if (e > 0) p.lcp[sg.begin + e] = LV[r];
+                }
+            }
+            if (lane == 0 && w.remaining) atomicSub(&w.remaining[sg.rid], m);
+            return;
+        }
         const uint64_t pre = k0 & ~shr_key(~0ull, sh);
 #pragma unroll
         for (uint32_t r = 0; r < (uint32_t)E; ++r) {
@@ -806,17 +887,24 @@ __device__ void dev_base_wave(const Work& w, const Params& p, int cur, int cls, 
         __builtin_amdgcn_wave_barrier();
         span = wave_max(span);
     }
-    const uint32_t obase = w.set_base[sg.rid];
 #pragma unroll
     for (uint32_t r = 0; r < (uint32_t)E; ++r) {
         const uint32_t e = lane * E + r;
         if (e < m) {
-            p.perm[sg.begin + e] = pr_idx(A[r]) - obase;
+            p.perm[sg.begin + e] = pr_idx(A[r]) - in.obase;
             if (e > 0) p.lcp[sg.begin + e] = LV[r];
         }
     }
     if (lane == 0 && w.remaining) atomicSub(&w.remaining[sg.rid], m);
     if (lane == 0 && rounds) atomicAdd(&w.ctl->base_rounds[si % ROUND_LINES].v, rounds);
+}
+template <int E>
+__device__ void dev_base_wave(const Work& w, const Params& p, int cur, int cls, uint32_t si, uint32_t nseg,
+                              SmWave& sm) {
+    const BaseDesc d = base_wave_desc<E>(w, p, cur, cls, si, nseg);
+    Rec x[E];
+    base_wave_recs<E>(w, cur, d, x);
+    dev_base_wave_run<E>(w, p, cur, d, x, si, sm);
 }
 
 // Waves take segments: wave g of the launch takes segment g, then chunks
@@ -845,7 +933,14 @@ void k_base_wave(Work w, Params p, int cur, int cls) {
         // its round trip overlaps the work
         uint32_t nlo = 0, nhi = 0, ok = 0;
         if (lane == 0) ok = feed_take(f, s0, n, part, BASE_WAVE_CHUNK, &nlo, &nhi) ? 1u : 0u;
-        for (uint32_t si = lo; si < hi; ++si) dev_base_wave<E>(w, p, cur, cls, si, n, sm);
+        BaseDesc d = base_wave_desc<E>(w, p, cur, cls, lo, n);
+        for (uint32_t si = lo; si < hi; ++si) {
+            Rec x[E];
+            base_wave_recs<E>(w, cur, d, x);
+            const BaseDesc nd = base_wave_desc<E>(w, p, cur, cls, si + 1 < hi ? si + 1 : n, n);
+            dev_base_wave_run<E>(w, p, cur, d, x, si, sm);
+            d = nd;
+        }
         ok = (uint32_t)__builtin_amdgcn_readfirstlane((int)ok);
         if (!ok) break;
         lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)nlo);
@@ -1007,8 +1102,25 @@ __device__ void dev_base_wg(const Work& w, const Params& p, int cur, uint32_t it
             aux[i] = (uint32_t)A[i];
             K[i] = p1_pack(K[i], (uint32_t)(A[i] >> 32), i, sh, PB);
         }
+        if (tid == 0) any = 0;
         __syncthreads();
         lds_block_sort1(K, P / 256);
+        for (uint32_t i = tid + 1; i < m; i += BLOCK) {
+            const uint64_t x = K[i], q = K[i - 1];
+            const uint32_t r1 = p1_r(x, PB), r0 = p1_r(q, PB);
+            if (((x ^ q) >> PB) == 0 && r1 == W) any = 1;
+            else lv[i] = h + p1_lcp(x, r1, q, r0, c);
+        }
+        __syncthreads();
+        if (!any) {  // no ties: order and LCPs are final
+            const uint32_t obase = w.set_base[sg.rid];
+            for (uint32_t i = tid; i < m; i += BLOCK) {
+                p.perm[sg.begin + i] = aux[p1_pos(K[i], PB)] - obase;
+                if (i > 0) p.lcp[sg.begin + i] = lv[i];
+            }
+            if (tid == 0 && w.remaining) atomicSub(&w.remaining[sg.rid], m);
+            return;
+        }
         const uint64_t pre = k0 & ~shr_key(~0ull, sh);
         for (uint32_t i = tid; i < m; i += BLOCK) {
             const uint64_t x = K[i];
