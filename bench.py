@@ -531,7 +531,10 @@ def run_profile(args):
     chars = torch.from_numpy(c).cuda()
     offs = torch.from_numpy(o.view(np.int64)).cuda()
     ctx = ss.Context(0)
-    for _ in range(args.warmup + args.steps):
+    for _ in range(args.warmup):  # each finished before the next: the level budget follows the workload
+        ctx.sort(chars, offs)
+        ctx.sync()
+    for _ in range(args.steps):
         ctx.sort(chars, offs)
     torch.cuda.synchronize()
     print(json.dumps({"mode": "profile", "workload": args.workload, "copy_gbs": 2 * nbytes / min(ts) / 1e9}))
@@ -640,10 +643,13 @@ def run_counters(args):
     for path in args.csv:
         rows = [per[k] for k in sorted(k for k in per if k[0] == path)]
         starts = [i for i, (name, _) in enumerate(rows) if "k_reset" in name]
+        seen = set(counters)  # a counter collected in several runs is taken from the first
         for name, vals in rows[starts[-1]:] if starts else rows:
             base = name.split("(")[0].replace("void ", "").replace("ss::", "")
             d = kern.setdefault(base, {})
             for c, v in vals.items():
+                if c in seen:
+                    continue
                 if c not in counters:
                     counters.append(c)
                 d[c] = d.get(c, 0.0) + v
@@ -674,14 +680,53 @@ def run_counters(args):
     print("\n".join(lines))
 
 
+def run_stats(args):
+    """Formats a rocprofv3 `--stats` kernel summary (kernel_stats.csv) of a
+    bench.py run as profiles/kernels_<workload>_stats.txt; the bench line of
+    the same run (--bench-json) adds its own event average of the dominant
+    kernel for comparison."""
+    import csv
+
+    rows = []
+    with open(args.csv[0]) as f:
+        for r in csv.DictReader(f):
+            rows.append((r["Name"], int(r["Calls"]), float(r["TotalDurationNs"]) / 1e6, float(r["AverageNs"]) / 1e3,
+                         float(r["MinNs"]) / 1e3, float(r["MaxNs"]) / 1e3, float(r["Percentage"])))
+    rows.sort(key=lambda x: -x[2])
+    lines = [f"# rocprofv3 kernel statistics, {args.workload}, one MI355X.",
+             "# Command (from /tmp, TMPDIR=/tmp):",
+             f"#   rocprofv3 --kernel-trace --stats --output-format csv -d <out> -o run -- python3 bench.py {args.command}",
+             f"# then: python3 bench.py --mode stats --workload {args.workload} --csv <kernel_stats.csv> "
+             "--bench-json <the run's bench line>"]
+    for note in args.note or []:
+        lines.append(f"# {note}")
+    if args.bench_json:
+        with open(args.bench_json) as f:
+            b = json.loads([ln for ln in f.read().splitlines() if ln.startswith("{")][-1])
+        rf = b.get("roofline", {})
+        if rf.get("avg_launch_ms"):
+            lines.append(f"# bench.py's HIP-event average of {rf.get('kernel')} in the same run: "
+                         f"{rf['avg_launch_ms'] * 1e3:.1f} us per launch; step {b['ms_per_step']:.3f} ms.")
+    lines += ["", f"{'kernel':60s} {'calls':>6s} {'total ms':>9s} {'avg us':>8s} {'min us':>8s} {'max us':>8s} {'%':>6s}"]
+    for name, calls, tot, avg, mn, mx, pct in rows:
+        lines.append(f"{name[:60]:60s} {calls:6d} {tot:9.3f} {avg:8.1f} {mn:8.1f} {mx:8.1f} {pct:6.2f}")
+    out = os.path.join(ROOT, "profiles", f"kernels_{args.workload}_stats.txt")
+    with open(out, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--mode", choices=["plain", "batch", "serve", "profile", "traffic", "counters", "merge", "sa"], default="plain")
+    ap.add_argument("--mode", choices=["plain", "batch", "serve", "profile", "traffic", "counters", "stats", "merge", "sa"], default="plain")
     ap.add_argument("--fetch-csv", help="traffic mode: rocprofv3 counter_collection.csv of the FETCH_SIZE run")
     ap.add_argument("--write-csv", help="traffic mode: rocprofv3 counter_collection.csv of the WRITE_SIZE run")
     ap.add_argument("--csv", action="append", help="counters mode: a rocprofv3 counter_collection.csv")
     ap.add_argument("--groups", action="append", help="counters mode: the --pmc counter list of each run")
+    ap.add_argument("--command", default="", help="stats mode: the bench.py arguments of the profiled run")
+    ap.add_argument("--note", action="append", help="stats mode: a comment line for the summary")
+    ap.add_argument("--bench-json", help="stats mode: the bench line printed by the profiled run")
     ap.add_argument("--pool", type=int, default=128)
     ap.add_argument("--runs", type=int, default=2, help="merge mode: number of sorted runs")
     ap.add_argument("--sa-n", type=int, default=1 << 24, help="sa mode: text length")
@@ -717,6 +762,9 @@ def main():
         return
     if args.mode == "counters":
         run_counters(args)
+        return
+    if args.mode == "stats":
+        run_stats(args)
         return
     if args.mode == "merge":
         run_merge(args)
