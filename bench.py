@@ -740,6 +740,8 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="plain mode: only the headline workload")
     ap.add_argument("--sort-mode", default="levels", choices=["levels", "host_levels", "persistent"],
                     help="how the recursion levels are driven (ss_config.mode)")
+    ap.add_argument("--alphabet", default="bytes", choices=["auto", "bytes", "compress"],
+                    help="key format (ss_config.alphabet): compressed keys where the input allows, or bytes")
     ap.add_argument("--cpu-sample", type=int, default=0,
                     help="strings for the oracle timing (a prefix of the workload; 0 = all)")
     args = ap.parse_args()
@@ -814,7 +816,8 @@ def copy_bandwidth(nbytes=2 << 30, reps=5):
     return {"bytes_each_way": nbytes, "ms": ms, "gbs": 2 * nbytes / (ms * 1e-3) / 1e9, "copied": ok}
 
 
-def sort_measure(workload, steps, warmup, mode="levels", breakdown=True, timed_kernel=None, cpu=False):
+def sort_measure(workload, steps, warmup, mode="levels", breakdown=True, timed_kernel=None, cpu=False,
+                 alphabet="bytes"):
     """One named workload: generation, warm-up sorts, a breakdown pass with
     HIP events around every kernel launch (untimed), then the timed region
     of `steps` complete sorts with events (on the sort's stream) only around
@@ -837,7 +840,7 @@ def sort_measure(workload, steps, warmup, mode="levels", breakdown=True, timed_k
     perm = torch.empty(n, dtype=torch.int32, device=dev)
     lcp = torch.empty(n, dtype=torch.int32, device=dev)
     ctx = ss.Context(0)
-    ctx.set_config(mode=mode)
+    ctx.set_config(mode=mode, alphabet=alphabet)
     stream = torch.cuda.current_stream()
     for _ in range(warmup):
         ctx.sort(chars, offs, perm, lcp, stream=stream)
@@ -908,7 +911,8 @@ def run_plain(args):
     import numpy as np
 
     bpu = dict(BYTES_PER_UNIT)
-    r = sort_measure(args.workload, args.steps, args.warmup, mode=args.sort_mode, timed_kernel="k_scatter")
+    r = sort_measure(args.workload, args.steps, args.warmup, mode=args.sort_mode, timed_kernel="k_scatter",
+                     alphabet=args.alphabet)
     n, N, sec, kt, stats = r["n"], r["N"], r["sec"], r["kt"], r["stats"]
     L = np.diff(r["offsets"].astype(np.int64))
     bpu["k_init"] = 8.0 + float(np.minimum(L, 8).mean()) + 13.0
@@ -957,7 +961,7 @@ def run_plain(args):
         "dtype": "u8",
         "data": "synthetic",
         "config": {"workload": args.workload, "model": r["model"], "seed": r["seed"], "n_strings": n, "n_chars": N,
-                   "parallelism": "single-gpu", "mode": args.sort_mode},
+                   "parallelism": "single-gpu", "mode": args.sort_mode, "alphabet": args.alphabet},
         "strings_per_s": n / sec,
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
@@ -980,10 +984,17 @@ def run_plain(args):
                          key=lambda kv: -kv[1])[:4]
             extras[w] = {"ms_per_sort": e["sec"] * 1e3, "chars_per_s": e["N"] / e["sec"],
                          "strings_per_s": e["n"] / e["sec"], "n_strings": e["n"], "n_chars": e["N"],
-                         "levels": e["stats"]["levels"], "top_kernels_ms": dict(top)}
+                         "levels": e["stats"]["levels"], "key_chars": e["stats"]["key_chars"],
+                         "top_kernels_ms": dict(top)}
             log(f"{w}: {e['sec'] * 1e3:.3f} ms, {e['N'] / e['sec'] / 1e9:.1f} G chars/s, levels "
-                f"{e['stats']['levels']}, top {top}")
+                f"{e['stats']['levels']}, {e['stats']['key_chars']} chars per key, top {top}")
             del e
+            if w == "c2b_suffixes_2m":  # DNA: the same workload with alphabet-compressed keys
+                e = sort_measure(w, args.steps, 2, mode=args.sort_mode, breakdown=False, alphabet="compress")
+                extras[w]["ms_per_sort_compressed_keys"] = e["sec"] * 1e3
+                extras[w]["compressed_key_chars"] = e["stats"]["key_chars"]
+                log(f"{w} with compressed keys ({e['stats']['key_chars']} per key): {e['sec'] * 1e3:.3f} ms")
+                del e
         extras["batched_4096_sets"] = batch_measure(max(4, args.steps // 2))
         extras["serving"] = serve_measure(args.pool, args.requests, args.serve_warmup)
         out["extras"] = extras

@@ -79,6 +79,10 @@ typedef struct ss_ctx ss_ctx;
 #define SS_MODE_PERSISTENT 1
 #define SS_MODE_HOST_LEVELS 2
 
+#define SS_ALPHABET_AUTO 0
+#define SS_ALPHABET_BYTES 1
+#define SS_ALPHABET_COMPRESS 2
+
 /* Tunable parameters (performance only; results never depend on them). */
 typedef struct {
     uint32_t max_log_splitters; /* d_max: at most v = 2^d_max - 1 splitters
@@ -101,6 +105,30 @@ typedef struct {
                                    reads each level's counts and enqueues it
                                    with exact grids (synchronises once per
                                    level; kept for comparison). */
+    uint32_t alphabet;          /* key format (alphabet compression, section
+                                   4.6.1).  A compressed key holds each
+                                   character as 1 + its rank among the bytes
+                                   the input uses, in 2, 3 or 4 bits (1..3,
+                                   4..7 or 8..15 distinct bytes; 32, 21 or 16
+                                   characters per 64-bit key instead of 8).
+                                   SS_ALPHABET_BYTES (default): always 8 bytes
+                                   per key; the call does not wait for the
+                                   device.  SS_ALPHABET_AUTO: the sort first
+                                   probes the first 16 bytes of 1024 strings;
+                                   for inputs of at most 3 distinct bytes and
+                                   at most 64 characters per string on average
+                                   one pass over chars[offsets[0], offsets[n])
+                                   checks every byte, and the keys are
+                                   compressed if the whole input qualifies.
+                                   SS_ALPHABET_COMPRESS: the same for inputs
+                                   of at most 15 distinct bytes and any
+                                   length.  With AUTO or COMPRESS the call
+                                   waits for the probe and the check (the level
+                                   kernels come in a byte-key and a compressed
+                                   form; the host launches one), except in
+                                   SS_MODE_PERSISTENT.  Graphs, ss_sort_noalloc
+                                   and serving use byte keys.  Results never
+                                   depend on this setting. */
 } ss_config;
 
 /* Returns a short description of a status code (static storage). */
@@ -356,6 +384,10 @@ typedef struct {
     uint32_t base_segments_by_class[4]; /* base-case segments of <= 64, <= 128,
                                            <= 256 and <= base_max strings */
     uint64_t base_strings_by_class[4];  /* strings in those segments */
+    uint32_t key_chars;     /* characters per 64-bit key: 8 (byte keys) or 16,
+                               21 or 32 (alphabet-compressed keys) */
+    uint32_t alphabet_size; /* distinct bytes of the input when the alphabet
+                               check ran to the end (keys compressed), else 0 */
 } ss_stats;
 ss_status ss_get_stats(ss_ctx* ctx, ss_stats* st);
 
@@ -404,6 +436,21 @@ uint64_t ss_host_key(const uint8_t* s, uint64_t len, uint64_t h, uint32_t* r_out
  * caller must make those words readable (the test places strings next to
  * unreadable pages to show that nothing else is read). */
 uint64_t ss_host_gather_key(const uint8_t* chars, uint64_t off, uint32_t h, uint32_t len);
+
+/* The kernels' alphabet-compressed key gather (alphabet compression,
+ * section 4.6.1) on the host: byte_set = the 256-bit set of bytes present
+ * (four words, bit c of word c/64); with 1..15 members each character is
+ * coded as 1 + its rank in the set in 2, 3 or 4 bits, 0 past the string's
+ * end, most significant first (*chars_per_key = 32, 21 or 16); otherwise
+ * the byte key of ss_host_gather_key (*chars_per_key = 8).  Reads only the
+ * aligned words that hold the key's bytes; *miss = 1 if one of them is not
+ * in the set.  Either output pointer may be NULL. */
+uint64_t ss_host_gather_packed(const uint8_t* chars, uint64_t off, uint32_t h, uint32_t len,
+                               const uint64_t* byte_set, uint32_t* chars_per_key, int* miss);
+/* Characters two strings of lengths len_a, len_b share inside their keys a,
+ * b at depth h, in the key format of byte_set (as above). */
+uint32_t ss_host_key_lcp(const uint64_t* byte_set, uint64_t a, uint32_t len_a, uint64_t b, uint32_t len_b,
+                         uint32_t h);
 
 /* Lemma 4.1 mapping: level-order index of in-order position j (d levels),
  * and its inverse. */

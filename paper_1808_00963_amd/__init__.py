@@ -23,6 +23,8 @@ LIB_PATH = os.path.join(_HERE, "libss.so")
 SS_OK, SS_INVALID_ARG, SS_OUT_OF_MEMORY, SS_HIP_ERROR, SS_LIMIT, SS_REJECTED, SS_TIMEOUT, SS_INTERNAL = range(8)
 MODE_LEVELS, MODE_PERSISTENT, MODE_HOST_LEVELS = range(3)
 MODES = {"levels": MODE_LEVELS, "persistent": MODE_PERSISTENT, "host_levels": MODE_HOST_LEVELS}
+ALPHABET_AUTO, ALPHABET_BYTES, ALPHABET_COMPRESS = range(3)
+ALPHABETS = {"auto": ALPHABET_AUTO, "bytes": ALPHABET_BYTES, "compress": ALPHABET_COMPRESS}
 
 _lib = None
 
@@ -35,7 +37,7 @@ class SSError(RuntimeError):
 
 class Config(ctypes.Structure):
     _fields_ = [("max_log_splitters", ctypes.c_uint32), ("bucket_target", ctypes.c_uint32),
-                ("base_max", ctypes.c_uint32), ("mode", ctypes.c_uint32)]
+                ("base_max", ctypes.c_uint32), ("mode", ctypes.c_uint32), ("alphabet", ctypes.c_uint32)]
 
 
 class Stats(ctypes.Structure):
@@ -43,7 +45,8 @@ class Stats(ctypes.Structure):
                 ("dist_tiles", ctypes.c_uint32), ("base_segments", ctypes.c_uint32),
                 ("pending_lcps", ctypes.c_uint32), ("max_depth", ctypes.c_uint32),
                 ("base_rounds", ctypes.c_uint32), ("base_segments_by_class", ctypes.c_uint32 * 4),
-                ("base_strings_by_class", ctypes.c_uint64 * 4)]
+                ("base_strings_by_class", ctypes.c_uint64 * 4), ("key_chars", ctypes.c_uint32),
+                ("alphabet_size", ctypes.c_uint32)]
 
 
 class KernelTime(ctypes.Structure):
@@ -114,6 +117,8 @@ def lib():
             "ss_suffix_array": (i32, [vp, vp, u32, vp, vp, ctypes.POINTER(u32), vp]),
             "ss_host_key": (u64, [vp, u64, u64, ctypes.POINTER(u32)]),
             "ss_host_gather_key": (u64, [vp, u64, u32, u32]),
+            "ss_host_gather_packed": (u64, [vp, u64, u32, u32, vp, vp, vp]),
+            "ss_host_key_lcp": (u32, [vp, u64, u32, u64, u32, u32]),
             "ss_host_level_index": (u32, [u32, u32]),
             "ss_host_inorder_index": (u32, [u32, u32]),
             "ss_host_classify": (i32, [vp, vp, u32, vp, vp, u32, vp]),
@@ -183,9 +188,10 @@ class Context:
         _check(lib().ss_get_config(self._h, ctypes.byref(c)), "ss_get_config")
         return c
 
-    def set_config(self, max_log_splitters=None, bucket_target=None, base_max=None, mode=None):
+    def set_config(self, max_log_splitters=None, bucket_target=None, base_max=None, mode=None, alphabet=None):
         """mode: "levels" (device-driven levels, default), "persistent" or
-        "host_levels" (or the MODE_* constants)."""
+        "host_levels" (or the MODE_* constants); alphabet: "auto" (default)
+        "bytes" or "compress" (or the ALPHABET_* constants)."""
         c = self.config
         if max_log_splitters is not None:
             c.max_log_splitters = max_log_splitters
@@ -195,6 +201,8 @@ class Context:
             c.base_max = base_max
         if mode is not None:
             c.mode = MODES[mode] if isinstance(mode, str) else int(mode)
+        if alphabet is not None:
+            c.alphabet = ALPHABETS[alphabet] if isinstance(alphabet, str) else int(alphabet)
         _check(lib().ss_set_config(self._h, ctypes.byref(c)), "ss_set_config")
 
     def stats(self) -> dict:

@@ -24,15 +24,15 @@ using namespace ss;
 namespace {
 enum KernelId {
     K_INIT, K_ROOTS, K_BASE_W1, K_BASE_W2, K_BASE_W4, K_BASE, K_SAMPLE, K_CLASSIFY, K_SCAN, K_SCATTER, K_CHILDREN,
-    K_LCP_FILL, K_PERSIST, K_LEVEL_BEGIN, K_MERGE_SPLIT, K_MERGE, K_SA_STRINGS, K_SA_RENAME, K_COUNT
+    K_LCP_FILL, K_PERSIST, K_LEVEL_BEGIN, K_MERGE_SPLIT, K_MERGE, K_SA_STRINGS, K_SA_RENAME, K_ALPHABET, K_COUNT
 };
 const char* const KNAME[K_COUNT] = {"k_init", "k_roots", "k_base_wave1", "k_base_wave2", "k_base_wave4", "k_base",
                                     "k_sample", "k_classify", "k_scan", "k_scatter", "k_children", "k_lcp_fill",
                                     "k_persist", "k_level_begin", "k_merge_split", "k_merge_tile", "k_sa_strings",
-                                    "k_sa_rename"};
+                                    "k_sa_rename", "k_alphabet"};
 const char* const KUNIT[K_COUNT] = {"strings", "sets", "strings", "strings", "strings", "strings", "segments",
                                     "strings", "counters", "strings", "segments", "boundaries", "strings", "levels",
-                                    "tiles", "strings", "suffixes", "suffixes"};
+                                    "tiles", "strings", "suffixes", "suffixes", "strings"};
 
 // What a timed launch counts (resolved once the sort's control block is on
 // the host): a constant, or a field of the work counts of its level.
@@ -76,7 +76,7 @@ struct ss_ctx {
     size_t scratch_limit = 0;
     Ws ws;                    // workspace of the context's own sorts
     Ctl* host_ctl = nullptr;  // pinned: the control block after the last sort
-    ss_config cfg{10, 64, 1024, SS_MODE_LEVELS};
+    ss_config cfg{10, 64, 1024, SS_MODE_LEVELS, SS_ALPHABET_BYTES};
     ss_status sticky = SS_OK;
     ss_stats stats{};
     bool pending = false;     // host_ctl of the last sort not yet absorbed
@@ -122,11 +122,16 @@ constexpr uint32_t MAX_LEVEL_LAUNCHES = 32;
 constexpr uint32_t FORK_MIN = 1u << 21;
 static_assert(NCLS == 4, "ss_stats reports four base-case classes");
 
+static_assert(SS_ALPHABET_AUTO == ALPHABET_AUTO && SS_ALPHABET_BYTES == ALPHABET_BYTES &&
+                  SS_ALPHABET_COMPRESS == ALPHABET_COMPRESS,
+              "alphabet setting passed to the kernels");
+
 void clamp_config(ss_config* c) {
     c->max_log_splitters = std::min<uint32_t>(std::max<uint32_t>(c->max_log_splitters, 1), MAX_LOGV);
     c->bucket_target = std::min<uint32_t>(std::max<uint32_t>(c->bucket_target, 16), 1u << 20);
     c->base_max = std::min<uint32_t>(std::max<uint32_t>(c->base_max, 64), BASE_CAP);
     if (c->mode > SS_MODE_HOST_LEVELS) c->mode = SS_MODE_LEVELS;
+    if (c->alphabet > SS_ALPHABET_COMPRESS) c->alphabet = SS_ALPHABET_BYTES;
 }
 
 // Worst-case pool sizes of one recursion level for n strings (the segments
@@ -327,6 +332,9 @@ void absorb(ss_ctx* ctx) {
     }
     st.pending_lcps = c.n_pend;
     st.base_rounds = base_rounds_of(c);
+    st.key_chars = c.alpha.bpc ? c.alpha.cpw : W;
+    if (c.alpha.bpc)
+        for (int q = 0; q < 4; ++q) st.alphabet_size += (uint32_t)__builtin_popcountll(c.alpha.seen[q]);
     ctx->stats = st;
     if (c.stats.levels) ctx->level_hint = c.stats.levels;
     // the device keeps the errors of every sort since the last clear, so an
@@ -483,9 +491,9 @@ ss_status enqueue_level(const Engine& e, const Work& w, const Params& p, int cur
 // classification); its grid covers every root that can be a distribution
 // segment.  Returns whether the first level's sampling was enqueued.
 ss_status enqueue_start(const Engine& e, const Work& w, const Params& p, const uint32_t* set_begin, uint32_t nroots,
-                        hipStream_t s, bool* sampled) {
+                        hipStream_t s, bool* sampled, bool started) {
     const uint32_t n = p.n;
-    SS_TRY(launch_reset(w, s));
+    if (!started) SS_TRY(launch_reset(w, s));  // else: reset and alphabet already enqueued (decide_alphabet)
     *sampled = n >= FORK_MIN && e.side[0];
     if (*sampled) {
         SS_TRY(timed(e.prof, s, K_ROOTS, units_const(nroots), [&] { return launch_roots(w, p, set_begin, nroots, s); }));
@@ -512,9 +520,9 @@ ss_status enqueue_start(const Engine& e, const Work& w, const Params& p, const u
 // finds nothing to do; otherwise it continues with that level's
 // distribution segments.  No host synchronisation; capturable.
 ss_status enqueue_sort_levels(const Engine& e, const Work& w, const Params& p, const uint32_t* set_begin,
-                              uint32_t nroots, uint32_t levels, hipStream_t s) {
+                              uint32_t nroots, uint32_t levels, hipStream_t s, bool started = false) {
     bool sampled = false;
-    ss_status st = enqueue_start(e, w, p, set_begin, nroots, s, &sampled);
+    ss_status st = enqueue_start(e, w, p, set_begin, nroots, s, &sampled, started);
     if (st != SS_OK) return st;
     bool one_root_base = false;
     if (!set_begin) {  // one root: a distribution segment (two levels at least), a base case or nothing
@@ -542,10 +550,10 @@ ss_status enqueue_sort_levels(const Engine& e, const Work& w, const Params& p, c
 // The host-driven sort: the host reads each level's counts and enqueues the
 // level with exact grids (synchronises once per level).
 ss_status run_sort_host_levels(ss_ctx* ctx, const Work& w, const Params& p, const uint32_t* set_begin,
-                               uint32_t nroots, hipStream_t s) {
+                               uint32_t nroots, hipStream_t s, bool started) {
     const Engine e = engine_of(ctx);
     bool sampled = false;
-    ss_status st = enqueue_start(e, w, p, set_begin, nroots, s, &sampled);
+    ss_status st = enqueue_start(e, w, p, set_begin, nroots, s, &sampled, started);
     if (st != SS_OK) return st;
     int cur = 0;
     for (uint32_t level = 0;; ++level) {
@@ -601,17 +609,46 @@ ss_status run_sort(ss_ctx* ctx, const uint8_t* chars, const uint64_t* offsets, u
     if (ctx->done_recorded) SS_TRY(hipStreamWaitEvent(s, ctx->done, 0));
     Work w = ctx->ws.work;
     if (set_begin) w.set_base = set_begin;  // perm entries are set-local
-    Params p{chars, offsets, n, perm, lcp, ctx->cfg.max_log_splitters, ctx->cfg.bucket_target, ctx->cfg.base_max};
+    Params p{chars,
+             offsets,
+             n,
+             perm,
+             lcp,
+             ctx->cfg.max_log_splitters,
+             ctx->cfg.bucket_target,
+             ctx->cfg.base_max,
+             ctx->cfg.alphabet};
     const uint32_t nroots = set_begin ? num_sets : 1;
-    if (ctx->cfg.mode == SS_MODE_PERSISTENT) {
+    if (ctx->cfg.mode == SS_MODE_PERSISTENT) {  // the persistent kernel reads the key format on the device
         SS_TRY(launch_reset(w, s));
+        SS_TRY(timed(&ctx->prof, s, K_ALPHABET, units_const(n),
+                     [&] { return launch_alphabet(w, p, ctx->kc.classify, s); }));
         SS_TRY(timed(&ctx->prof, s, K_PERSIST, units_const(n), [&] {
             return launch_persistent(w, p, set_begin, nroots, ctx->kc.persist, true, 0, 0, false, s);
         }));
-    } else if (ctx->cfg.mode == SS_MODE_HOST_LEVELS) {
-        if ((st = run_sort_host_levels(ctx, w, p, set_begin, nroots, s)) != SS_OK) return st;
     } else {
-        if ((st = enqueue_sort_levels(engine_of(ctx), w, p, set_begin, nroots, levels, s)) != SS_OK) return st;
+        // the level kernels come in a byte-key and a compressed-key form; the
+        // host picks one, so a sort that may compress its keys first waits
+        // for the alphabet kernels
+        bool started = false;
+        if (p.alphabet != SS_ALPHABET_BYTES) {
+            SS_TRY(launch_reset(w, s));
+            SS_TRY(timed(&ctx->prof, s, K_ALPHABET, units_const(n),
+                         [&] { return launch_alphabet(w, p, ctx->kc.classify, s); }));
+            decltype(Ctl::alpha) a;
+            SS_TRY(hipMemcpyAsync(&a, &w.ctl->alpha, sizeof(a), hipMemcpyDeviceToHost, s));
+            SS_TRY(hipStreamSynchronize(s));
+            uint64_t m[4] = {0, 0, 0, 0};
+            if (a.cand && !a.over)
+                for (int q = 0; q < 4; ++q) m[q] = a.seen[q];
+            p.ac = key_fmt_of(m).bpc != 0 ? 1u : 0u;
+            started = true;
+        }
+        if (ctx->cfg.mode == SS_MODE_HOST_LEVELS) {
+            if ((st = run_sort_host_levels(ctx, w, p, set_begin, nroots, s, started)) != SS_OK) return st;
+        } else if ((st = enqueue_sort_levels(engine_of(ctx), w, p, set_begin, nroots, levels, s, started)) != SS_OK) {
+            return st;
+        }
     }
     SS_TRY(hipMemcpyAsync(ctx->host_ctl, w.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
     SS_TRY(hipEventRecord(ctx->done, s));
@@ -808,6 +845,7 @@ ss_status run_suffix_array(ss_ctx* ctx, const uint8_t* text, uint32_t n, uint32_
         ~CfgGuard() { c->cfg = saved; }
     } guard{ctx, ctx->cfg};
     ctx->cfg.bucket_target = std::max<uint32_t>(ctx->cfg.bucket_target, 256u);
+    ctx->cfg.alphabet = SS_ALPHABET_BYTES;  // windows and name pairs are binary already
 
     SaArgs a{};
     a.n = n;
@@ -1015,7 +1053,7 @@ ss_status ss_set_config(ss_ctx* ctx, const ss_config* cfg) {
 
 ss_status ss_workspace_query(const ss_ctx* ctx, uint32_t n, size_t* bytes) {
     if (!bytes) return SS_INVALID_ARG;
-    ss_config c = ctx ? ctx->cfg : ss_config{10, 64, 1024, SS_MODE_LEVELS};
+    ss_config c = ctx ? ctx->cfg : ss_config{10, 64, 1024, SS_MODE_LEVELS, SS_ALPHABET_BYTES};
     *bytes = layout(n, caps_for(n, c), nullptr, nullptr);
     return SS_OK;
 }
@@ -1054,7 +1092,7 @@ ss_status ss_sort_noalloc(const uint8_t* chars, const uint64_t* offsets, uint32_
     hipStream_t s = (hipStream_t)stream;
     Engine e;
     e.kc = &d->kc;  // no profiler, no library streams: every launch goes to `stream`
-    const Params p{chars, offsets, n, perm_out, lcp_out, 10, 64, 1024};
+    const Params p{chars, offsets, n, perm_out, lcp_out, 10, 64, 1024, SS_ALPHABET_BYTES};
     ss_status st = enqueue_sort_levels(e, d->work, p, nullptr, 1, NOALLOC_LEVELS, s);
     if (st == SS_OK && err_out) st = hip_status(launch_report(d->work, err_out, s));
     return st;
@@ -1087,7 +1125,7 @@ ss_status ss_graph_create_batch(ss_ctx* ctx, const uint8_t* chars, const uint64_
     gr->ctx = ctx;
     if ((st = ws_ensure(gr->ws, n, ctx->cfg, ctx->scratch_limit)) != SS_OK) return st;
     Params p{chars, offsets, n, perm_out, lcp_out, ctx->cfg.max_log_splitters, ctx->cfg.bucket_target,
-             ctx->cfg.base_max};
+             ctx->cfg.base_max, ctx->cfg.alphabet};
     Work w = gr->ws.work;
     w.set_base = set_begin;
     hipStream_t cs = nullptr;
@@ -1097,7 +1135,7 @@ ss_status ss_graph_create_batch(ss_ctx* ctx, const uint8_t* chars, const uint64_
     // sizing run: the batched sort once, level by level from the host, on
     // the graph's workspace; the graph enqueues as many level launches as it
     // needed (a persistent tail runs any further levels of later contents)
-    st = run_sort_host_levels(ctx, w, p, set_begin, num_sets, cs);
+    st = run_sort_host_levels(ctx, w, p, set_begin, num_sets, cs, false);
     if (st == SS_OK) st = read_ctl(ctx, w, cs);
     if (st == SS_OK && ctx->host_ctl->err) st = device_error_status(ctx->host_ctl->err);
     hipGraph_t g = nullptr;
@@ -1263,7 +1301,7 @@ ss_status ss_autotune(ss_ctx* ctx, const uint8_t* chars, const uint64_t* offsets
     // parameters
     for (uint32_t d : {8u, 9u, 10u})
         for (uint32_t bt : {32u, 64u, 128u})
-            for (uint32_t bm : {512u, 1024u}) consider(ss_config{d, bt, bm, SS_MODE_LEVELS});
+            for (uint32_t bm : {512u, 1024u}) consider(ss_config{d, bt, bm, SS_MODE_LEVELS, start.alphabet});
     if (top_ms >= 0) {
         for (uint32_t m : {SS_MODE_HOST_LEVELS, SS_MODE_PERSISTENT}) {
             ss_config pc = top;
@@ -1431,6 +1469,34 @@ uint64_t ss_host_gather_key(const uint8_t* chars, uint64_t off, uint32_t h, uint
         std::memcpy(&w, q, sizeof(w));
         return w;
     });
+}
+
+uint64_t ss_host_gather_packed(const uint8_t* chars, uint64_t off, uint32_t h, uint32_t len, const uint64_t* byte_set,
+                               uint32_t* chars_per_key, int* miss) {
+    uint64_t m[4] = {0, 0, 0, 0};
+    if (byte_set)
+        for (int i = 0; i < 4; ++i) m[i] = byte_set[i];
+    const KeyFmt f = key_fmt_of(m);
+    if (chars_per_key) *chars_per_key = f.bpc ? f.cpw : W;
+    bool mi = false;
+    const uint64_t k = f.bpc ? gather_packed_with(chars, off, h, len, f,
+                                                  [](const uint64_t* q) {
+                                                      uint64_t w;
+                                                      std::memcpy(&w, q, sizeof(w));
+                                                      return w;
+                                                  },
+                                                  &mi)
+                             : ss_host_gather_key(chars, off, h, len);
+    if (miss) *miss = mi ? 1 : 0;
+    return k;
+}
+
+uint32_t ss_host_key_lcp(const uint64_t* byte_set, uint64_t a, uint32_t len_a, uint64_t b, uint32_t len_b, uint32_t h) {
+    uint64_t m[4] = {0, 0, 0, 0};
+    if (byte_set)
+        for (int i = 0; i < 4; ++i) m[i] = byte_set[i];
+    const KeyFmt f = key_fmt_of(m);
+    return kf_lcp_word(f, a, kf_r(f, len_a, h), b, kf_r(f, len_b, h));
 }
 
 uint32_t ss_host_level_index(uint32_t j, uint32_t d) { return level_index(j, d); }

@@ -53,6 +53,107 @@ SS_HD uint32_t common_bytes(uint64_t a, uint64_t b) {
     return x ? (uint32_t)(__builtin_clzll(x) >> 3) : 8u;
 }
 
+// Key format of a sort.  Byte keys (bpc = 0): 8 characters per word, as
+// above.  Alphabet-compressed keys (alphabet compression, §4.6.1): when the
+// strings use at most 15 distinct bytes, a character is coded as 1 + its
+// rank among the bytes present, in bpc = 2, 3 or 4 bits, 0 marking the end
+// of the string, and a key word holds cpw = 64 / bpc characters (32, 21 or
+// 16), most significant first.  The codes keep the byte order and the end
+// code is below every character, so keys compare like the strings' next
+// cpw characters; equal keys mean equal characters and an equal end.
+struct KeyFmt {
+    uint32_t bpc;       // 0: byte keys
+    uint32_t cpw;       // characters per key word
+    uint64_t m[4];      // bytes present (bit c of the 256-bit set)
+    uint32_t pre[4];    // bytes present below 64 * i
+};
+// Builds the compressed format of the byte set `m` (at most 15 members);
+// byte keys when the set has fewer than 1 or more than 15 members.
+SS_HD KeyFmt key_fmt_of(const uint64_t (&m)[4]) {
+    KeyFmt f{};
+    uint32_t s = 0;
+    for (int i = 0; i < 4; ++i) {
+        f.m[i] = m[i];
+        f.pre[i] = s;
+        s += (uint32_t)__builtin_popcountll(m[i]);
+    }
+    if (s < 1 || s > 15) {
+        f.bpc = 0;
+        f.cpw = W;
+    } else {
+        f.bpc = s <= 3 ? 2u : s <= 7 ? 3u : 4u;
+        f.cpw = 64u / f.bpc;
+    }
+    return f;
+}
+// Word i (0..3) of the set and the members below it, chosen by selects (a
+// per-lane index into the arrays would place them in scratch memory).
+SS_HD uint64_t kf_word(const KeyFmt& f, uint32_t i) {
+    const uint64_t m0 = f.m[0], m1 = f.m[1], m2 = f.m[2], m3 = f.m[3];
+    const uint64_t lo = (i & 1u) ? m1 : m0, hi = (i & 1u) ? m3 : m2;
+    return (i & 2u) ? hi : lo;
+}
+SS_HD uint32_t kf_pre(const KeyFmt& f, uint32_t i) {
+    const uint32_t p0 = f.pre[0], p1 = f.pre[1], p2 = f.pre[2], p3 = f.pre[3];
+    const uint32_t lo = (i & 1u) ? p1 : p0, hi = (i & 1u) ? p3 : p2;
+    return (i & 2u) ? hi : lo;
+}
+// Code of byte c (1 + rank among the bytes present).
+SS_HD uint32_t kf_code(const KeyFmt& f, uint32_t c) {
+    const uint32_t i = c >> 6;
+    const uint64_t below = kf_word(f, i) & ((1ull << (c & 63)) - 1);  // c & 63 < 64
+    return 1u + kf_pre(f, i) + (uint32_t)__builtin_popcountll(below);
+}
+// Whether byte c is in the set.
+SS_HD bool kf_has(const KeyFmt& f, uint32_t c) { return (kf_word(f, c >> 6) >> (c & 63)) & 1u; }
+// Characters of a string inside its word at depth h, as kept in a record:
+// r = min(len - h, cpw) for byte keys; for compressed keys 8 when the
+// string fills the word (r = cpw), else min(r, 7) — the exact count is read
+// off the key (kf_chars) where it is needed.  Either way a record's code is
+// 8 exactly when the string continues past the word, and equal keys have
+// equal codes.
+SS_HD uint32_t kf_r(const KeyFmt& f, uint32_t len, uint32_t h) {
+    const uint32_t cpw = f.bpc ? f.cpw : W;
+    const uint32_t r = len > h ? (len - h < cpw ? len - h : cpw) : 0u;
+    if (f.bpc == 0) return r;
+    return r == cpw ? W : (r < 7u ? r : 7u);
+}
+// Characters per key word: the depth step of an equality bucket or a tied run.
+SS_HD uint32_t kf_step(const KeyFmt& f) { return f.bpc ? f.cpw : W; }
+// Characters of the string inside a compressed key (codes before the first 0).
+SS_HD uint32_t kf_chars(const KeyFmt& f, uint64_t key) {
+    return key ? (63u - (uint32_t)__builtin_ctzll(key)) / f.bpc + 1u : 0u;
+}
+// Characters of the word past depth h that a string shares with the key of
+// an identical string (equal keys, code rc < 8): rc for byte keys.
+SS_HD uint32_t kf_tail(const KeyFmt& f, uint64_t key, uint32_t rc) { return f.bpc ? kf_chars(f, key) : rc; }
+// The compressed key of the string [off, off + len) at depth h: its next
+// min(len - h, cpw) bytes coded, most significant first, 0 past the end.
+// Reads, through `load`, only the aligned words that hold those bytes.
+// *miss is set when one of them is not in the set.
+template <typename Load>
+SS_HD uint64_t gather_packed_with(const uint8_t* chars, uint64_t off, uint32_t h, uint32_t len, const KeyFmt& f,
+                                  Load load, bool* miss) {
+    uint32_t rem = len > h ? len - h : 0u;
+    rem = rem < f.cpw ? rem : f.cpw;
+    uint64_t key = 0;
+    if (rem == 0) return 0;
+    const uintptr_t a = (uintptr_t)(chars + off + h);
+    const uint64_t* p = (const uint64_t*)(a & ~(uintptr_t)7);
+    uint32_t sh = (uint32_t)(a & 7);
+    uint32_t k = 0;  // characters coded so far
+    while (k < rem) {
+        const uint64_t wd = load(p++);
+        for (; sh < 8u && k < rem; ++sh, ++k) {
+            const uint32_t c = (uint32_t)(wd >> (8 * sh)) & 0xFFu;
+            if (!kf_has(f, c)) *miss = true;
+            key |= (uint64_t)kf_code(f, c) << (64 - f.bpc * (k + 1));
+        }
+        sh = 0;
+    }
+    return key;
+}
+
 // LCP contribution of one word: the strings agree on the first
 // common_bytes(a, b) characters of the word, but not beyond the end of the
 // shorter string (ra, rb = characters of each string inside the word).
@@ -60,6 +161,14 @@ SS_HD uint32_t lcp_word(uint64_t a, uint32_t ra, uint64_t b, uint32_t rb) {
     uint32_t c = common_bytes(a, b);
     c = c < ra ? c : ra;
     return c < rb ? c : rb;
+}
+// Characters a string inside its word shares with the next: lcp_word for
+// byte keys; for compressed keys the equal leading codes, or the string's
+// characters when the keys are equal.
+SS_HD uint32_t kf_lcp_word(const KeyFmt& f, uint64_t a, uint32_t ra, uint64_t b, uint32_t rb) {
+    if (f.bpc == 0) return lcp_word(a, ra, b, rb);
+    const uint64_t x = a ^ b;
+    return x ? (uint32_t)__builtin_clzll(x) / f.bpc : kf_chars(f, a);
 }
 
 // Total order on (key, r) pairs: the 8 characters first, then the number

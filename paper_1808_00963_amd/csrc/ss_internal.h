@@ -150,6 +150,21 @@ struct Ctl {
     } base_rounds[ROUND_LINES];
     DevStats stats;
     LevelRec lv[LEVEL_RECS];
+    // Alphabet of the sort (the key format follows from it, see KeyFmt):
+    // the probe sets `cand` when a sample of the strings shows at most
+    // `limit` distinct bytes and records them in `seen`; the check adds every
+    // other byte of the input to `seen` and sets `over` once more than
+    // `limit` are known.  Compressed keys exactly when cand && !over.
+    // The key gather (k_init) also writes the resulting code width and
+    // characters per word for the kernels after it (bpc = 0: byte keys).
+    struct alignas(128) {
+        uint32_t cand;
+        uint32_t over;
+        uint32_t bpc;
+        uint32_t cpw;
+        uint64_t seen[4];
+        uint32_t limit;  // most bytes the set may hold for compressed keys
+    } alpha;
 };
 inline uint32_t base_rounds_of(const Ctl& c) {
     uint32_t t = 0;
@@ -241,7 +256,11 @@ struct Params {
     uint32_t max_logv;
     uint32_t bucket_target;
     uint32_t base_max;
+    uint32_t alphabet;  // ALPHABET_*: which inputs get alphabet-compressed keys
+    uint32_t ac;        // the sort's keys are compressed (known to the host before the key gather)
 };
+// The C ABI's SS_ALPHABET_AUTO, _BYTES and _COMPRESS.
+constexpr uint32_t ALPHABET_AUTO = 0, ALPHABET_BYTES = 1, ALPHABET_COMPRESS = 2;
 
 // ---- launchers (ss_kernels.hip) ----
 // Every kernel of a recursion level reads its work counts from the control
@@ -251,6 +270,10 @@ struct Params {
 // it from what it knows (exact counts, or the pool capacities and the
 // device's resident capacity).
 hipError_t launch_reset(const Work& w, hipStream_t s);
+// The sort's alphabet (after launch_reset, before launch_init): a probe of
+// a sample of the strings, then, when it found at most 15 distinct bytes, a
+// check of every byte of the input.
+hipError_t launch_alphabet(const Work& w, const Params& p, uint32_t check_grid, hipStream_t s);
 hipError_t launch_init(const Work& w, const Params& p, hipStream_t s);
 hipError_t launch_roots(const Work& w, const Params& p, const uint32_t* set_begin, uint32_t num_sets,
                         hipStream_t s);

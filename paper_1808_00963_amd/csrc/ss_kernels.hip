@@ -43,16 +43,6 @@ __device__ __forceinline__ void rec_put(const Work& w, int buf, uint32_t i, uint
     if (w.wide) w.rw[buf][i] = (uint8_t)r;
 }
 
-// A string of an equality bucket moves on to depth h: its key there and the
-// number of its characters inside that key, from its offsets (the length is
-// not carried with the record).
-__device__ __forceinline__ void regather(const Params& p, uint32_t idx, uint32_t h, uint64_t& key, uint32_t& r) {
-    const uint64_t o0 = p.offsets[idx], o1 = p.offsets[idx + 1];
-    const uint32_t len = (uint32_t)(o1 - o0);
-    key = gather_key(p.chars, o0, h, len);
-    r = len > h ? min_u32(len - h, W) : 0u;
-}
-
 // Two counters in one 64-bit atomic word (low, high); neither half of a
 // level's counters reaches 2^32, so no carry crosses.
 __device__ __forceinline__ unsigned long long pack2(uint32_t lo, uint32_t hi) {
@@ -130,6 +120,85 @@ __device__ __forceinline__ uint32_t xcd_item(uint32_t b, uint32_t nt) {
 // mailbox), marked uniform so that what is derived from it (segment fields,
 // addresses) stays in scalar registers.
 __device__ __forceinline__ uint32_t uniform(uint32_t x) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)x); }
+
+// The sort's key format (KeyFmt; chosen by the alphabet kernels below and
+// kept in the control block).  fmt_full derives it from the byte set (the
+// key gather and the first sampling, and every compressed gather);
+// fmt_head reads the code width and characters per word that the key
+// gather stored, enough for everything but a gather (kernels that only
+// compare keys do not hold the set).
+__device__ __forceinline__ bool fmt_compressed(const Work& w) {
+    return uniform(w.ctl->alpha.cand) != 0u && uniform(w.ctl->alpha.over) == 0u;
+}
+__device__ __forceinline__ KeyFmt fmt_full(const Work& w) {
+    uint64_t m[4] = {0, 0, 0, 0};
+    if (fmt_compressed(w)) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const uint64_t v = w.ctl->alpha.seen[i];
+            m[i] = (uint64_t)uniform((uint32_t)v) | (uint64_t)uniform((uint32_t)(v >> 32)) << 32;
+        }
+    }
+    return key_fmt_of(m);  // byte keys for an empty set
+}
+__device__ __forceinline__ KeyFmt fmt_head(const Work& w) {
+    KeyFmt h{};
+    h.bpc = uniform(w.ctl->alpha.bpc);
+    h.cpw = uniform(w.ctl->alpha.cpw);
+    return h;
+}
+// The key format as a compile-time choice: kernels instantiate their
+// bodies for byte keys and for compressed keys and pick one per sort, so
+// the byte-key body carries none of the compressed code.
+template <bool AC>
+__device__ __forceinline__ KeyFmt fmt_of(const Work& w) {
+    if constexpr (AC) {
+        return fmt_head(w);
+    } else {
+        KeyFmt f{};
+        f.bpc = 0;
+        f.cpw = W;
+        return f;
+    }
+}
+// Stores the code width and characters per word for fmt_head (one thread
+// of the key gather).
+__device__ __forceinline__ void fmt_publish(const Work& w, const KeyFmt& f) {
+    w.ctl->alpha.bpc = f.bpc;
+    w.ctl->alpha.cpw = f.cpw;
+}
+// chars_h in the sort's key format.
+__device__ __forceinline__ uint64_t key_at_packed(const Work& w, const uint8_t* chars, uint64_t off, uint32_t h,
+                                                  uint32_t len) {
+    const KeyFmt f = fmt_full(w);
+    bool miss = false;  // every byte of the input is in the set (checked before the sort)
+    return gather_packed_with(chars, off, h, len, f, [](const uint64_t* q) { return __builtin_nontemporal_load(q); },
+                              &miss);
+}
+__device__ __forceinline__ uint64_t key_at(const Work& w, const KeyFmt& fh, const uint8_t* chars, uint64_t off,
+                                           uint32_t h, uint32_t len) {
+    if (fh.bpc == 0) return gather_key(chars, off, h, len);
+    return key_at_packed(w, chars, off, h, len);
+}
+// The same as a call: the scatter's write loop and the base cases'
+// refinement, at their register budgets, keep the compressed gather out of
+// line.
+__device__ __attribute__((noinline)) uint64_t key_at_packed_call(const Work& w, const uint8_t* chars, uint64_t off,
+                                                                 uint32_t h, uint32_t len) {
+    return key_at_packed(w, chars, off, h, len);
+}
+
+// A string of an equality bucket moves on to depth h: its key there and the
+// code of its characters inside that key, from its offsets (the length is
+// not carried with the record).
+__device__ __forceinline__ void regather(const Work& w, const KeyFmt& fh, const Params& p, uint32_t idx, uint32_t h,
+                                         uint64_t& key, uint32_t& r) {
+    const uint64_t o0 = p.offsets[idx], o1 = p.offsets[idx + 1];
+    const uint32_t len = (uint32_t)(o1 - o0);
+    key = fh.bpc == 0 ? gather_key(p.chars, o0, h, len) : key_at_packed_call(w, p.chars, o0, h, len);
+    r = kf_r(fh, len, h);
+}
+
 
 // One item of the dynamic part [first, n) for a work group (n when none is
 // left).
@@ -334,17 +403,24 @@ __global__ void k_level_begin(Work w, int cur, uint32_t level) {
 
 // Key gather at depth 0 for every string (Algorithm 4.1's chars_h with
 // h = 0), plus offset validation.
-__device__ __forceinline__ void dev_init_one(const Work& w, const Params& p, uint32_t i) {
+__device__ __forceinline__ void dev_init_one(const Work& w, const KeyFmt& fh, const Params& p, uint32_t i) {
     uint64_t o0 = p.offsets[i], o1 = p.offsets[i + 1];
     uint32_t len = 0;
     if (o1 < o0 || o1 - o0 > MAX_LEN || (o1 > o0 && p.chars == nullptr)) raise_err(w, ERR_OFFSETS);
     else len = (uint32_t)(o1 - o0);
-    rec_put(w, 0, i, gather_key(p.chars, o0, 0, len), i, min_u32(len, W));
+    rec_put(w, 0, i, key_at(w, fh, p.chars, o0, 0, len), i, kf_r(fh, len, 0));
 }
 
+template <bool AC>
 __global__ __launch_bounds__(BLOCK) void k_init(Work w, Params p) {
     uint32_t i = blockIdx.x * BLOCK + threadIdx.x;
-    if (i < p.n) dev_init_one(w, p, i);
+    if constexpr (AC) {
+        const KeyFmt f = fmt_full(w);
+        if (i == 0) fmt_publish(w, f);
+        if (i < p.n) dev_init_one(w, f, p, i);
+    } else {
+        if (i < p.n) dev_init_one(w, fmt_of<false>(w), p, i);
+    }
 }
 
 // One root segment per set (one set = the whole input for a plain sort).
@@ -581,9 +657,15 @@ __device__ __forceinline__ uint64_t p1_key(uint64_t x, uint64_t pre, uint32_t sh
     return pre | shr_key(x & ~0xFFFFull, sh);  // sh >= 16: the low 16 bits hold r and position
 }
 __device__ __forceinline__ uint32_t p1_r(uint64_t x, uint32_t pb) { return (uint32_t)(x >> pb) & 0xFu; }
-// LCP contribution of the words of two one-word records (their r values
-// r1, r0) whose keys share c leading bytes, as lcp_word gives it
-__device__ __forceinline__ uint32_t p1_lcp(uint64_t x1, uint32_t r1, uint64_t x0, uint32_t r0, uint32_t c) {
+// LCP contribution of the words of two one-word records (their r codes
+// r1, r0) whose keys share their first c bytes (sh = 8c bits), as
+// kf_lcp_word gives it for the full keys (`pre` holds the shared bytes)
+__device__ __forceinline__ uint32_t p1_lcp(const KeyFmt& fh, uint64_t x1, uint32_t r1, uint64_t x0, uint32_t r0,
+                                           uint32_t c, uint64_t pre, uint32_t sh) {
+    if (fh.bpc) {
+        const uint64_t d = (x1 ^ x0) & ~0xFFFFull;
+        return d ? (sh + (uint32_t)__builtin_clzll(d)) / fh.bpc : kf_chars(fh, p1_key(x1, pre, sh));
+    }
     uint32_t cb = c + common_bytes(x1 & ~0xFFFFull, x0 & ~0xFFFFull);
     cb = cb < W ? cb : W;
     cb = cb < r0 ? cb : r0;
@@ -684,7 +766,7 @@ __device__ __forceinline__ void base_wave_recs(const Work& w, int cur, const Bas
 // re-gathered only for those strings), LCP of neighbours from the word at
 // the depth where they separate.  Depth and LCP are kept per position
 // (a run never moves), keys and records move.
-template <int E>
+template <int E, bool AC>
 __device__ void dev_base_wave_run(const Work& w, const Params& p, int cur, const BaseDesc& in, const Rec (&X)[E],
                                   uint32_t si, SmWave& sm) {
     auto& LIDX = sm.LIDX;
@@ -693,6 +775,7 @@ __device__ void dev_base_wave_run(const Work& w, const Params& p, int cur, const
     if (!in.ok) return;  // uniform per wave
     const BaseSeg& sg = in.sg;
     const uint32_t m = sg.size, h = sg.depth;
+    const KeyFmt fh = fmt_of<AC>(w);
     uint32_t rounds = 0;
     uint64_t K[E], A[E];
     uint32_t D[E], LV[E];
@@ -737,6 +820,7 @@ __device__ void dev_base_wave_run(const Work& w, const Params& p, int cur, const
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         // neighbours: equal words with r = 8 tie, else the LCP is final
+        const uint64_t pre = k0 & ~shr_key(~0ull, sh);
         const uint64_t pl = __shfl_up(P[E - 1], 1, 64);
         uint32_t tb = 0;
 #pragma unroll
@@ -746,7 +830,7 @@ __device__ void dev_base_wave_run(const Work& w, const Params& p, int cur, const
             if (e > 0 && e < m) {
                 const uint32_t r1 = p1_r(P[r], PB), r0 = p1_r(q, PB);
                 if (((P[r] ^ q) >> PB) == 0 && r1 == W) tb |= 1u << r;
-                else LV[r] = h + p1_lcp(P[r], r1, q, r0, c);
+                else LV[r] = h + p1_lcp(fh, P[r], r1, q, r0, c, pre, sh);
             }
         }
         if (__ballot(tb != 0) == 0) {  // no ties: order and LCPs are final
@@ -762,7 +846,6 @@ __device__ void dev_base_wave_run(const Work& w, const Params& p, int cur, const
             if (lane == 0 && w.remaining) atomicSub(&w.remaining[sg.rid], m);
             return;
         }
-        const uint64_t pre = k0 & ~shr_key(~0ull, sh);
 #pragma unroll
         for (uint32_t r = 0; r < (uint32_t)E; ++r) {
             const uint32_t e = lane * E + r;
@@ -804,7 +887,7 @@ __device__ void dev_base_wave_run(const Work& w, const Params& p, int cur, const
                 // same group: equal words with r = 8 tie, else the LCP is final
                 const uint32_t r1 = pr_r(A[r]), r0 = pr_r(pa);
                 if (K[r] == pk && (A[r] >> 32) == (pa >> 32) && r1 == 8) tb |= 1u << r;
-                else LV[r] = D[r] + lcp_word(pr_key(pk, pa), r0, pr_key(K[r], A[r]), r1);
+                else LV[r] = D[r] + kf_lcp_word(fh, pr_key(pk, pa), r0, pr_key(K[r], A[r]), r1);
             }
         }
         if (__ballot(tb != 0) == 0) break;
@@ -846,7 +929,7 @@ __device__ void dev_base_wave_run(const Work& w, const Params& p, int cur, const
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         // common prefix of each run: members' LCP with the leader's string,
-        // starting 8 characters past the shared word; every string of a run
+        // starting past the shared word; every string of a run
         // keeps its offset and length for the re-gather below
         uint64_t OA[E];
         uint32_t LA[E];
@@ -865,7 +948,7 @@ __device__ void dev_base_wave_run(const Work& w, const Params& p, int cur, const
             const uint32_t b = LIDX[wv][RS[r]];
             const uint64_t ob = p.offsets[b];
             const uint32_t lb = (uint32_t)(p.offsets[b + 1] - ob);
-            atomicMin(&RMIN[wv][RS[r]], lcp_from(p.chars, oa, la, ob, lb, D[r] + W));
+            atomicMin(&RMIN[wv][RS[r]], lcp_from(p.chars, oa, la, ob, lb, D[r] + kf_step(fh)));
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
@@ -878,7 +961,9 @@ __device__ void dev_base_wave_run(const Work& w, const Params& p, int cur, const
             if ((act >> r) & 1u) {
                 const uint32_t d2 = RMIN[wv][RS[r]];
                 D[r] = d2;
-                pr_pack(RS[r], gather_key(p.chars, OA[r], d2, LA[r]), rem8(LA[r], d2), idx, K[r], A[r]);
+                const uint64_t key2 = fh.bpc == 0 ? gather_key(p.chars, OA[r], d2, LA[r])
+                                                  : key_at_packed_call(w, p.chars, OA[r], d2, LA[r]);
+                pr_pack(RS[r], key2, kf_r(fh, LA[r], d2), idx, K[r], A[r]);
             } else {
                 K[r] = pr_regroup(K[r], e);
             }
@@ -904,22 +989,21 @@ __device__ void dev_base_wave(const Work& w, const Params& p, int cur, int cls, 
     const BaseDesc d = base_wave_desc<E>(w, p, cur, cls, si, nseg);
     Rec x[E];
     base_wave_recs<E>(w, cur, d, x);
-    dev_base_wave_run<E>(w, p, cur, d, x, si, sm);
+    if (fmt_head(w).bpc) dev_base_wave_run<E, true>(w, p, cur, d, x, si, sm);
+    else dev_base_wave_run<E, false>(w, p, cur, d, x, si, sm);
 }
 
 // Waves take segments: wave g of the launch takes segment g, then chunks
 // of its XCD's part of the rest.
-constexpr uint32_t BASE_WAVE_CHUNK = 2;
+constexpr uint32_t BASE_WAVE_CHUNK = 4;
 // The item loops of the level kernels keep values of the loop around that a
 // one-item kernel would recompute; each kernel's register budget is pinned
 // to the occupancy its one-item body reaches (the waves that hide the
 // latency of its global loads matter more than the recomputation).
 template <int E>
 constexpr int base_wave_occupancy() { return E == 1 ? 7 : E == 2 ? 6 : 4; }
-template <int E>
-__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(base_wave_occupancy<E>())))
-void k_base_wave(Work w, Params p, int cur, int cls) {
-    __shared__ SmWave sm;
+template <int E, bool AC>
+__device__ __forceinline__ void base_wave_loop(const Work& w, const Params& p, int cur, int cls, SmWave& sm) {
     const uint32_t n = n_base_of(w, cur, cls);
     const uint32_t lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const uint32_t G = gridDim.x * WAVES, g = blockIdx.x * WAVES + wv;
@@ -938,7 +1022,7 @@ void k_base_wave(Work w, Params p, int cur, int cls) {
             Rec x[E];
             base_wave_recs<E>(w, cur, d, x);
             const BaseDesc nd = base_wave_desc<E>(w, p, cur, cls, si + 1 < hi ? si + 1 : n, n);
-            dev_base_wave_run<E>(w, p, cur, d, x, si, sm);
+            dev_base_wave_run<E, AC>(w, p, cur, d, x, si, sm);
             d = nd;
         }
         ok = (uint32_t)__builtin_amdgcn_readfirstlane((int)ok);
@@ -946,6 +1030,12 @@ void k_base_wave(Work w, Params p, int cur, int cls) {
         lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)nlo);
         hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)nhi);
     }
+}
+template <int E, bool AC>
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(base_wave_occupancy<E>())))
+void k_base_wave(Work w, Params p, int cur, int cls) {
+    __shared__ SmWave sm;
+    base_wave_loop<E, AC>(w, p, cur, cls, sm);
 }
 
 // ---------------------------------------------------------------------------
@@ -1044,6 +1134,7 @@ __device__ void lds_block_sort1(uint64_t* H, uint32_t NB) {
 // LCPs of neighbours separated at depth d are d plus the common bytes of
 // their words at d (the "last compared word"); the role of LCP-insertion
 // sort (Algorithm 4.6) as the paper's base case.
+template <bool AC>
 __device__ void dev_base_wg(const Work& w, const Params& p, int cur, uint32_t item, uint32_t nseg, SmBase& sm) {
     uint64_t* K = sm.K;
     uint64_t* A = sm.A;
@@ -1058,6 +1149,7 @@ __device__ void dev_base_wg(const Work& w, const Params& p, int cur, uint32_t it
     if (item >= nseg) return;  // uniform
     const BaseSeg sg = w.base[CLS_WG][cur][item];
     const uint32_t tid = threadIdx.x, m = sg.size, h = sg.depth;
+    const KeyFmt fh = fmt_of<AC>(w);
     uint32_t rounds = 0;
     if (m < 2 || m > BASE_CAP || m > p.base_max || sg.begin > p.n || m > p.n - sg.begin) {  // uniform
         if (tid == 0) raise_err(w, ERR_BOUNDS);
@@ -1105,11 +1197,12 @@ __device__ void dev_base_wg(const Work& w, const Params& p, int cur, uint32_t it
         if (tid == 0) any = 0;
         __syncthreads();
         lds_block_sort1(K, P / 256);
+        const uint64_t pre = k0 & ~shr_key(~0ull, sh);
         for (uint32_t i = tid + 1; i < m; i += BLOCK) {
             const uint64_t x = K[i], q = K[i - 1];
             const uint32_t r1 = p1_r(x, PB), r0 = p1_r(q, PB);
             if (((x ^ q) >> PB) == 0 && r1 == W) any = 1;
-            else lv[i] = h + p1_lcp(x, r1, q, r0, c);
+            else lv[i] = h + p1_lcp(fh, x, r1, q, r0, c, pre, sh);
         }
         __syncthreads();
         if (!any) {  // no ties: order and LCPs are final
@@ -1121,7 +1214,6 @@ __device__ void dev_base_wg(const Work& w, const Params& p, int cur, uint32_t it
             if (tid == 0 && w.remaining) atomicSub(&w.remaining[sg.rid], m);
             return;
         }
-        const uint64_t pre = k0 & ~shr_key(~0ull, sh);
         for (uint32_t i = tid; i < m; i += BLOCK) {
             const uint64_t x = K[i];
             pr_pack(0, p1_key(x, pre, sh), p1_r(x, PB), aux[p1_pos(x, PB)], K[i], A[i]);
@@ -1145,7 +1237,7 @@ __device__ void dev_base_wg(const Work& w, const Params& p, int cur, uint32_t it
                 if (pr_grp(k1) == pr_grp(k0)) {
                     const uint32_t r1 = pr_r(a1), r0 = pr_r(a0);
                     if (k1 == k0 && (a1 >> 32) == (a0 >> 32) && r1 == 8) t = 1;
-                    else lv[i] = dep[i] + lcp_word(pr_key(k0, a0), r0, pr_key(k1, a1), r1);
+                    else lv[i] = dep[i] + kf_lcp_word(fh, pr_key(k0, a0), r0, pr_key(k1, a1), r1);
                 }
             }
             aux[i] = t << 31;
@@ -1193,7 +1285,7 @@ __device__ void dev_base_wg(const Work& w, const Params& p, int cur, uint32_t it
                 const uint32_t a = pr_idx(A[i]), b = pr_idx(A[rs]);
                 const uint64_t oa = p.offsets[a], ob = p.offsets[b];
                 const uint32_t la = (uint32_t)(p.offsets[a + 1] - oa), lb = (uint32_t)(p.offsets[b + 1] - ob);
-                atomicMin(&rmin[rs], lcp_from(p.chars, oa, la, ob, lb, dep[i] + W));
+                atomicMin(&rmin[rs], lcp_from(p.chars, oa, la, ob, lb, dep[i] + kf_step(fh)));
             }
         }
         __syncthreads();
@@ -1208,7 +1300,9 @@ __device__ void dev_base_wg(const Work& w, const Params& p, int cur, uint32_t it
                 dep[i] = d2;
                 const uint64_t o0 = p.offsets[idx], o1 = p.offsets[idx + 1];
                 const uint32_t len = (uint32_t)(o1 - o0);
-                pr_pack(rs, gather_key(p.chars, o0, d2, len), rem8(len, d2), idx, K[i], A[i]);
+                const uint64_t key2 = fh.bpc == 0 ? gather_key(p.chars, o0, d2, len)
+                                                  : key_at_packed_call(w, p.chars, o0, d2, len);
+                pr_pack(rs, key2, kf_r(fh, len, d2), idx, K[i], A[i]);
             } else {
                 K[i] = pr_regroup(K[i], i);
             }
@@ -1226,8 +1320,8 @@ __device__ void dev_base_wg(const Work& w, const Params& p, int cur, uint32_t it
 
 // Work groups take segments: group b takes segment b, then segments of its
 // XCD's part of the rest.
-__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void k_base(Work w, Params p, int cur) {
-    __shared__ SmBase sm;
+template <bool AC>
+__device__ __forceinline__ void base_wg_loop(const Work& w, const Params& p, int cur, SmBase& sm) {
     uint32_t& s_item = sm.wtot[0];  // item mailbox: wtot is first written after the body's first barrier
     const uint32_t n = n_base_of(w, cur, CLS_WG);
     const uint32_t s0 = min_u32(gridDim.x, n);
@@ -1236,12 +1330,17 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
     while (item < n) {
         uint32_t nxt = n;
         if (threadIdx.x == 0) nxt = feed_one(f, s0, n, blockIdx.x % FEED_PARTS);  // overlaps the work
-        dev_base_wg(w, p, cur, item, n, sm);
+        dev_base_wg<AC>(w, p, cur, item, n, sm);
         __syncthreads();
         if (threadIdx.x == 0) s_item = nxt;
         __syncthreads();
         item = uniform(s_item);
     }
+}
+template <bool AC>
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void k_base(Work w, Params p, int cur) {
+    __shared__ SmBase sm;
+    base_wg_loop<AC>(w, p, cur, sm);
 }
 
 
@@ -1280,8 +1379,9 @@ __device__ __forceinline__ void sample_sort(const Work& w, const Params& p, int 
                     const uint64_t o0 = p.offsets[pos], o1 = p.offsets[pos + 1];
                     const bool bad = o1 < o0 || o1 - o0 > MAX_LEN || (o1 > o0 && p.chars == nullptr);
                     const uint32_t len = bad ? 0u : (uint32_t)(o1 - o0);
-                    key = gather_key(p.chars, o0, 0, len);
-                    rr = min_u32(len, W);
+                    const KeyFmt fh = fmt_full(w);  // beside the key gather, which publishes the format
+                    key = key_at(w, fh, p.chars, o0, 0, len);
+                    rr = kf_r(fh, len, 0);
                 } else {
                     const Rec x = in[pos];
                     key = rec_key(x);
@@ -1695,13 +1795,16 @@ __device__ void dev_scatter(const Work& w, const Params& p, int cur, uint32_t t,
         const uint32_t pos = WC[wv][b] + rank;
         if (pos < sg.begin || pos >= seg_end) { raise_err(w, ERR_BOUNDS); continue; }
         if (b & 1u) {
-            const uint32_t rx = gr[level_index(b >> 1, d) - 1];
+            const uint32_t lx = level_index(b >> 1, d) - 1;
+            const uint32_t rx = gr[lx];
+            const KeyFmt fh = fmt_head(w);
             if (rx < W) {  // identical strings ending inside this word: final
                 p.perm[pos] = idx - obase;
-                if (pos != sg.begin + sc[(size_t)b * T] - s0) p.lcp[pos] = sg.depth + rx;
+                if (pos != sg.begin + sc[(size_t)b * T] - s0)
+                    p.lcp[pos] = sg.depth + kf_tail(fh, fh.bpc ? w.tree_key[cur][sg.tree_off + lx] : 0ull, rx);
                 continue;
             }
-            regather(p, idx, sg.depth + W, key, rr);
+            regather(w, fh, p, idx, sg.depth + kf_step(fh), key, rr);
         }
         rec_put(w, cur ^ 1, pos, key, idx, rr);
     }
@@ -1743,6 +1846,7 @@ struct SmScatterTile {
     uint32_t delta[MAX_BUCKETS + 1];    // tile totals, then global position - slot
 };
 
+template <bool AC>
 __device__ void dev_scatter_half(const Work& w, const Params& p, int cur, uint32_t ht, uint32_t n_dist,
                                  SmScatterTile& sm) {
     const uint32_t t = ht >> 1, half = ht & 1u;
@@ -1884,16 +1988,19 @@ __device__ void dev_scatter_half(const Work& w, const Params& p, int cur, uint32
         const uint32_t pos = sm.delta[b] + j;
         if (pos < sg.begin || pos >= seg_end) { raise_err(w, ERR_BOUNDS); continue; }
         if (b & 1u) {
-            const uint32_t rx = gr[level_index(b >> 1, d) - 1];
+            const uint32_t lx = level_index(b >> 1, d) - 1;
+            const uint32_t rx = gr[lx];
             const uint32_t idx = rec_idx(w, x);
+            const KeyFmt fh = fmt_of<AC>(w);
             if (rx < W) {  // identical strings ending inside this word: final
                 p.perm[pos] = idx - obase;
-                if (pos != sg.begin + sc[(size_t)b * T] - s0) p.lcp[pos] = sg.depth + rx;
+                if (pos != sg.begin + sc[(size_t)b * T] - s0)
+                    p.lcp[pos] = sg.depth + kf_tail(fh, fh.bpc ? w.tree_key[cur][sg.tree_off + lx] : 0ull, rx);
                 continue;
             }
             uint64_t key;
             uint32_t rr;
-            regather(p, idx, sg.depth + W, key, rr);
+            regather(w, fh, p, idx, sg.depth + kf_step(fh), key, rr);  // byte keys: inline gather
             x = rec_make(w, key, idx, rr);
             if (w.wide) w.rw[cur ^ 1][pos] = (uint8_t)rr;
         } else if (w.wide) {
@@ -1909,17 +2016,19 @@ __device__ void dev_scatter_half(const Work& w, const Params& p, int cur, uint32
 // L2.  A loop over several items here would cost the body two of its four
 // waves per SIMD (values of the loop would be held in registers), so the
 // half tiles beyond the grid are left to k_scatter_more.
+template <bool AC>
 __global__ __launch_bounds__(SC_THREADS) __attribute__((amdgpu_waves_per_eu(8))) void k_scatter(Work w, Params p, int cur) {
     __shared__ SmScatterTile sm;
     const uint32_t n_half = 2 * n_tiles_of(w, cur);
     const uint32_t m = min_u32(gridDim.x, n_half);
     if (blockIdx.x >= m) return;
-    dev_scatter_half(w, p, cur, xcd_item(blockIdx.x, m), n_dist_of(w, cur), sm);
+    dev_scatter_half<AC>(w, p, cur, xcd_item(blockIdx.x, m), n_dist_of(w, cur), sm);
 }
 
 // The half tiles from `first` on (first = k_scatter's grid), taken from the
 // feed by the work groups of its XCD; nothing to do in the common case of a
 // level with at most `first` half tiles.
+template <bool AC>
 __global__ __launch_bounds__(SC_THREADS) __attribute__((amdgpu_waves_per_eu(8)))
 void k_scatter_more(Work w, Params p, int cur, uint32_t first) {
     __shared__ SmScatterTile sm;
@@ -1938,7 +2047,7 @@ void k_scatter_more(Work w, Params p, int cur, uint32_t first) {
     while (ht < n_half) {
         uint32_t nxt = n_half;
         if (threadIdx.x == 0) nxt = feed_one(f, first, n_half, part);  // overlaps the work
-        dev_scatter_half(w, p, cur, ht, n_dist, sm);
+        dev_scatter_half<AC>(w, p, cur, ht, n_dist, sm);
         __syncthreads();
         if (threadIdx.x == 0) s_ht = nxt;
         __syncthreads();
@@ -1985,6 +2094,7 @@ __device__ void dev_children(const Work& w, const Params& p, int cur, uint32_t i
     const uint8_t* gr = w.tree_r[cur] + sg.tree_off;
     const Rec* out = w.rec[nxt];
     const uint32_t obase = w.set_base[sg.rid];
+    const uint32_t step = kf_step(fmt_head(w));
     // bucket b -> (start, count, child depth); depth == ~0u: no child segment
     auto bucket = [&](uint32_t b, uint32_t& st, uint32_t& cnt, uint32_t& depth) {
         st = sm.ST[b - lo];
@@ -1994,7 +2104,7 @@ __device__ void dev_children(const Work& w, const Params& p, int cur, uint32_t i
         depth = sg.depth;
         if (b & 1u) {
             if (gr[level_index(b >> 1, d) - 1] < W) depth = ~0u;  // identical strings, written by the scatter
-            else depth += W;
+            else depth += step;
         }
     };
     // shape of a distribution child of `cnt` strings
@@ -2131,8 +2241,9 @@ __device__ __forceinline__ void resolve_pending(const Work& w, const Params& p, 
     const uint64_t oa = p.offsets[a], ob0 = p.offsets[b];
     const uint32_t la = (uint32_t)(p.offsets[a + 1] - oa), lb = (uint32_t)(p.offsets[b + 1] - ob0);
     if (la < h || lb < h) { raise_err(w, ERR_BOUNDS); return; }
-    const uint64_t ka = gather_key(p.chars, oa, h, la), kb = gather_key(p.chars, ob0, h, lb);
-    p.lcp[q] = h + lcp_word(ka, rem8(la, h), kb, rem8(lb, h));
+    const KeyFmt fh = fmt_head(w);
+    const uint64_t ka = key_at(w, fh, p.chars, oa, h, la), kb = key_at(w, fh, p.chars, ob0, h, lb);
+    p.lcp[q] = h + kf_lcp_word(fh, ka, kf_r(fh, la, h), kb, kf_r(fh, lb, h));
 }
 
 __device__ void dev_lcp_fill(const Work& w, const Params& p, uint32_t first, uint32_t stride) {
@@ -2199,7 +2310,9 @@ __global__ __launch_bounds__(BLOCK) void k_persist(Work w, Params p, const uint3
     uint32_t gen = 0;
 
     if (full) {
-        for (uint32_t i = bid * BLOCK + tid; i < p.n; i += G * BLOCK) dev_init_one(w, p, i);
+        const KeyFmt f = fmt_full(w);
+        if (bid == 0 && tid == 0) fmt_publish(w, f);
+        for (uint32_t i = bid * BLOCK + tid; i < p.n; i += G * BLOCK) dev_init_one(w, f, p, i);
         if (!grid_sync(w, G, gen, &s_ok)) return;
         const uint32_t nroots = set_begin ? num_sets : 1u;
         for (uint32_t j = bid * BLOCK + tid; j < nroots; j += G * BLOCK) dev_root_one(w, p, set_begin, nroots, j);
@@ -2249,7 +2362,10 @@ __global__ __launch_bounds__(BLOCK) void k_persist(Work w, Params p, const uint3
             else if (it < nb0 + nb1) dev_base_wave<2>(w, p, cur, 1, (it - nb0) * WAVES + wv, c.n_base[1], sm.wave);
             else if (it < nb0 + nb1 + nb2)
                 dev_base_wave<4>(w, p, cur, 2, (it - nb0 - nb1) * WAVES + wv, c.n_base[2], sm.wave);
-            else if (it < nb0 + nb1 + nb2 + nb3) dev_base_wg(w, p, cur, it - nb0 - nb1 - nb2, c.n_base[3], sm.base);
+            else if (it < nb0 + nb1 + nb2 + nb3) {
+                if (fmt_head(w).bpc) dev_base_wg<true>(w, p, cur, it - nb0 - nb1 - nb2, c.n_base[3], sm.base);
+                else dev_base_wg<false>(w, p, cur, it - nb0 - nb1 - nb2, c.n_base[3], sm.base);
+            }
             else dev_sample(w, p, cur, it - nb0 - nb1 - nb2 - nb3, false, sm.sample);
         }
         if (c.n_dist == 0) {
@@ -2311,7 +2427,8 @@ __global__ __launch_bounds__(BLOCK) void k_admit_init(Work w, Params p, int cur,
     uint32_t len = 0;
     if (o1 < o0 || o1 - o0 > MAX_LEN) raise_err(w, ERR_OFFSETS);
     else len = (uint32_t)(o1 - o0);
-    rec_put(w, cur, g, gather_key(p.chars, o0, 0, len), g, min_u32(len, W));
+    const KeyFmt fh = fmt_head(w);  // byte keys: serving runs no alphabet check
+    rec_put(w, cur, g, key_at(w, fh, p.chars, o0, 0, len), g, kf_r(fh, len, 0));
 }
 
 __global__ void k_admit_root(Work w, Params p, int cur, uint32_t pos, uint32_t m, uint32_t rid) {
@@ -2351,6 +2468,127 @@ hipError_t launch_reset(const Work& w, hipStream_t s) {
     hipLaunchKernelGGL(k_reset, dim3(1), dim3(BLOCK), 0, s, w);
     return hipGetLastError();
 }
+
+// ---------------------------------------------------------------------------
+// alphabet of a sort (alphabet compression, §4.6.1): probe, then check
+// ---------------------------------------------------------------------------
+
+// Sets the bit of byte c in a 256-bit set held as four words.
+__device__ __forceinline__ void set_add(uint64_t (&m)[4], uint32_t c) {
+    const uint64_t bit = 1ull << (c & 63);
+    const uint32_t q = c >> 6;
+    m[0] |= q == 0 ? bit : 0ull;
+    m[1] |= q == 1 ? bit : 0ull;
+    m[2] |= q == 2 ? bit : 0ull;
+    m[3] |= q == 3 ? bit : 0ull;
+}
+
+// The first 16 bytes of up to 1024 strings spread over the input: when they
+// hold few enough distinct values, they become the candidate set (cand).
+// ALPHABET_AUTO asks for at most 3 (2-bit codes, 32 characters per key
+// instead of 8) and at most COMPRESS_MAX_AVG characters per string on
+// average (the check below reads every character once, the sort moves about
+// 26 bytes per string and level); ALPHABET_COMPRESS asks for at most 15 and
+// any length.  Otherwise nothing is set and the sort uses byte keys (the
+// reset cleared the state).
+constexpr uint32_t PROBE_STRINGS = 1024, COMPRESS_MAX_AVG = 64, AUTO_MAX_SYMBOLS = 3;
+__global__ __launch_bounds__(PROBE_STRINGS) void k_alpha_probe(Work w, Params p) {
+    __shared__ unsigned long long acc[4];
+    const uint32_t t = threadIdx.x, lane = t & 63;
+    if (p.alphabet == ALPHABET_BYTES || p.n == 0 || p.chars == nullptr) return;  // uniform
+    const uint64_t b0 = p.offsets[0], b1 = p.offsets[p.n];
+    if (b1 < b0) return;  // malformed offsets are the key gather's to report
+    if (p.alphabet == ALPHABET_AUTO && b1 - b0 > (uint64_t)COMPRESS_MAX_AVG * p.n) return;  // uniform
+    const uint32_t max_symbols = p.alphabet == ALPHABET_AUTO ? AUTO_MAX_SYMBOLS : 15u;
+    if (t < 4) acc[t] = 0;
+    __syncthreads();
+    uint64_t m[4] = {0, 0, 0, 0};
+    const uint32_t S = min_u32(p.n, PROBE_STRINGS);
+    if (t < S) {
+        const uint32_t i = (uint32_t)(((2ull * t + 1) * p.n) / (2ull * S));
+        const uint64_t o0 = p.offsets[i], o1 = p.offsets[i + 1];
+        if (o1 > o0 && o1 - o0 <= MAX_LEN) {
+            const uint32_t len = (uint32_t)(o1 - o0);
+            const uint64_t k0 = gather_key(p.chars, o0, 0, len), k1 = gather_key(p.chars, o0, W, len);
+            const uint32_t lim = len < 2 * W ? len : 2 * W;
+            for (uint32_t k = 0; k < lim; ++k) set_add(m, (uint32_t)((k < W ? k0 : k1) >> (56 - 8 * (k & 7))) & 0xFFu);
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const uint64_t v = wave_or64(m[q]);
+        if (lane == 0 && v) atomicOr(&acc[q], (unsigned long long)v);
+    }
+    __syncthreads();
+    if (t == 0) {
+        uint32_t s = 0;
+        for (int q = 0; q < 4; ++q) s += (uint32_t)__popcll(acc[q]);
+        if (s <= max_symbols) {
+            for (int q = 0; q < 4; ++q) w.ctl->alpha.seen[q] = acc[q];
+            w.ctl->alpha.limit = max_symbols;
+            w.ctl->alpha.cand = 1;
+        }
+    }
+}
+
+// Every byte of chars[offsets[0], offsets[n]) against the set: a byte
+// outside it is added (each work group keeps a byte table in LDS, so a new
+// byte costs one global atomic per group), and once the set holds more than
+// the probe's limit `over` is set and every group stops.  Reads whole aligned
+// 16-byte blocks (inside the pages that hold the range); only the range's
+// bytes count.
+__global__ __launch_bounds__(BLOCK) void k_alpha_check(Work w, Params p) {
+    __shared__ uint8_t tab[256];
+    const uint32_t tid = threadIdx.x;
+    if (uniform(w.ctl->alpha.cand) == 0u) return;
+    const uint64_t b0 = p.offsets[0], b1 = p.offsets[p.n];
+    if (b1 <= b0) return;  // no characters (malformed offsets are reported by the key gather)
+    for (uint32_t c = tid; c < 256; c += BLOCK) tab[c] = (uint8_t)((w.ctl->alpha.seen[c >> 6] >> (c & 63)) & 1u);
+    __syncthreads();
+    const uintptr_t lo = (uintptr_t)(p.chars + b0), hi = (uintptr_t)(p.chars + b1);
+    const uintptr_t first = lo & ~(uintptr_t)15;
+    const uint64_t blocks = (uint64_t)((hi - first + 15) >> 4);
+    const uint64_t stride = (uint64_t)gridDim.x * BLOCK;
+    typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+    // four 16-byte blocks per thread and iteration, loaded before any is used
+    for (uint64_t k0 = (uint64_t)blockIdx.x * BLOCK + tid; k0 < blocks; k0 += 4 * stride) {
+        if (__builtin_nontemporal_load(&w.ctl->alpha.over) != 0u) break;  // the set is too large: byte keys
+        u32x4 v[4];
+#pragma unroll
+        for (uint32_t u = 0; u < 4; ++u) {
+            const uint64_t k = k0 + u * stride;
+            v[u] = k < blocks ? __builtin_nontemporal_load((const u32x4*)(first + 16 * k)) : u32x4{0, 0, 0, 0};
+        }
+#pragma unroll
+        for (uint32_t u = 0; u < 4; ++u) {
+            const uint64_t k = k0 + u * stride;
+            if (k >= blocks) break;
+            const uintptr_t a = first + 16 * k;
+            const uint32_t wd[4] = {v[u].x, v[u].y, v[u].z, v[u].w};
+#pragma unroll
+            for (uint32_t j = 0; j < 16; ++j) {
+                const uintptr_t at = a + j;
+                const uint32_t c = (wd[j >> 2] >> (8 * (j & 3))) & 0xFFu;
+                if (at < lo || at >= hi || tab[c]) continue;
+                tab[c] = 1;
+                const unsigned long long bit = 1ull << (c & 63);
+                const unsigned long long old = atomicOr((unsigned long long*)&w.ctl->alpha.seen[c >> 6], bit);
+                if (old & bit) continue;
+                uint32_t s = 0;
+                for (int q = 0; q < 4; ++q)
+                    s += (uint32_t)__popcll(atomicOr((unsigned long long*)&w.ctl->alpha.seen[q], 0ull));
+                if (s > w.ctl->alpha.limit) atomicOr(&w.ctl->alpha.over, 1u);
+            }
+        }
+    }
+}
+
+hipError_t launch_alphabet(const Work& w, const Params& p, uint32_t check_grid, hipStream_t s) {
+    if (p.alphabet == ALPHABET_BYTES) return hipSuccess;  // byte keys: the reset left the state empty
+    hipLaunchKernelGGL(k_alpha_probe, dim3(1), dim3(PROBE_STRINGS), 0, s, w, p);
+    hipLaunchKernelGGL(k_alpha_check, dim3(check_grid > 0 ? check_grid : 1), dim3(BLOCK), 0, s, w, p);
+    return hipGetLastError();
+}
 __global__ void k_report(Work w, uint32_t* out) {
     if (threadIdx.x == 0) out[0] = w.ctl->err;
 }
@@ -2364,7 +2602,8 @@ hipError_t launch_level_begin(const Work& w, int cur, uint32_t level, hipStream_
 }
 hipError_t launch_init(const Work& w, const Params& p, hipStream_t s) {
     if (p.n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_init, dim3(blocks_for(p.n, BLOCK)), dim3(BLOCK), 0, s, w, p);
+    if (p.ac) hipLaunchKernelGGL(k_init<true>, dim3(blocks_for(p.n, BLOCK)), dim3(BLOCK), 0, s, w, p);
+    else hipLaunchKernelGGL(k_init<false>, dim3(blocks_for(p.n, BLOCK)), dim3(BLOCK), 0, s, w, p);
     return hipGetLastError();
 }
 hipError_t launch_roots(const Work& w, const Params& p, const uint32_t* set_begin, uint32_t num_sets,
@@ -2374,15 +2613,20 @@ hipError_t launch_roots(const Work& w, const Params& p, const uint32_t* set_begi
     return hipGetLastError();
 }
 static inline dim3 grid_of(uint32_t g) { return dim3(g ? g : 1u); }
-hipError_t launch_base(const Work& w, const Params& p, int cur, int cls, uint32_t grid, hipStream_t s) {
+template <bool AC>
+static void launch_base_as(const Work& w, const Params& p, int cur, int cls, uint32_t grid, hipStream_t s) {
     if (cls == 0)
-        hipLaunchKernelGGL(k_base_wave<1>, grid_of(grid), dim3(BLOCK), 0, s, w, p, cur, 0);
+        hipLaunchKernelGGL((k_base_wave<1, AC>), grid_of(grid), dim3(BLOCK), 0, s, w, p, cur, 0);
     else if (cls == 1)
-        hipLaunchKernelGGL(k_base_wave<2>, grid_of(grid), dim3(BLOCK), 0, s, w, p, cur, 1);
+        hipLaunchKernelGGL((k_base_wave<2, AC>), grid_of(grid), dim3(BLOCK), 0, s, w, p, cur, 1);
     else if (cls == 2)
-        hipLaunchKernelGGL(k_base_wave<4>, grid_of(grid), dim3(BLOCK), 0, s, w, p, cur, 2);
+        hipLaunchKernelGGL((k_base_wave<4, AC>), grid_of(grid), dim3(BLOCK), 0, s, w, p, cur, 2);
     else
-        hipLaunchKernelGGL(k_base, grid_of(grid), dim3(BLOCK), 0, s, w, p, cur);
+        hipLaunchKernelGGL(k_base<AC>, grid_of(grid), dim3(BLOCK), 0, s, w, p, cur);
+}
+hipError_t launch_base(const Work& w, const Params& p, int cur, int cls, uint32_t grid, hipStream_t s) {
+    if (p.ac) launch_base_as<true>(w, p, cur, cls, grid, s);
+    else launch_base_as<false>(w, p, cur, cls, grid, s);
     return hipGetLastError();
 }
 hipError_t launch_sample(const Work& w, const Params& p, int cur, uint32_t grid, bool root_keys, hipStream_t s) {
@@ -2401,9 +2645,17 @@ hipError_t launch_scan(const Work& w, int cur, uint32_t grid, hipStream_t s) {
 }
 hipError_t launch_scatter(const Work& w, const Params& p, int cur, uint32_t grid, uint32_t more_grid,
                           hipStream_t s) {
-    hipLaunchKernelGGL(k_scatter, grid_of(grid), dim3(SC_THREADS), 0, s, w, p, cur);
-    if (more_grid)
-        hipLaunchKernelGGL(k_scatter_more, grid_of(more_grid), dim3(SC_THREADS), 0, s, w, p, cur, grid_of(grid).x);
+    if (p.ac) {
+        hipLaunchKernelGGL(k_scatter<true>, grid_of(grid), dim3(SC_THREADS), 0, s, w, p, cur);
+        if (more_grid)
+            hipLaunchKernelGGL(k_scatter_more<true>, grid_of(more_grid), dim3(SC_THREADS), 0, s, w, p, cur,
+                               grid_of(grid).x);
+    } else {
+        hipLaunchKernelGGL(k_scatter<false>, grid_of(grid), dim3(SC_THREADS), 0, s, w, p, cur);
+        if (more_grid)
+            hipLaunchKernelGGL(k_scatter_more<false>, grid_of(more_grid), dim3(SC_THREADS), 0, s, w, p, cur,
+                               grid_of(grid).x);
+    }
     return hipGetLastError();
 }
 hipError_t launch_children(const Work& w, const Params& p, int cur, uint32_t grid, hipStream_t s) {
@@ -2443,14 +2695,14 @@ static hipError_t resident(K kernel, int threads, int cus, uint32_t* out) {
 hipError_t kernel_caps(int device, KernelCaps* k) {
     int cus = 0;
     hipError_t e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
-    if (e == hipSuccess) e = resident(k_base_wave<1>, BLOCK, cus, &k->base[0]);
-    if (e == hipSuccess) e = resident(k_base_wave<2>, BLOCK, cus, &k->base[1]);
-    if (e == hipSuccess) e = resident(k_base_wave<4>, BLOCK, cus, &k->base[2]);
-    if (e == hipSuccess) e = resident(k_base, BLOCK, cus, &k->base[3]);
+    if (e == hipSuccess) e = resident(k_base_wave<1, false>, BLOCK, cus, &k->base[0]);
+    if (e == hipSuccess) e = resident(k_base_wave<2, false>, BLOCK, cus, &k->base[1]);
+    if (e == hipSuccess) e = resident(k_base_wave<4, false>, BLOCK, cus, &k->base[2]);
+    if (e == hipSuccess) e = resident(k_base<false>, BLOCK, cus, &k->base[3]);
     if (e == hipSuccess) e = resident(k_sample, BLOCK, cus, &k->sample);
     if (e == hipSuccess) e = resident(k_classify, BLOCK, cus, &k->classify);
     if (e == hipSuccess) e = resident(k_scan_reduce, BLOCK, cus, &k->scan);
-    if (e == hipSuccess) e = resident(k_scatter, SC_THREADS, cus, &k->scatter);
+    if (e == hipSuccess) e = resident(k_scatter<false>, SC_THREADS, cus, &k->scatter);
     if (e == hipSuccess) e = resident(k_children, BLOCK, cus, &k->children);
     if (e == hipSuccess) e = resident(k_persist, BLOCK, cus, &k->persist);
     return e;

@@ -139,6 +139,7 @@ def test_level_budget_and_persistent_tail():
     o = np.arange(n + 1, dtype=np.uint64) * L
     cd, od = to_device(c, o)
     ctx = ss.Context()
+    ctx.set_config(alphabet="bytes")  # 8 characters per level: more than 10 levels
     for rep in range(2):
         p, l = ctx.sort(cd, od)
         torch.cuda.synchronize()

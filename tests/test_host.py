@@ -1,5 +1,6 @@
 """Host logic of the HIP library, run on the CPU: exported symbols and the
 primitive functions the kernels share with the host test entry points."""
+import ctypes
 import os
 import random
 import re
@@ -165,3 +166,135 @@ def test_gather_exhaustive_with_guard_pages():
     r = subprocess.run([sys.executable, "-c", GATHER_CHILD, ROOT], capture_output=True, text=True, timeout=300)
     assert r.returncode == 0, f"child exit {r.returncode}: {r.stdout[-500:]} {r.stderr[-500:]}"
     assert r.stdout.startswith("ok ") and int(r.stdout.split()[1]) > 100000
+
+
+# ---- alphabet-compressed keys (alphabet compression, section 4.6.1) ----
+
+def packed_by_definition(s: bytes, h: int, alphabet):
+    """The compressed key of s at depth h written out: the next
+    64 // bits characters, each coded 1 + its rank in the sorted alphabet,
+    bits = 2, 3, 4 for up to 3, 7, 15 symbols, 0 past the end."""
+    syms = sorted(set(alphabet))
+    bits = 2 if len(syms) <= 3 else 3 if len(syms) <= 7 else 4
+    cpw = 64 // bits
+    key = 0
+    for k, c in enumerate(s[h:h + cpw]):
+        key |= (1 + syms.index(c)) << (64 - bits * (k + 1))
+    return key, cpw
+
+
+def byte_set_words(alphabet):
+    w = [0, 0, 0, 0]
+    for c in set(alphabet):
+        w[c >> 6] |= 1 << (c & 63)
+    return (ctypes.c_uint64 * 4)(*w)
+
+
+
+
+def host_packed(buf, off, h, L, alphabet):
+    cpw, miss = ctypes.c_uint32(0), ctypes.c_int(0)
+    addr = ctypes.addressof(buf) if not isinstance(buf, int) else buf
+    k = ss.lib().ss_host_gather_packed(ctypes.c_void_p(addr), off, h, L, byte_set_words(alphabet),
+                                       ctypes.byref(cpw), ctypes.byref(miss))
+    return k, cpw.value, miss.value
+
+
+def test_packed_key_matches_definition():
+    """Random strings over alphabets of 1..15 bytes (incl. 0x00 and 0xFF), every
+    depth: the kernels' compressed gather equals the definition; a set of 16
+    or more bytes gives the byte key."""
+    rng = random.Random(11)
+    for trial in range(300):
+        size = rng.randint(1, 15)
+        alphabet = bytes(rng.sample(range(256), size - 2) + [0, 255]) if size >= 3 else bytes(rng.sample(range(256), size))
+        s = bytes(rng.choice(alphabet) for _ in range(rng.randint(0, 70)))
+        pad = rng.randint(0, 7)
+        raw = bytes(pad) + s + bytes(8)
+        buf = (ctypes.c_uint8 * len(raw)).from_buffer_copy(raw)
+        for h in range(0, len(s) + 3):
+            k, cpw, miss = host_packed(buf, pad, h, len(s), alphabet)
+            want, wcpw = packed_by_definition(s, h, alphabet)
+            assert (k, cpw, miss) == (want, wcpw, 0), (trial, h, alphabet, s)
+    # 16 distinct bytes: byte keys
+    alphabet = bytes(range(16))
+    s = bytes(range(16)) * 2
+    buf = (ctypes.c_uint8 * (len(s) + 8)).from_buffer_copy(s + bytes(8))
+    k, cpw, _ = host_packed(buf, 0, 3, len(s), alphabet)
+    assert cpw == 8 and k == ss.lib().ss_host_gather_key(ctypes.c_void_p(ctypes.addressof(buf)), 0, 3, len(s))
+    # a byte outside the set is reported
+    k, cpw, miss = host_packed((ctypes.c_uint8 * 16).from_buffer_copy(b"ACGTNACG" + bytes(8)), 0, 0, 8, b"ACGT")
+    assert miss == 1 and cpw == 21
+
+
+def test_packed_keys_order_and_lcp():
+    """(key, r code) of the compressed format orders two strings' next
+    characters like the strings (a proper prefix first), and the word LCP
+    equals the brute-force LCP capped at the characters per key."""
+    rng = random.Random(12)
+    for trial in range(3000):
+        alphabet = bytes(rng.sample(range(256), rng.randint(1, 15)))
+        a = bytes(rng.choice(alphabet) for _ in range(rng.randint(0, 40)))
+        b = a[:rng.randint(0, len(a))] + bytes(rng.choice(alphabet) for _ in range(rng.randint(0, 40)))
+        h = rng.randint(0, 8)
+        ka, cpw = packed_by_definition(a, h, alphabet)
+        kb, _ = packed_by_definition(b, h, alphabet)
+        ta, tb = a[h:h + cpw], b[h:h + cpw]
+        assert (ka < kb) == (ta < tb) and (ka == kb) == (ta == tb), (trial, alphabet, a, b, h)
+        lcp = 0
+        while lcp < min(len(ta), len(tb)) and ta[lcp] == tb[lcp]:
+            lcp += 1
+        got = ss.lib().ss_host_key_lcp(byte_set_words(alphabet), ka, len(a), kb, len(b), h)
+        assert got == lcp, (trial, alphabet, a, b, h, got, lcp)
+
+
+PACKED_CHILD = r"""
+import ctypes, mmap, random, sys
+sys.path.insert(0, sys.argv[1])
+import paper_1808_00963_amd as ss
+lib = ss.lib()
+libc = ctypes.CDLL(None)
+libc.mprotect.argtypes = [ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int]
+PAGE = mmap.PAGESIZE
+buf = mmap.mmap(-1, 3 * PAGE)
+base = ctypes.addressof(ctypes.c_char.from_buffer(buf))
+mid = base + PAGE
+rng = random.Random(8)
+alphabet = b"ACGT"
+data = bytes(rng.choice(alphabet) for _ in range(PAGE))
+ctypes.memmove(mid, data, PAGE)
+assert libc.mprotect(base, PAGE, 0) == 0 and libc.mprotect(mid + PAGE, PAGE, 0) == 0
+words = [0, 0, 0, 0]
+for c in alphabet:
+    words[c >> 6] |= 1 << (c & 63)
+bs = (ctypes.c_uint64 * 4)(*words)
+checked = 0
+for L in range(0, 45):
+    for start in list(range(16)) + [PAGE - L - e for e in range(16)]:
+        s = data[start:start + L]
+        for shift in range(8):
+            if shift > start:
+                continue
+            chars = mid + start - shift
+            for h in range(0, L + 3):
+                cpw, miss = ctypes.c_uint32(0), ctypes.c_int(0)
+                got = lib.ss_host_gather_packed(ctypes.c_void_p(chars), shift, h, L, bs, ctypes.byref(cpw), ctypes.byref(miss))
+                want = 0
+                for k, c in enumerate(s[h:h + 21]):
+                    want |= (1 + sorted(alphabet).index(c)) << (64 - 3 * (k + 1))
+                if got != want or miss.value or cpw.value != 21:
+                    print(f"MISMATCH len={L} start={start} shift={shift} h={h}: {got:#x} != {want:#x}")
+                    sys.exit(1)
+                checked += 1
+print(f"ok {checked}")
+"""
+
+
+def test_packed_gather_with_guard_pages():
+    """The compressed gather reads only the aligned words holding the key's
+    bytes: every length up to 44, every depth, every alignment of the string
+    and of the chars pointer, against unreadable pages on both sides."""
+    import sys
+    r = subprocess.run([sys.executable, "-c", PACKED_CHILD, ROOT], capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0, f"child exit {r.returncode}: {r.stdout[-500:]} {r.stderr[-500:]}"
+    assert r.stdout.startswith("ok ") and int(r.stdout.split()[1]) > 50000
