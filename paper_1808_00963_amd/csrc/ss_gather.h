@@ -22,30 +22,38 @@ __device__ __forceinline__ uint32_t rem8(uint32_t len, uint32_t h) { return min_
 
 // Length of the common prefix of two strings known to agree on their first
 // `from` characters, by comparing 8-byte words (at most `limit` = the
-// shorter length).  AHEAD words of each string are loaded per step, so a
-// long common prefix costs one memory round trip per AHEAD words (callers
-// with registers to spare take more).
+// shorter length).  The first step compares one word (it usually decides);
+// later steps load AHEAD words of each string at once, so a long common
+// prefix costs one memory round trip per AHEAD words (callers with
+// registers to spare take more).
 template <uint32_t AHEAD = 1>
 __device__ __forceinline__ uint32_t lcp_from(const uint8_t* chars, uint64_t oa, uint32_t la, uint64_t ob, uint32_t lb,
                                              uint32_t from) {
-    constexpr uint32_t LCP_AHEAD = AHEAD;
     const uint32_t limit = la < lb ? la : lb;
     uint32_t d = from;
+    if (d < limit) {
+        const uint64_t ka = gather_key(chars, oa, d, la), kb = gather_key(chars, ob, d, lb);
+        if (ka != kb) {
+            const uint32_t c = d + common_bytes(ka, kb);
+            return c < limit ? c : limit;
+        }
+        d += W;
+    }
     while (d < limit) {
-        uint64_t ka[LCP_AHEAD], kb[LCP_AHEAD];
+        uint64_t ka[AHEAD], kb[AHEAD];
 #pragma unroll
-        for (uint32_t u = 0; u < LCP_AHEAD; ++u) {  // past an end a key is 0 and reads nothing
+        for (uint32_t u = 0; u < AHEAD; ++u) {  // past an end a key is 0 and reads nothing
             ka[u] = gather_key(chars, oa, d + u * W, la);
             kb[u] = gather_key(chars, ob, d + u * W, lb);
         }
 #pragma unroll
-        for (uint32_t u = 0; u < LCP_AHEAD; ++u) {
+        for (uint32_t u = 0; u < AHEAD; ++u) {
             if (ka[u] != kb[u]) {
                 const uint32_t c = d + u * W + common_bytes(ka[u], kb[u]);
                 return c < limit ? c : limit;
             }
         }
-        d += LCP_AHEAD * W;
+        d += AHEAD * W;
     }
     return limit;
 }
