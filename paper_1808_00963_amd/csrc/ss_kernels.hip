@@ -1904,16 +1904,19 @@ __device__ void dev_scatter_half(const Work& w, const Params& p, int cur, uint32
         }
     }
     // 2. ranks inside the wave
+    const uint32_t nbits = 32u - (uint32_t)__builtin_clz(k);  // bits of a bucket id (k = 2v + 1 buckets)
     uint32_t rank[SC_PER];
 #pragma unroll
     for (uint32_t r = 0; r < SC_PER; ++r) {
         const uint32_t b = bk[r] & 0xFFFFu;
         const bool valid = b != 0xFFFFu;
         uint64_t peers = __ballot(valid);
-#pragma unroll
-        for (uint32_t bit = 0; bit < MAX_LOGV + 1; ++bit) {
-            const uint64_t mk = __ballot((b >> bit) & 1u);
-            peers &= ((b >> bit) & 1u) ? mk : ~mk;
+        // peers: the lanes whose bucket id agrees with this lane's in each of
+        // the id's `nbits` bits (a lane with bit 0 keeps the complement)
+        for (uint32_t bit = 0; bit < nbits; ++bit) {
+            const uint32_t x = (b >> bit) & 1u;
+            const uint64_t mk = __ballot(x);
+            peers &= mk ^ ((uint64_t)x - 1u);
         }
         const uint32_t below = __builtin_amdgcn_mbcnt_hi((uint32_t)(peers >> 32),
                                                          __builtin_amdgcn_mbcnt_lo((uint32_t)peers, 0u));
