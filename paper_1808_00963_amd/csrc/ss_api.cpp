@@ -183,6 +183,8 @@ size_t layout(uint32_t n, const Caps& k, char* base, Work* w) {
     for (int i = 0; i < 2; ++i) t.tile_seg[i] = (uint32_t*)take(sizeof(uint32_t) * k.tiles);
     for (int i = 0; i < 2; ++i) t.tree_key[i] = (uint64_t*)take(sizeof(uint64_t) * k.tree);
     for (int i = 0; i < 2; ++i) t.tree_r[i] = (uint8_t*)take(k.tree);
+    for (int i = 0; i < 2; ++i) t.tree_next[i] = (uint64_t*)take(sizeof(uint64_t) * k.tree);
+    for (int i = 0; i < 2; ++i) t.tree_diff[i] = (uint32_t*)take(sizeof(uint32_t) * k.tree);
     t.pend = (Pend*)take(sizeof(Pend) * k.pend);
     t.pend2 = nullptr;
     t.ctl = (Ctl*)take(sizeof(Ctl));

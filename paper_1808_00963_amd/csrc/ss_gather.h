@@ -22,14 +22,14 @@ __device__ __forceinline__ uint32_t rem8(uint32_t len, uint32_t h) { return min_
 
 // Length of the common prefix of two strings known to agree on their first
 // `from` characters, by comparing 8-byte words (at most `limit` = the
-// shorter length).  The first step compares one word (it usually decides);
-// later steps load AHEAD words of each string at once, so a long common
-// prefix costs one memory round trip per AHEAD words (callers with
-// registers to spare take more).
+// shorter length, or `cap` when that is smaller).  The first step compares
+// one word (it usually decides); later steps load AHEAD words of each
+// string at once, so a long common prefix costs one memory round trip per
+// AHEAD words (callers with registers to spare take more).
 template <uint32_t AHEAD = 1>
 __device__ __forceinline__ uint32_t lcp_from(const uint8_t* chars, uint64_t oa, uint32_t la, uint64_t ob, uint32_t lb,
-                                             uint32_t from) {
-    const uint32_t limit = la < lb ? la : lb;
+                                             uint32_t from, uint32_t cap = ~0u) {
+    const uint32_t limit = min_u32(la < lb ? la : lb, cap);
     uint32_t d = from;
     if (d < limit) {
         const uint64_t ka = gather_key(chars, oa, d, la), kb = gather_key(chars, ob, d, lb);

@@ -37,6 +37,8 @@ struct Seg {
     uint32_t cnt_off;   // first counter in the counter pool
     uint32_t tile_off;  // first tile in the tile list
     uint32_t rid;       // set (batch) or request (serving) the segment belongs to
+    uint32_t regather;  // 1: the records hold keys of a smaller depth (an equality
+                        // bucket that skipped its common prefix); read them again at `depth`
 };
 
 // A boundary whose LCP is filled in once the final order is known: the
@@ -215,6 +217,9 @@ constexpr uint32_t TILE = BLOCK * IPT;      // strings per classify/scatter tile
 constexpr uint32_t MAX_LOGV = 10;           // at most 1023 splitters
 constexpr uint32_t MAX_BUCKETS = (2u << MAX_LOGV) - 1;
 constexpr uint32_t BASE_CAP = 1024;         // largest base-case segment
+constexpr uint32_t SKIP_MIN_SAMPLES = 4;    // equal samples before an equality bucket may skip a word
+constexpr uint32_t TR_CODE = 0x7F;          // a splitter's r code in its tree_r byte
+constexpr uint32_t TR_SKIP = 0x80;          // ... and whether its equality bucket may skip a word
 
 // Pool capacities of one level, derived from n (see ss_api.cpp).
 struct Caps {
@@ -233,7 +238,10 @@ struct Work {
     BaseSeg* base[NCLS][2];
     uint32_t* tile_seg[2];
     uint64_t* tree_key[2];
-    uint8_t* tree_r[2];
+    uint8_t* tree_r[2];      // r code | TR_SKIP
+    uint64_t* tree_next[2];  // per TR_SKIP splitter: its sample string's key one word deeper
+    uint32_t* tree_diff[2];  // per TR_SKIP splitter: 0 while every member of its equality
+                             // bucket has that next key (and a full word there), else 1
     Pend* pend;               // pending boundary LCPs
     Pend* pend2;              // filter target (serving)
     Ctl* ctl;

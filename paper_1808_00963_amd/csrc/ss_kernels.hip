@@ -199,6 +199,15 @@ __device__ __forceinline__ void regather(const Work& w, const KeyFmt& fh, const 
     r = kf_r(fh, len, h);
 }
 
+// A member of an equality bucket, with its key one word beyond the
+// splitter's: when that key differs from the splitter's sample string's
+// key there (or the member ends inside the word), the bucket cannot skip
+// the word (k_children).  The flag only ever goes from 0 to 1, so plain
+// stores suffice, and reading it first skips most of them.
+__device__ __forceinline__ void note_next(const Work& w, int cur, uint32_t t, uint64_t key, uint32_t r) {
+    uint32_t* const df = &w.tree_diff[cur][t];
+    if (*df == 0 && (key != w.tree_next[cur][t] || r != W)) *df = 1;
+}
 
 // One item of the dynamic part [first, n) for a work group (n when none is
 // left).
@@ -273,7 +282,7 @@ __device__ void emit_segment(const Work& w, const Params& p, int nxt, int buf, u
         return;
     }
     // the tile list entries are written by k_sample (one work group per segment)
-    w.dist[nxt][slot] = Seg{begin, size, depth, logv, toff, coff, tioff, rid};
+    w.dist[nxt][slot] = Seg{begin, size, depth, logv, toff, coff, tioff, rid, 0u};
 }
 
 // wave-level inclusive scans over 64 lanes
@@ -1353,6 +1362,19 @@ __device__ __forceinline__ bool kr_gt(uint64_t ka, uint32_t ra, uint64_t kb, uin
     return ka > kb || (ka == kb && ra > rb);
 }
 
+// A sorted sample's r code (bits 0..7) and sample number (bits 8..18;
+// a < 2^11); padding is all ones.  Comparisons see the r code only
+// (SampleR).  A chosen splitter adds the number of samples equal to it
+// (bits 19..31).
+static_assert((2u << MAX_LOGV) <= (1u << 11), "sample numbers fit 11 bits");
+__device__ __forceinline__ uint32_t sr_word(uint64_t lo) {
+    return lo == ~0ull ? 0xFFFFFFFFu : pr_r(lo) | pr_idx(lo) << 8;
+}
+struct SampleR {
+    const uint32_t* s;
+    __device__ uint32_t operator[](uint32_t i) const { return s[i] & 0xFFu; }
+};
+
 // The regular sample of a segment (a = 2v+1 keys at evenly spaced
 // positions) sorted by (key, r) into SK / SR, padded with maxima to a power
 // of two.  The NB blocks of 64E records are sorted in registers by the
@@ -1383,6 +1405,13 @@ __device__ __forceinline__ void sample_sort(const Work& w, const Params& p, int 
                     const KeyFmt fh = fmt_full(w);  // beside the key gather, which publishes the format
                     key = key_at(w, fh, p.chars, o0, 0, len);
                     rr = kf_r(fh, len, 0);
+                } else if (sg.regather) {  // records of an earlier depth: read the key at sg.depth
+                    const KeyFmt fh = fmt_full(w);
+                    const uint32_t idx = rec_idx(w, in[pos]);
+                    const uint64_t o0 = p.offsets[idx], o1 = p.offsets[idx + 1];
+                    const uint32_t len = (uint32_t)(o1 - o0);
+                    key = key_at(w, fh, p.chars, o0, sg.depth, len);
+                    rr = kf_r(fh, len, sg.depth);
                 } else {
                     const Rec x = in[pos];
                     key = rec_key(x);
@@ -1397,7 +1426,7 @@ __device__ __forceinline__ void sample_sort(const Work& w, const Params& p, int 
             const uint32_t j = b * R + lane * E + r;
             if (NB == 1) {
                 sm.SK[j] = pr_key(K[r], A[r]);
-                sm.SR[j] = A[r] == ~0ull ? 0xFFFFFFFFu : pr_r(A[r]);
+                sm.SR[j] = sr_word(A[r]);
             } else {
                 sm.SK[j] = K[r];
                 sm.SA[j] = A[r];
@@ -1435,7 +1464,7 @@ __device__ __forceinline__ void sample_sort(const Work& w, const Params& p, int 
                 const uint32_t j = b * R + lane * E + r;
                 if (last) {
                     sm.SK[j] = pr_key(K[r], A[r]);
-                    sm.SR[j] = A[r] == ~0ull ? 0xFFFFFFFFu : pr_r(A[r]);
+                    sm.SR[j] = sr_word(A[r]);
                 } else {
                     sm.SK[j] = K[r];
                     sm.SA[j] = A[r];
@@ -1482,9 +1511,9 @@ __device__ void dev_sample(const Work& w, const Params& p, int cur, uint32_t ite
             uint32_t llo = 0, lhi = 0, rlo = 0, rhi = 0;
             if (lo < hi) {
                 uint32_t mid, lh, rl;
-                select_node(SK, SR, lo, hi, &mid, &lh, &rl);
+                select_node(SK, SampleR{SR}, lo, hi, &mid, &lh, &rl);
                 TK[q] = SK[mid];
-                TR[q] = SR[mid];
+                TR[q] = (SR[mid] & 0x7FFFFu) | min_u32(rl - lh, 0x1FFFu) << 19;  // + samples equal to it
                 llo = lo; lhi = lh; rlo = rl; rhi = hi;
             } else {
                 TK[q] = TK[q >> 1];
@@ -1499,9 +1528,35 @@ __device__ void dev_sample(const Work& w, const Params& p, int cur, uint32_t ite
     }
     uint64_t* tk = w.tree_key[cur] + sg.tree_off;
     uint8_t* tr = w.tree_r[cur] + sg.tree_off;
+    uint64_t* tn = w.tree_next[cur] + sg.tree_off;
+    uint32_t* tdf = w.tree_diff[cur] + sg.tree_off;
+    const bool roots = root_keys && sg.depth == 0;
+    const KeyFmt fh = fmt_full(w);
+    const uint32_t h1 = sg.depth + kf_step(fh);
     for (uint32_t q = 1 + tid; q <= v; q += BLOCK) {
         tk[q - 1] = TK[q];
-        tr[q - 1] = (uint8_t)TR[q];
+        // The splitter's sample string is a member of its equality bucket
+        // (same key and r code); its key one word deeper is what the
+        // scatter compares the members' next keys with.  Only for buckets
+        // the sample suggests are large (a bucket of more than base_max
+        // strings holds about 16 or more of the samples) and a sample
+        // string that goes on for a whole word there; the others are not
+        // candidates for the skip (TR_SKIP clear) and cost the scatter
+        // nothing.
+        uint32_t code = TR[q] & 0xFFu;
+        if (code == W && (TR[q] >> 19) >= SKIP_MIN_SAMPLES) {
+            const uint32_t j = (TR[q] >> 8) & 0x7FFu;
+            const uint32_t pos = sg.begin + (uint32_t)(((2ull * j + 1) * sg.size) / (2ull * a));
+            const uint32_t idx = roots ? pos : rec_idx(w, w.rec[cur][pos]);
+            const uint64_t o0 = p.offsets[idx], o1 = p.offsets[idx + 1];
+            const uint32_t len = (uint32_t)(o1 - o0);
+            if (kf_r(fh, len, h1) == W) {
+                tn[q - 1] = key_at(w, fh, p.chars, o0, h1, len);
+                tdf[q - 1] = 0;
+                code |= TR_SKIP;
+            }
+        }
+        tr[q - 1] = (uint8_t)code;
     }
 }
 
@@ -1550,10 +1605,42 @@ __device__ void dev_classify(const Work& w, const Params& p, int cur, uint32_t t
     const uint32_t end = min_u32(start + TILE, sg.begin + sg.size);
     const uint64_t* gk = w.tree_key[cur] + sg.tree_off;
     const uint8_t* gr = w.tree_r[cur] + sg.tree_off;
-    for (uint32_t q = 1 + tid; q <= v; q += BLOCK) { TK[q] = gk[q - 1]; TR[q] = gr[q - 1]; }
+    for (uint32_t q = 1 + tid; q <= v; q += BLOCK) { TK[q] = gk[q - 1]; TR[q] = gr[q - 1] & TR_CODE; }
     for (uint32_t b = tid; b < k; b += BLOCK) H[b] = 0;
     __syncthreads();
     const Rec* in = w.rec[cur];
+    if (sg.regather) {  // an equality bucket that skipped a word: its keys at sg.depth, read
+                        // back below by the same thread (the scatter moves the new keys)
+        const KeyFmt fh = fmt_head(w);
+        if (fh.bpc == 0) {
+            constexpr uint32_t G = 4;  // gathers in flight per thread
+            for (uint32_t i0 = start + tid; i0 < end; i0 += G * BLOCK) {
+                uint32_t idx[G], len[G];
+                uint64_t o0[G];
+#pragma unroll
+                for (uint32_t u = 0; u < G; ++u) idx[u] = i0 + u * BLOCK < end ? rec_idx(w, in[i0 + u * BLOCK]) : 0u;
+#pragma unroll
+                for (uint32_t u = 0; u < G; ++u) {
+                    o0[u] = p.offsets[idx[u]];
+                    len[u] = (uint32_t)(p.offsets[idx[u] + 1] - o0[u]);
+                }
+#pragma unroll
+                for (uint32_t u = 0; u < G; ++u) {
+                    const uint32_t i = i0 + u * BLOCK;
+                    const uint64_t key = gather_key(p.chars, o0[u], sg.depth, len[u]);
+                    if (i < end) rec_put(w, cur, i, key, idx[u], kf_r(fh, len[u], sg.depth));
+                }
+            }
+        } else {
+            for (uint32_t i = start + tid; i < end; i += BLOCK) {
+                const uint32_t idx = rec_idx(w, in[i]);
+                uint64_t key;
+                uint32_t r;
+                regather(w, fh, p, idx, sg.depth, key, r);
+                rec_put(w, cur, i, key, idx, r);
+            }
+        }
+    }
     constexpr uint32_t U = 4;  // strings per thread and step, descents interleaved
     for (uint32_t i0 = start + tid; i0 < end; i0 += U * BLOCK) {
         uint64_t c[U];
@@ -1797,7 +1884,7 @@ __device__ void dev_scatter(const Work& w, const Params& p, int cur, uint32_t t,
         if (pos < sg.begin || pos >= seg_end) { raise_err(w, ERR_BOUNDS); continue; }
         if (b & 1u) {
             const uint32_t lx = level_index(b >> 1, d) - 1;
-            const uint32_t rx = gr[lx];
+            const uint32_t rx = gr[lx] & TR_CODE;
             const KeyFmt fh = fmt_head(w);
             if (rx < W) {  // identical strings ending inside this word: final
                 p.perm[pos] = idx - obase;
@@ -1806,6 +1893,7 @@ __device__ void dev_scatter(const Work& w, const Params& p, int cur, uint32_t t,
                 continue;
             }
             regather(w, fh, p, idx, sg.depth + kf_step(fh), key, rr);
+            if (gr[lx] & TR_SKIP) note_next(w, cur, sg.tree_off + lx, key, rr);
         }
         rec_put(w, cur ^ 1, pos, key, idx, rr);
     }
@@ -1993,7 +2081,7 @@ __device__ void dev_scatter_half(const Work& w, const Params& p, int cur, uint32
         if (pos < sg.begin || pos >= seg_end) { raise_err(w, ERR_BOUNDS); continue; }
         if (b & 1u) {
             const uint32_t lx = level_index(b >> 1, d) - 1;
-            const uint32_t rx = gr[lx];
+            const uint32_t rx = gr[lx] & TR_CODE;
             const uint32_t idx = rec_idx(w, x);
             const KeyFmt fh = fmt_of<AC>(w);
             if (rx < W) {  // identical strings ending inside this word: final
@@ -2005,6 +2093,7 @@ __device__ void dev_scatter_half(const Work& w, const Params& p, int cur, uint32
             uint64_t key;
             uint32_t rr;
             regather(w, fh, p, idx, sg.depth + kf_step(fh), key, rr);  // byte keys: inline gather
+            if (gr[lx] & TR_SKIP) note_next(w, cur, sg.tree_off + lx, key, rr);
             x = rec_make(w, key, idx, rr);
             if (w.wide) w.rw[cur ^ 1][pos] = (uint8_t)rr;
         } else if (w.wide) {
@@ -2065,7 +2154,10 @@ void k_scatter_more(Work w, Params p, int cur, uint32_t first) {
 
 // Output description of Algorithm 4.1: bucket i of a segment with common
 // prefix h holds strings with common prefix h (even i; the keys at h stay
-// valid) or h + 8 (odd i, equation 4.1 with the full word).  Every bucket
+// valid) or h + 8 (odd i, the full splitter word; section 4.2.2), or
+// h + 16 for a large equality bucket whose members all share the next word
+// too (note_next: any depth all members share is as valid a start for the
+// recursive sort).  Every bucket
 // start inside the segment gets a pending LCP (its neighbours differ within
 // the word at depth h); the value is filled in once the final order is
 // known (figure 4.7).  List slots for the children of the whole segment are
@@ -2096,19 +2188,31 @@ __device__ void dev_children(const Work& w, const Params& p, int cur, uint32_t i
     for (uint32_t b = lo + tid; b <= hi; b += BLOCK) sm.ST[b - lo] = b < k ? sc[(size_t)b * T] - s0 : sg.size;
     __syncthreads();
     const uint8_t* gr = w.tree_r[cur] + sg.tree_off;
+    const uint32_t* tdf = w.tree_diff[cur] + sg.tree_off;
     const Rec* out = w.rec[nxt];
     const uint32_t obase = w.set_base[sg.rid];
     const uint32_t step = kf_step(fmt_head(w));
-    // bucket b -> (start, count, child depth); depth == ~0u: no child segment
-    auto bucket = [&](uint32_t b, uint32_t& st, uint32_t& cnt, uint32_t& depth) {
+    // bucket b -> (start, count, child depth); depth == ~0u: no child
+    // segment.  An equality bucket that becomes a distribution segment and
+    // whose members all share the word after the splitter's (note_next)
+    // starts one more word deeper; its records hold keys of the word after
+    // the splitter's and are read again by the next level (`again`).
+    auto bucket = [&](uint32_t b, uint32_t& st, uint32_t& cnt, uint32_t& depth, uint32_t& again) {
         st = sm.ST[b - lo];
         const uint32_t en = sm.ST[b - lo + 1];
         cnt = en > st ? en - st : 0u;
         if (en > sg.size) { raise_err(w, ERR_BOUNDS); cnt = 0; }
         depth = sg.depth;
+        again = 0;
         if (b & 1u) {
-            if (gr[level_index(b >> 1, d) - 1] < W) depth = ~0u;  // identical strings, written by the scatter
-            else depth += step;
+            const uint32_t lx = level_index(b >> 1, d) - 1;
+            if ((gr[lx] & TR_CODE) < W) {
+                depth = ~0u;  // identical strings, written by the scatter
+            } else {
+                depth += step;
+                // every member has the sample string's next key: skip that word too
+                if ((gr[lx] & TR_SKIP) && cnt > p.base_max && tdf[lx] == 0) { depth += step; again = 1; }
+            }
         }
     };
     // shape of a distribution child of `cnt` strings
@@ -2120,8 +2224,8 @@ __device__ void dev_children(const Work& w, const Params& p, int cur, uint32_t i
     };
     // pass 1: count per list, finish singletons
     for (uint32_t b = lo + tid; b < hi; b += BLOCK) {
-        uint32_t st, cnt, depth;
-        bucket(b, st, cnt, depth);
+        uint32_t st, cnt, depth, again;
+        bucket(b, st, cnt, depth, again);
         if (cnt == 0) continue;
         const uint32_t pos = sg.begin + st;
         if (st > 0) atomicAdd(&sm.n_pend_l, 1u);
@@ -2183,8 +2287,8 @@ __device__ void dev_children(const Work& w, const Params& p, int cur, uint32_t i
     __syncthreads();
     // pass 2: write the reserved entries
     for (uint32_t b = lo + tid; b < hi; b += BLOCK) {
-        uint32_t st, cnt, depth;
-        bucket(b, st, cnt, depth);
+        uint32_t st, cnt, depth, again;
+        bucket(b, st, cnt, depth, again);
         if (cnt == 0) continue;
         const uint32_t pos = sg.begin + st;
         if (st > 0) {
@@ -2204,7 +2308,7 @@ __device__ void dev_children(const Work& w, const Params& p, int cur, uint32_t i
             const uint32_t coff = sm.bcnt + atomicAdd(&sm.ccnt, nk * nt);
             const uint32_t tioff = sm.btile + atomicAdd(&sm.ctile, nt);
             // the tile list entries are written by k_sample (one work group per segment)
-            w.dist[nxt][slot] = Seg{pos, cnt, depth, logv, toff, coff, tioff, sg.rid};
+            w.dist[nxt][slot] = Seg{pos, cnt, depth, logv, toff, coff, tioff, sg.rid, again};
         }
     }
 }

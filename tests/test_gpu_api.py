@@ -135,6 +135,10 @@ def test_level_budget_and_persistent_tail():
     rng = np.random.default_rng(12)
     rows = rng.integers(ord("a"), ord("d"), (n, L), dtype=np.uint8)
     rows[:, :100] = ord("k")  # a shared prefix: one equality bucket per 8 characters
+    # a few strings leave the prefix at the start of every word, so no level
+    # can skip more than the one word of its equality bucket
+    for j in range(1, 13):
+        rows[40 * j:40 * j + 40, 8 * j] = ord("a")
     c = rows.reshape(-1)
     o = np.arange(n + 1, dtype=np.uint64) * L
     cd, od = to_device(c, o)
@@ -145,3 +149,82 @@ def test_level_budget_and_persistent_tail():
         torch.cuda.synchronize()
         assert_equal_to_oracle(c, o, to_host(p), to_host(l), label=f"rep {rep}")
         assert ctx.stats()["levels"] > 10
+
+
+def shared_prefix_cases():
+    """Inputs whose large equality buckets share long prefixes."""
+    rng = np.random.default_rng(31)
+    out = []
+    # one prefix of 100 characters shared by all strings
+    n, L = 30000, 150
+    rows = rng.integers(ord("a"), ord("d"), (n, L), dtype=np.uint8)
+    rows[:, :100] = ord("k")
+    out.append(("prefix 100", rows.reshape(-1), np.arange(n + 1, dtype=np.uint64) * L))
+    # a prefix longer than one step can skip
+    n, L = 12000, 760
+    rows = rng.integers(ord("a"), ord("e"), (n, L), dtype=np.uint8)
+    rows[:, :700] = rng.integers(ord("a"), ord("z"), 700, dtype=np.uint8)
+    out.append(("prefix 700", rows.reshape(-1), np.arange(n + 1, dtype=np.uint64) * L))
+    # groups with prefixes of their own lengths behind a common one, plus
+    # exact duplicates of a few long strings and strings ending inside the
+    # prefixes
+    strings = []
+    for g in range(24):
+        plen = int(rng.integers(20, 220))
+        pre = bytes(rng.integers(ord("a"), ord("z"), plen, dtype=np.uint8))
+        for _ in range(int(rng.integers(1100, 2600))):
+            tail = bytes(rng.integers(ord("a"), ord("c"), int(rng.integers(0, 12)), dtype=np.uint8))
+            strings.append(b"http://www.site" + pre + tail)
+    for _ in range(3):
+        s = bytes(rng.integers(ord("a"), ord("z"), 300, dtype=np.uint8))
+        strings += [s] * 3000
+    for _ in range(2000):
+        s = strings[int(rng.integers(0, len(strings)))]
+        strings.append(s[:int(rng.integers(0, len(s) + 1))])
+    order = rng.permutation(len(strings))
+    strings = [strings[i] for i in order]
+    c, o = gen.from_list(strings)
+    out.append(("groups", c, o))
+    return out
+
+
+@pytest.mark.parametrize("mode", ["levels", "host_levels", "persistent"])
+def test_equality_buckets_skip_shared_prefixes(mode):
+    """Large equality buckets whose members all share the word after the
+    splitter's skip that word too (checked in the scatter of the level
+    modes; the persistent mode advances one word): every mode equals the
+    oracle, and the 100-character prefix takes fewer levels than one per
+    word."""
+    import paper_1808_00963_amd as ss
+    for label, c, o in shared_prefix_cases():
+        note(f"case shared prefix {label} mode {mode}")
+        cd, od = to_device(c, o)
+        ctx = ss.Context()
+        ctx.set_config(mode=mode, alphabet="bytes")
+        for rep in range(2):  # the second sort reuses the workspace and its tree arrays
+            p, l = ctx.sort(cd, od)
+            torch.cuda.synchronize()
+            assert_equal_to_oracle(c, o, to_host(p), to_host(l), label=f"{label} {mode} rep {rep}")
+        if label == "prefix 100" and mode != "persistent":
+            assert ctx.stats()["levels"] <= 9  # one word per level would take more than 12
+
+
+def test_shared_prefixes_with_compressed_keys():
+    """A shared prefix with keys of 2 bits per character (32 characters per
+    word): the skipped word is a compressed word."""
+    import paper_1808_00963_amd as ss
+    rng = np.random.default_rng(32)
+    n, L = 20000, 400
+    rows = rng.integers(ord("a"), ord("d"), (n, L), dtype=np.uint8)
+    rows[:, :300] = rng.integers(ord("a"), ord("d"), 300, dtype=np.uint8)
+    rows[:500, 150] = (rows[0, 150] - ord("a") + 1) % 3 + ord("a")  # a few leave the prefix in the middle
+    c = rows.reshape(-1)
+    o = np.arange(n + 1, dtype=np.uint64) * L
+    note("case shared prefix compressed")
+    cd, od = to_device(c, o)
+    ctx = ss.Context()
+    ctx.set_config(alphabet="compress")
+    p, l = ctx.sort(cd, od)
+    torch.cuda.synchronize()
+    assert_equal_to_oracle(c, o, to_host(p), to_host(l), label="compressed")
+    assert ctx.stats()["key_chars"] == 32
