@@ -577,9 +577,12 @@ def run_traffic(args):
         return rows[starts[-1]:]
 
     def short(name):
+        # library names: k_base_wave<E, AC> -> k_base_wave<E>, k_x<AC> -> k_x
         base = name.split("(")[0].replace("void ", "").replace("ss::", "")
-        return {"k_base_wave<1>": "k_base_wave1", "k_base_wave<2>": "k_base_wave2",
-                "k_base_wave<4>": "k_base_wave4"}.get(base, base)
+        if "<" in base:
+            kern, targs = base[:base.index("<")], base[base.index("<") + 1:].rstrip(">").split(",")
+            base = f"k_base_wave{targs[0].strip()}" if kern == "k_base_wave" else kern
+        return base
 
     kern = {}
     for (kf, vf), (kw, vw) in zip(last_sort(fetch), last_sort(write)):
