@@ -247,6 +247,11 @@ def serve_measure(pool_size=128, requests=2000, warmup=200, check=8):
         op[:] = o
         pool.append((cp, op))
     sizes = np.array([len(o) - 1 for _, o in pool])
+    # pinned result buffers per pool entry for the open-loop runs (at most a
+    # few dozen requests are in flight there, so entries j and j + P never
+    # overlap)
+    outs = [tuple(torch.empty(max(int(n), 1) * 4, dtype=torch.uint8, pin_memory=True).numpy().view(np.uint32)
+                  for _ in range(2)) for n in sizes]
     chars_of = np.array([int(o[-1]) for _, o in pool])
     log(f"serving pool: {P} requests, mean {sizes.mean():.0f} strings / {chars_of.mean() / 1e6:.2f} MB "
         f"({time.perf_counter() - t0:.1f}s)")
@@ -276,7 +281,7 @@ def serve_measure(pool_size=128, requests=2000, warmup=200, check=8):
                 d = start + arrivals[j] - time.perf_counter()
                 if d > 0:
                     time.sleep(d)
-                tickets[j] = (srv.submit(*pool[j % P]), time.perf_counter())
+                tickets[j] = (srv.submit(*pool[j % P], *outs[j % P]), time.perf_counter())
 
         th = threading.Thread(target=submitter)
         th.start()
@@ -295,10 +300,18 @@ def serve_measure(pool_size=128, requests=2000, warmup=200, check=8):
         t_end = time.perf_counter()
         L = np.array(lats[warm:]) / 1e3
         st = srv.stats()
+        # the slowest requests: index, strings, latency, submission time
+        # from the first measured request (for reading the tail)
+        worst = np.argsort(L)[::-1][:12]
+        tail = [[int(warm + q), int(sizes[(warm + q) % P]), round(float(L[q]), 3),
+                 round(float(arrivals[warm + q] - arrivals[warm]) * 1e3, 2)] for q in worst]
         return {"rate_req_s": rate, "requests": n_req - warm, "p50_ms": float(np.percentile(L, 50)),
                 "p99_ms": float(np.percentile(L, 99)), "mean_ms": float(L.mean()),
                 "chars_per_s": done_chars / (t_end - t_first), "inflight_max": st["inflight_max"],
-                "footprint_max_gb": st["footprint_max"] / 1e9}
+                "footprint_max_gb": st["footprint_max"] / 1e9,
+                "iter_max_ms": st["iter_max_us"] / 1e3, "iter_max_wait_ms": st["iter_max_wait_us"] / 1e3,
+                "iter_max_stage_ms": st["iter_max_stage_us"] / 1e3,
+                "slowest": {"columns": ["request", "strings", "latency_ms", "arrival_ms"], "rows": tail}}
 
     res = {}
     for frac in (0.5, 0.8):

@@ -343,6 +343,9 @@ typedef struct {
     uint64_t arena_bytes;         /* size of the device arena (<= hbm_budget) */
     double p50_us, p99_us, mean_us, max_us;  /* latency submit -> outputs on host */
     double busy_s;                /* wall time with requests in flight */
+    double iter_max_us;           /* longest engine iteration (admit, one level, completions) */
+    double iter_max_wait_us;      /* of it: time the worker waited for the device */
+    double iter_max_stage_us;     /* of it: time enqueueing the admitted requests' copies */
 } ss_server_stats;
 /* max_inflight: request slots on the device (1..65536); mean_len_hint:
  * expected characters per string used to split the budget between

@@ -66,7 +66,9 @@ class ServerStats(ctypes.Structure):
                 ("inflight_max", ctypes.c_uint32), ("pad", ctypes.c_uint32),
                 ("footprint_max", ctypes.c_uint64), ("arena_bytes", ctypes.c_uint64),
                 ("p50_us", ctypes.c_double), ("p99_us", ctypes.c_double), ("mean_us", ctypes.c_double),
-                ("max_us", ctypes.c_double), ("busy_s", ctypes.c_double)]
+                ("max_us", ctypes.c_double), ("busy_s", ctypes.c_double),
+                ("iter_max_us", ctypes.c_double), ("iter_max_wait_us", ctypes.c_double),
+                ("iter_max_stage_us", ctypes.c_double)]
 
 
 def lib():
@@ -421,14 +423,20 @@ class Server:
     def footprint(self, n: int, n_chars: int) -> int:
         return int(lib().ss_server_footprint(self._h, n, n_chars))
 
-    def submit(self, chars, offsets) -> int:
-        """Queues one request (numpy uint8 chars, uint64 offsets); returns a ticket."""
+    def submit(self, chars, offsets, perm_out=None, lcp_out=None) -> int:
+        """Queues one request (numpy uint8 chars, uint64 offsets); returns a
+        ticket.  perm_out / lcp_out: optional uint32 host arrays of at least
+        n entries for the results (pinned memory makes the copies back
+        asynchronous); new arrays otherwise."""
         import numpy as np
         chars = np.ascontiguousarray(chars, dtype=np.uint8)
         offsets = np.ascontiguousarray(offsets, dtype=np.uint64)
         n = offsets.size - 1
-        perm = np.empty(max(n, 1), dtype=np.uint32)
-        lcp = np.empty(max(n, 1), dtype=np.uint32)
+        perm = np.empty(max(n, 1), dtype=np.uint32) if perm_out is None else perm_out
+        lcp = np.empty(max(n, 1), dtype=np.uint32) if lcp_out is None else lcp_out
+        for a in (perm, lcp):
+            if a.dtype != np.uint32 or a.size < max(n, 1) or not a.flags.c_contiguous:
+                raise ValueError("output arrays must be contiguous uint32 with at least n entries")
         req = Request(chars.ctypes.data if chars.size else None, offsets.ctypes.data, n,
                       perm.ctypes.data, lcp.ctypes.data)
         t = ctypes.c_uint64()

@@ -1761,10 +1761,18 @@ void server_loop(ss_server* S) {
             }
         }
         const auto t_begin = Clock::now();
+        double wait_us = 0;  // time spent waiting for the device in this iteration
+        auto waited = [&](auto&& f) {
+            const auto a = Clock::now();
+            auto v = f();
+            wait_us += std::chrono::duration<double, std::micro>(Clock::now() - a).count();
+            return v;
+        };
         ss_status st = SS_OK;
         for (Req* r : admitted)
             if ((st = stage_request(S, r)) != SS_OK) break;
-        if (st == SS_OK) st = read_ctl(ctx, S->w, S->stream);
+        const double stage_us = std::chrono::duration<double, std::micro>(Clock::now() - t_begin).count();
+        if (st == SS_OK) st = waited([&] { return read_ctl(ctx, S->w, S->stream); });
         if (st == SS_OK && ctx->host_ctl->err) st = device_error_status(ctx->host_ctl->err);
         if (st == SS_OK) {
             LevelPlan L;
@@ -1779,7 +1787,7 @@ void server_loop(ss_server* S) {
         if (st == SS_OK) {
             hipError_t e = hipMemcpyAsync(S->h_remaining, S->d_remaining, sizeof(uint32_t) * S->max_inflight,
                                           hipMemcpyDeviceToHost, S->stream);
-            if (e == hipSuccess) e = hipStreamSynchronize(S->stream);
+            if (e == hipSuccess) e = waited([&] { return hipStreamSynchronize(S->stream); });
             if (e != hipSuccess) st = SS_HIP_ERROR;
         }
         if (st == SS_OK) {
@@ -1804,18 +1812,24 @@ void server_loop(ss_server* S) {
                                            hipMemcpyDeviceToHost, S->stream);
                 }
             }
-            if (e == hipSuccess) e = hipStreamSynchronize(S->stream);
+            if (e == hipSuccess) e = waited([&] { return hipStreamSynchronize(S->stream); });
             for (Req* r : finished) S->h_done[r->rid] = 0;
             if (e == hipSuccess) e = hipMemcpyAsync(S->d_done, S->h_done, S->max_inflight, hipMemcpyHostToDevice, S->stream);
             if (e != hipSuccess) st = SS_HIP_ERROR;
             if (st == SS_OK && ctx->host_ctl->err == 0) {
-                if (read_ctl(ctx, S->w, S->stream) != SS_OK) st = SS_HIP_ERROR;
+                if (waited([&] { return read_ctl(ctx, S->w, S->stream); }) != SS_OK) st = SS_HIP_ERROR;
                 else if (ctx->host_ctl->err) st = device_error_status(ctx->host_ctl->err);
             }
         }
         {
             std::lock_guard<std::mutex> lk(S->mu);
-            S->busy_s += std::chrono::duration<double>(Clock::now() - t_begin).count();
+            const double it_us = std::chrono::duration<double, std::micro>(Clock::now() - t_begin).count();
+            S->busy_s += it_us * 1e-6;
+            if (it_us > S->st.iter_max_us) {
+                S->st.iter_max_us = it_us;
+                S->st.iter_max_wait_us = wait_us;
+                S->st.iter_max_stage_us = stage_us;
+            }
             if (st != SS_OK) {
                 fail_all_locked(S, st);
                 // start over with an empty device state
