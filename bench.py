@@ -762,8 +762,8 @@ def main():
                     help="strings for the oracle timing (a prefix of the workload; 0 = all)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on exactly one GPU (asked for {args.gpus}); "
-              "the sort is single-GPU and multi-GPU sharding is not implemented.", file=sys.stderr)
+        print(f"bench.py: the sort runs on exactly one GPU (asked for {args.gpus}); "
+              "sharding across GPUs is not implemented.", file=sys.stderr)
         sys.exit(2)
 
     if args.mode == "batch":
