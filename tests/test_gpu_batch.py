@@ -283,3 +283,67 @@ def test_graph_tail_runs_deeper_contents():
     torch.cuda.synchronize()
     assert eager.stats()["levels"] > few
     g.close()
+
+
+def shared_prefix_batch(seed=41):
+    """Sets whose large equality buckets share long prefixes (so they skip
+    words) beside ordinary sets; one set of exact duplicates."""
+    rng = np.random.default_rng(seed)
+    strings, sb = [], [0]
+    for j in range(12):
+        if j % 3 == 0:  # ordinary Markov set
+            c, o = gen.generate("markov", int(rng.integers(500, 4000)), int(rng.integers(1, 1 << 30)))
+            strings += gen.to_list(c, o)
+        elif j % 3 == 1:  # a shared prefix of 40-120 characters, then short tails
+            pre = bytes(rng.integers(ord("a"), ord("z"), int(rng.integers(40, 120)), dtype=np.uint8))
+            for _ in range(int(rng.integers(1500, 5000))):
+                strings.append(pre + bytes(rng.integers(ord("a"), ord("d"), int(rng.integers(0, 10)), dtype=np.uint8)))
+        else:  # groups, each with a prefix of its own behind a common one
+            for _ in range(4):
+                pre = b"http://" + bytes(rng.integers(ord("a"), ord("z"), int(rng.integers(20, 80)), dtype=np.uint8))
+                for _ in range(int(rng.integers(1100, 1600))):
+                    strings.append(pre + bytes(rng.integers(ord("a"), ord("c"), int(rng.integers(0, 8)), dtype=np.uint8)))
+        sb.append(len(strings))
+    strings += [b"y" * 90] * 3000  # exact duplicates
+    sb.append(len(strings))
+    c, o = gen.from_list(strings)
+    return c, o, np.array(sb, dtype=np.uint32)
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_batch_with_shared_prefixes(mode):
+    """Sets whose large equality buckets skip shared words, every mode:
+    each set equals the oracle on that set."""
+    import paper_1808_00963_amd as ss
+    note(f"case batch shared prefixes mode={mode}")
+    c, o, sb = shared_prefix_batch()
+    ctx = ss.Context()
+    ctx.set_config(mode=mode)
+    p, l = run_batch(c, o, sb, ctx)
+    check_sets(c, o, sb, p, l)
+
+
+def test_graph_with_shared_prefixes():
+    """The captured batched sort on sets that skip shared words: every replay
+    equals the eager result, which equals the oracle."""
+    import paper_1808_00963_amd as ss
+    note("case graph shared prefixes")
+    c, o, sb = shared_prefix_batch(seed=43)
+    ctx = ss.Context()
+    eager = run_batch(c, o, sb, ctx)
+    check_sets(c, o, sb, *eager)
+    cd, od = to_device(c, o)
+    sbd = torch.from_numpy(sb.astype(np.int32)).cuda()
+    n = len(o) - 1
+    perm = torch.full((n,), -1, dtype=torch.int32, device="cuda")
+    lcp = torch.full((n,), -1, dtype=torch.int32, device="cuda")
+    g = ctx.graph_batch(cd, od, sbd, perm, lcp)
+    stream = torch.cuda.current_stream()
+    for rep in range(3):
+        perm.fill_(-1)
+        lcp.fill_(-1)
+        g.launch(stream)
+        ctx.sync(stream)
+        assert np.array_equal(to_host(perm), eager[0]), f"replay {rep} perm"
+        assert np.array_equal(to_host(lcp), eager[1]), f"replay {rep} lcp"
+    g.close()
