@@ -192,3 +192,25 @@ def test_serving_workload_sizes_8gb_budget():
         p, l, _ = srv.wait(srv.submit(*r))
         assert np.array_equal(p, mix[i][0]) and np.array_equal(l, mix[i][1]), f"request {i} alone vs mix"
     srv.close()
+
+
+def test_requests_with_shared_prefixes():
+    """Requests whose large equality buckets skip shared words, submitted
+    together with ordinary ones: each result equals the oracle's."""
+    import paper_1808_00963_amd as ss
+    note("case serve shared prefixes")
+    rng = np.random.default_rng(44)
+    reqs = request_pool(6, seed=45, hi=5e4)
+    for j in range(4):
+        pre = bytes(rng.integers(ord("a"), ord("z"), int(rng.integers(30, 150)), dtype=np.uint8))
+        strings = [pre + bytes(rng.integers(ord("a"), ord("d"), int(rng.integers(0, 12)), dtype=np.uint8))
+                   for _ in range(int(rng.integers(2000, 8000)))]
+        reqs.append(gen.from_list(strings))
+    reqs.append(gen.from_list([b"z" * 70] * 2500))  # exact duplicates
+    exp = [expect(r) for r in reqs]
+    srv = ss.Server(2 << 30, max_inflight=64)
+    tickets = [srv.submit(*r) for r in reqs]
+    got = [srv.wait(t)[:2] for t in tickets]
+    srv.close()
+    for i, (g, e) in enumerate(zip(got, exp)):
+        assert np.array_equal(g[0], e[0]) and np.array_equal(g[1], e[1]), f"request {i}"
