@@ -117,18 +117,25 @@ typedef struct {
                                    probes the first 16 bytes of 1024 strings;
                                    for inputs of at most 3 distinct bytes and
                                    at most 64 characters per string on average
-                                   one pass over chars[offsets[0], offsets[n])
-                                   checks every byte, and the keys are
-                                   compressed if the whole input qualifies.
+                                   the keys are compressed with the probed
+                                   byte set.  Every compressed key gather
+                                   checks its bytes against the set; if one
+                                   lies outside, the sort runs again after a
+                                   pass over chars[offsets[0], offsets[n])
+                                   that finds every byte (compressed if the
+                                   whole input qualifies, else byte keys;
+                                   ss_stats.alphabet_retries counts it).
                                    SS_ALPHABET_COMPRESS: the same for inputs
                                    of at most 15 distinct bytes and any
                                    length.  With AUTO or COMPRESS the call
-                                   waits for the probe and the check (the level
-                                   kernels come in a byte-key and a compressed
-                                   form; the host launches one), except in
-                                   SS_MODE_PERSISTENT.  Graphs, ss_sort_noalloc
-                                   and serving use byte keys.  Results never
-                                   depend on this setting. */
+                                   waits for the probe and, when the keys are
+                                   compressed, for the sort (the level kernels
+                                   come in a byte-key and a compressed form;
+                                   the host launches one); SS_MODE_PERSISTENT
+                                   checks every byte before its single
+                                   launch and does not wait.  Graphs,
+                                   ss_sort_noalloc and serving use byte keys.
+                                   Results never depend on this setting. */
 } ss_config;
 
 /* Returns a short description of a status code (static storage). */
@@ -389,8 +396,10 @@ typedef struct {
     uint64_t base_strings_by_class[4];  /* strings in those segments */
     uint32_t key_chars;     /* characters per 64-bit key: 8 (byte keys) or 16,
                                21 or 32 (alphabet-compressed keys) */
-    uint32_t alphabet_size; /* distinct bytes of the input when the alphabet
-                               check ran to the end (keys compressed), else 0 */
+    uint32_t alphabet_size; /* distinct bytes of the key format's byte set
+                               when the keys were compressed, else 0 */
+    uint32_t alphabet_retries; /* 1 when compressed keys met a byte outside the
+                                  probed set and the sort ran again */
 } ss_stats;
 ss_status ss_get_stats(ss_ctx* ctx, ss_stats* st);
 

@@ -46,7 +46,7 @@ class Stats(ctypes.Structure):
                 ("pending_lcps", ctypes.c_uint32), ("max_depth", ctypes.c_uint32),
                 ("base_rounds", ctypes.c_uint32), ("base_segments_by_class", ctypes.c_uint32 * 4),
                 ("base_strings_by_class", ctypes.c_uint64 * 4), ("key_chars", ctypes.c_uint32),
-                ("alphabet_size", ctypes.c_uint32)]
+                ("alphabet_size", ctypes.c_uint32), ("alphabet_retries", ctypes.c_uint32)]
 
 
 class KernelTime(ctypes.Structure):

@@ -77,6 +77,7 @@ struct ss_ctx {
     Ws ws;                    // workspace of the context's own sorts
     Ctl* host_ctl = nullptr;  // pinned: the control block after the last sort
     ss_config cfg{10, 64, 1024, SS_MODE_LEVELS, SS_ALPHABET_BYTES};
+    uint32_t alphabet_retries = 0;  // of the last sort: compressed keys met a byte outside the probed set
     ss_status sticky = SS_OK;
     ss_stats stats{};
     bool pending = false;     // host_ctl of the last sort not yet absorbed
@@ -337,6 +338,7 @@ void absorb(ss_ctx* ctx) {
     st.key_chars = c.alpha.bpc ? c.alpha.cpw : W;
     if (c.alpha.bpc)
         for (int q = 0; q < 4; ++q) st.alphabet_size += (uint32_t)__builtin_popcountll(c.alpha.seen[q]);
+    st.alphabet_retries = ctx->alphabet_retries;
     ctx->stats = st;
     if (c.stats.levels) ctx->level_hint = c.stats.levels;
     // the device keeps the errors of every sort since the last clear, so an
@@ -621,35 +623,49 @@ ss_status run_sort(ss_ctx* ctx, const uint8_t* chars, const uint64_t* offsets, u
              ctx->cfg.base_max,
              ctx->cfg.alphabet};
     const uint32_t nroots = set_begin ? num_sets : 1;
+    ctx->alphabet_retries = 0;
     if (ctx->cfg.mode == SS_MODE_PERSISTENT) {  // the persistent kernel reads the key format on the device
         SS_TRY(launch_reset(w, s));
         SS_TRY(timed(&ctx->prof, s, K_ALPHABET, units_const(n),
-                     [&] { return launch_alphabet(w, p, ctx->kc.classify, s); }));
+                     [&] { return launch_alphabet(w, p, ctx->kc.classify, true, s); }));
         SS_TRY(timed(&ctx->prof, s, K_PERSIST, units_const(n), [&] {
             return launch_persistent(w, p, set_begin, nroots, ctx->kc.persist, true, 0, 0, false, s);
         }));
     } else {
         // the level kernels come in a byte-key and a compressed-key form; the
         // host picks one, so a sort that may compress its keys first waits
-        // for the alphabet kernels
-        bool started = false;
-        if (p.alphabet != SS_ALPHABET_BYTES) {
-            SS_TRY(launch_reset(w, s));
-            SS_TRY(timed(&ctx->prof, s, K_ALPHABET, units_const(n),
-                         [&] { return launch_alphabet(w, p, ctx->kc.classify, s); }));
-            decltype(Ctl::alpha) a;
-            SS_TRY(hipMemcpyAsync(&a, &w.ctl->alpha, sizeof(a), hipMemcpyDeviceToHost, s));
+        // for the alphabet probe.  The first attempt trusts the probe's byte
+        // set (no pass over every character); a compressed gather that meets
+        // another byte flags it, and the sort is run again with the set
+        // checked in full (the results depend only on gathered bytes, so an
+        // unflagged attempt equals the byte-key sort).
+        for (bool checked = false;; checked = true) {
+            bool started = false;
+            if (p.alphabet != SS_ALPHABET_BYTES) {
+                SS_TRY(launch_reset(w, s));
+                SS_TRY(timed(&ctx->prof, s, K_ALPHABET, units_const(n),
+                             [&] { return launch_alphabet(w, p, ctx->kc.classify, checked, s); }));
+                decltype(Ctl::alpha) a;
+                SS_TRY(hipMemcpyAsync(&a, &w.ctl->alpha, sizeof(a), hipMemcpyDeviceToHost, s));
+                SS_TRY(hipStreamSynchronize(s));
+                uint64_t m[4] = {0, 0, 0, 0};
+                if (a.cand && !a.over)
+                    for (int q = 0; q < 4; ++q) m[q] = a.seen[q];
+                p.ac = key_fmt_of(m).bpc != 0 ? 1u : 0u;
+                started = true;
+            }
+            if (ctx->cfg.mode == SS_MODE_HOST_LEVELS) {
+                if ((st = run_sort_host_levels(ctx, w, p, set_begin, nroots, s, started)) != SS_OK) return st;
+            } else if ((st = enqueue_sort_levels(engine_of(ctx), w, p, set_begin, nroots, levels, s, started)) !=
+                       SS_OK) {
+                return st;
+            }
+            if (!p.ac || checked) break;
+            uint32_t miss = 0;
+            SS_TRY(hipMemcpyAsync(&miss, &w.ctl->alpha.miss, sizeof(miss), hipMemcpyDeviceToHost, s));
             SS_TRY(hipStreamSynchronize(s));
-            uint64_t m[4] = {0, 0, 0, 0};
-            if (a.cand && !a.over)
-                for (int q = 0; q < 4; ++q) m[q] = a.seen[q];
-            p.ac = key_fmt_of(m).bpc != 0 ? 1u : 0u;
-            started = true;
-        }
-        if (ctx->cfg.mode == SS_MODE_HOST_LEVELS) {
-            if ((st = run_sort_host_levels(ctx, w, p, set_begin, nroots, s, started)) != SS_OK) return st;
-        } else if ((st = enqueue_sort_levels(engine_of(ctx), w, p, set_begin, nroots, levels, s, started)) != SS_OK) {
-            return st;
+            if (!miss) break;
+            ++ctx->alphabet_retries;
         }
     }
     SS_TRY(hipMemcpyAsync(ctx->host_ctl, w.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));

@@ -154,9 +154,11 @@ struct Ctl {
     LevelRec lv[LEVEL_RECS];
     // Alphabet of the sort (the key format follows from it, see KeyFmt):
     // the probe sets `cand` when a sample of the strings shows at most
-    // `limit` distinct bytes and records them in `seen`; the check adds every
-    // other byte of the input to `seen` and sets `over` once more than
-    // `limit` are known.  Compressed keys exactly when cand && !over.
+    // `limit` distinct bytes and records them in `seen`; the check (when
+    // run) adds every other byte of the input to `seen` and sets `over` once
+    // more than `limit` are known.  Compressed keys exactly when
+    // cand && !over.  Without the check, every compressed gather sets
+    // `miss` when it meets a byte outside `seen`, and the host sorts again.
     // The key gather (k_init) also writes the resulting code width and
     // characters per word for the kernels after it (bpc = 0: byte keys).
     struct alignas(128) {
@@ -166,6 +168,7 @@ struct Ctl {
         uint32_t cpw;
         uint64_t seen[4];
         uint32_t limit;  // most bytes the set may hold for compressed keys
+        uint32_t miss;   // a compressed gather met a byte outside the set
     } alpha;
 };
 inline uint32_t base_rounds_of(const Ctl& c) {
@@ -281,7 +284,7 @@ hipError_t launch_reset(const Work& w, hipStream_t s);
 // The sort's alphabet (after launch_reset, before launch_init): a probe of
 // a sample of the strings, then, when it found at most 15 distinct bytes, a
 // check of every byte of the input.
-hipError_t launch_alphabet(const Work& w, const Params& p, uint32_t check_grid, hipStream_t s);
+hipError_t launch_alphabet(const Work& w, const Params& p, uint32_t check_grid, bool check, hipStream_t s);
 hipError_t launch_init(const Work& w, const Params& p, hipStream_t s);
 hipError_t launch_roots(const Work& w, const Params& p, const uint32_t* set_begin, uint32_t num_sets,
                         hipStream_t s);

@@ -171,9 +171,13 @@ __device__ __forceinline__ void fmt_publish(const Work& w, const KeyFmt& f) {
 __device__ __forceinline__ uint64_t key_at_packed(const Work& w, const uint8_t* chars, uint64_t off, uint32_t h,
                                                   uint32_t len) {
     const KeyFmt f = fmt_full(w);
-    bool miss = false;  // every byte of the input is in the set (checked before the sort)
-    return gather_packed_with(chars, off, h, len, f, [](const uint64_t* q) { return __builtin_nontemporal_load(q); },
-                              &miss);
+    bool miss = false;
+    const uint64_t key = gather_packed_with(
+        chars, off, h, len, f, [](const uint64_t* q) { return __builtin_nontemporal_load(q); }, &miss);
+    // a byte outside the set (possible when the input was not checked in
+    // full): the key is not to be trusted, the host sorts again
+    if (miss) w.ctl->alpha.miss = 1;
+    return key;
 }
 __device__ __forceinline__ uint64_t key_at(const Work& w, const KeyFmt& fh, const uint8_t* chars, uint64_t off,
                                            uint32_t h, uint32_t len) {
@@ -2595,8 +2599,8 @@ __device__ __forceinline__ void set_add(uint64_t (&m)[4], uint32_t c) {
 // hold few enough distinct values, they become the candidate set (cand).
 // ALPHABET_AUTO asks for at most 3 (2-bit codes, 32 characters per key
 // instead of 8) and at most COMPRESS_MAX_AVG characters per string on
-// average (the check below reads every character once, the sort moves about
-// 26 bytes per string and level); ALPHABET_COMPRESS asks for at most 15 and
+// average (a retry's check below reads every character once, the sort moves
+// about 26 bytes per string and level); ALPHABET_COMPRESS asks for at most 15 and
 // any length.  Otherwise nothing is set and the sort uses byte keys (the
 // reset cleared the state).
 constexpr uint32_t PROBE_STRINGS = 1024, COMPRESS_MAX_AVG = 64, AUTO_MAX_SYMBOLS = 3;
@@ -2639,7 +2643,8 @@ __global__ __launch_bounds__(PROBE_STRINGS) void k_alpha_probe(Work w, Params p)
     }
 }
 
-// Every byte of chars[offsets[0], offsets[n]) against the set: a byte
+// Every byte of chars[offsets[0], offsets[n]) against the set (before a
+// persistent sort, or when a sort with the probed set met another byte): a byte
 // outside it is added (each work group keeps a byte table in LDS, so a new
 // byte costs one global atomic per group), and once the set holds more than
 // the probe's limit `over` is set and every group stops.  Reads whole aligned
@@ -2691,10 +2696,10 @@ __global__ __launch_bounds__(BLOCK) void k_alpha_check(Work w, Params p) {
     }
 }
 
-hipError_t launch_alphabet(const Work& w, const Params& p, uint32_t check_grid, hipStream_t s) {
+hipError_t launch_alphabet(const Work& w, const Params& p, uint32_t check_grid, bool check, hipStream_t s) {
     if (p.alphabet == ALPHABET_BYTES) return hipSuccess;  // byte keys: the reset left the state empty
     hipLaunchKernelGGL(k_alpha_probe, dim3(1), dim3(PROBE_STRINGS), 0, s, w, p);
-    hipLaunchKernelGGL(k_alpha_check, dim3(check_grid > 0 ? check_grid : 1), dim3(BLOCK), 0, s, w, p);
+    if (check) hipLaunchKernelGGL(k_alpha_check, dim3(check_grid > 0 ? check_grid : 1), dim3(BLOCK), 0, s, w, p);
     return hipGetLastError();
 }
 __global__ void k_report(Work w, uint32_t* out) {

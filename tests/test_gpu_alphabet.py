@@ -59,28 +59,58 @@ def test_alphabets_vs_oracle(alphabet, key_chars, n):
 
 
 def test_rare_byte_beyond_the_probe():
-    """A fifth symbol only deep inside a few strings: the probe sees four,
-    the check finds the fifth, keys stay compressed (21 per key)."""
+    """A fifth symbol in a few strings, after the 16 bytes the probe reads
+    but inside every string's first key: the first attempt's key gather
+    meets it, the sort runs again with the full check, which finds the
+    fifth symbol; keys stay compressed (21 per key)."""
     note("case rare byte")
     strings = strings_over(b"ACGT", 30000, 5, max_len=100)
     for i in range(7, 30000, 4999):
         s = strings[i]
-        strings[i] = (s + b"ACGTACGTACGTACGTACGTACGT")[:40] + b"N" + s[40:]
+        strings[i] = (s + b"ACGTACGTACGTACGTACGTACGT")[:17] + b"N" + s[17:]
     c, o, p, l, st = sort_with(strings, "compress")
     assert_equal_to_oracle(c, o, p, l, label="rare byte")
     assert st["key_chars"] == 21 and st["alphabet_size"] == 5
+    assert st["alphabet_retries"] == 1
+
+
+def test_byte_the_sort_never_reads():
+    """A fourth symbol only far inside strings that differ from every other
+    string within their first key: no gather reads it, so the first attempt
+    (keys compressed with the three probed symbols, 32 per key) stands and
+    still equals the oracle."""
+    note("case unread byte")
+    strings = strings_over(b"ACG", 30000, 8, max_len=100)
+    heads = {}
+    for s in strings:
+        heads[s[:32]] = heads.get(s[:32], 0) + 1
+    marked = 0
+    for i in range(11, 30000, 331):
+        s = strings[i]
+        if len(s) > 70 and heads[s[:32]] == 1:  # no other string shares its first key
+            strings[i] = s[:60] + b"T" + s[61:]
+            marked += 1
+    assert marked >= 10
+    c, o, p, l, st = sort_with(strings, "compress")
+    assert_equal_to_oracle(c, o, p, l, label="unread byte")
+    assert st["alphabet_retries"] == 0
+    assert st["key_chars"] == 32 and st["alphabet_size"] == 3
 
 
 def test_too_many_bytes_after_the_probe():
-    """Fifteen symbols in the strings' first bytes, more later: the check
-    gives up and the sort uses byte keys."""
+    """Fifteen symbols in the strings' first bytes, more later: some strings
+    share their first key (16 characters) and differ in a byte outside the
+    probed set, the gather one key further meets it, and the check of the
+    second attempt gives up: byte keys."""
     note("case over")
-    strings = strings_over(bytes(range(97, 112)), 20000, 6, max_len=60)
+    syms = bytes(range(97, 112))
+    strings = strings_over(syms, 20000, 6, max_len=60)
+    head = bytes(syms[(7 * k) % 15] for k in range(16))
     for i in range(3, 20000, 97):
-        strings[i] = strings[i] + bytes([200 + (i % 30)])
+        strings[i] = head + bytes([200 + (i % 30)]) + strings[i][:20]
     c, o, p, l, st = sort_with(strings, "compress")
     assert_equal_to_oracle(c, o, p, l, label="over")
-    assert st["key_chars"] == 8
+    assert st["key_chars"] == 8 and st["alphabet_retries"] == 1
 
 
 @pytest.mark.parametrize("model", ["binary", "dna_reads"])
