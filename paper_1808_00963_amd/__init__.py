@@ -192,8 +192,8 @@ class Context:
 
     def set_config(self, max_log_splitters=None, bucket_target=None, base_max=None, mode=None, alphabet=None):
         """mode: "levels" (device-driven levels, default), "persistent" or
-        "host_levels" (or the MODE_* constants); alphabet: "auto" (default)
-        "bytes" or "compress" (or the ALPHABET_* constants)."""
+        "host_levels" (or the MODE_* constants); alphabet: "bytes"
+        (default), "auto" or "compress" (or the ALPHABET_* constants)."""
         c = self.config
         if max_log_splitters is not None:
             c.max_log_splitters = max_log_splitters
