@@ -147,6 +147,44 @@ def test_auto_policy():
         assert st2["key_chars"] == compress_chars
 
 
+@pytest.mark.parametrize("mode", ["levels", "host_levels", "persistent"])
+@pytest.mark.parametrize("form", ["single", "batch"])
+def test_retry_in_every_mode_and_in_a_batch(mode, form):
+    """A symbol outside the probed set inside the first key of a few strings
+    of one set: the level modes sort a second time with the full check
+    (one retry), the persistent mode checks before its launch (none); either
+    way every set equals the oracle with 5 symbols, 21 per key."""
+    import paper_1808_00963_amd as ss
+    import torch
+    from gpu_util import to_device, to_host
+    note(f"case retry mode={mode} form={form}")
+    strings = strings_over(b"ACGT", 9000, 12, max_len=80, shared=0.2)
+    for i in range(5003, 5400, 97):  # inside the fourth set of the batch
+        s = strings[i]
+        strings[i] = (s + b"TTGCATTGCATTGCATTGCA")[:18] + b"N" + s[18:]
+    c, o = gen.from_list(strings)
+    ctx = ss.Context()
+    ctx.set_config(mode=mode, alphabet="compress")
+    if form == "single":
+        p, l = gpu_sort(c, o, ctx=ctx)
+        assert_equal_to_oracle(c, o, p, l, label=f"{mode}")
+    else:
+        sb = np.array([0, 1, 1, 4000, 8999, 9000], dtype=np.uint32)
+        cd, od = to_device(c, o)
+        pd, ld = ctx.sort_batch(cd, od, torch.from_numpy(sb.astype(np.int32)).cuda())
+        torch.cuda.synchronize()
+        p, l = to_host(pd), to_host(ld)
+        for j in range(len(sb) - 1):
+            b, e = int(sb[j]), int(sb[j + 1])
+            if e > b:
+                cj = c[int(o[b]):int(o[e])]
+                oj = o[b:e + 1] - o[b]
+                assert_equal_to_oracle(cj, oj, p[b:e], l[b:e], label=f"{mode} set {j}")
+    st = ctx.stats()
+    assert st["key_chars"] == 21 and st["alphabet_size"] == 5
+    assert st["alphabet_retries"] == (0 if mode == "persistent" else 1)
+
+
 def test_compressed_modes_and_batch():
     """Compressed keys in the host-driven and persistent modes and in a batch
     of DNA sets."""
