@@ -424,13 +424,68 @@ __device__ __forceinline__ void dev_init_one(const Work& w, const KeyFmt& fh, co
     rec_put(w, 0, i, key_at(w, fh, p.chars, o0, 0, len), i, kf_r(fh, len, 0));
 }
 
+// The key gather with compressed keys codes every string's first word.  It
+// reads each byte's code from a table in LDS (tab[c]: the code of c, or
+// TAB_MISS for a byte outside the set) instead of ranking the byte in the
+// set as key_at_packed does, loads the (at most five) aligned words that
+// hold the first CPW = 64 / BPC characters at once, aligns them into 8-byte
+// groups and codes every character position unrolled (positions past the
+// string's end code 0), so the loads and the table reads are all in flight
+// together.
+constexpr uint32_t TAB_MISS = 0x80;
+template <uint32_t BPC>
+__device__ __forceinline__ uint64_t gather_packed_tab(const uint8_t* chars, uint64_t off, uint32_t len,
+                                                      const uint8_t* tab, uint32_t& bad) {
+    constexpr uint32_t CPW = 64 / BPC, NG = (CPW + 7) / 8;
+    const uint32_t rem = len < CPW ? len : CPW;
+    if (rem == 0) return 0;
+    const uintptr_t a = (uintptr_t)(chars + off);
+    const uint64_t* q = (const uint64_t*)(a & ~(uintptr_t)7);
+    const uint32_t sh = (uint32_t)(a & 7), nw = (sh + rem + 7) >> 3;  // words that hold the characters
+    uint64_t wd[NG + 1];
+#pragma unroll
+    for (uint32_t u = 0; u <= NG; ++u) wd[u] = u < nw ? __builtin_nontemporal_load(q + u) : 0ull;
+    uint64_t key = 0;
+#pragma unroll
+    for (uint32_t g = 0; g < NG; ++g) {
+        // characters 8g .. 8g+7 of the string
+        const uint64_t grp = sh ? (wd[g] >> (8 * sh)) | (wd[g + 1] << (64 - 8 * sh)) : wd[g];
+#pragma unroll
+        for (uint32_t j = 0; j < 8; ++j) {
+            const uint32_t k = 8 * g + j;
+            if (k >= CPW) break;
+            const uint32_t t = k < rem ? (uint32_t)tab[(uint32_t)(grp >> (8 * j)) & 0xFFu] : 0u;
+            bad |= t;
+            key |= (uint64_t)(t & 0x0Fu) << (64 - BPC * (k + 1));
+        }
+    }
+    return key;
+}
+
 template <bool AC>
 __global__ __launch_bounds__(BLOCK) void k_init(Work w, Params p) {
     uint32_t i = blockIdx.x * BLOCK + threadIdx.x;
     if constexpr (AC) {
+        __shared__ uint8_t tab[256];
         const KeyFmt f = fmt_full(w);
         if (i == 0) fmt_publish(w, f);
-        if (i < p.n) dev_init_one(w, f, p, i);
+        for (uint32_t c = threadIdx.x; c < 256; c += BLOCK)
+            tab[c] = (uint8_t)(kf_has(f, c) ? kf_code(f, c) : TAB_MISS);
+        __syncthreads();
+        if (i < p.n) {
+            uint64_t o0 = p.offsets[i], o1 = p.offsets[i + 1];
+            uint32_t len = 0;
+            if (o1 < o0 || o1 - o0 > MAX_LEN || (o1 > o0 && p.chars == nullptr)) raise_err(w, ERR_OFFSETS);
+            else len = (uint32_t)(o1 - o0);
+            uint32_t bad = 0;
+            const uint64_t key = f.bpc == 2   ? gather_packed_tab<2>(p.chars, o0, len, tab, bad)
+                                 : f.bpc == 3 ? gather_packed_tab<3>(p.chars, o0, len, tab, bad)
+                                              : gather_packed_tab<4>(p.chars, o0, len, tab, bad);
+            // a byte outside the set (the input was not checked in full): the
+            // host sorts again
+            if (bad & TAB_MISS) w.ctl->alpha.miss = 1;
+            rec_put(w, 0, i, key, i, kf_r(f, len, 0));
+        }
     } else {
         if (i < p.n) dev_init_one(w, fmt_of<false>(w), p, i);
     }
