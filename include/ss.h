@@ -449,6 +449,16 @@ uint64_t ss_host_key(const uint8_t* s, uint64_t len, uint64_t h, uint32_t* r_out
  * unreadable pages to show that nothing else is read). */
 uint64_t ss_host_gather_key(const uint8_t* chars, uint64_t off, uint32_t h, uint32_t len);
 
+/* The base cases' common-prefix scan (the LCP of two strings known to
+ * agree on their first `from` characters, at most min(la, lb, cap); the
+ * "last compared word" of section 4.2.8's LCP computation) on the host:
+ * strings chars[oa, oa + la) and chars[ob, ob + lb), each string's aligned
+ * words read once, `ahead` (1, 2 or 4) words per string per step.  Reads
+ * only aligned words that hold characters of the strings; the caller
+ * guarantees the first `from` characters agree. */
+uint32_t ss_host_lcp_stream(const uint8_t* chars, uint64_t oa, uint32_t la, uint64_t ob, uint32_t lb,
+                            uint32_t from, uint32_t cap, uint32_t ahead);
+
 /* The kernels' alphabet-compressed key gather (alphabet compression,
  * section 4.6.1) on the host: byte_set = the 256-bit set of bytes present
  * (four words, bit c of word c/64); with 1..15 members each character is

@@ -120,6 +120,7 @@ def lib():
             "ss_host_key": (u64, [vp, u64, u64, ctypes.POINTER(u32)]),
             "ss_host_gather_key": (u64, [vp, u64, u32, u32]),
             "ss_host_gather_packed": (u64, [vp, u64, u32, u32, vp, vp, vp]),
+            "ss_host_lcp_stream": (u32, [vp, u64, u32, u64, u32, u32, u32, u32]),
             "ss_host_key_lcp": (u32, [vp, u64, u32, u64, u32, u32]),
             "ss_host_level_index": (u32, [u32, u32]),
             "ss_host_inorder_index": (u32, [u32, u32]),

@@ -1489,6 +1489,18 @@ uint64_t ss_host_gather_key(const uint8_t* chars, uint64_t off, uint32_t h, uint
     });
 }
 
+uint32_t ss_host_lcp_stream(const uint8_t* chars, uint64_t oa, uint32_t la, uint64_t ob, uint32_t lb, uint32_t from,
+                            uint32_t cap, uint32_t ahead) {
+    auto load = [](const uint64_t* q) {
+        uint64_t w;
+        std::memcpy(&w, q, sizeof(w));
+        return w;
+    };
+    if (ahead <= 1) return lcp_stream_with<1>(chars, oa, la, ob, lb, from, cap, load);
+    if (ahead <= 2) return lcp_stream_with<2>(chars, oa, la, ob, lb, from, cap, load);
+    return lcp_stream_with<4>(chars, oa, la, ob, lb, from, cap, load);
+}
+
 uint64_t ss_host_gather_packed(const uint8_t* chars, uint64_t off, uint32_t h, uint32_t len, const uint64_t* byte_set,
                                uint32_t* chars_per_key, int* miss) {
     uint64_t m[4] = {0, 0, 0, 0};

@@ -53,6 +53,59 @@ SS_HD uint32_t common_bytes(uint64_t a, uint64_t b) {
     return x ? (uint32_t)(__builtin_clzll(x) >> 3) : 8u;
 }
 
+// Length of the common prefix of two strings a = chars[oa, oa + la) and
+// b = chars[ob, ob + lb) that agree on their first `from` characters, at
+// most limit = min(la, lb, cap).  The first 8 characters past `from` are
+// compared as keys (they usually decide); after that each string's aligned
+// words are read once, in steps of AHEAD words per string loaded together,
+// and every 8 characters are compared as a little-endian group formed from
+// two neighbouring words (the first difference is the lowest differing
+// byte).  Like gather_key_with, it reads only words that hold characters
+// of the string.
+template <uint32_t AHEAD, typename Load>
+SS_HD uint32_t lcp_stream_with(const uint8_t* chars, uint64_t oa, uint32_t la, uint64_t ob, uint32_t lb,
+                               uint32_t from, uint32_t cap, Load load) {
+    uint32_t limit = la < lb ? la : lb;
+    limit = limit < cap ? limit : cap;
+    uint32_t d = from;
+    if (d >= limit) return limit;
+    {
+        const uint64_t ka = gather_key_with(chars, oa, d, la, load), kb = gather_key_with(chars, ob, d, lb, load);
+        if (ka != kb) {
+            const uint32_t c = d + common_bytes(ka, kb);
+            return c < limit ? c : limit;
+        }
+        d += 8;
+        if (d >= limit) return limit;
+    }
+    const uintptr_t xa = (uintptr_t)(chars + oa + d), xb = (uintptr_t)(chars + ob + d);
+    const uint64_t* pa = (const uint64_t*)(xa & ~(uintptr_t)7);
+    const uint64_t* pb = (const uint64_t*)(xb & ~(uintptr_t)7);
+    const uint32_t sa = 8 * (uint32_t)(xa & 7), sb = 8 * (uint32_t)(xb & 7);
+    // words from pa (pb) on that hold a character of the string
+    const uint32_t na = (uint32_t)(((xa & 7) + (la - d) + 7) >> 3), nb = (uint32_t)(((xb & 7) + (lb - d) + 7) >> 3);
+    uint64_t ca = load(pa), cb = load(pb);  // they hold character d
+    for (uint32_t u = 1;; u += AHEAD) {
+        uint64_t wa[AHEAD], wb[AHEAD];
+        for (uint32_t v = 0; v < AHEAD; ++v) {
+            wa[v] = u + v < na ? load(pa + u + v) : 0ull;
+            wb[v] = u + v < nb ? load(pb + u + v) : 0ull;
+        }
+        for (uint32_t v = 0; v < AHEAD; ++v) {
+            const uint64_t ga = sa ? (ca >> sa) | (wa[v] << (64 - sa)) : ca;
+            const uint64_t gb = sb ? (cb >> sb) | (wb[v] << (64 - sb)) : cb;
+            uint64_t x = ga ^ gb;
+            const uint32_t m = limit - d;  // > 0
+            if (m < 8) x &= (1ull << (8 * m)) - 1;
+            if (x) return d + ((uint32_t)__builtin_ctzll(x) >> 3);
+            d += 8;
+            if (d >= limit) return limit;
+            ca = wa[v];
+            cb = wb[v];
+        }
+    }
+}
+
 // Key format of a sort.  Byte keys (bpc = 0): 8 characters per word, as
 // above.  Alphabet-compressed keys (alphabet compression, §4.6.1): when the
 // strings use at most 15 distinct bytes, a character is coded as 1 + its

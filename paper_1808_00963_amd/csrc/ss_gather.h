@@ -58,4 +58,14 @@ __device__ __forceinline__ uint32_t lcp_from(const uint8_t* chars, uint64_t oa, 
     return limit;
 }
 
+// lcp_from with each string's words read once (lcp_stream_with in
+// ss_device.h): AHEAD words per string per memory round trip at the
+// registers lcp_from needs for half as many.
+template <uint32_t AHEAD = 2>
+__device__ __forceinline__ uint32_t lcp_stream(const uint8_t* chars, uint64_t oa, uint32_t la, uint64_t ob, uint32_t lb,
+                                               uint32_t from, uint32_t cap = ~0u) {
+    return lcp_stream_with<AHEAD>(chars, oa, la, ob, lb, from, cap,
+                                  [](const uint64_t* q) { return __builtin_nontemporal_load(q); });
+}
+
 }  // namespace ss

@@ -1017,7 +1017,10 @@ __device__ void dev_base_wave_run(const Work& w, const Params& p, int cur, const
             const uint64_t ob = p.offsets[b];
             const uint32_t lb = (uint32_t)(p.offsets[b + 1] - ob);
             // (a lookahead only where the registers allow it at the kernel's occupancy)
-            atomicMin(&RMIN[wv][RS[r]], lcp_from<E == 4 ? 2 : 1>(p.chars, oa, la, ob, lb, D[r] + kf_step(fh)));
+            uint32_t l;
+            if constexpr (E == 4) l = lcp_stream<4>(p.chars, oa, la, ob, lb, D[r] + kf_step(fh));
+            else l = lcp_from<1>(p.chars, oa, la, ob, lb, D[r] + kf_step(fh));
+            atomicMin(&RMIN[wv][RS[r]], l);
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
@@ -1354,7 +1357,7 @@ __device__ void dev_base_wg(const Work& w, const Params& p, int cur, uint32_t it
                 const uint32_t a = pr_idx(A[i]), b = pr_idx(A[rs]);
                 const uint64_t oa = p.offsets[a], ob = p.offsets[b];
                 const uint32_t la = (uint32_t)(p.offsets[a + 1] - oa), lb = (uint32_t)(p.offsets[b + 1] - ob);
-                atomicMin(&rmin[rs], lcp_from<4>(p.chars, oa, la, ob, lb, dep[i] + kf_step(fh)));
+                atomicMin(&rmin[rs], lcp_stream<4>(p.chars, oa, la, ob, lb, dep[i] + kf_step(fh)));
             }
         }
         __syncthreads();

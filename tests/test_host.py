@@ -168,6 +168,80 @@ def test_gather_exhaustive_with_guard_pages():
     assert r.stdout.startswith("ok ") and int(r.stdout.split()[1]) > 100000
 
 
+LCP_CHILD = r"""
+import ctypes, mmap, random, sys
+sys.path.insert(0, sys.argv[1])
+import paper_1808_00963_amd as ss
+lib = ss.lib()
+libc = ctypes.CDLL(None)
+libc.mprotect.argtypes = [ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int]
+PAGE = mmap.PAGESIZE
+buf = mmap.mmap(-1, 3 * PAGE)
+base = ctypes.addressof(ctypes.c_char.from_buffer(buf))
+mid = base + PAGE
+rng = random.Random(11)
+assert libc.mprotect(base, PAGE, 0) == 0 and libc.mprotect(mid + PAGE, PAGE, 0) == 0
+
+
+def brute(a, b, frm, cap):
+    lim = min(len(a), len(b), cap)
+    d = min(frm, lim)
+    while d < lim and a[d] == b[d]:
+        d += 1
+    return d
+
+
+checked = 0
+for trial in range(6000):
+    # two strings sharing a prefix of random length, placed against the
+    # unreadable pages (one at the start of the page, one at its end) or
+    # anywhere inside, at every alignment
+    common = rng.choice([0, 1, 7, 8, 9, 15, 16, 17, 31, 33, 64, 100, 257, 700])
+    la = common + rng.choice([0, 0, 1, 2, 5, 8, 13, 40])
+    lb = common + rng.choice([0, 0, 1, 3, 6, 8, 20, 41])
+    la, lb = min(la, 1500), min(lb, 1500)
+    head = bytes(rng.randrange(256) for _ in range(common))
+    a = (head + bytes(rng.randrange(256) for _ in range(la)))[:la]
+    b = (head + bytes(rng.randrange(256) for _ in range(lb)))[:lb]
+    if rng.random() < 0.3 and la == lb and la > common:  # equal strings
+        b = a
+    sa = rng.choice([0, rng.randrange(0, 8), rng.randrange(0, 100)])
+    sb = PAGE - lb - rng.choice([0, rng.randrange(0, 8), rng.randrange(0, 100)])
+    if sa + la > sb:
+        sb = PAGE - lb
+        if sa + la > sb:
+            continue
+    ctypes.memset(mid, 0, PAGE)
+    ctypes.memmove(mid + sa, a, la)
+    ctypes.memmove(mid + sb, b, lb)
+    frm = rng.randrange(0, common + 1)
+    cap = rng.choice([0xFFFFFFFF, 0xFFFFFFFF, rng.randrange(0, 1600)])
+    want = brute(a, b, frm, cap)
+    for ahead in (1, 2, 4):
+        # the pointer passed is mid - shift (offsets count from it)
+        shift = rng.randrange(0, 8)
+        got = lib.ss_host_lcp_stream(ctypes.c_void_p(mid - shift), sa + shift, la, sb + shift, lb, frm, cap, ahead)
+        if got != want:
+            print(f"MISMATCH la={la} lb={lb} common={common} sa={sa} sb={sb} from={frm} cap={cap} "
+                  f"ahead={ahead}: {got} != {want}")
+            sys.exit(1)
+        checked += 1
+print(f"ok {checked}")
+"""
+
+
+def test_lcp_scan_with_guard_pages():
+    """The base cases' common-prefix scan (host loads, the kernels' address
+    arithmetic) against a character-by-character LCP, for strings sharing
+    prefixes of 0 to 700 bytes, every alignment, caps, and the strings
+    placed against unreadable pages on either side: a read of a word
+    without string data would kill the child."""
+    import sys
+    r = subprocess.run([sys.executable, "-c", LCP_CHILD, ROOT], capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0, f"child exit {r.returncode}: {r.stdout[-500:]} {r.stderr[-500:]}"
+    assert r.stdout.startswith("ok ") and int(r.stdout.split()[1]) > 10000
+
+
 # ---- alphabet-compressed keys (alphabet compression, section 4.6.1) ----
 
 def packed_by_definition(s: bytes, h: int, alphabet):
