@@ -1357,7 +1357,7 @@ __device__ void dev_base_wg(const Work& w, const Params& p, int cur, uint32_t it
                 const uint32_t a = pr_idx(A[i]), b = pr_idx(A[rs]);
                 const uint64_t oa = p.offsets[a], ob = p.offsets[b];
                 const uint32_t la = (uint32_t)(p.offsets[a + 1] - oa), lb = (uint32_t)(p.offsets[b + 1] - ob);
-                atomicMin(&rmin[rs], lcp_stream<4>(p.chars, oa, la, ob, lb, dep[i] + kf_step(fh)));
+                atomicMin(&rmin[rs], lcp_stream<8>(p.chars, oa, la, ob, lb, dep[i] + kf_step(fh)));
             }
         }
         __syncthreads();
