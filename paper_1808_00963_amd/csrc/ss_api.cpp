@@ -864,6 +864,12 @@ ss_status run_suffix_array(ss_ctx* ctx, const uint8_t* text, uint32_t n, uint32_
     } guard{ctx, ctx->cfg};
     ctx->cfg.bucket_target = std::max<uint32_t>(ctx->cfg.bucket_target, 256u);
     ctx->cfg.alphabet = SS_ALPHABET_BYTES;  // windows and name pairs are binary already
+    // the rounds' sorts need different numbers of levels (the first sorts
+    // every suffix, later ones the unfinished few), so a level count
+    // carried over from the previous round would send deeper rounds to the
+    // persistent tail; the host reads each level's counts instead (every
+    // round synchronises anyway)
+    ctx->cfg.mode = SS_MODE_HOST_LEVELS;
 
     SaArgs a{};
     a.n = n;
