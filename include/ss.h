@@ -98,7 +98,12 @@ typedef struct {
                                    read the level's work counts on the device,
                                    as many levels as the context's last sort
                                    needed, then one persistent launch runs any
-                                   levels left; no host synchronisation.
+                                   levels left; no host synchronisation.  The
+                                   persistent launch is the slow form: a
+                                   context that alternates between inputs of
+                                   different depth (or a first sort deeper
+                                   than 4 levels) pays for it once per deeper
+                                   sort; HOST_LEVELS avoids it.
                                    SS_MODE_PERSISTENT: the whole sort in ONE
                                    persistent launch that walks the levels on
                                    the device.  SS_MODE_HOST_LEVELS: the host
