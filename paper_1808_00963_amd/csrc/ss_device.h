@@ -182,29 +182,46 @@ SS_HD uint32_t kf_chars(const KeyFmt& f, uint64_t key) {
 SS_HD uint32_t kf_tail(const KeyFmt& f, uint64_t key, uint32_t rc) { return f.bpc ? kf_chars(f, key) : rc; }
 // The compressed key of the string [off, off + len) at depth h: its next
 // min(len - h, cpw) bytes coded, most significant first, 0 past the end.
-// Reads, through `load`, only the aligned words that hold those bytes.
-// *miss is set when one of them is not in the set.
+// Reads, through `load`, only the aligned words that hold those bytes, all
+// of them at once (at most five), aligns them into 8-byte groups and codes
+// every character position unrolled for the code width BPC.  *miss is set
+// when one of the bytes is not in the set.
+template <uint32_t BPC, typename Load>
+SS_HD uint64_t gather_packed_fixed(const uint8_t* chars, uint64_t off, uint32_t h, uint32_t len, const KeyFmt& f,
+                                   Load load, bool* miss) {
+    constexpr uint32_t CPW = 64 / BPC, NG = (CPW + 7) / 8;
+    uint32_t rem = len > h ? len - h : 0u;
+    rem = rem < CPW ? rem : CPW;
+    if (rem == 0) return 0;
+    const uintptr_t a = (uintptr_t)(chars + off + h);
+    const uint64_t* q = (const uint64_t*)(a & ~(uintptr_t)7);
+    const uint32_t sh = (uint32_t)(a & 7), nw = (sh + rem + 7) >> 3;  // words that hold the characters
+    uint64_t wd[NG + 1];
+    for (uint32_t u = 0; u <= NG; ++u) wd[u] = u < nw ? load(q + u) : 0ull;
+    uint64_t key = 0;
+    bool bad = false;
+    for (uint32_t g = 0; g < NG; ++g) {
+        const uint64_t grp = sh ? (wd[g] >> (8 * sh)) | (wd[g + 1] << (64 - 8 * sh)) : wd[g];
+        for (uint32_t j = 0; j < 8; ++j) {
+            const uint32_t k = 8 * g + j;
+            if (k >= CPW) break;
+            if (k < rem) {
+                const uint32_t c = (uint32_t)(grp >> (8 * j)) & 0xFFu;
+                if (!kf_has(f, c)) bad = true;
+                key |= (uint64_t)kf_code(f, c) << (64 - BPC * (k + 1));
+            }
+        }
+    }
+    if (bad) *miss = true;
+    return key;
+}
+// The same for the code width of f (2, 3 or 4 bits).
 template <typename Load>
 SS_HD uint64_t gather_packed_with(const uint8_t* chars, uint64_t off, uint32_t h, uint32_t len, const KeyFmt& f,
                                   Load load, bool* miss) {
-    uint32_t rem = len > h ? len - h : 0u;
-    rem = rem < f.cpw ? rem : f.cpw;
-    uint64_t key = 0;
-    if (rem == 0) return 0;
-    const uintptr_t a = (uintptr_t)(chars + off + h);
-    const uint64_t* p = (const uint64_t*)(a & ~(uintptr_t)7);
-    uint32_t sh = (uint32_t)(a & 7);
-    uint32_t k = 0;  // characters coded so far
-    while (k < rem) {
-        const uint64_t wd = load(p++);
-        for (; sh < 8u && k < rem; ++sh, ++k) {
-            const uint32_t c = (uint32_t)(wd >> (8 * sh)) & 0xFFu;
-            if (!kf_has(f, c)) *miss = true;
-            key |= (uint64_t)kf_code(f, c) << (64 - f.bpc * (k + 1));
-        }
-        sh = 0;
-    }
-    return key;
+    if (f.bpc == 2) return gather_packed_fixed<2>(chars, off, h, len, f, load, miss);
+    if (f.bpc == 3) return gather_packed_fixed<3>(chars, off, h, len, f, load, miss);
+    return gather_packed_fixed<4>(chars, off, h, len, f, load, miss);
 }
 
 // LCP contribution of one word: the strings agree on the first
