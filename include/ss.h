@@ -455,8 +455,9 @@ uint64_t ss_host_key(const uint8_t* s, uint64_t len, uint64_t h, uint32_t* r_out
 uint64_t ss_host_gather_key(const uint8_t* chars, uint64_t off, uint32_t h, uint32_t len);
 
 /* The base cases' common-prefix scan (the LCP of two strings known to
- * agree on their first `from` characters, at most min(la, lb, cap); the
- * "last compared word" of section 4.2.8's LCP computation) on the host:
+ * agree on their first `from` characters, at most min(la, lb, cap): the
+ * LCPs of neighbours inside a base case, section 4.2.8, a role LCP-insertion
+ * sort, Algorithm 4.6, plays in the paper) on the host:
  * strings chars[oa, oa + la) and chars[ob, ob + lb), each string's aligned
  * words read once, `ahead` (1, 2 or 4) words per string per step.  Reads
  * only aligned words that hold characters of the strings; the caller
