@@ -162,3 +162,25 @@ def test_empty_text_and_context_reuse(ctx):
     p, l = gpu_sort(c, o, ctx=ctx)
     assert_equal_to_oracle(c, o, p, l)
     assert ctx.last_error() == ss.SS_OK
+
+
+def test_plain_sort_after_a_large_suffix_array():
+    """One context: a suffix array of 2^21 characters (its sorts run with a
+    bucket target of at least 256 and host-read level counts), then plain
+    sorts of 2^21 and 2^22 Markov strings, which need the pools of the
+    default bucket target of 64 and the device-driven levels: both equal to
+    the oracle, and the context reports no error."""
+    import paper_1808_00963_amd as ss
+    from gpu_util import assert_equal_to_oracle, gpu_sort
+    note("case sa then plain sorts")
+    c2 = ss.Context()
+    t = gen.text("dna", 1 << 21, 9)
+    sa, _, _ = gpu_sa(c2, t)
+    assert np.array_equal(sa, oracle.suffix_array(t))
+    for n in (1 << 21, 1 << 22):
+        c, o = gen.generate("markov", n, 3)
+        p, l = gpu_sort(c, o, ctx=c2)
+        assert_equal_to_oracle(c, o, p, l, full=False, label=f"markov {n} after the suffix array")
+    assert c2.last_error() == ss.SS_OK
+    cfg = c2.config
+    assert cfg.bucket_target == 64 and cfg.mode == ss.MODE_LEVELS
